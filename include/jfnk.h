@@ -1,0 +1,161 @@
+/*
+ * jfnk.h -- C-ABI of the MI355X implicit-step library.
+ *
+ * One Crank-Nicolson implicit time step of the compressible Euler equations
+ * with gravity and thermal (radiative) conduction, solved by Jacobian-free
+ * Newton-Krylov with a physics-based preconditioner, after Goffrey et al.,
+ * "Benchmarking the Multi-dimensional Stellar Implicit Code MUSIC"
+ * (arXiv:1610.10053), section 2:
+ *   - equations (1)-(3) (discretised in total-energy conservative form),
+ *     ideal-gas closure, conductivity chi = chi0 T^3 (stand-in for eq. 4);
+ *   - staggered grid: rho and E at cell centres, momentum on cell faces;
+ *     upstream linear reconstruction limited by van Leer;
+ *   - ghost-cell boundaries: periodic, or reflecting/stress-free walls with
+ *     linearly extrapolated temperature and hydrostatic ghost density
+ *     (section 3.1) and a constant-luminosity wall energy flux (section 6);
+ *   - Crank-Nicolson in time, Newton-Raphson, restarted GMRES, Jacobian-free
+ *     matrix-vector products, a semi-implicit physics-based preconditioner
+ *     that treats sound waves (and optionally thermal diffusion) implicitly;
+ *   - time step from the CFL numbers of eqs. (5)-(7), the most restrictive
+ *     constraint applying (section 2.1).
+ *
+ * Conventions
+ *   - Every function returns int: 0 success; > 0 solver outcome
+ *     (1 Newton did not converge, 2 GMRES stagnated, 3 non-finite residual);
+ *     < 0 usage or system error (-1 bad argument, -2 out of device memory,
+ *     -3 HIP runtime error, -4 unsupported configuration).  jfnk_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - State layout: one array of (2 + ndim) * N doubles, N = n[0]*n[1]*n[2]:
+ *     rho, E, m_x, m_y (, m_z) one after another, each in C order with x
+ *     fastest (index i + n0*(j + n1*k)).  m_d at index c is the momentum on
+ *     the lower face of cell c along d.  Along a wall direction the face with
+ *     i_d = 0 is the wall: its entry must be 0, stays 0 and is not an unknown.
+ *   - Pointers flagged on_device = 1 are device (HIP) pointers on the
+ *     problem's device; on_device = 0 means host memory.  The library copies
+ *     in and out; callers keep ownership of their buffers.
+ *   - All device work is enqueued on the HIP stream given at creation
+ *     (NULL = the default stream).  Calls that return host values
+ *     synchronise that stream.  A problem may be used by one host thread at
+ *     a time.
+ */
+#ifndef JFNK_H
+#define JFNK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { JFNK_BC_PERIODIC = 0, JFNK_BC_WALL = 1 };
+enum { JFNK_PC_NONE = 0, JFNK_PC_ACOUSTIC = 1, JFNK_PC_ACOUSTIC_DIFFUSION = 2 };
+enum { JFNK_PCS_MULTIGRID = 0, JFNK_PCS_ADI = 1 };
+enum { JFNK_FP64 = 0, JFNK_MIXED = 1 };
+
+/* Problem: grid, boundaries, gas and forces (section 2). */
+typedef struct {
+    int ndim;          /* 2 or 3 */
+    int n[3];          /* cells per axis (n[2] = 1 in 2D); periodic axes need even n >= 4 */
+    double lo[3], hi[3];
+    int bc[3];         /* JFNK_BC_PERIODIC or JFNK_BC_WALL (both ends of an axis) */
+    double gamma;      /* ideal-gas ratio of specific heats, p = rho T */
+    double g[3];       /* constant gravitational acceleration (body force) */
+    double chi0;       /* conductivity chi = chi0 T^3 (0: no conduction) */
+    int heat_balance;  /* 1: add the time-independent source that cancels the
+                          conductive divergence of the creation state */
+} jfnk_problem_desc;
+
+/* Solver options.  Defaults (jfnk_default_opts): rtol 1e-8, atol 1e-14,
+ * corr_tol 1e-12, newton_max 20, GMRES(30) x 10 cycles, eta 1e-4, acoustic
+ * preconditioner with one multigrid V(2,2) cycle, FP64. */
+typedef struct {
+    double newton_rtol;     /* stop when |S^-1 F| <= max(rtol |S^-1 F0|, atol sqrt(N_unknowns)) */
+    double newton_atol;
+    double newton_corr_tol; /* ... or when max |d rho / rho| of a Newton correction <= corr_tol */
+    int newton_max;
+    int gmres_restart;      /* Krylov basis size m (<= 64) */
+    int gmres_max_cycles;
+    double gmres_eta;       /* relative linear tolerance */
+    int pc;                 /* JFNK_PC_* */
+    int pc_solver;          /* JFNK_PCS_*: elliptic solves by multigrid or ADI lines */
+    int mg_nu1, mg_nu2, mg_nuc, mg_cycles;
+    int prec;               /* JFNK_FP64, or JFNK_MIXED: FP32 preconditioner and Krylov basis */
+    double cfl_hydro;       /* eq. (5) target */
+    double cfl_adv_max;     /* eq. (6) cap, 0 = off */
+    double cfl_rad_max;     /* eq. (7) cap with D = chi/(rho c_P), 0 = off */
+    double dt_max;          /* 0 = off */
+    int max_halvings;       /* step retries at dt/2 after a failed Newton solve */
+} jfnk_solver_opts;
+
+/* Statistics of the last step. */
+typedef struct {
+    double t, dt, cfl_hydro, cfl_adv, cfl_rad;
+    double rel_res;       /* final |S^-1 F| / |S^-1 F0| */
+    double max_rel_corr;  /* max |d rho / rho| of the last Newton correction */
+    double mass_drift, energy_drift;  /* relative change of sum rho, sum E */
+    double f0, f;         /* initial and final |S^-1 F| */
+    int newton_its, gmres_its, rejections, status;
+    double wall_ms;       /* host wall time of the call */
+} jfnk_step_stats;
+
+typedef struct jfnk_problem jfnk_problem;
+
+/* Fill opts with the defaults listed above. */
+void jfnk_default_opts(jfnk_solver_opts* opts);
+
+/* Device bytes a problem would allocate (admission control). */
+int jfnk_footprint_bytes(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, size_t* out);
+
+/* Create a problem with initial state u0 (layout above).  The frozen wall
+ * conductive fluxes and the heat-balance source are computed from u0.
+ * hip_stream: a hipStream_t (NULL for the default stream). */
+int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts,
+                        const double* u0, int on_device, void* hip_stream, jfnk_problem** out);
+int jfnk_destroy_problem(jfnk_problem* p);
+
+/* Copy the state in or out; t is carried separately (jfnk_set_time). */
+int jfnk_set_state(jfnk_problem* p, const double* u, int on_device);
+int jfnk_get_state(jfnk_problem* p, double* u, int on_device);
+int jfnk_set_time(jfnk_problem* p, double t);
+int jfnk_set_opts(jfnk_problem* p, const jfnk_solver_opts* opts);
+
+/* One adaptive implicit step: dt from the CFL limits of the current state,
+ * Newton solve, and on failure state restored and dt halved up to
+ * max_halvings times.  On a final failure the state is u^n and the status
+ * code is returned. */
+int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out);
+
+/* One Crank-Nicolson step at the given dt with no retry.  On failure the
+ * state is restored to u^n. */
+int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out);
+
+/* ---- component entry points (operate on caller buffers of nvec doubles) ---- */
+
+/* R(u): right-hand side of eqs. (1)-(3) on the staggered grid. */
+int jfnk_eval_rhs(jfnk_problem* p, const double* u, double* R, int on_device);
+/* b = u^n + dt/2 R(u^n) */
+int jfnk_eval_cn_old(jfnk_problem* p, const double* un, double dt, double* b, int on_device);
+/* F(u) = (u - b) - dt/2 R(u) */
+int jfnk_eval_residual(jfnk_problem* p, const double* u, const double* b, double dt, double* F,
+                       int on_device);
+/* dt and limits for state u: out[0..8] = dt, max (|u|+c)/dx, max |u|/dx,
+ * max D/dx^2, scales rho_ref, E_ref, m_ref (x3).  Also sets the problem's
+ * variable scales S used by jv and precond. */
+int jfnk_eval_time_step(jfnk_problem* p, const double* u, double* out9, int on_device);
+/* Override the variable scales S (5 values: rho, E, m_x, m_y, m_z). */
+int jfnk_set_scales(jfnk_problem* p, const double* s5);
+/* Jacobian-free product in scaled variables:
+ * w = S^-1 (F(u + eps S v) - F(u)) / eps, eps = sqrt(2^-52)(1 + rms(S^-1 u))/rms(v). */
+int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, const double* v,
+                  double* w, int on_device);
+/* Preconditioner with coefficients frozen at u: z = S^-1 P^-1 (S v). */
+int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z,
+                       int on_device);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* jfnk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JFNK_H */

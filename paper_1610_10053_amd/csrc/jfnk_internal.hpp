@@ -1,0 +1,118 @@
+// Internal definitions shared by the HIP kernels and the host driver of the
+// implicit-step library.  Grid geometry, boundary handling and the small
+// device helpers (limiter, upstream extrapolation, reductions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace jfnk {
+
+constexpr int kBlock = 256;        // threads per block of the sweep kernels
+constexpr int kMaxRestart = 64;    // largest Krylov basis
+constexpr int kRedBlocks = 1024;   // blocks of the multi-dot reductions
+
+enum Bc : int { PERIODIC = 0, WALL = 1 };
+
+// Geometry and physics constants passed by value to every kernel.
+struct Grid {
+    int ndim;
+    int n[3];
+    int bc[3];
+    long N;          // cells
+    long nvec;       // (2 + ndim) * N
+    long stride[3];  // 1, n0, n0*n1
+    double dx[3], idx[3];
+    double gamma, gm1, g[3], chi0;
+    int heat_balance;
+    int has_wall, has_chi;
+};
+
+// Cell coordinates from a flat index.
+struct Ijk {
+    int v[3];
+};
+
+__device__ __forceinline__ Ijk cell_coords(const Grid& G, long c) {
+    Ijk r;
+    r.v[0] = (int)(c % G.n[0]);
+    long t = c / G.n[0];
+    r.v[1] = (int)(t % G.n[1]);
+    r.v[2] = (int)(t / G.n[1]);
+    return r;
+}
+
+__device__ __forceinline__ long flat(const Grid& G, int i, int j, int k) {
+    return (long)i + (long)G.n[0] * ((long)j + (long)G.n[1] * (long)k);
+}
+
+// Flat index of the cell shifted by s along axis d, with periodic wrap.
+// The caller guarantees the shift stays inside along a wall axis.
+__device__ __forceinline__ long shifted(const Grid& G, const Ijk& q, int d, int s) {
+    int a = q.v[d] + s;
+    const int n = G.n[d];
+    if (a < 0) a += n;
+    else if (a >= n) a -= n;
+    return flat(G, d == 0 ? a : q.v[0], d == 1 ? a : q.v[1], d == 2 ? a : q.v[2]);
+}
+
+// Index of the transverse position of a wall-normal axis d (for the frozen
+// wall-flux arrays): r1 = (d+1)%3 fastest.
+__device__ __forceinline__ long transverse(const Grid& G, const Ijk& q, int d) {
+    const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+    return (long)q.v[r1] + (long)G.n[r1] * (long)q.v[r2];
+}
+
+// van Leer's harmonic limiter of two one-sided differences.
+__device__ __forceinline__ double van_leer(double a, double b) {
+    const double ab = a * b;
+    return ab > 0.0 ? (ab + ab) / (a + b) : 0.0;
+}
+
+// Upstream linear extrapolation: operands are selected first and then one
+// shared expression is evaluated, so that mirror-image faces give
+// mirror-image values bit for bit.
+__device__ __forceinline__ double upstream(double vel, double ql, double sl, double qr, double sr) {
+    const bool left = vel >= 0.0;
+    const double qu = left ? ql : qr;
+    const double su = left ? 0.5 * sl : -0.5 * sr;
+    return qu + su;
+}
+
+// Block-wide sum of one double per thread (kBlock threads, wave64).
+// Fixed reduction order, so results are reproducible run to run.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    }
+    return s;  // valid in thread 0
+}
+
+__device__ __forceinline__ double block_max(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        s = sh[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, sh[w]);
+    }
+    return s;
+}
+
+inline int grid_blocks(long n, int block = kBlock) {
+    long b = (n + block - 1) / block;
+    return (int)(b < 1 ? 1 : b);
+}
+
+}  // namespace jfnk

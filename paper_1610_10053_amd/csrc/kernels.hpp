@@ -1,0 +1,163 @@
+// Kernel-side data views and the host launchers of every kernel of the
+// implicit-step library.
+#pragma once
+
+#include "jfnk_internal.hpp"
+
+namespace jfnk {
+
+struct Scales5 {
+    double v[5];
+};
+
+// A state, optionally perturbed along v: u + (eps * scale[f]) * v, with the
+// step eps read from device memory (v may be null).
+struct StateView {
+    const double* u;
+    const double* v;
+    const double* eps;
+    double scale[5];
+    long N;
+};
+
+// Cell primitives and face velocities of one state.
+struct Prim {
+    double* rho;
+    double* uf[3];
+    double* p;
+    double* eps;
+    double* T;
+    double* chi;
+    double* q;
+};
+
+// Mass and total-energy fluxes on the lower face of each cell, per axis.
+struct Flux {
+    double* fr[3];
+    double* fe[3];
+};
+
+// Frozen conductive fluxes through the lower/upper wall of each wall axis,
+// indexed by the transverse position (null when absent).
+struct WallFlux {
+    const double* lo[3];
+    const double* hi[3];
+};
+
+enum OutMode : int { OUT_RHS = 0, OUT_CN_OLD = 1, OUT_RESIDUAL = 2, OUT_JV = 3 };
+
+struct OutSpec {
+    int mode;
+    double h;            // dt / 2
+    double* out;         // R, b, F or w
+    double* out2;        // F (OUT_CN_OLD)
+    const double* b;     // Crank-Nicolson old-time term
+    const double* Fu;    // F(u) for OUT_JV
+    double scale[5];     // variable scales for the fused norm
+    double* partial;     // per-block sum of (F/S)^2, or null
+};
+
+// residual.hip
+void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                     const double* sbal, const OutSpec& o, hipStream_t stream);
+void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream);
+void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream);
+
+// krylov.hip: deterministic two-stage reductions and Krylov vector kernels
+// partial layout: part[col * nblk + block]
+void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
+void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
+void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale5, double* part, int nblk,
+                         hipStream_t stream);
+template <typename T>
+void launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, int nblk,
+                 hipStream_t stream);
+template <typename T>
+void launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
+                        int nblk, bool want_dots, hipStream_t stream);
+template <typename T>
+void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream);
+template <typename T>
+void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, hipStream_t stream);
+void launch_add(double* x, const double* z, long n, hipStream_t stream);
+void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* scale5, hipStream_t stream);
+void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t stream);
+void launch_update_state(double* u, const double* x, const Grid& G, const double* scale5, double* part,
+                         int nblk, hipStream_t stream);
+void launch_copy(double* dst, const double* src, long n, hipStream_t stream);
+void launch_zero_walls(double* u, const Grid& G, hipStream_t stream);
+void launch_sum(const double* x, long n, double* part, int nblk, hipStream_t stream);
+template <typename T>
+void launch_widen(const T* v, double* out, long n, hipStream_t stream);
+
+// precond.hip
+// One level of the geometric multigrid hierarchy of an operator
+//   (M x)_c = sig_c x_c + sum over faces f of c of a_f (x_c - x_neighbour(f))
+// in precision R (FP64, or FP32 in the mixed form).
+constexpr int kMaxLevels = 16;
+template <typename R>
+struct LevelT {
+    int n[3];
+    long N;
+    R* sig;   // diagonal mass term
+    R* a[3];  // face couplings on the lower face of each cell (0 on walls)
+    R* D;     // sig + sum of the cell's couplings
+    R* x;
+    R* b;
+};
+template <typename R>
+struct LevelSet {
+    LevelT<R> L[kMaxLevels];
+};
+
+struct PcCoef {
+    double* hf[3];    // face enthalpy
+    double* kap[3];   // acoustic couplings tau^2 (gamma-1) h_f / dx^2
+    double* beta[3];  // conduction couplings tau chi_f / dx^2
+    double* W;        // (gamma-1)/rho
+    double tau;
+};
+
+void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
+                    hipStream_t stream);
+// which = 0: acoustic operator (sig = 1, a = kap); 1: conduction (sig = 1/W, a = beta)
+template <typename R>
+void launch_level0(const Grid& G, const PcCoef& C, int which, const LevelT<R>& L0, hipStream_t stream);
+template <typename R>
+void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream);
+template <typename R>
+void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream);
+// V-cycles on b of level 0; levels >= coarse_from run in one single-block kernel
+template <typename R>
+void mg_vcycle(const Grid& G, const LevelSet<R>& S, int nlev, int coarse_from, int nu1, int nu2, int nuc,
+               bool first, hipStream_t stream);
+
+// r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
+template <typename R>
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc, R* rp,
+                   hipStream_t stream);
+// conduction block: rE = S_E v_E + tau D(chi_f G s)
+template <typename R>
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const R* s, Scales5 sc, double* rE,
+                         hipStream_t stream);
+// dm = r_m - tau G dp, drho = r_rho - tau D dm, dE = r_E - tau D(h_f dm),
+// z = S^-1 delta and per-block |z|^2
+template <typename R>
+void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp, Scales5 sc,
+                    double* z, double* part, int nblk, hipStream_t stream);
+// out = s * v[off : off + N] in precision R
+template <typename R>
+void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream);
+// z = v and per-block |z|^2 (no preconditioner)
+void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream);
+// eps of the Jacobian-free product from sum (S^-1 u)^2 and sum v^2
+void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
+                   hipStream_t stream);
+
+// ADI: solve every line along axis d of the acoustic (kind 0) or conduction
+// (kind 1) operator in place; scratch4 holds 4 N doubles
+template <typename R>
+void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, double* scratch4,
+                       hipStream_t stream);
+
+}  // namespace jfnk

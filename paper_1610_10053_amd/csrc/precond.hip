@@ -1,0 +1,589 @@
+// Physics-based preconditioner (section 2 of Goffrey et al. 2016): a
+// semi-implicit approximate solve in which sound waves, and optionally
+// thermal diffusion, are implicit while advection and gravity are left to
+// the Krylov iteration.  Coefficients are frozen at the Newton iterate.
+//   conduction (optional):  (1/W - tau D chi_f G) s = r_E,
+//                           r_E <- r_E + tau D(chi_f G s)
+//   acoustic:               (I - tau^2 D (gamma-1) h_f G) dp
+//                               = (gamma-1)(r_E - tau D(h_f r_m))
+//                           dm = r_m - tau G dp, drho = r_rho - tau D dm,
+//                           dE = r_E - tau D(h_f dm)
+// The elliptic solves use geometric multigrid V-cycles with red-black
+// Gauss-Seidel smoothing (default) or alternating-direction line solves.
+// Divergence-form back-substitution keeps the sums of rho, E and m.
+#include "kernels.hpp"
+
+namespace jfnk {
+
+// ---------------------------------------------------------------- coefficients
+__global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __restrict__ u, Prim P, PcCoef C,
+                                                    double tau) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    const double* E = u + G.N;
+    for (int d = 0; d < G.ndim; ++d) {
+        double hf = 0.0, chif = 0.0;
+        if (!(G.bc[d] == WALL && q.v[d] == 0)) {
+            const long xl = shifted(G, q, d, -1);
+            const double hl = (E[xl] + P.p[xl]) / P.rho[xl];
+            const double hr = (E[c] + P.p[c]) / P.rho[c];
+            hf = 0.5 * (hl + hr);
+            if (G.has_chi) chif = 0.5 * (P.chi[xl] + P.chi[c]);
+        }
+        const double i2 = G.idx[d] * G.idx[d];
+        C.hf[d][c] = hf;
+        C.kap[d][c] = ((tau * tau) * G.gm1) * hf * i2;
+        C.beta[d][c] = (tau * chif) * i2;
+    }
+    C.W[c] = G.gm1 / P.rho[c];
+}
+
+void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
+                    hipStream_t stream) {
+    hipLaunchKernelGGL(k_pc_coef, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, u, P, C, 0.5 * dt);
+}
+
+// ---------------------------------------------------------------- multigrid level helpers
+struct LIjk {
+    int v[3];
+};
+template <typename R>
+__device__ __forceinline__ LIjk lcoords(const LevelT<R>& L, long c) {
+    LIjk r;
+    r.v[0] = (int)(c % L.n[0]);
+    const long t = c / L.n[0];
+    r.v[1] = (int)(t % L.n[1]);
+    r.v[2] = (int)(t / L.n[1]);
+    return r;
+}
+template <typename R>
+__device__ __forceinline__ long lflat(const LevelT<R>& L, int i, int j, int k) {
+    return (long)i + (long)L.n[0] * ((long)j + (long)L.n[1] * (long)k);
+}
+// neighbour along d on a level: periodic wrap, -1 beyond a wall
+template <typename R>
+__device__ __forceinline__ long lnb(const Grid& G, const LevelT<R>& L, LIjk q, int d, int s) {
+    int a = q.v[d] + s;
+    if (a < 0 || a >= L.n[d]) {
+        if (G.bc[d] == WALL) return -1;
+        a = a < 0 ? a + L.n[d] : a - L.n[d];
+    }
+    q.v[d] = a;
+    return lflat(L, q.v[0], q.v[1], q.v[2]);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_level0(Grid G, PcCoef C, int which, LevelT<R> L) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    L.sig[c] = which == 0 ? (R)1.0 : (R)(1.0 / C.W[c]);
+    for (int d = 0; d < G.ndim; ++d) L.a[d][c] = which == 0 ? (R)C.kap[d][c] : (R)C.beta[d][c];
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_level_diag(Grid G, LevelT<R> L) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    const LIjk q = lcoords(L, c);
+    R den = L.sig[c];
+    for (int d = 0; d < G.ndim; ++d) {
+        const long up = lnb(G, L, q, d, 1);
+        const R alo = L.a[d][c], ahi = up >= 0 ? L.a[d][up] : (R)0.0;
+        den = den + alo;
+        den = den + ahi;
+    }
+    L.D[c] = den;
+}
+
+// coarse coefficients by re-discretisation: sig averaged over the children,
+// face couplings averaged over the fine faces of a coarse face and divided by
+// 4 (couplings scale as 1/dx^2)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Cl.N) return;
+    const LIjk q = lcoords(Cl, c);
+    const int nch = 1 << G.ndim;
+    const R inv_ch = (R)(1.0 / nch), inv_face = (R)(1.0 / ((nch / 2) * 4));
+    const int kk = G.ndim > 2 ? 2 : 1;
+    R s = 0.0;
+    for (int dk = 0; dk < kk; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di)
+                s = s + F.sig[lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2])];
+    Cl.sig[c] = s * inv_ch;
+    for (int d = 0; d < G.ndim; ++d) {
+        R t = 0.0;
+        for (int dk = 0; dk < kk; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di) {
+                    const int off[3] = {di, dj, dk};
+                    if (off[d] != 0) continue;
+                    t = t + F.a[d][lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2])];
+                }
+        Cl.a[d][c] = t * inv_face;
+    }
+}
+
+template <typename R>
+void launch_level0(const Grid& G, const PcCoef& C, int which, const LevelT<R>& L0, hipStream_t stream) {
+    hipLaunchKernelGGL((k_level0<R>), dim3(grid_blocks(L0.N)), dim3(kBlock), 0, stream, G, C, which, L0);
+}
+template <typename R>
+void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream) {
+    hipLaunchKernelGGL((k_coarsen<R>), dim3(grid_blocks(C.N)), dim3(kBlock), 0, stream, G, F, C);
+}
+template <typename R>
+void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
+    hipLaunchKernelGGL((k_level_diag<R>), dim3(grid_blocks(L.N)), dim3(kBlock), 0, stream, G, L);
+}
+
+// ---------------------------------------------------------------- multigrid cell operations
+
+// red-black Gauss-Seidel update of one cell (first: neighbours taken as 0)
+template <typename R>
+__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, long c, bool first) {
+    const LIjk q = lcoords(L, c);
+    R num = L.b[c];
+    for (int d = 0; d < G.ndim; ++d) {
+        const long up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
+        if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : L.x[dn]);
+        if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : L.x[up]);
+    }
+    L.x[c] = num / L.D[c];
+}
+
+template <typename R>
+__device__ __forceinline__ int color_of(const LevelT<R>& L, long c) {
+    const LIjk q = lcoords(L, c);
+    return (q.v[0] + q.v[1] + q.v[2]) & 1;
+}
+
+// residual of one fine cell
+template <typename R>
+__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, long c) {
+    const LIjk q = lcoords(L, c);
+    const R xc = L.x[c];
+    R acc = L.sig[c] * xc;
+    for (int d = 0; d < G.ndim; ++d) {
+        const long up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
+        if (dn >= 0) acc = acc + L.a[d][c] * (xc - L.x[dn]);
+        if (up >= 0) acc = acc + L.a[d][up] * (xc - L.x[up]);
+    }
+    return L.b[c] - acc;
+}
+
+// coarse right-hand side: mean of the children's residuals
+template <typename R>
+__device__ __forceinline__ void restrict_cell(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, long c) {
+    const LIjk q = lcoords(Cl, c);
+    const int kk = G.ndim > 2 ? 2 : 1;
+    const R inv_ch = (R)(1.0 / (1 << G.ndim));
+    R s = 0.0;
+    for (int dk = 0; dk < kk; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di)
+                s = s + resid_cell(G, F, lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj,
+                                               G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2]));
+    Cl.b[c] = s * inv_ch;
+}
+
+// cell-centred (bi/tri)linear prolongation of the coarse correction, weights
+// 3/4 and 1/4 per axis; beyond a wall the parent value is reused
+template <typename R>
+__device__ __forceinline__ void prolong_cell(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, long c) {
+    const LIjk f = lcoords(F, c);
+    const int P[3] = {f.v[0] / 2, f.v[1] / 2, G.ndim > 2 ? f.v[2] / 2 : f.v[2]};
+    R e = 0.0;
+    for (int m = 0; m < (1 << G.ndim); ++m) {
+        int qq[3] = {P[0], P[1], P[2]};
+        R w = 1.0;
+        for (int d = 0; d < G.ndim; ++d) {
+            if (m & (1 << d)) {
+                const int off = (f.v[d] % 2 == 0) ? -1 : 1;
+                w = w * (R)0.25;
+                qq[d] += off;
+                if (qq[d] < 0 || qq[d] >= Cl.n[d]) {
+                    if (G.bc[d] == WALL) qq[d] -= off;
+                    else qq[d] = qq[d] < 0 ? qq[d] + Cl.n[d] : qq[d] - Cl.n[d];
+                }
+            } else {
+                w = w * (R)0.75;
+            }
+        }
+        e = e + w * Cl.x[lflat(Cl, qq[0], qq[1], qq[2])];
+    }
+    F.x[c] = F.x[c] + e;
+}
+
+// ---------------------------------------------------------------- multigrid kernels (multi-block levels)
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color, int first) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= L.N) return;
+    if (color_of(L, c) != color) return;
+    gs_cell(G, L, c, first != 0);
+}
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Cl.N) return;
+    restrict_cell(G, F, Cl, c);
+}
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= F.N) return;
+    prolong_cell(G, F, Cl, c);
+}
+
+// the rest of the V-cycle, levels from..nlev-1, in one workgroup
+constexpr int kCoarseThreads = 1024;
+template <typename R>
+__device__ void block_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
+    for (int s = 0; s < sweeps; ++s)
+        for (int color = 0; color < 2; ++color) {
+            for (long c = threadIdx.x; c < L.N; c += blockDim.x)
+                if (color_of(L, c) == color) gs_cell(G, L, c, first && s == 0 && color == 0);
+            __syncthreads();
+        }
+}
+template <typename R>
+__global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, LevelSet<R> S, int from, int nlev,
+                                                                   int nu1, int nu2, int nuc, int first_top) {
+    for (int l = from; l < nlev - 1; ++l) {
+        const bool first = l == from ? first_top != 0 : true;
+        block_smooth(G, S.L[l], nu1, first);
+        for (long c = threadIdx.x; c < S.L[l + 1].N; c += blockDim.x) restrict_cell(G, S.L[l], S.L[l + 1], c);
+        __syncthreads();
+    }
+    block_smooth(G, S.L[nlev - 1], nuc, nlev - 1 == from ? first_top != 0 : true);
+    for (int l = nlev - 2; l >= from; --l) {
+        for (long c = threadIdx.x; c < S.L[l].N; c += blockDim.x) prolong_cell(G, S.L[l], S.L[l + 1], c);
+        __syncthreads();
+        block_smooth(G, S.L[l], nu2, false);
+    }
+}
+
+template <typename R>
+static void vcycle_level(const Grid& G, const LevelSet<R>& S, int l, int nlev, int coarse_from, int nu1,
+                         int nu2, int nuc, bool first, hipStream_t stream) {
+    if (l >= coarse_from) {
+        hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1,
+                           nu2, nuc, first ? 1 : 0);
+        return;
+    }
+    const LevelT<R>& L = S.L[l];
+    const int nb = grid_blocks(L.N);
+    for (int s = 0; s < nu1; ++s) {
+        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+    }
+    hipLaunchKernelGGL((k_restrict<R>), dim3(grid_blocks(S.L[l + 1].N)), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    vcycle_level(G, S, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
+    hipLaunchKernelGGL((k_prolong<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    for (int s = 0; s < nu2; ++s) {
+        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, 0);
+        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+    }
+}
+
+template <typename R>
+void mg_vcycle(const Grid& G, const LevelSet<R>& S, int nlev, int coarse_from, int nu1, int nu2, int nuc,
+               bool first, hipStream_t stream) {
+    vcycle_level(G, S, 0, nlev, coarse_from, nu1, nu2, nuc, first, stream);
+}
+
+// ---------------------------------------------------------------- right-hand sides and back-substitution
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
+                                                   const double* __restrict__ rE, Scales5 sc, R* __restrict__ rp) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
+    double acc = 0.0;
+    for (int d = 0; d < G.ndim; ++d) {
+        const double* vm = v + (long)(2 + d) * G.N;
+        const double s = sc.v[2 + d];
+        const double flo = C.hf[d][c] * (s * vm[c]);
+        double fhi = 0.0;
+        if (!(G.bc[d] == WALL && q.v[d] == G.n[d] - 1)) {
+            const long up = shifted(G, q, d, 1);
+            fhi = C.hf[d][up] * (s * vm[up]);
+        }
+        acc = acc + (fhi - flo) * G.idx[d];
+    }
+    rp[c] = (R)(G.gm1 * (re - C.tau * acc));
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const double* __restrict__ v,
+                                                         const R* __restrict__ s, Scales5 sc,
+                                                         double* __restrict__ rE) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    double acc = sc.v[1] * v[G.N + c];
+    const double sc0 = (double)s[c];
+    for (int d = 0; d < G.ndim; ++d) {
+        const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+        const bool bot = G.bc[d] == WALL && q.v[d] == 0;
+        double thi = 0.0, tlo = 0.0;
+        if (!top) {
+            const long up = shifted(G, q, d, 1);
+            thi = C.beta[d][up] * ((double)s[up] - sc0);
+        }
+        if (!bot) {
+            const long dn = shifted(G, q, d, -1);
+            tlo = C.beta[d][c] * (sc0 - (double)s[dn]);
+        }
+        acc = acc + (thi - tlo);
+    }
+    rE[c] = acc;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
+                                                    const double* __restrict__ rE, const R* __restrict__ dp,
+                                                    Scales5 sc, double* __restrict__ z, double* __restrict__ part) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double ss = 0.0;
+    if (c < G.N) {
+        const Ijk q = cell_coords(G, c);
+        const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
+        const double dpc = (double)dp[c];
+        double dmlo[3], dmhi[3];
+        bool top[3];
+        long upi[3];
+        for (int d = 0; d < G.ndim; ++d) {
+            const double* vm = v + (long)(2 + d) * G.N;
+            const double s = sc.v[2 + d];
+            if (G.bc[d] == WALL && q.v[d] == 0) {
+                dmlo[d] = 0.0;
+            } else {
+                const long lo = shifted(G, q, d, -1);
+                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[lo]) * G.idx[d]);
+            }
+            top[d] = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+            dmhi[d] = 0.0;
+            upi[d] = c;
+            if (!top[d]) {
+                const long up = shifted(G, q, d, 1);
+                upi[d] = up;
+                dmhi[d] = s * vm[up] - C.tau * (((double)dp[up] - dpc) * G.idx[d]);
+            }
+        }
+        double acc = 0.0;
+        for (int d = 0; d < G.ndim; ++d) acc = acc + (dmhi[d] - dmlo[d]) * G.idx[d];
+        const double drho = sc.v[0] * v[c] - C.tau * acc;
+        acc = 0.0;
+        for (int d = 0; d < G.ndim; ++d) {
+            const double flo = C.hf[d][c] * dmlo[d];
+            const double fhi = top[d] ? 0.0 : C.hf[d][upi[d]] * dmhi[d];
+            acc = acc + (fhi - flo) * G.idx[d];
+        }
+        const double dE = re - C.tau * acc;
+        double t = drho / sc.v[0];
+        z[c] = t;
+        ss += t * t;
+        t = dE / sc.v[1];
+        z[G.N + c] = t;
+        ss += t * t;
+        for (int d = 0; d < G.ndim; ++d) {
+            t = dmlo[d] / sc.v[2 + d];
+            z[(long)(2 + d) * G.N + c] = t;
+            ss += t * t;
+        }
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t = block_sum(ss, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_field_scaled(const double* __restrict__ v, double s,
+                                                         R* __restrict__ out, long N) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < N) out[c] = (R)(s * v[c]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy_sumsq(const double* __restrict__ v, double* __restrict__ z,
+                                                       long n, double* __restrict__ part) {
+    double ss = 0.0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const double t = v[e];
+        z[e] = t;
+        ss += t * t;
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t = block_sum(ss, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBlock) k_jv_eps(const double* __restrict__ usumsq,
+                                                   const double* __restrict__ part, int nblk, double nunk,
+                                                   double* __restrict__ eps) {
+    __shared__ double sh[kBlock / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[i];
+    const double vs = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const double urms = sqrt(usumsq[0]) / sqrt(nunk);
+        const double vn = sqrt(vs) / sqrt(nunk);
+        eps[0] = vn == 0.0 ? 0.0 : sqrt(2.220446049250313e-16) * (1.0 + urms) / vn;
+    }
+}
+
+template <typename R>
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc, R* rp,
+                   hipStream_t stream) {
+    hipLaunchKernelGGL((k_pc_rhs<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, sc, rp);
+}
+template <typename R>
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const R* s, Scales5 sc, double* rE,
+                         hipStream_t stream) {
+    hipLaunchKernelGGL((k_pc_diff_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, s, sc, rE);
+}
+template <typename R>
+void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp, Scales5 sc,
+                    double* z, double* part, int nblk, hipStream_t stream) {
+    (void)nblk;
+    hipLaunchKernelGGL((k_pc_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, dp, sc, z,
+                       part);
+}
+template <typename R>
+void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream) {
+    hipLaunchKernelGGL((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
+}
+void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream) {
+    hipLaunchKernelGGL(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
+}
+void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
+                   hipStream_t stream) {
+    hipLaunchKernelGGL(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
+}
+
+// ---------------------------------------------------------------- alternating-direction line solves
+// One thread per line along axis d; Thomas algorithm, and for periodic lines
+// the Sherman-Morrison correction of a modified Thomas system.  Scratch per
+// line lives in the cell-indexed arrays cp, dp, bb, zz.
+template <typename R>
+__device__ __forceinline__ void line_row(const Grid& G, const PcCoef& C, int d, int kind, const Ijk& q0, int t,
+                                         double& a, double& b, double& cc) {
+    Ijk q = q0;
+    q.v[d] = t;
+    const long c = flat(G, q.v[0], q.v[1], q.v[2]);
+    const int n = G.n[d];
+    const bool wall = G.bc[d] == WALL;
+    const bool has_up = !(wall && t == n - 1), has_dn = !(wall && t == 0);
+    const long up = has_up ? shifted(G, q, d, 1) : -1;
+    const long dn = has_dn ? shifted(G, q, d, -1) : -1;
+    if (kind == 0) {
+        const double klo = C.kap[d][c], khi = has_up ? C.kap[d][up] : 0.0;
+        a = -klo;
+        cc = -khi;
+        b = 1.0 + (klo + khi);
+    } else {
+        const double klo = C.beta[d][c], khi = has_up ? C.beta[d][up] : 0.0;
+        const double wl = has_dn ? C.W[dn] : 0.0, wr = has_up ? C.W[up] : 0.0;
+        a = -klo * wl;
+        cc = -khi * wr;
+        b = 1.0 + (klo + khi) * C.W[c];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kBlock) k_line(Grid G, PcCoef C, int d, int kind, R* __restrict__ x,
+                                                 double* __restrict__ cp, double* __restrict__ dpv,
+                                                 double* __restrict__ x1, double* __restrict__ zz) {
+    const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+    const long nl = (long)G.n[r1] * G.n[r2];
+    const long line = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (line >= nl) return;
+    Ijk q0;
+    q0.v[d] = 0;
+    q0.v[r1] = (int)(line % G.n[r1]);
+    q0.v[r2] = (int)(line / G.n[r1]);
+    const int n = G.n[d];
+    const long sd = G.stride[d];
+    const long base = flat(G, q0.v[0], q0.v[1], q0.v[2]);
+    const bool periodic = G.bc[d] == PERIODIC;
+    double a0, b0, c0, an, bn, cn;
+    line_row<R>(G, C, d, kind, q0, 0, a0, b0, c0);
+    line_row<R>(G, C, d, kind, q0, n - 1, an, bn, cn);
+    const double gam = -b0, alpha = a0, beta = cn;
+    // pass 1: Thomas on (a, bb, c, x)
+    for (int rhs = 0; rhs < (periodic ? 2 : 1); ++rhs) {
+        double cprev = 0.0, dprev = 0.0;
+        for (int t = 0; t < n; ++t) {
+            double a, b, cc;
+            line_row<R>(G, C, d, kind, q0, t, a, b, cc);
+            if (periodic) {
+                if (t == 0) b = b0 - gam;
+                if (t == n - 1) b = bn - beta * alpha / gam;
+            }
+            double dv;
+            if (rhs == 0) dv = (double)x[base + t * sd];
+            else dv = t == 0 ? gam : (t == n - 1 ? beta : 0.0);
+            double cpt, dpt;
+            if (t == 0) {
+                cpt = cc / b;
+                dpt = dv / b;
+            } else {
+                const double den = b - a * cprev;
+                cpt = cc / den;
+                dpt = (dv - a * dprev) / den;
+            }
+            cp[base + t * sd] = cpt;
+            dpv[base + t * sd] = dpt;
+            cprev = cpt;
+            dprev = dpt;
+        }
+        double xn = dpv[base + (long)(n - 1) * sd];
+        double* out = rhs == 0 ? x1 : zz;
+        out[base + (long)(n - 1) * sd] = xn;
+        for (int t = n - 2; t >= 0; --t) {
+            xn = dpv[base + t * sd] - cp[base + t * sd] * xn;
+            out[base + t * sd] = xn;
+        }
+    }
+    if (periodic) {
+        const double x0 = x1[base], xl = x1[base + (long)(n - 1) * sd];
+        const double z0 = zz[base], zl = zz[base + (long)(n - 1) * sd];
+        const double fact = (x0 + alpha * xl / gam) / (1.0 + z0 + alpha * zl / gam);
+        for (int t = 0; t < n; ++t) x[base + t * sd] = (R)(x1[base + t * sd] - fact * zz[base + t * sd]);
+    } else {
+        for (int t = 0; t < n; ++t) x[base + t * sd] = (R)x1[base + t * sd];
+    }
+}
+
+template <typename R>
+void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, double* scratch4,
+                       hipStream_t stream) {
+    const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+    const long nl = (long)G.n[r1] * G.n[r2];
+    hipLaunchKernelGGL((k_line<R>), dim3(grid_blocks(nl)), dim3(kBlock), 0, stream, G, C, d, kind, x, scratch4,
+                       scratch4 + G.N, scratch4 + 2 * G.N, scratch4 + 3 * G.N);
+}
+
+// ---------------------------------------------------------------- instantiations
+#define INST(R)                                                                                              \
+    template void launch_level0<R>(const Grid&, const PcCoef&, int, const LevelT<R>&, hipStream_t);          \
+    template void launch_coarsen<R>(const Grid&, const LevelT<R>&, const LevelT<R>&, hipStream_t);           \
+    template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
+    template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, int, int, int, int, int, bool, hipStream_t); \
+    template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5, R*,    \
+                                   hipStream_t);                                                             \
+    template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const R*, Scales5,       \
+                                         double*, hipStream_t);                                              \
+    template void launch_pc_back<R>(const Grid&, const PcCoef&, const double*, const double*, const R*,      \
+                                    Scales5, double*, double*, int, hipStream_t);                            \
+    template void launch_field_scaled<R>(const double*, double, R*, long, hipStream_t);                      \
+    template void launch_line_solve<R>(const Grid&, const PcCoef&, int, int, R*, double*, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace jfnk

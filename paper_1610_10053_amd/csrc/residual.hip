@@ -1,0 +1,349 @@
+// Residual of the Crank-Nicolson system on the staggered grid (section 2 of
+// Goffrey et al. 2016): R(u) of eqs. (1)-(3) in total-energy form with
+// gravity as a body force and conduction chi = chi0 T^3, upstream linear
+// extrapolation with the van Leer limiter, and the three consumers
+//   b = u + dt/2 R(u)                 (old-time half of Crank-Nicolson)
+//   F = (u - b) - dt/2 R(u)           (residual)
+//   w = (F(u + eps S v) - F(u)) / (eps S)   (Jacobian-free product)
+// Three sweeps: cell primitives, face fluxes, then cell and face outputs.
+#include "kernels.hpp"
+
+namespace jfnk {
+
+// value of state field f at cell c, optionally perturbed along v
+__device__ __forceinline__ double st(const StateView& s, int f, long c) {
+    const long x = (long)f * s.N + c;
+    double a = s.u[x];
+    if (s.v) a = a + (s.eps[0] * s.scale[f]) * s.v[x];
+    return a;
+}
+
+// ---------------------------------------------------------------- sweep 1: primitives per cell
+__global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    const double rho = st(s, 0, c), E = st(s, 1, c);
+    double qk = 0.0;
+    for (int d = 0; d < G.ndim; ++d) {
+        const bool wall = G.bc[d] == WALL;
+        double a = 0.0, b = 0.0;
+        if (!(wall && q.v[d] == 0)) {
+            const double rl = st(s, 0, shifted(G, q, d, -1));
+            const double rf = 0.5 * (rl + rho);
+            a = st(s, 2 + d, c) / rf;
+        }
+        if (!(wall && q.v[d] == G.n[d] - 1)) {
+            const long cu = shifted(G, q, d, 1);
+            const double ru = st(s, 0, cu);
+            const double rf = 0.5 * (rho + ru);
+            b = st(s, 2 + d, cu) / rf;
+        }
+        qk = qk + 0.5 * (a * a + b * b);
+        P.uf[d][c] = a;
+    }
+    const double kin = 0.5 * rho * qk;
+    const double p = G.gm1 * (E - kin);
+    P.rho[c] = rho;
+    P.p[c] = p;
+    P.eps[c] = E / rho;
+    if (G.has_wall || G.has_chi) {
+        const double T = p / rho;
+        P.T[c] = T;
+        if (G.has_chi) P.chi[c] = G.chi0 * (T * T * T);
+    }
+    if (G.has_wall) P.q[c] = qk;
+}
+
+// ---------------------------------------------------------------- sweep 2: fluxes on lower faces
+
+// Ghost-cell values one layer beyond a wall: temperature extrapolated
+// linearly, density from the discrete hydrostatic balance across the wall
+// face, specific energy from the ghost temperature and the mirrored kinetic
+// energy (section 3.1).  c0 is the wall cell, c1 its inner neighbour.
+struct Ghost {
+    double rho, eps;
+};
+__device__ __forceinline__ Ghost wall_ghost(const Grid& G, const Prim& P, long c0, long c1, int d,
+                                            bool top) {
+    const double hg = 0.5 * G.g[d] * G.dx[d];
+    const double T0 = P.T[c0], T1 = P.T[c1];
+    const double Tg = 2.0 * T0 - T1;
+    Ghost gh;
+    gh.rho = top ? P.rho[c0] * (T0 + hg) / (Tg - hg) : P.rho[c0] * (T0 - hg) / (Tg + hg);
+    gh.eps = Tg / G.gm1 + 0.5 * P.q[c0];
+    return gh;
+}
+
+__global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFlux W) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    for (int d = 0; d < G.ndim; ++d) {
+        const bool wall = G.bc[d] == WALL;
+        const int id = q.v[d];
+        if (wall && id == 0) {
+            Fx.fr[d][c] = 0.0;
+            Fx.fe[d][c] = W.lo[d] ? W.lo[d][transverse(G, q, d)] : 0.0;
+            continue;
+        }
+        const long L = shifted(G, q, d, -1);
+        const double v = P.uf[d][c];
+        const double rc = P.rho[c], rL = P.rho[L], ec = P.eps[c], eL = P.eps[L];
+        double rLL, eLL, rR, eR;
+        if (wall && id == 1) {
+            const Ghost gh = wall_ghost(G, P, L, c, d, false);
+            rLL = gh.rho;
+            eLL = gh.eps;
+        } else {
+            const long LL = shifted(G, q, d, -2);
+            rLL = P.rho[LL];
+            eLL = P.eps[LL];
+        }
+        if (wall && id == G.n[d] - 1) {
+            const Ghost gh = wall_ghost(G, P, c, L, d, true);
+            rR = gh.rho;
+            eR = gh.eps;
+        } else {
+            const long R = shifted(G, q, d, 1);
+            rR = P.rho[R];
+            eR = P.eps[R];
+        }
+        const double sl = van_leer(rc - rL, rL - rLL);
+        const double sr = van_leer(rR - rc, rc - rL);
+        const double rf = upstream(v, rL, sl, rc, sr);
+        const double el = van_leer(ec - eL, eL - eLL);
+        const double er = van_leer(eR - ec, ec - eL);
+        const double ef = upstream(v, eL, el, ec, er);
+        const double f_rho = v * rf;
+        double f_e = f_rho * ef + v * (0.5 * (P.p[L] + P.p[c]));
+        if (G.has_chi) {
+            f_e = f_e + ((-0.5 * (P.chi[L] + P.chi[c])) * (P.T[c] - P.T[L])) * G.idx[d];
+        }
+        Fx.fr[d][c] = f_rho;
+        Fx.fe[d][c] = f_e;
+    }
+}
+
+// ---------------------------------------------------------------- sweep 3: outputs
+
+// Velocity component d on the d-face with index a along d (row of the
+// other coordinates of q), across walls: the wall faces carry 0 and faces
+// beyond a wall are the negated mirror images (reflecting wall).
+__device__ __forceinline__ double uf_normal(const Grid& G, const Prim& P, const Ijk& q, int d, int a) {
+    const int n = G.n[d];
+    if (G.bc[d] == WALL) {
+        double sgn = 1.0;
+        if (a < 0) { a = -a; sgn = -1.0; }
+        else if (a > n) { a = 2 * n - a; sgn = -1.0; }
+        if (a == n) return 0.0;
+        return sgn * P.uf[d][flat(G, d == 0 ? a : q.v[0], d == 1 ? a : q.v[1], d == 2 ? a : q.v[2])];
+    }
+    if (a < 0) a += n;
+    else if (a >= n) a -= n;
+    return P.uf[d][flat(G, d == 0 ? a : q.v[0], d == 1 ? a : q.v[1], d == 2 ? a : q.v[2])];
+}
+
+// Velocity component c on its face at row a along another axis e, across
+// walls of e: stress-free mirror images.
+__device__ __forceinline__ double uf_tangential(const Grid& G, const Prim& P, const Ijk& q, int c, int e,
+                                                int a) {
+    const int n = G.n[e];
+    if (G.bc[e] == WALL) {
+        if (a < 0) a = -1 - a;
+        else if (a >= n) a = 2 * n - 1 - a;
+    } else {
+        if (a < 0) a += n;
+        else if (a >= n) a -= n;
+    }
+    return P.uf[c][flat(G, e == 0 ? a : q.v[0], e == 1 ? a : q.v[1], e == 2 ? a : q.v[2])];
+}
+
+// Cell-centred momentum flux of component d along d at the cell with
+// coordinates x (x on or inside the domain along d).
+__device__ __forceinline__ double phi_cell(const Grid& G, const Prim& P, const Flux& Fx, const Ijk& x,
+                                           int d) {
+    const long c = flat(G, x.v[0], x.v[1], x.v[2]);
+    const bool top = G.bc[d] == WALL && x.v[d] == G.n[d] - 1;
+    const double fhi = top ? 0.0 : Fx.fr[d][shifted(G, x, d, 1)];
+    const double Fb = 0.5 * (Fx.fr[d][c] + fhi);
+    const int a0 = x.v[d];
+    const double ua = uf_normal(G, P, x, d, a0 - 1), ub = uf_normal(G, P, x, d, a0);
+    const double uc = uf_normal(G, P, x, d, a0 + 1), ud = uf_normal(G, P, x, d, a0 + 2);
+    const double sl = van_leer(uc - ub, ub - ua);
+    const double sr = van_leer(ud - uc, uc - ub);
+    return Fb * upstream(Fb, ub, sl, uc, sr);
+}
+
+// Edge momentum flux of component d along e != d at the lower e-side of the
+// d-face whose cell has coordinates x; x.v[e] may equal n_e (upper edge).
+__device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const Flux& Fx, Ijk x, int d,
+                                           int e) {
+    const int ne = G.n[e];
+    double Gm;
+    const int a0 = x.v[e];
+    if (G.bc[e] == WALL && (a0 == 0 || a0 == ne)) {
+        Gm = 0.0;
+    } else {
+        Ijk xw = x;
+        if (xw.v[e] >= ne) xw.v[e] -= ne;  // periodic wrap of the upper edge
+        const long cx = flat(G, xw.v[0], xw.v[1], xw.v[2]);
+        const long cl = shifted(G, xw, d, -1);
+        Gm = 0.5 * (Fx.fr[e][cl] + Fx.fr[e][cx]);
+    }
+    const double ua = uf_tangential(G, P, x, d, e, a0 - 2), ub = uf_tangential(G, P, x, d, e, a0 - 1);
+    const double uc = uf_tangential(G, P, x, d, e, a0), ud = uf_tangential(G, P, x, d, e, a0 + 1);
+    const double sl = van_leer(uc - ub, ub - ua);
+    const double sr = van_leer(ud - uc, uc - ub);
+    return Gm * upstream(Gm, ub, sl, uc, sr);
+}
+
+__global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
+                                                const double* __restrict__ sbal, OutSpec o) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double part = 0.0;
+    if (c < G.N) {
+        const Ijk q = cell_coords(G, c);
+        double R[5];
+        // mass and energy in the cell
+        double ar = 0.0, ae = 0.0;
+        for (int d = 0; d < G.ndim; ++d) {
+            const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+            double frh, feh;
+            if (top) {
+                frh = 0.0;
+                feh = W.hi[d] ? W.hi[d][transverse(G, q, d)] : 0.0;
+            } else {
+                const long cu = shifted(G, q, d, 1);
+                frh = Fx.fr[d][cu];
+                feh = Fx.fe[d][cu];
+            }
+            ar = ar - (frh - Fx.fr[d][c]) * G.idx[d];
+            ae = ae - (feh - Fx.fe[d][c]) * G.idx[d];
+        }
+        for (int d = 0; d < G.ndim; ++d) {
+            if (G.g[d] == 0.0) continue;
+            const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+            const double mlo = st(s, 2 + d, c);
+            const double mhi = top ? 0.0 : st(s, 2 + d, shifted(G, q, d, 1));
+            ae = ae + G.g[d] * (0.5 * (mlo + mhi));
+        }
+        if (G.heat_balance && sbal) ae = ae + sbal[c];
+        R[0] = ar;
+        R[1] = ae;
+        // momentum on the lower faces
+        for (int d = 0; d < G.ndim; ++d) {
+            if (G.bc[d] == WALL && q.v[d] == 0) {
+                R[2 + d] = 0.0;
+                continue;
+            }
+            double a = 0.0;
+            for (int e = 0; e < G.ndim; ++e) {
+                if (e == d) {
+                    Ijk lo = q;
+                    lo.v[d] = q.v[d] - 1;
+                    if (lo.v[d] < 0) lo.v[d] += G.n[d];
+                    a = a - (phi_cell(G, P, Fx, q, d) - phi_cell(G, P, Fx, lo, d)) * G.idx[d];
+                } else {
+                    Ijk up = q;
+                    up.v[e] = q.v[e] + 1;
+                    a = a - (phi_edge(G, P, Fx, up, d, e) - phi_edge(G, P, Fx, q, d, e)) * G.idx[e];
+                }
+            }
+            const long cl = shifted(G, q, d, -1);
+            a = a - (P.p[c] - P.p[cl]) * G.idx[d];
+            if (G.g[d] != 0.0) a = a + (0.5 * (P.rho[cl] + P.rho[c])) * G.g[d];
+            R[2 + d] = a;
+        }
+        // consumers
+        const int nv = 2 + G.ndim;
+        for (int f = 0; f < nv; ++f) {
+            const long x = (long)f * G.N + c;
+            const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
+            if (o.mode == OUT_RHS) {
+                o.out[x] = R[f];
+            } else if (o.mode == OUT_CN_OLD) {
+                const double u0 = s.u[x];
+                const double b = u0 + o.h * R[f];
+                o.out[x] = b;
+                const double F = wallface ? 0.0 : (u0 - b) - o.h * R[f];
+                o.out2[x] = F;
+                const double t = F / o.scale[f];
+                part += t * t;
+            } else if (o.mode == OUT_RESIDUAL) {
+                const double F = wallface ? 0.0 : (st(s, f, c) - o.b[x]) - o.h * R[f];
+                o.out[x] = F;
+                const double t = F / o.scale[f];
+                part += t * t;
+            } else {  // OUT_JV
+                double w = 0.0;
+                const double e = s.eps[0];
+                if (!wallface && e != 0.0) {
+                    const double F = (st(s, f, c) - o.b[x]) - o.h * R[f];
+                    w = (F - o.Fu[x]) / (e * s.scale[f]);
+                }
+                o.out[x] = w;
+            }
+        }
+    }
+    if (o.partial) {
+        __shared__ double sh[kBlock / 64];
+        const double t = block_sum(part, sh);
+        if (threadIdx.x == 0) o.partial[blockIdx.x] = t;
+    }
+}
+
+// ---------------------------------------------------------------- time step and scales (eqs. 5-7)
+__global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const double* __restrict__ u,
+                                                        double* __restrict__ part) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double hyd = 0.0, adv = 0.0, rad = 0.0, rmax = 0.0, emax = 0.0, cmax = 0.0;
+    if (c < G.N) {
+        const Ijk q = cell_coords(G, c);
+        const double r = P.rho[c];
+        const double cs = sqrt(G.gamma * P.p[c] / r);
+        const double cp = G.gamma / G.gm1;
+        for (int d = 0; d < G.ndim; ++d) {
+            const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+            const double a = fabs(P.uf[d][c]);
+            const double b = top ? 0.0 : fabs(P.uf[d][shifted(G, q, d, 1)]);
+            const double ud = a > b ? a : b;
+            hyd = fmax(hyd, (ud + cs) * G.idx[d]);
+            adv = fmax(adv, ud * G.idx[d]);
+            if (G.has_chi) {
+                const double D = P.chi[c] / (r * cp);
+                rad = fmax(rad, D * (G.idx[d] * G.idx[d]));
+            }
+        }
+        rmax = r;
+        emax = u[G.N + c];
+        cmax = cs;
+    }
+    __shared__ double sh[kBlock / 64];
+    double vals[6] = {hyd, adv, rad, rmax, emax, cmax};
+    for (int k = 0; k < 6; ++k) {
+        const double m = block_max(vals[k], sh);
+        if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = m;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- host launchers
+
+void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                     const double* sbal, const OutSpec& o, hipStream_t stream) {
+    const int nb = grid_blocks(G.N);
+    hipLaunchKernelGGL(k_prim, dim3(nb), dim3(kBlock), 0, stream, G, s, P);
+    hipLaunchKernelGGL(k_flux, dim3(nb), dim3(kBlock), 0, stream, G, P, Fx, W);
+    hipLaunchKernelGGL(k_out, dim3(nb), dim3(kBlock), 0, stream, G, s, P, Fx, W, sbal, o);
+}
+
+void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
+    hipLaunchKernelGGL(k_prim, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, s, P);
+}
+
+void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream) {
+    hipLaunchKernelGGL(k_dt_partial, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, P, u, part);
+}
+
+}  // namespace jfnk

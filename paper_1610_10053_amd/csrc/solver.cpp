@@ -1,0 +1,1020 @@
+// Host driver and C-ABI of the implicit-step library: Newton-Raphson on the
+// Crank-Nicolson system, restarted right-preconditioned GMRES with CGS2 and
+// Givens rotations, Jacobian-free products, CFL time step with step halving
+// (section 2 and section 2.1 of Goffrey et al. 2016).  All vectors live on
+// the device; the host reads back a handful of scalars per Krylov iteration.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/jfnk.h"
+#include "kernels.hpp"
+
+using namespace jfnk;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(-3, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kDsum = 512;  // device scalar area
+// offsets in the device scalar area
+constexpr int D_H1 = 0, D_H2 = 80, D_HN = 160, D_Y = 170, D_USQ = 250, D_EPS = 251, D_TMP = 260;
+
+struct Buffers {
+    std::vector<void*> ptrs;
+    size_t bytes = 0;
+    ~Buffers() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct jfnk_problem {
+    Grid G{};
+    jfnk_problem_desc desc{};
+    jfnk_solver_opts opts{};
+    hipStream_t stream = nullptr;
+    Buffers buf;
+    // vectors of nvec doubles
+    double *u = nullptr, *un = nullptr, *b = nullptr, *F = nullptr, *x = nullptr, *rhs = nullptr,
+           *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
+           *s2 = nullptr;
+    void* V = nullptr;
+    Prim P{};
+    Flux Fx{};
+    WallFlux W{};
+    double* sbal = nullptr;
+    PcCoef C{};
+    LevelSet<double> ac64{}, df64{};
+    LevelSet<float> ac32{}, df32{};
+    int nlev = 1, coarse_from = 0;
+    double* rEd = nullptr;
+    double* lines = nullptr;
+    double* part = nullptr;
+    int npart = 0;
+    double* dsum = nullptr;
+    double* hpin = nullptr;
+    double scale[5] = {1, 1, 1, 1, 1};
+    double t_now = 0.0;
+    long nunk = 0;
+    int nred = 1, ncell_blk = 1;
+    // last dt limits
+    double hyd = 0, adv = 0, rad = 0;
+};
+
+namespace {
+
+template <typename Tp>
+int dalloc(jfnk_problem* p, Tp** out, size_t count) {
+    void* ptr = nullptr;
+    const size_t bytes = count * sizeof(Tp);
+    hipError_t e = hipMalloc(&ptr, bytes == 0 ? 8 : bytes);
+    if (e != hipSuccess) return fail(-2, std::string("hipMalloc: ") + hipGetErrorString(e));
+    p->buf.ptrs.push_back(ptr);
+    p->buf.bytes += bytes;
+    *out = (Tp*)ptr;
+    return 0;
+}
+
+#define CK(expr)              \
+    do {                      \
+        int rc_ = (expr);     \
+        if (rc_ != 0) return rc_; \
+    } while (0)
+
+int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
+    if (!d || !o) return fail(-1, "null descriptor or options");
+    if (d->ndim != 2 && d->ndim != 3) return fail(-1, "ndim must be 2 or 3");
+    for (int a = 0; a < d->ndim; ++a) {
+        if (d->n[a] < 4) return fail(-1, "every axis needs at least 4 cells");
+        if (d->bc[a] != JFNK_BC_PERIODIC && d->bc[a] != JFNK_BC_WALL) return fail(-1, "unknown boundary type");
+        if (d->bc[a] == JFNK_BC_PERIODIC && d->n[a] % 2) return fail(-1, "periodic axes need an even cell count");
+        if (!(d->hi[a] > d->lo[a])) return fail(-1, "empty domain");
+    }
+    if (d->ndim == 2 && d->n[2] != 1) return fail(-1, "2D problems need n[2] = 1");
+    if (!(d->gamma > 1.0)) return fail(-1, "gamma must exceed 1");
+    if (d->chi0 < 0.0) return fail(-1, "chi0 must be >= 0");
+    if (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart) return fail(-1, "gmres_restart out of range");
+    if (o->gmres_max_cycles < 0 || o->newton_max < 0) return fail(-1, "negative iteration limits");
+    if (o->pc < JFNK_PC_NONE || o->pc > JFNK_PC_ACOUSTIC_DIFFUSION) return fail(-1, "unknown preconditioner");
+    if (o->pc_solver != JFNK_PCS_MULTIGRID && o->pc_solver != JFNK_PCS_ADI) return fail(-1, "unknown pc_solver");
+    if (o->mg_nu1 < 1 || o->mg_nu2 < 0 || o->mg_nuc < 1 || o->mg_cycles < 1)
+        return fail(-1, "multigrid sweeps: nu1 >= 1, nu2 >= 0, nuc >= 1, cycles >= 1");
+    if (o->prec != JFNK_FP64 && o->prec != JFNK_MIXED) return fail(-1, "unknown precision");
+    if (o->prec == JFNK_MIXED && o->pc_solver == JFNK_PCS_ADI)
+        return fail(-4, "the mixed-precision form supports the multigrid preconditioner only");
+    if (!(o->cfl_hydro > 0.0)) return fail(-1, "cfl_hydro must be positive");
+    if (o->max_halvings < 0) return fail(-1, "max_halvings must be >= 0");
+    return 0;
+}
+
+void make_grid(const jfnk_problem_desc& d, Grid& G) {
+    std::memset(&G, 0, sizeof(G));
+    G.ndim = d.ndim;
+    for (int a = 0; a < 3; ++a) {
+        G.n[a] = a < d.ndim ? d.n[a] : 1;
+        G.bc[a] = a < d.ndim ? d.bc[a] : PERIODIC;
+        const double lo = a < d.ndim ? d.lo[a] : 0.0, hi = a < d.ndim ? d.hi[a] : 1.0;
+        G.dx[a] = (hi - lo) / G.n[a];
+        G.idx[a] = 1.0 / G.dx[a];
+        G.g[a] = a < d.ndim ? d.g[a] : 0.0;
+        if (a < d.ndim && G.bc[a] == WALL) G.has_wall = 1;
+    }
+    G.N = (long)G.n[0] * G.n[1] * G.n[2];
+    G.nvec = (2 + G.ndim) * G.N;
+    G.stride[0] = 1;
+    G.stride[1] = G.n[0];
+    G.stride[2] = (long)G.n[0] * G.n[1];
+    G.gamma = d.gamma;
+    G.gm1 = d.gamma - 1.0;
+    G.chi0 = d.chi0;
+    G.has_chi = d.chi0 != 0.0;
+    G.heat_balance = d.heat_balance && d.chi0 != 0.0;
+}
+
+// multigrid depth: halve every active axis while all are even and >= 4
+int count_levels(const Grid& G, int n_out[][3]) {
+    int n[3] = {G.n[0], G.n[1], G.n[2]}, L = 0;
+    for (;;) {
+        for (int a = 0; a < 3; ++a) n_out[L][a] = n[a];
+        L++;
+        bool ok = true;
+        for (int a = 0; a < G.ndim; ++a)
+            if (n[a] % 2 || n[a] < 4) ok = false;
+        if (!ok || L >= kMaxLevels) break;
+        for (int a = 0; a < G.ndim; ++a) n[a] /= 2;
+    }
+    return L;
+}
+
+constexpr long kCoarseCells = 4096;  // levels at or below this size run in one workgroup
+
+size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
+
+template <typename R>
+int alloc_levels(jfnk_problem* p, LevelSet<R>& S, int nl[][3]) {
+    for (int l = 0; l < p->nlev; ++l) {
+        LevelT<R>& L = S.L[l];
+        for (int a = 0; a < 3; ++a) L.n[a] = nl[l][a];
+        L.N = (long)L.n[0] * L.n[1] * L.n[2];
+        R* blk = nullptr;
+        CK(dalloc(p, &blk, (size_t)L.N * 7));
+        L.sig = blk;
+        L.a[0] = blk + L.N;
+        L.a[1] = blk + 2 * L.N;
+        L.a[2] = blk + 3 * L.N;
+        L.D = blk + 4 * L.N;
+        L.x = blk + 5 * L.N;
+        L.b = blk + 6 * L.N;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------- reductions with read-back
+int read_scalars(jfnk_problem* p, int off, int count, double* out) {
+    HIPCHK(hipMemcpyAsync(p->hpin, p->dsum + off, sizeof(double) * count, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    std::memcpy(out, p->hpin, sizeof(double) * count);
+    return 0;
+}
+
+StateView view(jfnk_problem* p, const double* u, const double* v) {
+    StateView s;
+    s.u = u;
+    s.v = v;
+    s.eps = p->dsum + D_EPS;
+    for (int f = 0; f < 5; ++f) s.scale[f] = p->scale[f];
+    s.N = p->G.N;
+    return s;
+}
+
+OutSpec outspec(jfnk_problem* p, int mode, double dt, double* out, double* out2, const double* b,
+                const double* Fu, bool want_norm) {
+    OutSpec o;
+    o.mode = mode;
+    o.h = 0.5 * dt;
+    o.out = out;
+    o.out2 = out2;
+    o.b = b;
+    o.Fu = Fu;
+    for (int f = 0; f < 5; ++f) o.scale[f] = p->scale[f];
+    o.partial = want_norm ? p->part : nullptr;
+    return o;
+}
+
+// dt and limits of eqs. (5)-(7) for state u; sets the variable scales
+int time_step(jfnk_problem* p, const double* u, double* dt_out) {
+    const Grid& G = p->G;
+    StateView s = view(p, u, nullptr);
+    launch_prim(G, s, p->P, p->stream);
+    launch_dt_partial(G, p->P, u, p->part, p->stream);
+    launch_final_max(p->part, p->ncell_blk, 6, p->dsum + D_TMP, p->stream);
+    HIPCHK(hipGetLastError());
+    double m[6];
+    CK(read_scalars(p, D_TMP, 6, m));
+    const double hyd = m[0], adv = m[1], rad = m[2];
+    const jfnk_solver_opts& o = p->opts;
+    double dt = o.cfl_hydro / hyd;
+    if (o.cfl_adv_max > 0.0 && adv > 0.0 && o.cfl_adv_max / adv < dt) dt = o.cfl_adv_max / adv;
+    if (o.cfl_rad_max > 0.0 && rad > 0.0 && o.cfl_rad_max / rad < dt) dt = o.cfl_rad_max / rad;
+    if (o.dt_max > 0.0 && o.dt_max < dt) dt = o.dt_max;
+    p->scale[0] = m[3];
+    p->scale[1] = m[4];
+    for (int d = 0; d < G.ndim; ++d) p->scale[2 + d] = m[3] * m[5];
+    for (int d = G.ndim; d < 3; ++d) p->scale[2 + d] = 1.0;
+    p->hyd = hyd;
+    p->adv = adv;
+    p->rad = rad;
+    if (dt_out) *dt_out = dt;
+    return 0;
+}
+
+// sum of squares of F/S from the fused partials of the output sweep
+int residual_norm(jfnk_problem* p, double* f) {
+    launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
+    double s;
+    CK(read_scalars(p, D_TMP, 1, &s));
+    *f = std::sqrt(s);
+    return 0;
+}
+
+// ---------------------------------------------------------------- preconditioner
+template <typename R>
+LevelSet<R>& levels(jfnk_problem* p, int which);
+template <>
+LevelSet<double>& levels<double>(jfnk_problem* p, int which) {
+    return which == 0 ? p->ac64 : p->df64;
+}
+template <>
+LevelSet<float>& levels<float>(jfnk_problem* p, int which) {
+    return which == 0 ? p->ac32 : p->df32;
+}
+
+template <typename R>
+void build_hierarchy(jfnk_problem* p, int which) {
+    const Grid& G = p->G;
+    LevelSet<R>& S = levels<R>(p, which);
+    launch_level0<R>(G, p->C, which, S.L[0], p->stream);
+    launch_level_diag<R>(G, S.L[0], p->stream);
+    for (int l = 1; l < p->nlev; ++l) {
+        launch_coarsen<R>(G, S.L[l - 1], S.L[l], p->stream);
+        launch_level_diag<R>(G, S.L[l], p->stream);
+    }
+}
+
+// frozen coefficients at state u
+int pc_build(jfnk_problem* p, const double* u, double dt) {
+    const Grid& G = p->G;
+    p->C.tau = 0.5 * dt;
+    if (p->opts.pc == JFNK_PC_NONE) return 0;
+    launch_prim(G, view(p, u, nullptr), p->P, p->stream);
+    launch_pc_coef(G, u, p->P, p->C, dt, p->stream);
+    if (p->opts.pc_solver == JFNK_PCS_MULTIGRID) {
+        const bool diff = p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION;
+        if (p->opts.prec == JFNK_MIXED) {
+            build_hierarchy<float>(p, 0);
+            if (diff) build_hierarchy<float>(p, 1);
+        } else {
+            build_hierarchy<double>(p, 0);
+            if (diff) build_hierarchy<double>(p, 1);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+template <typename R>
+void mg_solve(jfnk_problem* p, int which) {
+    const LevelSet<R>& S = levels<R>(p, which);
+    for (int c = 0; c < p->opts.mg_cycles; ++c)
+        mg_vcycle<R>(p->G, S, p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2, p->opts.mg_nuc, c == 0,
+                     p->stream);
+}
+
+// z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z
+template <typename R>
+void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
+    const Grid& G = p->G;
+    Scales5 sc;
+    for (int f = 0; f < 5; ++f) sc.v[f] = p->scale[f];
+    const double* rE = nullptr;
+    const bool mg = p->opts.pc_solver == JFNK_PCS_MULTIGRID;
+    if (p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION) {
+        if (mg) {
+            LevelSet<R>& S = levels<R>(p, 1);
+            launch_field_scaled<R>(v + G.N, sc.v[1], S.L[0].b, G.N, p->stream);
+            mg_solve<R>(p, 1);
+            launch_pc_diff_back<R>(G, p->C, v, S.L[0].x, sc, p->rEd, p->stream);
+        } else {
+            launch_field_scaled<double>(v + G.N, sc.v[1], p->rEd, G.N, p->stream);
+            for (int d = 0; d < G.ndim; ++d) launch_line_solve<double>(G, p->C, d, 1, p->rEd, p->lines, p->stream);
+        }
+        rE = p->rEd;
+    }
+    LevelSet<R>& A = levels<R>(p, 0);
+    launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0].b, p->stream);
+    const R* dp;
+    if (mg) {
+        mg_solve<R>(p, 0);
+        dp = A.L[0].x;
+    } else {
+        for (int d = 0; d < G.ndim; ++d) launch_line_solve<R>(G, p->C, d, 0, A.L[0].b, p->lines, p->stream);
+        dp = A.L[0].b;
+    }
+    launch_pc_back<R>(G, p->C, v, rE, dp, sc, z, p->part, p->ncell_blk, p->stream);
+}
+
+void pc_apply(jfnk_problem* p, const double* v, double* z) {
+    int nb;
+    if (p->opts.pc == JFNK_PC_NONE) {
+        nb = p->nred;
+        launch_copy_sumsq(v, z, p->G.nvec, p->part, nb, p->stream);
+    } else {
+        nb = p->ncell_blk;
+        if (p->opts.prec == JFNK_MIXED) pc_apply_t<float>(p, v, z);
+        else pc_apply_t<double>(p, v, z);
+    }
+    launch_jv_eps(p->dsum + D_USQ, p->part, nb, (double)p->nunk, p->dsum + D_EPS, p->stream);
+}
+
+// Jacobian-free product along v (eps already on the device)
+void jv(jfnk_problem* p, const double* u, const double* Fu, const double* b, double dt, const double* v,
+        double* w) {
+    launch_residual(p->G, view(p, u, v), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_JV, dt, w, nullptr, b, Fu, false), p->stream);
+}
+
+// eps for a product along x from |x|
+void eps_for(jfnk_problem* p, const double* x) {
+    launch_scaled_sumsq(x, p->G, nullptr, p->part, p->nred, p->stream);
+    launch_jv_eps(p->dsum + D_USQ, p->part, p->nred, (double)p->nunk, p->dsum + D_EPS, p->stream);
+}
+
+// sum of (S^-1 u)^2 into the device scalar used by eps
+void set_usq(jfnk_problem* p, const double* u) {
+    double inv[5];
+    for (int f = 0; f < 5; ++f) inv[f] = 1.0 / p->scale[f];
+    launch_scaled_sumsq(u, p->G, inv, p->part, p->nred, p->stream);
+    launch_final_sum(p->part, p->nred, 1, p->dsum + D_USQ, p->stream);
+}
+
+// |v|^2 (plain) read back
+int plain_norm(jfnk_problem* p, const double* v, double* out) {
+    launch_scaled_sumsq(v, p->G, nullptr, p->part, p->nred, p->stream);
+    launch_final_sum(p->part, p->nred, 1, p->dsum + D_TMP, p->stream);
+    double s;
+    CK(read_scalars(p, D_TMP, 1, &s));
+    *out = std::sqrt(s);
+    return 0;
+}
+
+struct GmresInfo {
+    int its = 0, cycles = 0, converged = 0;
+    double res = 0.0, beta0 = 0.0;
+};
+
+// ---------------------------------------------------------------- GMRES(m), right preconditioned, CGS2
+template <typename T>
+int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
+    const Grid& G = p->G;
+    const long n = G.nvec;
+    const int m = p->opts.gmres_restart;
+    const double eta = p->opts.gmres_eta;
+    T* V = (T*)p->V;
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
+    HIPCHK(hipMemsetAsync(p->x, 0, sizeof(double) * n, p->stream));
+    launch_copy(p->r, p->rhs, n, p->stream);
+    double beta0;
+    CK(plain_norm(p, p->rhs, &beta0));
+    info->its = 0;
+    info->cycles = 0;
+    info->converged = 0;
+    info->res = beta0;
+    info->beta0 = beta0;
+    if (beta0 == 0.0) {
+        info->converged = 1;
+        return 0;
+    }
+    std::vector<double> hb(D_HN + 1);
+    for (int cyc = 0; cyc < p->opts.gmres_max_cycles; ++cyc) {
+        double beta = beta0;
+        if (cyc > 0) CK(plain_norm(p, p->r, &beta));
+        info->res = beta;
+        if (beta <= eta * beta0) {
+            info->converged = 1;
+            break;
+        }
+        info->cycles++;
+        launch_store_scaled<T>(p->r, V, beta, n, p->stream);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kdim = 0;
+        bool conv = false;
+        for (int j = 0; j < m; ++j) {
+            const T* vj = V + (long)j * n;
+            const double* vin;
+            if (sizeof(T) == sizeof(double)) {
+                vin = (const double*)vj;
+            } else {
+                launch_widen<T>(vj, p->vj, n, p->stream);
+                vin = p->vj;
+            }
+            pc_apply(p, vin, p->z);
+            jv(p, u, p->F, p->b, dt, p->z, p->w);
+            launch_mdot<T>(V, n, j + 1, p->w, n, p->part, p->nred, p->stream);
+            launch_final_sum(p->part, p->nred, j + 2, p->dsum + D_H1, p->stream);
+            launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, p->w, n, p->part, p->nred, true, p->stream);
+            launch_final_sum(p->part, p->nred, j + 1, p->dsum + D_H2, p->stream);
+            launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, p->w, n, p->part, p->nred, false, p->stream);
+            launch_final_sum(p->part, p->nred, 1, p->dsum + D_HN, p->stream);
+            HIPCHK(hipGetLastError());
+            CK(read_scalars(p, 0, D_HN + 1, hb.data()));
+            const double w0 = std::sqrt(hb[D_H1 + j + 1]);
+            const double hn = std::sqrt(hb[D_HN]);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[D_H1 + i] + hb[D_H2 + i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = H[(size_t)i * m + j], bb = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+            const double den = std::sqrt(a * a + bb * bb);
+            cs[j] = a / den;
+            sn[j] = bb / den;
+            H[(size_t)j * m + j] = den;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            info->its++;
+            kdim = j + 1;
+            info->res = std::fabs(g[j + 1]);
+            if (hn <= 1e-14 * w0) {
+                conv = true;
+                break;
+            }
+            launch_store_scaled<T>(p->w, V + (long)(j + 1) * n, hn, n, p->stream);
+            if (info->res <= eta * beta0) {
+                conv = true;
+                break;
+            }
+        }
+        for (int i = kdim - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < kdim; ++l) s -= H[(size_t)i * m + l] * y[l];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
+        HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
+        launch_combine<T>(V, n, kdim, p->dsum + D_Y, p->t, n, p->stream);
+        pc_apply(p, p->t, p->z);
+        launch_add(p->x, p->z, n, p->stream);
+        if (conv) {
+            info->converged = 1;
+            HIPCHK(hipStreamSynchronize(p->stream));
+            break;
+        }
+        eps_for(p, p->x);
+        jv(p, u, p->F, p->b, dt, p->x, p->t);
+        launch_sub(p->rhs, p->t, p->r, n, p->stream);
+        CK(plain_norm(p, p->r, &info->res));
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
+// Newton-Raphson from u^n at dt; on failure the state is restored
+int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
+    const Grid& G = p->G;
+    const long n = G.nvec;
+    const jfnk_solver_opts& o = p->opts;
+    launch_copy(p->un, p->u, n, p->stream);
+    CK(time_step(p, p->u, nullptr));  // scales from u^n
+    launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_CN_OLD, dt, p->b, p->F, nullptr, nullptr, true), p->stream);
+    HIPCHK(hipGetLastError());
+    double f0;
+    CK(residual_norm(p, &f0));
+    double f = f0;
+    double tol = o.newton_rtol * f0;
+    const double floor_ = o.newton_atol * std::sqrt((double)p->nunk);
+    if (floor_ > tol) tol = floor_;
+    int status = 0, its = 0, gits = 0;
+    double max_corr = 0.0;
+    if (!std::isfinite(f0)) status = 3;
+    while (status == 0 && f > tol) {
+        if (its >= o.newton_max) {
+            status = 1;
+            break;
+        }
+        CK(pc_build(p, p->u, dt));
+        set_usq(p, p->u);
+        launch_neg_scaled(p->F, p->rhs, G, p->scale, p->stream);
+        GmresInfo gi;
+        int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi) : gmres<double>(p, p->u, dt, &gi);
+        if (rc) return rc;
+        gits += gi.its;
+        if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
+            status = 2;
+            break;
+        }
+        launch_update_state(p->u, p->x, G, p->scale, p->part, p->nred, p->stream);
+        launch_final_max(p->part, p->nred, 1, p->dsum + D_TMP + 1, p->stream);
+        launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
+                        outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->b, nullptr, true), p->stream);
+        launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
+        HIPCHK(hipGetLastError());
+        double rb[2];
+        CK(read_scalars(p, D_TMP, 2, rb));
+        f = std::sqrt(rb[0]);
+        max_corr = rb[1];
+        its++;
+        if (!std::isfinite(f)) {
+            status = 3;
+            break;
+        }
+        if (max_corr <= o.newton_corr_tol) break;
+    }
+    if (st) {
+        st->newton_its = its;
+        st->gmres_its = gits;
+        st->f0 = f0;
+        st->f = f;
+        st->rel_res = f0 > 0.0 ? f / f0 : 0.0;
+        st->max_rel_corr = max_corr;
+        st->dt = dt;
+        st->status = status;
+    }
+    if (status != 0) launch_copy(p->u, p->un, n, p->stream);
+    HIPCHK(hipGetLastError());
+    return status;
+}
+
+// sums of rho and E (drift report), two-stage device reduction
+int field_sums(jfnk_problem* p, const double* u, double* m, double* e) {
+    const long N = p->G.N;
+    launch_sum(u, N, p->part, p->nred, p->stream);
+    launch_final_sum(p->part, p->nred, 1, p->dsum + D_TMP + 4, p->stream);
+    launch_sum(u + N, N, p->part, p->nred, p->stream);
+    launch_final_sum(p->part, p->nred, 1, p->dsum + D_TMP + 5, p->stream);
+    HIPCHK(hipGetLastError());
+    double r[2];
+    CK(read_scalars(p, D_TMP + 4, 2, r));
+    *m = r[0];
+    *e = r[1];
+    return 0;
+}
+
+int copy_in(jfnk_problem* p, double* dst, const double* src, int on_device) {
+    HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * p->G.nvec,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, p->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(p->stream));
+    return 0;
+}
+int copy_out(jfnk_problem* p, double* dst, const double* src, int on_device) {
+    HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * p->G.nvec,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return 0;
+}
+
+// frozen wall conductive fluxes and heat-balance source from the creation state
+int freeze_sources(jfnk_problem* p);
+
+}  // namespace
+
+// ---------------------------------------------------------------- sources (device kernels in this file)
+namespace jfnk {
+__global__ void k_wall_flux(Grid G, Prim P, int d, double* lo, double* hi) {
+    const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+    const long nt = (long)G.n[r1] * G.n[r2];
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    Ijk q;
+    q.v[r1] = (int)(t % G.n[r1]);
+    q.v[r2] = (int)(t / G.n[r1]);
+    const double hg = 0.5 * G.g[d] * G.dx[d];
+    (void)hg;
+    // bottom: ghost T = 2 T0 - T1 and chi of the ghost
+    q.v[d] = 0;
+    const long c0 = flat(G, q.v[0], q.v[1], q.v[2]);
+    q.v[d] = 1;
+    const long c1 = flat(G, q.v[0], q.v[1], q.v[2]);
+    double Tg = 2.0 * P.T[c0] - P.T[c1];
+    double chig = G.chi0 * (Tg * Tg * Tg);
+    lo[t] = ((-0.5 * (chig + P.chi[c0])) * (P.T[c0] - Tg)) * G.idx[d];
+    q.v[d] = G.n[d] - 1;
+    const long cn = flat(G, q.v[0], q.v[1], q.v[2]);
+    q.v[d] = G.n[d] - 2;
+    const long cm = flat(G, q.v[0], q.v[1], q.v[2]);
+    Tg = 2.0 * P.T[cn] - P.T[cm];
+    chig = G.chi0 * (Tg * Tg * Tg);
+    hi[t] = ((-0.5 * (P.chi[cn] + chig)) * (Tg - P.T[cn])) * G.idx[d];
+}
+
+// heat-balance source: + sum_d (f_T(up) - f_T(lo)) / dx of the conductive flux
+__global__ void k_sbal(Grid G, Prim P, WallFlux W, double* sbal) {
+    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= G.N) return;
+    const Ijk q = cell_coords(G, c);
+    double acc = 0.0;
+    for (int d = 0; d < G.ndim; ++d) {
+        double flo, fhi;
+        if (G.bc[d] == WALL && q.v[d] == 0) {
+            flo = W.lo[d] ? W.lo[d][transverse(G, q, d)] : 0.0;
+        } else {
+            const long l = shifted(G, q, d, -1);
+            flo = ((-0.5 * (P.chi[l] + P.chi[c])) * (P.T[c] - P.T[l])) * G.idx[d];
+        }
+        if (G.bc[d] == WALL && q.v[d] == G.n[d] - 1) {
+            fhi = W.hi[d] ? W.hi[d][transverse(G, q, d)] : 0.0;
+        } else {
+            const long up = shifted(G, q, d, 1);
+            fhi = ((-0.5 * (P.chi[c] + P.chi[up])) * (P.T[up] - P.T[c])) * G.idx[d];
+        }
+        acc = acc + (fhi - flo) * G.idx[d];
+    }
+    sbal[c] = acc;
+}
+}  // namespace jfnk
+
+namespace {
+int freeze_sources(jfnk_problem* p) {
+    const Grid& G = p->G;
+    launch_prim(G, view(p, p->u, nullptr), p->P, p->stream);
+    for (int d = 0; d < G.ndim; ++d) {
+        if (!p->W.lo[d]) continue;
+        const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+        const long nt = (long)G.n[r1] * G.n[r2];
+        hipLaunchKernelGGL(k_wall_flux, dim3(grid_blocks(nt)), dim3(kBlock), 0, p->stream, G, p->P, d,
+                           (double*)p->W.lo[d], (double*)p->W.hi[d]);
+    }
+    if (p->sbal) hipLaunchKernelGGL(k_sbal, dim3(grid_blocks(G.N)), dim3(kBlock), 0, p->stream, G, p->P, p->W, p->sbal);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return 0;
+}
+
+size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
+    const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
+    size_t b = 13 * nv * 8;                                                // vectors
+    b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);  // basis
+    b += 9 * N * 8 + 6 * N * 8;                                            // primitives, fluxes
+    b += (3 * 3 + 1) * N * 8 + N * 8 + 4 * N * 8;                          // pc coefficients, rE, lines
+    const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
+    for (int l = 0; l < nlev; ++l) b += 2 * level_bytes((long)nl[l][0] * nl[l][1] * nl[l][2], rs);
+    const size_t nred = std::max<size_t>((size_t)grid_blocks((long)N), (size_t)kRedBlocks);
+    b += nred * (kMaxRestart + 2) * 8 + kDsum * 8;
+    if (G.has_chi) b += N * 8;
+    return b;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C-ABI
+extern "C" {
+
+void jfnk_default_opts(jfnk_solver_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->newton_rtol = 1e-8;
+    o->newton_atol = 1e-14;
+    o->newton_corr_tol = 1e-12;
+    o->newton_max = 20;
+    o->gmres_restart = 30;
+    o->gmres_max_cycles = 10;
+    o->gmres_eta = 1e-4;
+    o->pc = JFNK_PC_ACOUSTIC;
+    o->pc_solver = JFNK_PCS_MULTIGRID;
+    o->mg_nu1 = 2;
+    o->mg_nu2 = 2;
+    o->mg_nuc = 16;
+    o->mg_cycles = 1;
+    o->prec = JFNK_FP64;
+    o->cfl_hydro = 1.0;
+    o->max_halvings = 5;
+}
+
+const char* jfnk_last_error(void) { return g_err.c_str(); }
+
+int jfnk_footprint_bytes(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, size_t* out) {
+    int rc = validate(desc, opts);
+    if (rc) return rc;
+    if (!out) return fail(-1, "null output");
+    Grid G;
+    make_grid(*desc, G);
+    int nl[kMaxLevels][3];
+    const int nlev = count_levels(G, nl);
+    *out = footprint(G, *opts, nlev, nl);
+    return 0;
+}
+
+int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, const double* u0,
+                        int on_device, void* hip_stream, jfnk_problem** out) {
+    g_err.clear();
+    int rc = validate(desc, opts);
+    if (rc) return rc;
+    if (!u0 || !out) return fail(-1, "null state or output pointer");
+    jfnk_problem* p = new (std::nothrow) jfnk_problem();
+    if (!p) return fail(-2, "host allocation failed");
+    p->desc = *desc;
+    p->opts = *opts;
+    p->stream = (hipStream_t)hip_stream;
+    make_grid(*desc, p->G);
+    Grid& G = p->G;
+    p->nunk = G.nvec;
+    for (int d = 0; d < G.ndim; ++d)
+        if (G.bc[d] == WALL) p->nunk -= G.N / G.n[d];
+    int nl[kMaxLevels][3];
+    p->nlev = count_levels(G, nl);
+    p->coarse_from = p->nlev;
+    for (int l = 0; l < p->nlev; ++l)
+        if ((long)nl[l][0] * nl[l][1] * nl[l][2] <= kCoarseCells) {
+            p->coarse_from = l;
+            break;
+        }
+    if (p->coarse_from >= p->nlev) p->coarse_from = p->nlev - 1;
+    p->ncell_blk = grid_blocks(G.N);
+    p->nred = std::min(kRedBlocks, grid_blocks(G.nvec));
+    p->npart = std::max(p->ncell_blk, kRedBlocks) * (kMaxRestart + 2);
+    const long n = G.nvec, N = G.N;
+    auto cleanup = [&](int code) {
+        delete p;
+        return code;
+    };
+#define AL(ptr, cnt)                     \
+    do {                                 \
+        int r_ = dalloc(p, &(ptr), (cnt)); \
+        if (r_) return cleanup(r_);      \
+    } while (0)
+    AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->F, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n);
+    AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->vj, n); AL(p->s1, n); AL(p->s2, n);
+    if (opts->prec == JFNK_MIXED) {
+        float* V = nullptr;
+        AL(V, (size_t)(opts->gmres_restart + 1) * n);
+        p->V = V;
+    } else {
+        double* V = nullptr;
+        AL(V, (size_t)(opts->gmres_restart + 1) * n);
+        p->V = V;
+    }
+    double* prim = nullptr;
+    AL(prim, (size_t)9 * N);
+    p->P.rho = prim;
+    for (int d = 0; d < 3; ++d) p->P.uf[d] = prim + (1 + d) * N;
+    p->P.p = prim + 4 * N;
+    p->P.eps = prim + 5 * N;
+    p->P.T = prim + 6 * N;
+    p->P.chi = prim + 7 * N;
+    p->P.q = prim + 8 * N;
+    double* flux = nullptr;
+    AL(flux, (size_t)6 * N);
+    for (int d = 0; d < 3; ++d) {
+        p->Fx.fr[d] = flux + d * N;
+        p->Fx.fe[d] = flux + (3 + d) * N;
+    }
+    for (int d = 0; d < G.ndim; ++d) {
+        if (G.bc[d] == WALL && G.has_chi) {
+            const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+            const long nt = (long)G.n[r1] * G.n[r2];
+            double* wl = nullptr;
+            AL(wl, (size_t)2 * nt);
+            p->W.lo[d] = wl;
+            p->W.hi[d] = wl + nt;
+        }
+    }
+    if (G.heat_balance) AL(p->sbal, N);
+    double* pcb = nullptr;
+    AL(pcb, (size_t)10 * N);
+    for (int d = 0; d < 3; ++d) {
+        p->C.hf[d] = pcb + d * N;
+        p->C.kap[d] = pcb + (3 + d) * N;
+        p->C.beta[d] = pcb + (6 + d) * N;
+    }
+    p->C.W = pcb + 9 * N;
+    AL(p->rEd, N);
+    AL(p->lines, (size_t)4 * N);
+    if (opts->prec == JFNK_MIXED) {
+        if ((rc = alloc_levels<float>(p, p->ac32, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->df32, nl))) return cleanup(rc);
+    } else {
+        if ((rc = alloc_levels<double>(p, p->ac64, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->df64, nl))) return cleanup(rc);
+    }
+    AL(p->part, (size_t)p->npart);
+    AL(p->dsum, (size_t)kDsum);
+#undef AL
+    {
+        hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(double) * kDsum, hipHostMallocDefault);
+        if (e != hipSuccess) return cleanup(fail(-2, "hipHostMalloc failed"));
+    }
+    if (hipMemsetAsync(p->dsum, 0, sizeof(double) * kDsum, p->stream) != hipSuccess) return cleanup(fail(-3, "memset"));
+    if ((rc = copy_in(p, p->u, u0, on_device))) return cleanup(rc);
+    launch_zero_walls(p->u, G, p->stream);
+    if ((rc = freeze_sources(p))) return cleanup(rc);
+    *out = p;
+    return 0;
+}
+
+int jfnk_destroy_problem(jfnk_problem* p) {
+    if (!p) return 0;
+    (void)hipStreamSynchronize(p->stream);
+    if (p->hpin) (void)hipHostFree(p->hpin);
+    delete p;
+    return 0;
+}
+
+int jfnk_set_state(jfnk_problem* p, const double* u, int on_device) {
+    if (!p || !u) return fail(-1, "null argument");
+    int rc = copy_in(p, p->u, u, on_device);
+    if (rc) return rc;
+    launch_zero_walls(p->u, p->G, p->stream);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return 0;
+}
+
+int jfnk_get_state(jfnk_problem* p, double* u, int on_device) {
+    if (!p || !u) return fail(-1, "null argument");
+    return copy_out(p, u, p->u, on_device);
+}
+
+int jfnk_set_time(jfnk_problem* p, double t) {
+    if (!p) return fail(-1, "null problem");
+    p->t_now = t;
+    return 0;
+}
+
+int jfnk_set_opts(jfnk_problem* p, const jfnk_solver_opts* opts) {
+    if (!p) return fail(-1, "null problem");
+    int rc = validate(&p->desc, opts);
+    if (rc) return rc;
+    if (opts->prec != p->opts.prec || opts->gmres_restart > p->opts.gmres_restart)
+        return fail(-1, "precision and a larger restart need a new problem");
+    p->opts = *opts;
+    return 0;
+}
+
+int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out) {
+    if (!p) return fail(-1, "null problem");
+    if (!(dt > 0.0)) return fail(-1, "dt must be positive");
+    auto t0 = std::chrono::steady_clock::now();
+    jfnk_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    double m0, e0;
+    int rc = field_sums(p, p->u, &m0, &e0);
+    if (rc) return rc;
+    rc = newton(p, dt, &st);
+    if (rc < 0) return rc;
+    if (rc == 0) {
+        p->t_now += dt;
+        double m1, e1;
+        int r2 = field_sums(p, p->u, &m1, &e1);
+        if (r2) return r2;
+        st.mass_drift = (m1 - m0) / m0;
+        st.energy_drift = (e1 - e0) / e0;
+    }
+    st.cfl_hydro = dt * p->hyd;
+    st.cfl_adv = dt * p->adv;
+    st.cfl_rad = dt * p->rad;
+    st.t = p->t_now;
+    st.status = rc;
+    st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = st;
+    return rc;
+}
+
+int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
+    if (!p) return fail(-1, "null problem");
+    auto t0 = std::chrono::steady_clock::now();
+    jfnk_step_stats st;
+    std::memset(&st, 0, sizeof(st));
+    double dt;
+    int rc = time_step(p, p->u, &dt);
+    if (rc) return rc;
+    const double hyd = p->hyd, adv = p->adv, rad = p->rad;
+    int rej = 0;
+    for (;;) {
+        rc = newton(p, dt, &st);
+        if (rc < 0) return rc;
+        if (rc == 0 || rej >= p->opts.max_halvings) break;
+        rej++;
+        dt = 0.5 * dt;
+    }
+    if (rc == 0) p->t_now += dt;
+    st.rejections = rej;
+    st.dt = dt;
+    st.cfl_hydro = dt * hyd;
+    st.cfl_adv = dt * adv;
+    st.cfl_rad = dt * rad;
+    st.t = p->t_now;
+    st.status = rc;
+    HIPCHK(hipStreamSynchronize(p->stream));
+    st.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (out) *out = st;
+    return rc;
+}
+
+int jfnk_eval_rhs(jfnk_problem* p, const double* u, double* R, int on_device) {
+    if (!p || !u || !R) return fail(-1, "null argument");
+    int rc = copy_in(p, p->s1, u, on_device);
+    if (rc) return rc;
+    launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_RHS, 0.0, p->s2, nullptr, nullptr, nullptr, false), p->stream);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, R, p->s2, on_device);
+}
+
+int jfnk_eval_cn_old(jfnk_problem* p, const double* un, double dt, double* b, int on_device) {
+    if (!p || !un || !b) return fail(-1, "null argument");
+    int rc = copy_in(p, p->s1, un, on_device);
+    if (rc) return rc;
+    launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_CN_OLD, dt, p->s2, p->t, nullptr, nullptr, false), p->stream);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, b, p->s2, on_device);
+}
+
+int jfnk_eval_residual(jfnk_problem* p, const double* u, const double* b, double dt, double* F, int on_device) {
+    if (!p || !u || !b || !F) return fail(-1, "null argument");
+    int rc = copy_in(p, p->s1, u, on_device);
+    if (rc) return rc;
+    rc = copy_in(p, p->s2, b, on_device);
+    if (rc) return rc;
+    launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_RESIDUAL, dt, p->t, nullptr, p->s2, nullptr, false), p->stream);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, F, p->t, on_device);
+}
+
+int jfnk_eval_time_step(jfnk_problem* p, const double* u, double* out9, int on_device) {
+    if (!p || !u || !out9) return fail(-1, "null argument");
+    int rc = copy_in(p, p->s1, u, on_device);
+    if (rc) return rc;
+    double dt;
+    rc = time_step(p, p->s1, &dt);
+    if (rc) return rc;
+    out9[0] = dt;
+    out9[1] = p->hyd;
+    out9[2] = p->adv;
+    out9[3] = p->rad;
+    for (int f = 0; f < 5; ++f) out9[4 + f] = p->scale[f];
+    return 0;
+}
+
+int jfnk_set_scales(jfnk_problem* p, const double* s5) {
+    if (!p || !s5) return fail(-1, "null argument");
+    for (int f = 0; f < 5; ++f) {
+        if (!(s5[f] > 0.0)) return fail(-1, "scales must be positive");
+        p->scale[f] = s5[f];
+    }
+    return 0;
+}
+
+int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, const double* v, double* w,
+                  int on_device) {
+    if (!p || !u || !b || !v || !w) return fail(-1, "null argument");
+    int rc;
+    if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
+    if ((rc = copy_in(p, p->s2, b, on_device))) return rc;
+    if ((rc = copy_in(p, p->z, v, on_device))) return rc;
+    launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->s2, nullptr, false), p->stream);
+    set_usq(p, p->s1);
+    eps_for(p, p->z);
+    jv(p, p->s1, p->F, p->s2, dt, p->z, p->w);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, w, p->w, on_device);
+}
+
+int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z, int on_device) {
+    if (!p || !u || !v || !z) return fail(-1, "null argument");
+    if (!(dt > 0.0)) return fail(-1, "dt must be positive");
+    int rc;
+    if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
+    if ((rc = copy_in(p, p->s2, v, on_device))) return rc;
+    if ((rc = pc_build(p, p->s1, dt))) return rc;
+    HIPCHK(hipMemsetAsync(p->dsum + D_USQ, 0, sizeof(double), p->stream));
+    pc_apply(p, p->s2, p->w);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, z, p->w, on_device);
+}
+
+}  // extern "C"

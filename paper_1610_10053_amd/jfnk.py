@@ -1,0 +1,316 @@
+"""Python binding of the implicit-step C-ABI (include/jfnk.h).
+
+Argument marshalling only: every step of the solve runs in the HIP library
+libjfnk.so.  Host inputs are numpy arrays; device inputs are torch CUDA
+tensors (float64, contiguous), passed by pointer with on_device = 1.  Work is
+enqueued on torch's current stream of the problem's device unless another
+stream handle is given.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libjfnk.so")
+
+BC_PERIODIC, BC_WALL = 0, 1
+PC_NONE, PC_ACOUSTIC, PC_ACOUSTIC_DIFFUSION = 0, 1, 2
+PCS_MULTIGRID, PCS_ADI = 0, 1
+FP64, MIXED = 0, 1
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("bc", C.c_int * 3), ("gamma", C.c_double), ("g", C.c_double * 3), ("chi0", C.c_double),
+                ("heat_balance", C.c_int)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("newton_rtol", C.c_double), ("newton_atol", C.c_double), ("newton_corr_tol", C.c_double),
+                ("newton_max", C.c_int), ("gmres_restart", C.c_int), ("gmres_max_cycles", C.c_int),
+                ("gmres_eta", C.c_double), ("pc", C.c_int), ("pc_solver", C.c_int), ("mg_nu1", C.c_int),
+                ("mg_nu2", C.c_int), ("mg_nuc", C.c_int), ("mg_cycles", C.c_int), ("prec", C.c_int),
+                ("cfl_hydro", C.c_double), ("cfl_adv_max", C.c_double), ("cfl_rad_max", C.c_double),
+                ("dt_max", C.c_double), ("max_halvings", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("cfl_hydro", C.c_double), ("cfl_adv", C.c_double),
+                ("cfl_rad", C.c_double), ("rel_res", C.c_double), ("max_rel_corr", C.c_double),
+                ("mass_drift", C.c_double), ("energy_drift", C.c_double), ("f0", C.c_double),
+                ("f", C.c_double), ("newton_its", C.c_int), ("gmres_its", C.c_int),
+                ("rejections", C.c_int), ("status", C.c_int), ("wall_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "jfnk_destroy_problem",
+           "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
+           "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
+           "jfnk_eval_time_step", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
+           "jfnk_last_error")
+
+_lib = None
+
+
+class JfnkError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("jfnk error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load():
+    """Load libjfnk.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libjfnk.so is not built (run __graft_entry__.build() or "
+                          "python paper_1610_10053_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, dp, ip = C.c_void_p, C.POINTER(C.c_double), C.c_int
+    P = C.POINTER
+    sig = {
+        "jfnk_default_opts": (None, [P(SolverOpts)]),
+        "jfnk_footprint_bytes": (ip, [P(ProblemDesc), P(SolverOpts), P(C.c_size_t)]),
+        "jfnk_create_problem": (ip, [P(ProblemDesc), P(SolverOpts), vp, ip, vp, P(vp)]),
+        "jfnk_destroy_problem": (ip, [vp]),
+        "jfnk_set_state": (ip, [vp, vp, ip]),
+        "jfnk_get_state": (ip, [vp, vp, ip]),
+        "jfnk_set_time": (ip, [vp, C.c_double]),
+        "jfnk_set_opts": (ip, [vp, P(SolverOpts)]),
+        "jfnk_implicit_step": (ip, [vp, P(StepStats)]),
+        "jfnk_newton_solve": (ip, [vp, C.c_double, P(StepStats)]),
+        "jfnk_eval_rhs": (ip, [vp, vp, vp, ip]),
+        "jfnk_eval_cn_old": (ip, [vp, vp, C.c_double, vp, ip]),
+        "jfnk_eval_residual": (ip, [vp, vp, vp, C.c_double, vp, ip]),
+        "jfnk_eval_time_step": (ip, [vp, vp, dp, ip]),
+        "jfnk_set_scales": (ip, [vp, dp]),
+        "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
+        "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
+        "jfnk_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().jfnk_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise JfnkError(rc, last_error())
+    return rc
+
+
+def default_opts():
+    o = SolverOpts()
+    load().jfnk_default_opts(C.byref(o))
+    return o
+
+
+def make_desc(d):
+    """ProblemDesc from a dict with keys ndim, n, lo, hi, bc, gamma, g, chi0, heat_balance."""
+    pd = ProblemDesc()
+    pd.ndim = d["ndim"]
+    for a in range(3):
+        pd.n[a] = d["n"][a]
+        pd.lo[a] = d["lo"][a]
+        pd.hi[a] = d["hi"][a]
+        pd.bc[a] = d["bc"][a]
+        pd.g[a] = d["g"][a]
+    pd.gamma = d["gamma"]
+    pd.chi0 = d["chi0"]
+    pd.heat_balance = d["heat_balance"]
+    return pd
+
+
+def make_opts(o):
+    """SolverOpts from a dict (keys as in the header; newton_corr_tol etc.)."""
+    so = default_opts()
+    for k, _ in SolverOpts._fields_:
+        if k in o:
+            setattr(so, k, o[k])
+    return so
+
+
+def _ptr(a):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        return a.ctypes.data, 0, a
+    # torch tensor
+    if a.dtype.is_floating_point and a.element_size() != 8:
+        raise TypeError("device buffers must be float64")
+    if not a.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return a.data_ptr(), 1 if a.is_cuda else 0, a
+
+
+def _current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Problem:
+    """One simulation: state, Krylov workspace and solver options on the device."""
+
+    def __init__(self, desc, opts, u0, stream=None):
+        lib = load()
+        self.desc = dict(desc)
+        self._pd = make_desc(desc)
+        self._po = make_opts(opts)
+        n = desc["n"]
+        self.N = n[0] * n[1] * n[2]
+        self.nvec = (2 + desc["ndim"]) * self.N
+        p, on_dev, keep = _ptr(u0)
+        self._check_size(keep)
+        h = C.c_void_p()
+        if stream is None:
+            stream = _current_stream()
+        _check(lib.jfnk_create_problem(C.byref(self._pd), C.byref(self._po), p, on_dev, stream, C.byref(h)))
+        self._h = h
+
+    def _check_size(self, a):
+        size = a.size if isinstance(a, np.ndarray) else a.numel()
+        if size != self.nvec:
+            raise ValueError("expected %d values, got %d" % (self.nvec, size))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.jfnk_destroy_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def _out(self, like):
+        if isinstance(like, np.ndarray):
+            return np.empty(self.nvec)
+        import torch
+        return torch.empty(self.nvec, dtype=torch.float64, device=like.device)
+
+    # ---- state
+    def set_state(self, u):
+        p, d, keep = _ptr(u)
+        self._check_size(keep)
+        _check(_lib.jfnk_set_state(self._h, p, d))
+
+    def get_state(self, out=None):
+        out = np.empty(self.nvec) if out is None else out
+        p, d, keep = _ptr(out)
+        self._check_size(keep)
+        _check(_lib.jfnk_get_state(self._h, p, d))
+        return out
+
+    def set_time(self, t):
+        _check(_lib.jfnk_set_time(self._h, float(t)))
+
+    def set_opts(self, opts):
+        self._po = make_opts(opts)
+        _check(_lib.jfnk_set_opts(self._h, C.byref(self._po)))
+
+    # ---- stepping
+    def implicit_step(self):
+        st = StepStats()
+        rc = _check(_lib.jfnk_implicit_step(self._h, C.byref(st)))
+        return rc, st.as_dict()
+
+    def newton_solve(self, dt):
+        st = StepStats()
+        rc = _check(_lib.jfnk_newton_solve(self._h, float(dt), C.byref(st)))
+        return rc, st.as_dict()
+
+    # ---- components
+    def eval_rhs(self, u):
+        out = self._out(u)
+        pu, d, k1 = _ptr(u)
+        po, _, k2 = _ptr(out)
+        _check(_lib.jfnk_eval_rhs(self._h, pu, po, d))
+        return out
+
+    def eval_cn_old(self, un, dt):
+        out = self._out(un)
+        pu, d, k1 = _ptr(un)
+        po, _, k2 = _ptr(out)
+        _check(_lib.jfnk_eval_cn_old(self._h, pu, float(dt), po, d))
+        return out
+
+    def eval_residual(self, u, b, dt):
+        out = self._out(u)
+        pu, d, k1 = _ptr(u)
+        pb, _, k2 = _ptr(b)
+        po, _, k3 = _ptr(out)
+        _check(_lib.jfnk_eval_residual(self._h, pu, pb, float(dt), po, d))
+        return out
+
+    def eval_time_step(self, u):
+        out = np.empty(9)
+        pu, d, k1 = _ptr(u)
+        _check(_lib.jfnk_eval_time_step(self._h, pu, out.ctypes.data_as(C.POINTER(C.c_double)), d))
+        return dict(dt=out[0], hyd=out[1], adv=out[2], rad=out[3], scales=out[4:9].copy())
+
+    def set_scales(self, s):
+        s = np.ascontiguousarray(list(s) + [1.0] * (5 - len(s)), dtype=np.float64)
+        _check(_lib.jfnk_set_scales(self._h, s.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def apply_jv(self, u, b, dt, v):
+        out = self._out(u)
+        pu, d, k1 = _ptr(u)
+        pb, _, k2 = _ptr(b)
+        pv, _, k3 = _ptr(v)
+        po, _, k4 = _ptr(out)
+        _check(_lib.jfnk_apply_jv(self._h, pu, pb, float(dt), pv, po, d))
+        return out
+
+    def apply_precond(self, u, dt, v):
+        out = self._out(u)
+        pu, d, k1 = _ptr(u)
+        pv, _, k2 = _ptr(v)
+        po, _, k3 = _ptr(out)
+        _check(_lib.jfnk_apply_precond(self._h, pu, float(dt), pv, po, d))
+        return out
+
+
+def footprint_bytes(desc, opts):
+    lib = load()
+    out = C.c_size_t()
+    _check(lib.jfnk_footprint_bytes(C.byref(make_desc(desc)), C.byref(make_opts(opts)), C.byref(out)))
+    return out.value
+
+
+# C-ABI names
+def create_problem(desc, opts, u0, stream=None):
+    return Problem(desc, opts, u0, stream)
+
+
+def implicit_step(problem):
+    return problem.implicit_step()
+
+
+def newton_solve(problem, dt):
+    return problem.newton_solve(dt)
+
+
+def get_state(problem, out=None):
+    return problem.get_state(out)
+
+
+def set_state(problem, u):
+    return problem.set_state(u)
+
+
+def destroy_problem(problem):
+    problem.close()

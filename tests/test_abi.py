@@ -1,0 +1,67 @@
+"""The C-ABI library builds, loads and exports every declared entry point
+(no GPU needed: nothing here launches a kernel)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "jfnk.h")).read()
+    return sorted(set(re.findall(r"\b(jfnk_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    from paper_1610_10053_amd import jfnk
+    assert sorted(jfnk.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1610_10053_amd import jfnk
+    if not os.path.exists(jfnk.LIB_PATH):
+        pytest.skip("libjfnk.so not built")
+    lib = jfnk.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_header_sizes():
+    import ctypes as C
+    from paper_1610_10053_amd import jfnk
+    assert C.sizeof(jfnk.ProblemDesc) == 128
+    assert C.sizeof(jfnk.SolverOpts) == 120
+    assert C.sizeof(jfnk.StepStats) == 112
+
+
+def test_default_opts_and_footprint_are_host_only():
+    from paper_1610_10053_amd import jfnk
+    from workloads import make_config
+    if not os.path.exists(jfnk.LIB_PATH):
+        pytest.skip("libjfnk.so not built")
+    o = jfnk.default_opts()
+    assert o.newton_rtol == 1e-8 and o.gmres_restart == 30 and o.mg_nu1 == 2
+    desc, opts, u = make_config("tg")
+    b = jfnk.footprint_bytes(desc, opts)
+    # 128^3 FP64: 31 basis vectors of 84 MB dominate
+    assert 3.0e9 < b < 6.0e9
+    opts["prec"] = jfnk.MIXED
+    assert jfnk.footprint_bytes(desc, opts) < b
+
+
+def test_invalid_arguments_are_rejected_on_host():
+    from paper_1610_10053_amd import jfnk
+    from workloads import make_config
+    if not os.path.exists(jfnk.LIB_PATH):
+        pytest.skip("libjfnk.so not built")
+    desc, opts, u = make_config("kh", n=16)
+    bad = dict(desc, n=[15, 16, 1])
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.footprint_bytes(bad, opts)
+    assert e.value.code == -1 and "even" in str(e.value)
+    with pytest.raises(jfnk.JfnkError):
+        jfnk.footprint_bytes(desc, dict(opts, gmres_restart=0))
+    with pytest.raises(jfnk.JfnkError) as e:
+        jfnk.footprint_bytes(desc, dict(opts, prec=jfnk.MIXED, pc_solver=jfnk.PCS_ADI))
+    assert e.value.code == -4
