@@ -1,0 +1,173 @@
+"""Benchmark: implicit cell-steps per second of the Crank-Nicolson JFNK step
+on the 3D Taylor-Green vortex at 128^3 (CFL_hydro 20, Newton rtol 1e-8,
+GMRES(30), multigrid physics-based preconditioner), on one MI355X.
+
+A step is one full implicit time step (time-step selection, Crank-Nicolson
+old-time term, Newton iterations with preconditioned GMRES).  The state is
+resident in HBM before the timed region.  Two forms are timed: plain FP64,
+and the mixed form (FP32 preconditioner and Krylov basis, FP64 residual,
+Jacobian-free differences and orthogonalisation).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "implicit cell-steps/s at Newton rtol 1e-8 (3D TG 128^3) + % HBM peak; p50/p99"
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(jfnk, torch, desc, opts, u0, steps, warmup):
+    dev = torch.from_numpy(u0).cuda()
+    prob = jfnk.Problem(desc, opts, dev)
+    names = jfnk.profile_class_names()
+    # warm-up steps with every kernel class timed: per-class table and the
+    # dominant class
+    prob.profile_enable(names)
+    for _ in range(warmup):
+        rc, st = prob.implicit_step()
+        if rc != 0:
+            raise RuntimeError("warm-up step failed: %s" % st)
+    table = prob.profile_read()
+    timed = {k: v for k, v in table.items() if v[2] > 0}
+    dominant = max(timed, key=lambda k: timed[k][0]) if timed else "residual_out"
+    # timed region: events around the dominant class only
+    prob.profile_enable([dominant])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        rc, st = prob.implicit_step()
+        ev[k][1].record()
+        if rc != 0:
+            raise RuntimeError("timed step %d failed: %s" % (k, st))
+        stats.append(st)
+        log("  step %d dt %.4f newton %d gmres %d %.1f ms" % (k, st["dt"], st["newton_its"], st["gmres_its"],
+                                                              st["wall_ms"]))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom = prob.profile_read().get(dominant, (0.0, 0, 0.0))
+    step_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    state = prob.get_state()
+    prob.close()
+    return dict(wall=t1 - t0, step_ms=step_ms, stats=stats, table=table, dominant=dominant, dom=dom,
+                state=state)
+
+
+def cpu_baseline(n, steps):
+    from oracle import Oracle
+    from workloads import make_config
+    desc, opts, u0 = make_config("tg", n=n)
+    orc = Oracle(desc, opts, u0)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, st = orc.implicit_step()
+        if rc != 0:
+            raise RuntimeError("oracle step failed")
+    t = time.perf_counter() - t0
+    cells = n ** 3
+    return dict(value=cells * steps / t, unit="cell-steps/s", cores=1, kind="oracle",
+                sample="Taylor-Green %d^3 (same set-up: CFL 20, Newton rtol 1e-8, GMRES(30), multigrid "
+                       "preconditioner), %d implicit steps from t=0 on one host core, %.1f s" % (n, steps, t))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--cpu-n", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the implicit step of one grid runs on one device here, and a "
+              "multi-GPU run would need the domain-decomposed path, which this build does not include.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1610_10053_amd import jfnk
+    from workloads import make_config, PREC_FP64, PREC_MIXED
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    jfnk.load()
+    desc, opts, u0 = make_config("tg", n=args.n)
+    cells = desc["n"][0] * desc["n"][1] * desc["n"][2]
+    forms = [f for f in args.forms.split(",") if f]
+    res = {}
+    for f in forms:
+        log("form", f)
+        o = dict(opts, prec=PREC_MIXED if f == "mixed" else PREC_FP64)
+        res[f] = run_form(jfnk, torch, desc, o, u0, args.steps, args.warmup)
+
+    def summary(r):
+        ms = r["step_ms"]
+        st = r["stats"]
+        value = cells * len(ms) / r["wall"]
+        ms_d, cnt, by = r["dom"]
+        achieved = (by / (ms_d * 1e-3)) / 1e9 if ms_d > 0 else None
+        kern = {}
+        for k, (t, c, b) in sorted(r["table"].items(), key=lambda kv: -kv[1][0]):
+            kern[k] = dict(ms=round(t, 3), launches=c, avg_us=round(1e3 * t / c, 2),
+                           gbs=round(b / (t * 1e-3) / 1e9, 1) if b > 0 and t > 0 else None)
+        return dict(value=value, ms_per_step=1e3 * r["wall"] / len(ms), p50_ms=float(np.percentile(ms, 50)),
+                    p99_ms=float(np.percentile(ms, 99)), first_step_ms=float(ms[0]),
+                    newton_its_per_step=float(np.mean([s["newton_its"] for s in st])),
+                    gmres_its_per_step=float(np.mean([s["gmres_its"] for s in st])),
+                    dominant=r["dominant"], dominant_gbs=achieved,
+                    dominant_avg_us=1e3 * ms_d / cnt if cnt else None, kernels=kern)
+
+    main_form = forms[0]
+    s0 = summary(res[main_form])
+    out = {
+        "metric": METRIC, "value": s0["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": s0["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if main_form == "fp64" else "f64+f32", "data": "synthetic",
+        "config": {"workload": "taylor_green_%d^3" % args.n, "cells": cells, "grid": desc["n"],
+                   "cfl_hydro": opts["cfl_hydro"], "newton_rtol": opts["newton_rtol"],
+                   "gmres_restart": opts["gmres_restart"], "preconditioner": "acoustic, multigrid V(2,2)",
+                   "form": main_form, "timed_steps": "steps %d..%d of the run from t=0" %
+                   (args.warmup + 1, args.warmup + args.steps)},
+        "p50_ms": s0["p50_ms"], "p99_ms": s0["p99_ms"], "first_step_ms": s0["first_step_ms"],
+        "newton_its_per_step": s0["newton_its_per_step"], "gmres_its_per_step": s0["gmres_its_per_step"],
+        "roofline": {"bound": "hbm", "kernel": s0["dominant"], "achieved": s0["dominant_gbs"],
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": (s0["dominant_gbs"] / PEAK_HBM_GBS) if s0["dominant_gbs"] else None,
+                     "avg_launch_us": s0["dominant_avg_us"], "traffic": None},
+        "kernels": s0["kernels"],
+    }
+    for f in forms[1:]:
+        sf = summary(res[f])
+        a, b = res[f]["state"], res[main_form]["state"]
+        sf["state_rel_l2_vs_%s" % main_form] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        sf.pop("kernels")
+        sf["speedup_vs_%s" % main_form] = sf["value"] / s0["value"]
+        out.setdefault("forms", {})[f] = sf
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

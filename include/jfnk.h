@@ -152,6 +152,18 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
 int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z,
                        int on_device);
 
+/* ---- kernel-class timing ----
+ * Record a HIP event pair around every launch of the kernel classes in
+ * class_mask (bit c = class c; 0 disables) during later calls on p.  Events
+ * are read at the host synchronisation points the solver already has.
+ * jfnk_profile_read copies the accumulated milliseconds, launch counts and
+ * compulsory bytes (every array a launch reads or writes counted once) of the
+ * first nclass classes, resets them, and returns the number of classes.
+ * jfnk_profile_class_name names class c ("residual_out", "cgs2_update_dot", ...). */
+int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask);
+int jfnk_profile_read(jfnk_problem* p, double* ms, long long* count, double* bytes, int nclass);
+const char* jfnk_profile_class_name(int cls);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* jfnk_last_error(void);
 

@@ -116,3 +116,47 @@ inline int grid_blocks(long n, int block = kBlock) {
 }
 
 }  // namespace jfnk
+
+// ---------------------------------------------------------------- kernel-class timing with HIP events
+// When a problem has profiling enabled, its API calls install a profiler;
+// launchers record an event pair around each launch of a selected class on
+// the launch stream.  Completed pairs are drained at the host's existing
+// synchronisation points, so profiling adds no synchronisation.
+#include <vector>
+namespace jfnk {
+enum KClass : int {
+    KC_PRIM = 0, KC_FLUX, KC_OUT, KC_MDOT, KC_UPDATE_DOT, KC_UPDATE_NORM, KC_STORE, KC_COMBINE,
+    KC_MG_SMOOTH, KC_MG_RESTRICT, KC_MG_PROLONG, KC_MG_COARSE, KC_PC_RHS, KC_PC_BACK, KC_PC_BUILD,
+    KC_REDUCE, KC_LINES, KC_OTHER, KC_COUNT
+};
+struct Profiler {
+    unsigned mask = 0;
+    std::vector<hipEvent_t> pool;
+    std::vector<int> cls;  // class of each recorded pair
+    size_t used = 0;       // events in use (2 per pair)
+    double ms[KC_COUNT] = {};
+    long long count[KC_COUNT] = {};
+    double bytes[KC_COUNT] = {};  // compulsory bytes of the timed launches
+    std::vector<double> pend;     // bytes of each recorded pair
+    int begin(int c, hipStream_t s, double b);
+    void end(int c, hipStream_t s, int token);
+    void drain();  // caller has synchronised the stream
+    void release();
+};
+extern thread_local Profiler* g_prof;
+
+struct ProfScope {
+    int c, token;
+    hipStream_t s;
+    ProfScope(int cls_, hipStream_t st, double b = 0.0) : c(cls_), token(-1), s(st) {
+        if (g_prof && (g_prof->mask >> cls_ & 1u)) token = g_prof->begin(cls_, st, b);
+    }
+    ~ProfScope() {
+        if (token >= 0 && g_prof) g_prof->end(c, s, token);
+    }
+};
+}  // namespace jfnk
+#define JFNK_CAT2(a, b) a##b
+#define JFNK_CAT(a, b) JFNK_CAT2(a, b)
+#define JFNK_PROF(cls, stream) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (stream))
+#define JFNK_PROFB(cls, stream, b) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (stream), (double)(b))

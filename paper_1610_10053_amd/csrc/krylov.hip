@@ -32,10 +32,16 @@ __global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__
 }
 
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
-    hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
+    {
+        JFNK_PROF(KC_REDUCE, stream);
+        hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
+    }
 }
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
-    hipLaunchKernelGGL(k_final_max, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
+    {
+        JFNK_PROF(KC_REDUCE, stream);
+        hipLaunchKernelGGL(k_final_max, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
+    }
 }
 
 // ---------------------------------------------------------------- sum of (x/S)^2 over a state-shaped vector
@@ -56,7 +62,10 @@ void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale
                          hipStream_t stream) {
     Scales5 inv;
     for (int f = 0; f < 5; ++f) inv.v[f] = inv_scale5 ? inv_scale5[f] : 1.0;
-    hipLaunchKernelGGL(k_scaled_sumsq, dim3(nblk), dim3(kBlock), 0, stream, x, G.N, 2 + G.ndim, inv, part);
+    {
+        JFNK_PROF(KC_REDUCE, stream);
+        hipLaunchKernelGGL(k_scaled_sumsq, dim3(nblk), dim3(kBlock), 0, stream, x, G.N, 2 + G.ndim, inv, part);
+    }
 }
 
 // ---------------------------------------------------------------- CGS2 passes
@@ -138,6 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_update_mdot(const T* __restrict__ V,
 template <typename T>
 void launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, int nblk,
                  hipStream_t stream) {
+    JFNK_PROFB(KC_MDOT, stream, (double)n * (k * sizeof(T) + 8));
     if (k <= 8)
         hipLaunchKernelGGL((k_mdot<T, 8>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, w, n, part);
     else if (k <= 16)
@@ -152,6 +162,7 @@ template <typename T>
 void launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
                         int nblk, bool want_dots, hipStream_t stream) {
     const int wd = want_dots ? 1 : 0;
+    JFNK_PROFB((wd ? KC_UPDATE_DOT : KC_UPDATE_NORM), stream, (double)n * (k * sizeof(T) + 16));
     if (k <= 8)
         hipLaunchKernelGGL((k_update_mdot<T, 8>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, h, w, n, part, wd);
     else if (k <= 16)
@@ -172,7 +183,10 @@ __global__ void __launch_bounds__(kBlock) k_store_scaled(const double* __restric
 
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream) {
-    hipLaunchKernelGGL((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
+    {
+        JFNK_PROFB(KC_STORE, stream, (double)n * (8 + sizeof(T)));
+        hipLaunchKernelGGL((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
+    }
 }
 
 // t = sum_i y_i V_i, accumulated in order of i
@@ -195,6 +209,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, lon
 template <typename T>
 void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, hipStream_t stream) {
     const int nb = grid_blocks(n, kBlock * 4);
+    JFNK_PROFB(KC_COMBINE, stream, (double)n * (k * sizeof(T) + 8));
     if (k <= 8)
         hipLaunchKernelGGL((k_combine<T, 8>), dim3(nb), dim3(kBlock), 0, stream, V, ld, k, y, t, n);
     else if (k <= 16)
@@ -211,7 +226,10 @@ __global__ void __launch_bounds__(kBlock) k_add(double* __restrict__ x, const do
         x[e] += z[e];
 }
 void launch_add(double* x, const double* z, long n, hipStream_t stream) {
-    hipLaunchKernelGGL(k_add, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, x, z, n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_add, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, x, z, n);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_neg_scaled(const double* __restrict__ F, double* __restrict__ r,
@@ -222,8 +240,11 @@ __global__ void __launch_bounds__(kBlock) k_neg_scaled(const double* __restrict_
 void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* scale5, hipStream_t stream) {
     Scales5 s;
     for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
-    hipLaunchKernelGGL(k_neg_scaled, dim3(grid_blocks(G.nvec, kBlock * 4)), dim3(kBlock), 0, stream, F, r, G.N,
-                       G.nvec, s);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_neg_scaled, dim3(grid_blocks(G.nvec, kBlock * 4)), dim3(kBlock), 0, stream, F, r, G.N,
+                           G.nvec, s);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a, const double* __restrict__ b,
@@ -232,7 +253,10 @@ __global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a, co
         r[e] = a[e] - b[e];
 }
 void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t stream) {
-    hipLaunchKernelGGL(k_sub, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, a, b, r, n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_sub, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, a, b, r, n);
+    }
 }
 
 __global__ void __launch_bounds__(kBlock) k_copy(double* __restrict__ d, const double* __restrict__ s, long n) {
@@ -240,7 +264,10 @@ __global__ void __launch_bounds__(kBlock) k_copy(double* __restrict__ d, const d
         d[e] = s[e];
 }
 void launch_copy(double* dst, const double* src, long n, hipStream_t stream) {
-    hipLaunchKernelGGL(k_copy, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, dst, src, n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_copy, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, dst, src, n);
+    }
 }
 
 // u += S x, with the largest relative density correction |S_rho x / u_new|
@@ -261,7 +288,10 @@ void launch_update_state(double* u, const double* x, const Grid& G, const double
                          int nblk, hipStream_t stream) {
     Scales5 s;
     for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
-    hipLaunchKernelGGL(k_update_state, dim3(nblk), dim3(kBlock), 0, stream, u, x, G.N, G.nvec, s, part);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_update_state, dim3(nblk), dim3(kBlock), 0, stream, u, x, G.N, G.nvec, s, part);
+    }
 }
 
 // stored wall faces are not unknowns: force them to zero
@@ -274,7 +304,10 @@ __global__ void __launch_bounds__(kBlock) k_zero_walls(double* __restrict__ u, G
 }
 void launch_zero_walls(double* u, const Grid& G, hipStream_t stream) {
     if (!G.has_wall) return;
-    hipLaunchKernelGGL(k_zero_walls, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, u, G);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_zero_walls, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, u, G);
+    }
 }
 
 // plain sum of a vector (per-block partials)
@@ -286,7 +319,10 @@ __global__ void __launch_bounds__(kBlock) k_sum(const double* __restrict__ x, lo
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 void launch_sum(const double* x, long n, double* part, int nblk, hipStream_t stream) {
-    hipLaunchKernelGGL(k_sum, dim3(nblk), dim3(kBlock), 0, stream, x, n, part);
+    {
+        JFNK_PROF(KC_REDUCE, stream);
+        hipLaunchKernelGGL(k_sum, dim3(nblk), dim3(kBlock), 0, stream, x, n, part);
+    }
 }
 
 // basis vector to FP64
@@ -297,7 +333,10 @@ __global__ void __launch_bounds__(kBlock) k_widen(const T* __restrict__ v, doubl
 }
 template <typename T>
 void launch_widen(const T* v, double* out, long n, hipStream_t stream) {
-    hipLaunchKernelGGL((k_widen<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, v, out, n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL((k_widen<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, v, out, n);
+    }
 }
 
 // explicit instantiations

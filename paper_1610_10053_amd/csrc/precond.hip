@@ -41,7 +41,10 @@ __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __rest
 
 void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
                     hipStream_t stream) {
-    hipLaunchKernelGGL(k_pc_coef, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, u, P, C, 0.5 * dt);
+    {
+        JFNK_PROF(KC_PC_BUILD, stream);
+        hipLaunchKernelGGL(k_pc_coef, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, u, P, C, 0.5 * dt);
+    }
 }
 
 // ---------------------------------------------------------------- multigrid level helpers
@@ -128,15 +131,24 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<
 
 template <typename R>
 void launch_level0(const Grid& G, const PcCoef& C, int which, const LevelT<R>& L0, hipStream_t stream) {
-    hipLaunchKernelGGL((k_level0<R>), dim3(grid_blocks(L0.N)), dim3(kBlock), 0, stream, G, C, which, L0);
+    {
+        JFNK_PROF(KC_PC_BUILD, stream);
+        hipLaunchKernelGGL((k_level0<R>), dim3(grid_blocks(L0.N)), dim3(kBlock), 0, stream, G, C, which, L0);
+    }
 }
 template <typename R>
 void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream) {
-    hipLaunchKernelGGL((k_coarsen<R>), dim3(grid_blocks(C.N)), dim3(kBlock), 0, stream, G, F, C);
+    {
+        JFNK_PROF(KC_PC_BUILD, stream);
+        hipLaunchKernelGGL((k_coarsen<R>), dim3(grid_blocks(C.N)), dim3(kBlock), 0, stream, G, F, C);
+    }
 }
 template <typename R>
 void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
-    hipLaunchKernelGGL((k_level_diag<R>), dim3(grid_blocks(L.N)), dim3(kBlock), 0, stream, G, L);
+    {
+        JFNK_PROF(KC_PC_BUILD, stream);
+        hipLaunchKernelGGL((k_level_diag<R>), dim3(grid_blocks(L.N)), dim3(kBlock), 0, stream, G, L);
+    }
 }
 
 // ---------------------------------------------------------------- multigrid cell operations
@@ -270,22 +282,44 @@ template <typename R>
 static void vcycle_level(const Grid& G, const LevelSet<R>& S, int l, int nlev, int coarse_from, int nu1,
                          int nu2, int nuc, bool first, hipStream_t stream) {
     if (l >= coarse_from) {
-        hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1,
-                           nu2, nuc, first ? 1 : 0);
+        {
+            JFNK_PROF(KC_MG_COARSE, stream);
+            hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1,
+                               nu2, nuc, first ? 1 : 0);
+        }
         return;
     }
     const LevelT<R>& L = S.L[l];
     const int nb = grid_blocks(L.N);
+    const double bs = (double)L.N * sizeof(R) * (2.5 + G.ndim);
     for (int s = 0; s < nu1; ++s) {
-        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
-        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+        {
+            JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+        }
+        {
+            JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+        }
     }
-    hipLaunchKernelGGL((k_restrict<R>), dim3(grid_blocks(S.L[l + 1].N)), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    {
+        JFNK_PROFB(KC_MG_RESTRICT, stream, (double)L.N * sizeof(R) * (3 + G.ndim) + (double)S.L[l + 1].N * sizeof(R));
+        hipLaunchKernelGGL((k_restrict<R>), dim3(grid_blocks(S.L[l + 1].N)), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    }
     vcycle_level(G, S, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
-    hipLaunchKernelGGL((k_prolong<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    {
+        JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) * 2 + (double)S.L[l + 1].N * sizeof(R));
+        hipLaunchKernelGGL((k_prolong<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+    }
     for (int s = 0; s < nu2; ++s) {
-        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, 0);
-        hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+        {
+            JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, 0);
+        }
+        {
+            JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+        }
     }
 }
 
@@ -439,30 +473,48 @@ __global__ void __launch_bounds__(kBlock) k_jv_eps(const double* __restrict__ us
 template <typename R>
 void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc, R* rp,
                    hipStream_t stream) {
-    hipLaunchKernelGGL((k_pc_rhs<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, sc, rp);
+    {
+        JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (1 + 2 * G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        hipLaunchKernelGGL((k_pc_rhs<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, sc, rp);
+    }
 }
 template <typename R>
 void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const R* s, Scales5 sc, double* rE,
                          hipStream_t stream) {
-    hipLaunchKernelGGL((k_pc_diff_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, s, sc, rE);
+    {
+        JFNK_PROF(KC_PC_RHS, stream);
+        hipLaunchKernelGGL((k_pc_diff_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, s, sc, rE);
+    }
 }
 template <typename R>
 void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp, Scales5 sc,
                     double* z, double* part, int nblk, hipStream_t stream) {
     (void)nblk;
-    hipLaunchKernelGGL((k_pc_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, dp, sc, z,
-                       part);
+    {
+        JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        hipLaunchKernelGGL((k_pc_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, dp, sc, z,
+                           part);
+    }
 }
 template <typename R>
 void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream) {
-    hipLaunchKernelGGL((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
+    {
+        JFNK_PROF(KC_PC_RHS, stream);
+        hipLaunchKernelGGL((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
+    }
 }
 void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream) {
-    hipLaunchKernelGGL(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
+    }
 }
 void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
                    hipStream_t stream) {
-    hipLaunchKernelGGL(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
+    {
+        JFNK_PROF(KC_REDUCE, stream);
+        hipLaunchKernelGGL(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
+    }
 }
 
 // ---------------------------------------------------------------- alternating-direction line solves
@@ -564,8 +616,11 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
                        hipStream_t stream) {
     const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
     const long nl = (long)G.n[r1] * G.n[r2];
-    hipLaunchKernelGGL((k_line<R>), dim3(grid_blocks(nl)), dim3(kBlock), 0, stream, G, C, d, kind, x, scratch4,
-                       scratch4 + G.N, scratch4 + 2 * G.N, scratch4 + 3 * G.N);
+    {
+        JFNK_PROF(KC_LINES, stream);
+        hipLaunchKernelGGL((k_line<R>), dim3(grid_blocks(nl)), dim3(kBlock), 0, stream, G, C, d, kind, x, scratch4,
+                           scratch4 + G.N, scratch4 + 2 * G.N, scratch4 + 3 * G.N);
+    }
 }
 
 // ---------------------------------------------------------------- instantiations

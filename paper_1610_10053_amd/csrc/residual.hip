@@ -330,20 +330,47 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
 
 // ---------------------------------------------------------------- host launchers
 
+// compulsory bytes of the three sweeps (each array read or written once)
+static double prim_writes(const Grid& G) {
+    return 8.0 * G.N * (3 + G.ndim + ((G.has_wall || G.has_chi) ? 1 : 0) + (G.has_chi ? 1 : 0) + (G.has_wall ? 1 : 0));
+}
+
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                      const double* sbal, const OutSpec& o, hipStream_t stream) {
     const int nb = grid_blocks(G.N);
-    hipLaunchKernelGGL(k_prim, dim3(nb), dim3(kBlock), 0, stream, G, s, P);
-    hipLaunchKernelGGL(k_flux, dim3(nb), dim3(kBlock), 0, stream, G, P, Fx, W);
-    hipLaunchKernelGGL(k_out, dim3(nb), dim3(kBlock), 0, stream, G, s, P, Fx, W, sbal, o);
+    const double vec = 8.0 * G.nvec;
+    const double b_prim = (s.v ? 2.0 : 1.0) * vec + prim_writes(G);
+    const double b_flux = prim_writes(G) + 8.0 * G.N * 2 * G.ndim;
+    double b_out = 8.0 * G.N * (3 * G.ndim + 2 + (sbal ? 1 : 0)) + (s.v ? 2.0 : 1.0) * vec + vec;
+    if (o.mode == OUT_CN_OLD) b_out += vec;
+    if (o.mode == OUT_RESIDUAL) b_out += vec;
+    if (o.mode == OUT_JV) b_out += 2.0 * vec;
+    {
+        JFNK_PROFB(KC_PRIM, stream, b_prim);
+        hipLaunchKernelGGL(k_prim, dim3(nb), dim3(kBlock), 0, stream, G, s, P);
+    }
+    {
+        JFNK_PROFB(KC_FLUX, stream, b_flux);
+        hipLaunchKernelGGL(k_flux, dim3(nb), dim3(kBlock), 0, stream, G, P, Fx, W);
+    }
+    {
+        JFNK_PROFB(KC_OUT, stream, b_out);
+        hipLaunchKernelGGL(k_out, dim3(nb), dim3(kBlock), 0, stream, G, s, P, Fx, W, sbal, o);
+    }
 }
 
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
-    hipLaunchKernelGGL(k_prim, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, s, P);
+    {
+        JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));
+        hipLaunchKernelGGL(k_prim, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, s, P);
+    }
 }
 
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream) {
-    hipLaunchKernelGGL(k_dt_partial, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, P, u, part);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        hipLaunchKernelGGL(k_dt_partial, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, P, u, part);
+    }
 }
 
 }  // namespace jfnk

@@ -78,6 +78,8 @@ struct jfnk_problem {
     int nred = 1, ncell_blk = 1;
     // last dt limits
     double hyd = 0, adv = 0, rad = 0;
+    Profiler prof;
+    bool prof_on = false;
 };
 
 namespace {
@@ -193,8 +195,22 @@ int read_scalars(jfnk_problem* p, int off, int count, double* out) {
     HIPCHK(hipMemcpyAsync(p->hpin, p->dsum + off, sizeof(double) * count, hipMemcpyDeviceToHost, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
     std::memcpy(out, p->hpin, sizeof(double) * count);
+    if (g_prof) g_prof->drain();
     return 0;
 }
+
+// installs the problem's profiler for the duration of an API call
+struct ProfGuard {
+    jfnk_problem* p;
+    explicit ProfGuard(jfnk_problem* pp) : p(pp) { g_prof = (pp && pp->prof_on) ? &pp->prof : nullptr; }
+    ~ProfGuard() {
+        if (g_prof && p) {
+            (void)hipStreamSynchronize(p->stream);
+            g_prof->drain();
+        }
+        g_prof = nullptr;
+    }
+};
 
 StateView view(jfnk_problem* p, const double* u, const double* v) {
     StateView s;
@@ -664,10 +680,16 @@ int freeze_sources(jfnk_problem* p) {
         if (!p->W.lo[d]) continue;
         const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
         const long nt = (long)G.n[r1] * G.n[r2];
-        hipLaunchKernelGGL(k_wall_flux, dim3(grid_blocks(nt)), dim3(kBlock), 0, p->stream, G, p->P, d,
-                           (double*)p->W.lo[d], (double*)p->W.hi[d]);
+        {
+            JFNK_PROF(KC_OTHER, p->stream);
+            hipLaunchKernelGGL(k_wall_flux, dim3(grid_blocks(nt)), dim3(kBlock), 0, p->stream, G, p->P, d,
+                               (double*)p->W.lo[d], (double*)p->W.hi[d]);
+        }
     }
-    if (p->sbal) hipLaunchKernelGGL(k_sbal, dim3(grid_blocks(G.N)), dim3(kBlock), 0, p->stream, G, p->P, p->W, p->sbal);
+    {
+        JFNK_PROF(KC_OTHER, p->stream);
+        if (p->sbal) hipLaunchKernelGGL(k_sbal, dim3(grid_blocks(G.N)), dim3(kBlock), 0, p->stream, G, p->P, p->W, p->sbal);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(p->stream));
     return 0;
@@ -837,6 +859,7 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
 int jfnk_destroy_problem(jfnk_problem* p) {
     if (!p) return 0;
     (void)hipStreamSynchronize(p->stream);
+    p->prof.release();
     if (p->hpin) (void)hipHostFree(p->hpin);
     delete p;
     return 0;
@@ -874,6 +897,7 @@ int jfnk_set_opts(jfnk_problem* p, const jfnk_solver_opts* opts) {
 
 int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out) {
     if (!p) return fail(-1, "null problem");
+    ProfGuard guard(p);
     if (!(dt > 0.0)) return fail(-1, "dt must be positive");
     auto t0 = std::chrono::steady_clock::now();
     jfnk_step_stats st;
@@ -903,6 +927,7 @@ int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out) {
 
 int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
     if (!p) return fail(-1, "null problem");
+    ProfGuard guard(p);
     auto t0 = std::chrono::steady_clock::now();
     jfnk_step_stats st;
     std::memset(&st, 0, sizeof(st));
@@ -934,6 +959,7 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
 
 int jfnk_eval_rhs(jfnk_problem* p, const double* u, double* R, int on_device) {
     if (!p || !u || !R) return fail(-1, "null argument");
+    ProfGuard guard(p);
     int rc = copy_in(p, p->s1, u, on_device);
     if (rc) return rc;
     launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
@@ -944,6 +970,7 @@ int jfnk_eval_rhs(jfnk_problem* p, const double* u, double* R, int on_device) {
 
 int jfnk_eval_cn_old(jfnk_problem* p, const double* un, double dt, double* b, int on_device) {
     if (!p || !un || !b) return fail(-1, "null argument");
+    ProfGuard guard(p);
     int rc = copy_in(p, p->s1, un, on_device);
     if (rc) return rc;
     launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
@@ -954,6 +981,7 @@ int jfnk_eval_cn_old(jfnk_problem* p, const double* un, double dt, double* b, in
 
 int jfnk_eval_residual(jfnk_problem* p, const double* u, const double* b, double dt, double* F, int on_device) {
     if (!p || !u || !b || !F) return fail(-1, "null argument");
+    ProfGuard guard(p);
     int rc = copy_in(p, p->s1, u, on_device);
     if (rc) return rc;
     rc = copy_in(p, p->s2, b, on_device);
@@ -966,6 +994,7 @@ int jfnk_eval_residual(jfnk_problem* p, const double* u, const double* b, double
 
 int jfnk_eval_time_step(jfnk_problem* p, const double* u, double* out9, int on_device) {
     if (!p || !u || !out9) return fail(-1, "null argument");
+    ProfGuard guard(p);
     int rc = copy_in(p, p->s1, u, on_device);
     if (rc) return rc;
     double dt;
@@ -991,6 +1020,7 @@ int jfnk_set_scales(jfnk_problem* p, const double* s5) {
 int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, const double* v, double* w,
                   int on_device) {
     if (!p || !u || !b || !v || !w) return fail(-1, "null argument");
+    ProfGuard guard(p);
     int rc;
     if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
     if ((rc = copy_in(p, p->s2, b, on_device))) return rc;
@@ -1006,6 +1036,7 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
 
 int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z, int on_device) {
     if (!p || !u || !v || !z) return fail(-1, "null argument");
+    ProfGuard guard(p);
     if (!(dt > 0.0)) return fail(-1, "dt must be positive");
     int rc;
     if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
@@ -1015,6 +1046,44 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
     pc_apply(p, p->s2, p->w);
     HIPCHK(hipGetLastError());
     return copy_out(p, z, p->w, on_device);
+}
+
+static const char* kClassNames[KC_COUNT] = {
+    "residual_prim", "residual_flux", "residual_out", "cgs2_dot", "cgs2_update_dot", "cgs2_update_norm",
+    "basis_store", "basis_combine", "mg_smooth", "mg_restrict", "mg_prolong", "mg_coarse", "pc_rhs",
+    "pc_back", "pc_build", "reduce", "adi_lines", "other"};
+
+int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask) {
+    if (!p) return fail(-1, "null problem");
+    p->prof.mask = class_mask;
+    p->prof_on = class_mask != 0;
+    for (int c = 0; c < KC_COUNT; ++c) {
+        p->prof.ms[c] = 0.0;
+        p->prof.count[c] = 0;
+        p->prof.bytes[c] = 0.0;
+    }
+    return 0;
+}
+
+int jfnk_profile_read(jfnk_problem* p, double* ms, long long* count, double* bytes, int nclass) {
+    if (!p || !ms || !count || !bytes) return fail(-1, "null argument");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->prof.drain();
+    for (int c = 0; c < nclass; ++c) {
+        ms[c] = c < KC_COUNT ? p->prof.ms[c] : 0.0;
+        count[c] = c < KC_COUNT ? p->prof.count[c] : 0;
+        bytes[c] = c < KC_COUNT ? p->prof.bytes[c] : 0.0;
+        if (c < KC_COUNT) {
+            p->prof.ms[c] = 0.0;
+            p->prof.count[c] = 0;
+            p->prof.bytes[c] = 0.0;
+        }
+    }
+    return KC_COUNT;
+}
+
+const char* jfnk_profile_class_name(int cls) {
+    return cls >= 0 && cls < KC_COUNT ? kClassNames[cls] : "";
 }
 
 }  // extern "C"

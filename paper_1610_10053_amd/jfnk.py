@@ -50,7 +50,7 @@ EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
            "jfnk_eval_time_step", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
-           "jfnk_last_error")
+           "jfnk_profile_enable", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_last_error")
 
 _lib = None
 
@@ -90,6 +90,9 @@ def load():
         "jfnk_set_scales": (ip, [vp, dp]),
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
+        "jfnk_profile_enable": (ip, [vp, C.c_uint]),
+        "jfnk_profile_read": (ip, [vp, dp, C.POINTER(C.c_longlong), dp, ip]),
+        "jfnk_profile_class_name": (C.c_char_p, [ip]),
         "jfnk_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -275,6 +278,24 @@ class Problem:
         _check(_lib.jfnk_apply_jv(self._h, pu, pb, float(dt), pv, po, d))
         return out
 
+    def profile_enable(self, classes):
+        """classes: iterable of class names or indices; empty disables."""
+        mask = 0
+        names = profile_class_names()
+        for c in classes:
+            mask |= 1 << (names.index(c) if isinstance(c, str) else int(c))
+        _check(_lib.jfnk_profile_enable(self._h, mask))
+
+    def profile_read(self):
+        """{class name: (milliseconds, launches, compulsory bytes)} since enable / last read."""
+        names = profile_class_names()
+        ms = np.zeros(len(names))
+        by = np.zeros(len(names))
+        cnt = (C.c_longlong * len(names))()
+        dpp = C.POINTER(C.c_double)
+        _check(_lib.jfnk_profile_read(self._h, ms.ctypes.data_as(dpp), cnt, by.ctypes.data_as(dpp), len(names)))
+        return {names[i]: (float(ms[i]), int(cnt[i]), float(by[i])) for i in range(len(names)) if cnt[i]}
+
     def apply_precond(self, u, dt, v):
         out = self._out(u)
         pu, d, k1 = _ptr(u)
@@ -282,6 +303,17 @@ class Problem:
         po, _, k3 = _ptr(out)
         _check(_lib.jfnk_apply_precond(self._h, pu, float(dt), pv, po, d))
         return out
+
+
+def profile_class_names():
+    lib = load()
+    out = []
+    for c in range(64):
+        s = lib.jfnk_profile_class_name(c).decode()
+        if not s:
+            break
+        out.append(s)
+    return out
 
 
 def footprint_bytes(desc, opts):

@@ -1,0 +1,254 @@
+"""GPU (MI355X) parity of the HIP library against the oracle, through the
+C-ABI.  Same seeded inputs on both sides; tolerances stated per test.
+
+FP64 residual, time step and preconditioner follow the same evaluation order
+on both sides (no floating-point contraction), so they are compared bit for
+bit.  The Jacobian-free product takes its step eps from two norms whose
+summation order differs, so the two sides difference F at states that differ
+in the last bits; a roundoff change of F, about 1e-16 of its largest terms,
+divided by eps ~ 1.5e-8 bounds the product's relative difference by ~1e-8 in
+the worst case (measured: up to 3.4e-12); it is compared to 1e-9.  Newton
+steps are compared in relative L2 per field against the 1e-10 bar.
+"""
+import numpy as np
+import pytest
+
+from _helpers import exact_sum, rel_l2
+from workloads import (PC_ACOUSTIC, PC_ACOUSTIC_DIFFUSION, PC_NONE, PCS_ADI, make_config, mirror_x,
+                       split_state, unknown_mask)
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("rt", 16), ("kh", 32), ("tg", 16), ("rad", 16)]
+FULL = [("rt", None), ("kh", None), ("rad", None)]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _lib():
+    from paper_1610_10053_amd import jfnk
+    jfnk.load()  # fails loudly if the HIP library is missing
+    return jfnk
+
+
+def _pair(name, n, **over):
+    from oracle import Oracle
+    jfnk = _lib()
+    desc, opts, u = make_config(name, n=n, **over)
+    print("case", name, n, over, flush=True)
+    return desc, opts, u, jfnk.Problem(desc, opts, u), Oracle(desc, opts, u)
+
+
+def _direction(desc, seed):
+    rng = np.random.default_rng(seed)
+    n = (2 + desc["ndim"]) * desc["n"][0] * desc["n"][1] * desc["n"][2]
+    return np.where(unknown_mask(desc), rng.uniform(-1, 1, n), 0.0)
+
+
+def _fields_rel(a, b, desc):
+    fa, fb = split_state(a, desc), split_state(b, desc)
+    return {k: rel_l2(fa[k], fb[k]) if np.linalg.norm(fb[k]) > 0 else np.linalg.norm(fa[k]) for k in fa}
+
+
+# ---------------------------------------------------------------- components
+
+@pytest.mark.parametrize("name,n", CASES + FULL)
+def test_residual_components_bitwise(torch_cuda, name, n):
+    desc, opts, u, g, o = _pair(name, n)
+    assert np.array_equal(g.eval_rhs(u), o.rhs(u))
+    tg, to = g.eval_time_step(u), o.time_step(u)
+    assert tg["dt"] == to["dt"] and np.array_equal(tg["scales"], to["scales"])
+    dt = to["dt"]
+    b = o.cn_old(u, dt)
+    assert np.array_equal(g.eval_cn_old(u, dt), b)
+    u1 = u + 1e-3 * np.abs(u) * _direction(desc, 3)
+    assert np.array_equal(g.eval_residual(u1, b, dt), o.residual(u1, b, dt))
+
+
+@pytest.mark.parametrize("name,n", CASES + FULL)
+def test_jv_parity(torch_cuda, name, n):
+    desc, opts, u, g, o = _pair(name, n)
+    ts = o.time_step(u)
+    g.eval_time_step(u)  # same scales on both sides
+    dt = ts["dt"]
+    b = o.cn_old(u, dt)
+    u1 = u + 1e-3 * np.abs(u) * _direction(desc, 4)
+    v = _direction(desc, 5)
+    assert rel_l2(g.apply_jv(u1, b, dt, v), o.jv(u1, b, dt, v)) < 1e-9
+
+
+@pytest.mark.parametrize("solver", ["mg", "adi"])
+@pytest.mark.parametrize("name,n", CASES + FULL)
+def test_preconditioner_bitwise(torch_cuda, name, n, solver):
+    over = {"pc_solver": PCS_ADI} if solver == "adi" else {}
+    desc, opts, u, g, o = _pair(name, n, **over)
+    dt = o.time_step(u)["dt"]
+    g.eval_time_step(u)
+    v = _direction(desc, 6)
+    assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
+
+
+# ---------------------------------------------------------------- Newton steps
+
+@pytest.mark.parametrize("name,n", CASES)
+def test_newton_solve_parity(torch_cuda, name, n):
+    desc, opts, u, g, o = _pair(name, n)
+    dt = o.time_step(u)["dt"]
+    rg, sg = g.newton_solve(dt)
+    ro, so = o.newton_solve(dt)
+    assert rg == 0 and ro == 0
+    assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+    ug, uo = g.get_state(), o.get_state()
+    assert rel_l2(ug, uo) <= 1e-10
+    for k, e in _fields_rel(ug, uo, desc).items():
+        assert e <= 1e-10, (k, e)
+
+
+@pytest.mark.parametrize("name,n,steps", [("rt", None, 10), ("kh", 64, 5), ("tg", 16, 4), ("rad", 32, 5)])
+def test_steps_from_identical_states(torch_cuda, name, n, steps):
+    """Each step starts both sides from the same state (the GPU's)."""
+    desc, opts, u, g, o = _pair(name, n)
+    for k in range(steps):
+        o.set_state(g.get_state())
+        rg, sg = g.implicit_step()
+        ro, so = o.implicit_step()
+        assert rg == 0 and ro == 0
+        assert sg["dt"] == so["dt"]
+        e = rel_l2(g.get_state(), o.get_state())
+        print("step", k, sg["newton_its"], sg["gmres_its"], e, flush=True)
+        assert e <= 1e-10
+
+
+@pytest.mark.parametrize("name,n", [("tg", 16), ("rad", 16)])
+def test_adi_and_unpreconditioned_paths(torch_cuda, name, n):
+    for over in ({"pc_solver": PCS_ADI, "gmres_max_cycles": 40}, {"pc": PC_NONE, "gmres_max_cycles": 40}):
+        if name == "rad" and over.get("pc") == PC_NONE:
+            continue
+        desc, opts, u, g, o = _pair(name, n, **over)
+        dt = o.time_step(u)["dt"] * (0.25 if name == "rad" else 1.0)
+        rg, sg = g.newton_solve(dt)
+        ro, so = o.newton_solve(dt)
+        assert rg == ro
+        if rg == 0:
+            assert rel_l2(g.get_state(), o.get_state()) <= 1e-10
+
+
+# ---------------------------------------------------------------- invariants on the GPU path
+
+@pytest.mark.parametrize("name,n", [("kh", 64), ("tg", 16)])
+def test_gpu_conservation(torch_cuda, name, n):
+    jfnk = _lib()
+    desc, opts, u = make_config(name, n=n)
+    g = jfnk.Problem(desc, opts, u)
+    f0 = split_state(u, desc)
+    s0 = {k: exact_sum(v) for k, v in f0.items()}
+    mom = sum(np.abs(f0[k]).sum() for k in f0 if k.startswith("m"))
+    for _ in range(3):
+        assert g.implicit_step()[0] == 0
+    f1 = split_state(g.get_state(), desc)
+    for k in s0:
+        scale = mom if k.startswith("m") else np.abs(f0[k]).sum()
+        assert abs(exact_sum(f1[k]) - s0[k]) <= 1e-13 * scale, k
+
+
+@pytest.mark.parametrize("name,n,steps", [("rt", None, 10), ("rad", 32, 10)])
+def test_gpu_hydrostatic_state_preserved(torch_cuda, name, n, steps):
+    jfnk = _lib()
+    desc, opts, u = make_config(name, n=n, noise=False, perturb=False)
+    g = jfnk.Problem(desc, opts, u)
+    for _ in range(steps):
+        rc, st = g.implicit_step()
+        assert rc == 0 and st["newton_its"] == 0
+    assert rel_l2(g.get_state(), u) <= 1e-14
+
+
+def test_gpu_rt_mirror_symmetry_bitwise(torch_cuda):
+    jfnk = _lib()
+    desc, opts, u = make_config("rt", pc=PC_NONE)
+    g = jfnk.Problem(desc, opts, u)
+    for _ in range(5):
+        assert g.implicit_step()[0] == 0
+        s = g.get_state()
+        assert np.array_equal(mirror_x(s, desc), s)
+
+
+def test_device_buffers_and_determinism(torch_cuda):
+    torch = torch_cuda
+    jfnk = _lib()
+    desc, opts, u = make_config("kh", n=64)
+    outs = []
+    for _ in range(2):
+        g = jfnk.Problem(desc, opts, torch.from_numpy(u).cuda())
+        for _ in range(2):
+            assert g.implicit_step()[0] == 0
+        d = torch.empty(u.size, dtype=torch.float64, device="cuda")
+        g.get_state(d)
+        outs.append(d.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------- failure handling forced from the host
+
+def test_gpu_failures_restore_state(torch_cuda):
+    jfnk = _lib()
+    desc, opts, u = make_config("kh", n=32, newton_max=1, max_halvings=0)
+    g = jfnk.Problem(desc, opts, u)
+    rc, st = g.implicit_step()
+    assert rc == 1 and np.array_equal(g.get_state(), u)
+    desc, opts, u = make_config("kh", n=32, gmres_max_cycles=0, max_halvings=0)
+    g = jfnk.Problem(desc, opts, u)
+    assert g.implicit_step()[0] == 2 and np.array_equal(g.get_state(), u)
+    bad = u.copy()
+    bad[7] = np.nan
+    desc, opts, _ = make_config("kh", n=32, max_halvings=0)
+    g = jfnk.Problem(desc, opts, bad)
+    assert g.implicit_step()[0] == 3
+
+
+# ---------------------------------------------------------------- full size, launch configuration of the benchmark
+
+def test_tg128_components_against_oracle(torch_cuda):
+    """Taylor-Green 128^3: residual, time step and preconditioner bitwise,
+    Jacobian-free product to 1e-9, at the benchmark's full size."""
+    desc, opts, u, g, o = _pair("tg", None)
+    assert np.array_equal(g.eval_rhs(u), o.rhs(u))
+    ts = o.time_step(u)
+    assert g.eval_time_step(u)["dt"] == ts["dt"]
+    dt = ts["dt"]
+    b = o.cn_old(u, dt)
+    v = _direction(desc, 8)
+    assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
+    assert rel_l2(g.apply_jv(u, b, dt, v), o.jv(u, b, dt, v)) < 1e-9
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tg128_step_converges_by_oracle_residual(torch_cuda, prec):
+    """One full-size step (FP64 and mixed): the oracle evaluates the
+    Crank-Nicolson residual of the GPU's new state and confirms the Newton
+    tolerance, and the conserved sums are unchanged."""
+    desc, opts, u, g, o = _pair("tg", None, prec=prec)
+    rc, st = g.implicit_step()
+    assert rc == 0
+    un = u
+    o.time_step(un)
+    b = o.cn_old(un, st["dt"])
+    F0 = o.residual(un, b, st["dt"])
+    unew = g.get_state()
+    F1 = o.residual(unew, b, st["dt"])
+    S = o.time_step(un)["scales"]
+    N = desc["n"][0] ** 3
+
+    def snorm(F):
+        return np.sqrt(sum(np.sum((F[f * N:(f + 1) * N] / S[f]) ** 2) for f in range(5)))
+    f0, f1 = snorm(F0), snorm(F1)
+    print("tg128 prec", prec, "newton", st["newton_its"], "gmres", st["gmres_its"], "f1/f0", f1 / f0, flush=True)
+    assert f1 <= 1.05e-8 * f0 or st["max_rel_corr"] <= 1e-12
+    for k in ("rho", "E"):
+        a0, a1 = split_state(un, desc)[k], split_state(unew, desc)[k]
+        assert abs(exact_sum(a1) - exact_sum(a0)) <= 1e-13 * np.abs(a0).sum()
