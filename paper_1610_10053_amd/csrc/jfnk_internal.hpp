@@ -44,9 +44,29 @@ __device__ __forceinline__ Ijk cell_coords(const Grid& G, long c) {
     return r;
 }
 
+// cell indices fit in 32 bits (checked at creation)
 __device__ __forceinline__ long flat(const Grid& G, int i, int j, int k) {
-    return (long)i + (long)G.n[0] * ((long)j + (long)G.n[1] * (long)k);
+    return (long)(i + G.n[0] * (j + G.n[1] * k));
 }
+
+// 3D launches of the cell sweeps: blocks of kBx x kBy threads (one wave per
+// row of kBx), grid (ceil(n0/kBx), ceil(n1/kBy), n2)
+constexpr int kBx = 64, kBy = 4;
+inline dim3 cell_grid3(const int n[3]) { return dim3((n[0] + kBx - 1) / kBx, (n[1] + kBy - 1) / kBy, n[2]); }
+inline int cell_blocks(const int n[3]) {
+    const dim3 g = cell_grid3(n);
+    return (int)(g.x * g.y * g.z);
+}
+__device__ __forceinline__ bool cell_from_launch(const Grid& G, Ijk& q, long& c) {
+    q.v[0] = (int)(blockIdx.x * kBx + threadIdx.x);
+    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
+    q.v[2] = (int)blockIdx.z;
+    if (q.v[0] >= G.n[0] || q.v[1] >= G.n[1]) return false;
+    c = flat(G, q.v[0], q.v[1], q.v[2]);
+    return true;
+}
+__device__ __forceinline__ int lin_block() { return (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)); }
+__device__ __forceinline__ int lin_thread() { return (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z)); }
 
 // Flat index of the cell shifted by s along axis d, with periodic wrap.
 // The caller guarantees the shift stays inside along a wall axis.
@@ -85,27 +105,31 @@ __device__ __forceinline__ double upstream(double vel, double ql, double sl, dou
 // Fixed reduction order, so results are reproducible run to run.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t = lin_thread();
+    const int lane = t & 63, wv = t >> 6;
+    const int nw = (int)(blockDim.x * blockDim.y * blockDim.z) >> 6;
     __syncthreads();
     if (lane == 0) sh[wv] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0) {
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    if (t == 0) {
+        for (int w = 0; w < nw; ++w) s += sh[w];
     }
     return s;  // valid in thread 0
 }
 
 __device__ __forceinline__ double block_max(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int t = lin_thread();
+    const int lane = t & 63, wv = t >> 6;
+    const int nw = (int)(blockDim.x * blockDim.y * blockDim.z) >> 6;
     __syncthreads();
     if (lane == 0) sh[wv] = v;
     __syncthreads();
     double s = 0.0;
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         s = sh[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) s = fmax(s, sh[w]);
+        for (int w = 1; w < nw; ++w) s = fmax(s, sh[w]);
     }
     return s;
 }

@@ -95,6 +95,9 @@ void launch_widen(const T* v, double* out, long n, hipStream_t stream);
 //   (M x)_c = sig_c x_c + sum over faces f of c of a_f (x_c - x_neighbour(f))
 // in precision R (FP64, or FP32 in the mixed form).
 constexpr int kMaxLevels = 16;
+// x and b of the levels solved by the single-workgroup coarse kernel live in
+// LDS: at most this many cells over those levels
+constexpr int kCoarseLdsCells = 5504;
 template <typename R>
 struct LevelT {
     int n[3];

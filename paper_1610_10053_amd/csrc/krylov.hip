@@ -296,9 +296,9 @@ void launch_update_state(double* u, const double* x, const Grid& G, const double
 
 // stored wall faces are not unknowns: force them to zero
 __global__ void __launch_bounds__(kBlock) k_zero_walls(double* __restrict__ u, Grid G) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     for (int d = 0; d < G.ndim; ++d)
         if (G.bc[d] == WALL && q.v[d] == 0) u[(long)(2 + d) * G.N + c] = 0.0;
 }
@@ -306,7 +306,7 @@ void launch_zero_walls(double* u, const Grid& G, hipStream_t stream) {
     if (!G.has_wall) return;
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_zero_walls, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, u, G);
+        hipLaunchKernelGGL(k_zero_walls, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, u, G);
     }
 }
 

@@ -18,9 +18,9 @@ namespace jfnk {
 // ---------------------------------------------------------------- coefficients
 __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __restrict__ u, Prim P, PcCoef C,
                                                     double tau) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     const double* E = u + G.N;
     for (int d = 0; d < G.ndim; ++d) {
         double hf = 0.0, chif = 0.0;
@@ -43,7 +43,7 @@ void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef&
                     hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_BUILD, stream);
-        hipLaunchKernelGGL(k_pc_coef, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, u, P, C, 0.5 * dt);
+        hipLaunchKernelGGL(k_pc_coef, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, u, P, C, 0.5 * dt);
     }
 }
 
@@ -52,21 +52,21 @@ struct LIjk {
     int v[3];
 };
 template <typename R>
-__device__ __forceinline__ LIjk lcoords(const LevelT<R>& L, long c) {
+__device__ __forceinline__ LIjk lcoords(const LevelT<R>& L, int c) {
     LIjk r;
-    r.v[0] = (int)(c % L.n[0]);
-    const long t = c / L.n[0];
-    r.v[1] = (int)(t % L.n[1]);
-    r.v[2] = (int)(t / L.n[1]);
+    r.v[0] = c % L.n[0];
+    const int t = c / L.n[0];
+    r.v[1] = t % L.n[1];
+    r.v[2] = t / L.n[1];
     return r;
 }
 template <typename R>
-__device__ __forceinline__ long lflat(const LevelT<R>& L, int i, int j, int k) {
-    return (long)i + (long)L.n[0] * ((long)j + (long)L.n[1] * (long)k);
+__device__ __forceinline__ int lflat(const LevelT<R>& L, int i, int j, int k) {
+    return i + L.n[0] * (j + L.n[1] * k);
 }
 // neighbour along d on a level: periodic wrap, -1 beyond a wall
 template <typename R>
-__device__ __forceinline__ long lnb(const Grid& G, const LevelT<R>& L, LIjk q, int d, int s) {
+__device__ __forceinline__ int lnb(const Grid& G, const LevelT<R>& L, LIjk q, int d, int s) {
     int a = q.v[d] + s;
     if (a < 0 || a >= L.n[d]) {
         if (G.bc[d] == WALL) return -1;
@@ -75,23 +75,49 @@ __device__ __forceinline__ long lnb(const Grid& G, const LevelT<R>& L, LIjk q, i
     q.v[d] = a;
     return lflat(L, q.v[0], q.v[1], q.v[2]);
 }
+// cell of a 3D launch over a level
+template <typename R>
+__device__ __forceinline__ bool lcell(const LevelT<R>& L, LIjk& q, int& c) {
+    q.v[0] = (int)(blockIdx.x * kBx + threadIdx.x);
+    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
+    q.v[2] = (int)blockIdx.z;
+    if (q.v[0] >= L.n[0] || q.v[1] >= L.n[1]) return false;
+    c = lflat(L, q.v[0], q.v[1], q.v[2]);
+    return true;
+}
+// cell of one colour (i + j + k parity) of a launch over half the x extent
+template <typename R>
+__device__ __forceinline__ bool lcell_color(const LevelT<R>& L, int color, LIjk& q, int& c) {
+    const int t = (int)(blockIdx.x * kBx + threadIdx.x);
+    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
+    q.v[2] = (int)blockIdx.z;
+    q.v[0] = 2 * t + ((q.v[1] + q.v[2] + color) & 1);
+    if (q.v[0] >= L.n[0] || q.v[1] >= L.n[1]) return false;
+    c = lflat(L, q.v[0], q.v[1], q.v[2]);
+    return true;
+}
+inline dim3 color_grid3(const int n[3]) {
+    const int half = (n[0] + 1) / 2;
+    return dim3((half + kBx - 1) / kBx, (n[1] + kBy - 1) / kBy, n[2]);
+}
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_level0(Grid G, PcCoef C, int which, LevelT<R> L) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= L.N) return;
+    LIjk q;
+    int c;
+    if (!lcell(L, q, c)) return;
     L.sig[c] = which == 0 ? (R)1.0 : (R)(1.0 / C.W[c]);
     for (int d = 0; d < G.ndim; ++d) L.a[d][c] = which == 0 ? (R)C.kap[d][c] : (R)C.beta[d][c];
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_level_diag(Grid G, LevelT<R> L) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= L.N) return;
-    const LIjk q = lcoords(L, c);
+    LIjk q;
+    int c;
+    if (!lcell(L, q, c)) return;
     R den = L.sig[c];
     for (int d = 0; d < G.ndim; ++d) {
-        const long up = lnb(G, L, q, d, 1);
+        const int up = lnb(G, L, q, d, 1);
         const R alo = L.a[d][c], ahi = up >= 0 ? L.a[d][up] : (R)0.0;
         den = den + alo;
         den = den + ahi;
@@ -104,9 +130,9 @@ __global__ void __launch_bounds__(kBlock) k_level_diag(Grid G, LevelT<R> L) {
 // 4 (couplings scale as 1/dx^2)
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<R> Cl) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= Cl.N) return;
-    const LIjk q = lcoords(Cl, c);
+    LIjk q;
+    int c;
+    if (!lcell(Cl, q, c)) return;
     const int nch = 1 << G.ndim;
     const R inv_ch = (R)(1.0 / nch), inv_face = (R)(1.0 / ((nch / 2) * 4));
     const int kk = G.ndim > 2 ? 2 : 1;
@@ -131,81 +157,73 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<
 
 template <typename R>
 void launch_level0(const Grid& G, const PcCoef& C, int which, const LevelT<R>& L0, hipStream_t stream) {
-    {
-        JFNK_PROF(KC_PC_BUILD, stream);
-        hipLaunchKernelGGL((k_level0<R>), dim3(grid_blocks(L0.N)), dim3(kBlock), 0, stream, G, C, which, L0);
-    }
+    JFNK_PROF(KC_PC_BUILD, stream);
+    hipLaunchKernelGGL((k_level0<R>), cell_grid3(L0.n), dim3(kBx, kBy), 0, stream, G, C, which, L0);
 }
 template <typename R>
 void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream) {
-    {
-        JFNK_PROF(KC_PC_BUILD, stream);
-        hipLaunchKernelGGL((k_coarsen<R>), dim3(grid_blocks(C.N)), dim3(kBlock), 0, stream, G, F, C);
-    }
+    JFNK_PROF(KC_PC_BUILD, stream);
+    hipLaunchKernelGGL((k_coarsen<R>), cell_grid3(C.n), dim3(kBx, kBy), 0, stream, G, F, C);
 }
 template <typename R>
 void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
-    {
-        JFNK_PROF(KC_PC_BUILD, stream);
-        hipLaunchKernelGGL((k_level_diag<R>), dim3(grid_blocks(L.N)), dim3(kBlock), 0, stream, G, L);
-    }
+    JFNK_PROF(KC_PC_BUILD, stream);
+    hipLaunchKernelGGL((k_level_diag<R>), cell_grid3(L.n), dim3(kBx, kBy), 0, stream, G, L);
 }
 
 // ---------------------------------------------------------------- multigrid cell operations
+// x and b are read and written through pointers so that the single-workgroup
+// coarse solver can keep them in LDS.
 
 // red-black Gauss-Seidel update of one cell (first: neighbours taken as 0)
 template <typename R>
-__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, long c, bool first) {
-    const LIjk q = lcoords(L, c);
-    R num = L.b[c];
+__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
+                                        bool first) {
+    R num = b[c];
     for (int d = 0; d < G.ndim; ++d) {
-        const long up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
-        if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : L.x[dn]);
-        if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : L.x[up]);
+        const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
+        if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : x[dn]);
+        if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : x[up]);
     }
-    L.x[c] = num / L.D[c];
-}
-
-template <typename R>
-__device__ __forceinline__ int color_of(const LevelT<R>& L, long c) {
-    const LIjk q = lcoords(L, c);
-    return (q.v[0] + q.v[1] + q.v[2]) & 1;
+    x[c] = num / L.D[c];
 }
 
 // residual of one fine cell
 template <typename R>
-__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, long c) {
-    const LIjk q = lcoords(L, c);
-    const R xc = L.x[c];
+__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
+                                        int c) {
+    const R xc = x[c];
     R acc = L.sig[c] * xc;
     for (int d = 0; d < G.ndim; ++d) {
-        const long up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
-        if (dn >= 0) acc = acc + L.a[d][c] * (xc - L.x[dn]);
-        if (up >= 0) acc = acc + L.a[d][up] * (xc - L.x[up]);
+        const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
+        if (dn >= 0) acc = acc + L.a[d][c] * (xc - x[dn]);
+        if (up >= 0) acc = acc + L.a[d][up] * (xc - x[up]);
     }
-    return L.b[c] - acc;
+    return b[c] - acc;
 }
 
 // coarse right-hand side: mean of the children's residuals
 template <typename R>
-__device__ __forceinline__ void restrict_cell(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, long c) {
-    const LIjk q = lcoords(Cl, c);
+__device__ __forceinline__ R restrict_cell(const Grid& G, const LevelT<R>& F, const R* fb, const R* fx, LIjk q) {
     const int kk = G.ndim > 2 ? 2 : 1;
     const R inv_ch = (R)(1.0 / (1 << G.ndim));
     R s = 0.0;
     for (int dk = 0; dk < kk; ++dk)
         for (int dj = 0; dj < 2; ++dj)
-            for (int di = 0; di < 2; ++di)
-                s = s + resid_cell(G, F, lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj,
-                                               G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2]));
-    Cl.b[c] = s * inv_ch;
+            for (int di = 0; di < 2; ++di) {
+                LIjk f;
+                f.v[0] = 2 * q.v[0] + di;
+                f.v[1] = 2 * q.v[1] + dj;
+                f.v[2] = G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2];
+                s = s + resid_cell(G, F, fb, fx, f, lflat(F, f.v[0], f.v[1], f.v[2]));
+            }
+    return s * inv_ch;
 }
 
 // cell-centred (bi/tri)linear prolongation of the coarse correction, weights
 // 3/4 and 1/4 per axis; beyond a wall the parent value is reused
 template <typename R>
-__device__ __forceinline__ void prolong_cell(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, long c) {
-    const LIjk f = lcoords(F, c);
+__device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, const R* cx, LIjk f) {
     const int P[3] = {f.v[0] / 2, f.v[1] / 2, G.ndim > 2 ? f.v[2] / 2 : f.v[2]};
     R e = 0.0;
     for (int m = 0; m < (1 << G.ndim); ++m) {
@@ -224,101 +242,123 @@ __device__ __forceinline__ void prolong_cell(const Grid& G, const LevelT<R>& F, 
                 w = w * (R)0.75;
             }
         }
-        e = e + w * Cl.x[lflat(Cl, qq[0], qq[1], qq[2])];
+        e = e + w * cx[lflat(Cl, qq[0], qq[1], qq[2])];
     }
-    F.x[c] = F.x[c] + e;
+    return e;
 }
 
 // ---------------------------------------------------------------- multigrid kernels (multi-block levels)
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color, int first) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= L.N) return;
-    if (color_of(L, c) != color) return;
-    gs_cell(G, L, c, first != 0);
+    LIjk q;
+    int c;
+    if (!lcell_color(L, color, q, c)) return;
+    gs_cell(G, L, L.b, L.x, q, c, first != 0);
 }
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= Cl.N) return;
-    restrict_cell(G, F, Cl, c);
+    LIjk q;
+    int c;
+    if (!lcell(Cl, q, c)) return;
+    Cl.b[c] = restrict_cell(G, F, F.b, F.x, q);
 }
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= F.N) return;
-    prolong_cell(G, F, Cl, c);
+    LIjk q;
+    int c;
+    if (!lcell(F, q, c)) return;
+    F.x[c] = F.x[c] + prolong_cell(G, Cl, Cl.x, q);
 }
 
-// the rest of the V-cycle, levels from..nlev-1, in one workgroup
+// The rest of the V-cycle, levels from..nlev-1, in one workgroup with x and
+// b of every level in LDS.
 constexpr int kCoarseThreads = 1024;
+
 template <typename R>
-__device__ void block_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
+__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, const R* b, R* x, int sweeps, bool first) {
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
-            for (long c = threadIdx.x; c < L.N; c += blockDim.x)
-                if (color_of(L, c) == color) gs_cell(G, L, c, first && s == 0 && color == 0);
+            for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+                const LIjk q = lcoords(L, c);
+                if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) gs_cell(G, L, b, x, q, c, first && s == 0 && color == 0);
+            }
             __syncthreads();
         }
 }
 template <typename R>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, LevelSet<R> S, int from, int nlev,
                                                                    int nu1, int nu2, int nuc, int first_top) {
+    __shared__ R xs[kCoarseLdsCells], bs[kCoarseLdsCells];
+    R* xl[kMaxLevels];
+    R* bl[kMaxLevels];
+    int off = 0;
+    for (int l = from; l < nlev; ++l) {
+        xl[l] = xs + off;
+        bl[l] = bs + off;
+        off += (int)S.L[l].N;
+    }
+    const bool top_first = first_top != 0;
+    for (int c = threadIdx.x; c < S.L[from].N; c += blockDim.x) {
+        bl[from][c] = S.L[from].b[c];
+        if (!top_first) xl[from][c] = S.L[from].x[c];
+    }
+    __syncthreads();
     for (int l = from; l < nlev - 1; ++l) {
-        const bool first = l == from ? first_top != 0 : true;
-        block_smooth(G, S.L[l], nu1, first);
-        for (long c = threadIdx.x; c < S.L[l + 1].N; c += blockDim.x) restrict_cell(G, S.L[l], S.L[l + 1], c);
+        const bool first = l == from ? top_first : true;
+        lds_smooth(G, S.L[l], bl[l], xl[l], nu1, first);
+        for (int c = threadIdx.x; c < S.L[l + 1].N; c += blockDim.x)
+            bl[l + 1][c] = restrict_cell(G, S.L[l], bl[l], xl[l], lcoords(S.L[l + 1], c));
         __syncthreads();
     }
-    block_smooth(G, S.L[nlev - 1], nuc, nlev - 1 == from ? first_top != 0 : true);
+    lds_smooth(G, S.L[nlev - 1], bl[nlev - 1], xl[nlev - 1], nuc, nlev - 1 == from ? top_first : true);
     for (int l = nlev - 2; l >= from; --l) {
-        for (long c = threadIdx.x; c < S.L[l].N; c += blockDim.x) prolong_cell(G, S.L[l], S.L[l + 1], c);
+        for (int c = threadIdx.x; c < S.L[l].N; c += blockDim.x)
+            xl[l][c] = xl[l][c] + prolong_cell(G, S.L[l + 1], xl[l + 1], lcoords(S.L[l], c));
         __syncthreads();
-        block_smooth(G, S.L[l], nu2, false);
+        lds_smooth(G, S.L[l], bl[l], xl[l], nu2, false);
     }
+    for (int c = threadIdx.x; c < S.L[from].N; c += blockDim.x) S.L[from].x[c] = xl[from][c];
 }
 
 template <typename R>
 static void vcycle_level(const Grid& G, const LevelSet<R>& S, int l, int nlev, int coarse_from, int nu1,
                          int nu2, int nuc, bool first, hipStream_t stream) {
     if (l >= coarse_from) {
-        {
-            JFNK_PROF(KC_MG_COARSE, stream);
-            hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1,
-                               nu2, nuc, first ? 1 : 0);
-        }
+        JFNK_PROF(KC_MG_COARSE, stream);
+        hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1, nu2,
+                           nuc, first ? 1 : 0);
         return;
     }
     const LevelT<R>& L = S.L[l];
-    const int nb = grid_blocks(L.N);
+    const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
     const double bs = (double)L.N * sizeof(R) * (2.5 + G.ndim);
     for (int s = 0; s < nu1; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 1, 0);
         }
     }
     {
         JFNK_PROFB(KC_MG_RESTRICT, stream, (double)L.N * sizeof(R) * (3 + G.ndim) + (double)S.L[l + 1].N * sizeof(R));
-        hipLaunchKernelGGL((k_restrict<R>), dim3(grid_blocks(S.L[l + 1].N)), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+        hipLaunchKernelGGL((k_restrict<R>), cell_grid3(S.L[l + 1].n), bl, 0, stream, G, L, S.L[l + 1]);
     }
     vcycle_level(G, S, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
     {
         JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) * 2 + (double)S.L[l + 1].N * sizeof(R));
-        hipLaunchKernelGGL((k_prolong<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, S.L[l + 1]);
+        hipLaunchKernelGGL((k_prolong<R>), cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1]);
     }
     for (int s = 0; s < nu2; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 0, 0);
+            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 0, 0);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), dim3(nb), dim3(kBlock), 0, stream, G, L, 1, 0);
+            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 1, 0);
         }
     }
 }
@@ -333,9 +373,9 @@ void mg_vcycle(const Grid& G, const LevelSet<R>& S, int nlev, int coarse_from, i
 template <typename R>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, R* __restrict__ rp) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
     double acc = 0.0;
     for (int d = 0; d < G.ndim; ++d) {
@@ -356,9 +396,9 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                          const R* __restrict__ s, Scales5 sc,
                                                          double* __restrict__ rE) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     double acc = sc.v[1] * v[G.N + c];
     const double sc0 = (double)s[c];
     for (int d = 0; d < G.ndim; ++d) {
@@ -382,10 +422,10 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                     const double* __restrict__ rE, const R* __restrict__ dp,
                                                     Scales5 sc, double* __restrict__ z, double* __restrict__ part) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    Ijk q;
+    long c = 0;
     double ss = 0.0;
-    if (c < G.N) {
-        const Ijk q = cell_coords(G, c);
+    if (cell_from_launch(G, q, c)) {
         const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
         const double dpc = (double)dp[c];
         double dmlo[3], dmhi[3];
@@ -433,7 +473,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
     }
     __shared__ double sh[kBlock / 64];
     const double t = block_sum(ss, sh);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    if (lin_thread() == 0) part[lin_block()] = t;
 }
 
 template <typename R>
@@ -475,7 +515,7 @@ void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double
                    hipStream_t stream) {
     {
         JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (1 + 2 * G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        hipLaunchKernelGGL((k_pc_rhs<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, sc, rp);
+        hipLaunchKernelGGL((k_pc_rhs<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, rp);
     }
 }
 template <typename R>
@@ -483,7 +523,7 @@ void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const 
                          hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
-        hipLaunchKernelGGL((k_pc_diff_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, s, sc, rE);
+        hipLaunchKernelGGL((k_pc_diff_back<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, s, sc, rE);
     }
 }
 template <typename R>
@@ -492,7 +532,7 @@ void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const doubl
     (void)nblk;
     {
         JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        hipLaunchKernelGGL((k_pc_back<R>), dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, C, v, rE, dp, sc, z,
+        hipLaunchKernelGGL((k_pc_back<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, sc, z,
                            part);
     }
 }

@@ -20,9 +20,9 @@ __device__ __forceinline__ double st(const StateView& s, int f, long c) {
 
 // ---------------------------------------------------------------- sweep 1: primitives per cell
 __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     const double rho = st(s, 0, c), E = st(s, 1, c);
     double qk = 0.0;
     for (int d = 0; d < G.ndim; ++d) {
@@ -76,9 +76,9 @@ __device__ __forceinline__ Ghost wall_ghost(const Grid& G, const Prim& P, long c
 }
 
 __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFlux W) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     for (int d = 0; d < G.ndim; ++d) {
         const bool wall = G.bc[d] == WALL;
         const int id = q.v[d];
@@ -200,10 +200,10 @@ __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const F
 
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    Ijk q;
+    long c = 0;
     double part = 0.0;
-    if (c < G.N) {
-        const Ijk q = cell_coords(G, c);
+    if (cell_from_launch(G, q, c)) {
         double R[5];
         // mass and energy in the cell
         double ar = 0.0, ae = 0.0;
@@ -289,17 +289,17 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
     if (o.partial) {
         __shared__ double sh[kBlock / 64];
         const double t = block_sum(part, sh);
-        if (threadIdx.x == 0) o.partial[blockIdx.x] = t;
+        if (lin_thread() == 0) o.partial[lin_block()] = t;
     }
 }
 
 // ---------------------------------------------------------------- time step and scales (eqs. 5-7)
 __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const double* __restrict__ u,
                                                         double* __restrict__ part) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    Ijk q;
+    long c = 0;
     double hyd = 0.0, adv = 0.0, rad = 0.0, rmax = 0.0, emax = 0.0, cmax = 0.0;
-    if (c < G.N) {
-        const Ijk q = cell_coords(G, c);
+    if (cell_from_launch(G, q, c)) {
         const double r = P.rho[c];
         const double cs = sqrt(G.gamma * P.p[c] / r);
         const double cp = G.gamma / G.gm1;
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
     double vals[6] = {hyd, adv, rad, rmax, emax, cmax};
     for (int k = 0; k < 6; ++k) {
         const double m = block_max(vals[k], sh);
-        if (threadIdx.x == 0) part[(long)k * gridDim.x + blockIdx.x] = m;
+        if (lin_thread() == 0) part[(long)k * (gridDim.x * gridDim.y * gridDim.z) + lin_block()] = m;
         __syncthreads();
     }
 }
@@ -337,7 +337,6 @@ static double prim_writes(const Grid& G) {
 
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                      const double* sbal, const OutSpec& o, hipStream_t stream) {
-    const int nb = grid_blocks(G.N);
     const double vec = 8.0 * G.nvec;
     const double b_prim = (s.v ? 2.0 : 1.0) * vec + prim_writes(G);
     const double b_flux = prim_writes(G) + 8.0 * G.N * 2 * G.ndim;
@@ -347,29 +346,29 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     if (o.mode == OUT_JV) b_out += 2.0 * vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
-        hipLaunchKernelGGL(k_prim, dim3(nb), dim3(kBlock), 0, stream, G, s, P);
+        hipLaunchKernelGGL(k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
     }
     {
         JFNK_PROFB(KC_FLUX, stream, b_flux);
-        hipLaunchKernelGGL(k_flux, dim3(nb), dim3(kBlock), 0, stream, G, P, Fx, W);
+        hipLaunchKernelGGL(k_flux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx, W);
     }
     {
         JFNK_PROFB(KC_OUT, stream, b_out);
-        hipLaunchKernelGGL(k_out, dim3(nb), dim3(kBlock), 0, stream, G, s, P, Fx, W, sbal, o);
+        hipLaunchKernelGGL(k_out, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P, Fx, W, sbal, o);
     }
 }
 
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));
-        hipLaunchKernelGGL(k_prim, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, s, P);
+        hipLaunchKernelGGL(k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
     }
 }
 
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_dt_partial, dim3(grid_blocks(G.N)), dim3(kBlock), 0, stream, G, P, u, part);
+        hipLaunchKernelGGL(k_dt_partial, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, u, part);
     }
 }
 

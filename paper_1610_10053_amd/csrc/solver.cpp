@@ -167,7 +167,7 @@ int count_levels(const Grid& G, int n_out[][3]) {
     return L;
 }
 
-constexpr long kCoarseCells = 4096;  // levels at or below this size run in one workgroup
+constexpr long kCoarseCells = 4096;  // levels at or below this size run in one workgroup (x, b in LDS)
 
 size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
 
@@ -648,9 +648,9 @@ __global__ void k_wall_flux(Grid G, Prim P, int d, double* lo, double* hi) {
 
 // heat-balance source: + sum_d (f_T(up) - f_T(lo)) / dx of the conductive flux
 __global__ void k_sbal(Grid G, Prim P, WallFlux W, double* sbal) {
-    const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= G.N) return;
-    const Ijk q = cell_coords(G, c);
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
     double acc = 0.0;
     for (int d = 0; d < G.ndim; ++d) {
         double flo, fhi;
@@ -688,7 +688,7 @@ int freeze_sources(jfnk_problem* p) {
     }
     {
         JFNK_PROF(KC_OTHER, p->stream);
-        if (p->sbal) hipLaunchKernelGGL(k_sbal, dim3(grid_blocks(G.N)), dim3(kBlock), 0, p->stream, G, p->P, p->W, p->sbal);
+        if (p->sbal) hipLaunchKernelGGL(k_sbal, cell_grid3(G.n), dim3(kBx, kBy), 0, p->stream, G, p->P, p->W, p->sbal);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(p->stream));
@@ -697,7 +697,7 @@ int freeze_sources(jfnk_problem* p) {
 
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 13 * nv * 8;                                                // vectors
+    size_t b = 13 * nv * 8;  // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);  // basis
     b += 9 * N * 8 + 6 * N * 8;                                            // primitives, fluxes
     b += (3 * 3 + 1) * N * 8 + N * 8 + 4 * N * 8;                          // pc coefficients, rE, lines
@@ -765,16 +765,27 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     p->nunk = G.nvec;
     for (int d = 0; d < G.ndim; ++d)
         if (G.bc[d] == WALL) p->nunk -= G.N / G.n[d];
+    if (G.nvec >= (1L << 31) / 2) {
+        delete p;
+        return fail(-4, "grid too large for 32-bit cell indexing");
+    }
     int nl[kMaxLevels][3];
     p->nlev = count_levels(G, nl);
-    p->coarse_from = p->nlev;
-    for (int l = 0; l < p->nlev; ++l)
-        if ((long)nl[l][0] * nl[l][1] * nl[l][2] <= kCoarseCells) {
+    // the coarse kernel takes the deepest levels whose cells fit in its LDS
+    p->coarse_from = p->nlev - 1;
+    {
+        long tail = 0;
+        for (int l = p->nlev - 1; l >= 0; --l) {
+            tail += (long)nl[l][0] * nl[l][1] * nl[l][2];
+            if (tail > kCoarseLdsCells || (long)nl[l][0] * nl[l][1] * nl[l][2] > kCoarseCells) break;
             p->coarse_from = l;
-            break;
         }
-    if (p->coarse_from >= p->nlev) p->coarse_from = p->nlev - 1;
-    p->ncell_blk = grid_blocks(G.N);
+    }
+    if ((long)nl[p->nlev - 1][0] * nl[p->nlev - 1][1] * nl[p->nlev - 1][2] > kCoarseLdsCells) {
+        delete p;
+        return fail(-4, "coarsest multigrid level does not fit the coarse solver");
+    }
+    p->ncell_blk = cell_blocks(G.n);
     p->nred = std::min(kRedBlocks, grid_blocks(G.nvec));
     p->npart = std::max(p->ncell_blk, kRedBlocks) * (kMaxRestart + 2);
     const long n = G.nvec, N = G.N;
