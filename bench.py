@@ -31,13 +31,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(jfnk, torch, desc, opts, u0, steps, warmup):
+def run_form(jfnk, torch, desc, opts, u0, steps, warmup, prof=True):
     dev = torch.from_numpy(u0).cuda()
     prob = jfnk.Problem(desc, opts, dev)
     names = jfnk.profile_class_names()
     # warm-up steps with every kernel class timed: per-class table and the
     # dominant class
-    prob.profile_enable(names)
+    prob.profile_enable(names if prof else [])
     for _ in range(warmup):
         rc, st = prob.implicit_step()
         if rc != 0:
@@ -46,7 +46,7 @@ def run_form(jfnk, torch, desc, opts, u0, steps, warmup):
     timed = {k: v for k, v in table.items() if v[2] > 0}
     dominant = max(timed, key=lambda k: timed[k][0]) if timed else "residual_out"
     # timed region: events around the dominant class only
-    prob.profile_enable([dominant])
+    prob.profile_enable([dominant] if prof else [])
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     stats = []
@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the implicit step of one grid runs on one device here, and a "
@@ -118,7 +119,7 @@ def main():
     for f in forms:
         log("form", f)
         o = dict(opts, prec=PREC_MIXED if f == "mixed" else PREC_FP64)
-        res[f] = run_form(jfnk, torch, desc, o, u0, args.steps, args.warmup)
+        res[f] = run_form(jfnk, torch, desc, o, u0, args.steps, args.warmup, prof=not args.no_prof)
 
     def summary(r):
         ms = r["step_ms"]

@@ -73,7 +73,7 @@ typedef struct {
     double newton_atol;
     double newton_corr_tol; /* ... or when max |d rho / rho| of a Newton correction <= corr_tol */
     int newton_max;
-    int gmres_restart;      /* Krylov basis size m (<= 64) */
+    int gmres_restart;      /* Krylov basis size m (<= 32) */
     int gmres_max_cycles;
     double gmres_eta;       /* relative linear tolerance */
     int pc;                 /* JFNK_PC_* */

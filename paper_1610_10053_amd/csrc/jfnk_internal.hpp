@@ -11,8 +11,8 @@
 namespace jfnk {
 
 constexpr int kBlock = 256;        // threads per block of the sweep kernels
-constexpr int kMaxRestart = 64;    // largest Krylov basis
-constexpr int kRedBlocks = 1024;   // blocks of the multi-dot reductions
+constexpr int kMaxRestart = 32;    // largest Krylov basis
+constexpr int kRedBlocks = 2048;   // most blocks of a multi-dot reduction
 
 enum Bc : int { PERIODIC = 0, WALL = 1 };
 
@@ -134,6 +134,19 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
     return s;
 }
 
+// launch a kernel templated on the number of dimensions (2 or 3), so that
+// every loop over axes unrolls and all axis indices are compile-time
+#define JFNK_LAUNCH_ND(ndim, kern, ...)                                   \
+    do {                                                                  \
+        if ((ndim) == 3) hipLaunchKernelGGL((kern<3>), __VA_ARGS__);     \
+        else hipLaunchKernelGGL((kern<2>), __VA_ARGS__);                  \
+    } while (0)
+#define JFNK_LAUNCH_RND(ndim, kern, R, ...)                               \
+    do {                                                                  \
+        if ((ndim) == 3) hipLaunchKernelGGL((kern<R, 3>), __VA_ARGS__);  \
+        else hipLaunchKernelGGL((kern<R, 2>), __VA_ARGS__);               \
+    } while (0)
+
 inline int grid_blocks(long n, int block = kBlock) {
     long b = (n + block - 1) / block;
     return (int)(b < 1 ? 1 : b);
@@ -149,7 +162,7 @@ inline int grid_blocks(long n, int block = kBlock) {
 #include <vector>
 namespace jfnk {
 enum KClass : int {
-    KC_PRIM = 0, KC_FLUX, KC_OUT, KC_MDOT, KC_UPDATE_DOT, KC_UPDATE_NORM, KC_STORE, KC_COMBINE,
+    KC_PRIM = 0, KC_FLUX, KC_MFLUX, KC_OUT, KC_MDOT, KC_UPDATE_DOT, KC_UPDATE_NORM, KC_STORE, KC_COMBINE,
     KC_MG_SMOOTH, KC_MG_RESTRICT, KC_MG_PROLONG, KC_MG_COARSE, KC_PC_RHS, KC_PC_BACK, KC_PC_BUILD,
     KC_REDUCE, KC_LINES, KC_OTHER, KC_COUNT
 };

@@ -31,10 +31,14 @@ struct Prim {
     double* q;
 };
 
-// Mass and total-energy fluxes on the lower face of each cell, per axis.
+// Mass and total-energy fluxes on the lower face of each cell, per axis, and
+// the momentum transport fluxes: phic[d] cell-centred flux of m_d along d,
+// phie[d][e] (e != d) flux of m_d along e at the lower e-edge of the d-face.
 struct Flux {
     double* fr[3];
     double* fe[3];
+    double* phic[3];
+    double* phie[3][3];
 };
 
 // Frozen conductive fluxes through the lower/upper wall of each wall axis,
@@ -69,12 +73,12 @@ void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipSt
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
 void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale5, double* part, int nblk,
                          hipStream_t stream);
+// the multi-dot launchers return the number of blocks (partials per column)
 template <typename T>
-void launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, int nblk,
-                 hipStream_t stream);
+int launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, hipStream_t stream);
 template <typename T>
-void launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
-                        int nblk, bool want_dots, hipStream_t stream);
+int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
+                       bool want_dots, hipStream_t stream);
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream);
 template <typename T>
@@ -97,7 +101,7 @@ void launch_widen(const T* v, double* out, long n, hipStream_t stream);
 constexpr int kMaxLevels = 16;
 // x and b of the levels solved by the single-workgroup coarse kernel live in
 // LDS: at most this many cells over those levels
-constexpr int kCoarseLdsCells = 5504;
+constexpr int kCoarseLdsCells = 704;
 template <typename R>
 struct LevelT {
     int n[3];
@@ -132,8 +136,8 @@ template <typename R>
 void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream);
 // V-cycles on b of level 0; levels >= coarse_from run in one single-block kernel
 template <typename R>
-void mg_vcycle(const Grid& G, const LevelSet<R>& S, int nlev, int coarse_from, int nu1, int nu2, int nuc,
-               bool first, hipStream_t stream);
+void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
+               int nuc, bool first, hipStream_t stream);
 
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>

@@ -2,46 +2,40 @@
 // multi-dot / update passes of classical Gram-Schmidt applied twice (CGS2),
 // basis combination and Newton update.  The basis may be stored in FP64 or
 // FP32; every dot product and update is accumulated in FP64.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace jfnk {
 
-// ---------------------------------------------------------------- final reductions (single block, fixed order)
-__global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nblk, int ncol,
+// ---------------------------------------------------------------- final reductions (one block per column, fixed order)
+__global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nblk,
                                                       double* __restrict__ out) {
     __shared__ double sh[kBlock / 64];
-    for (int col = 0; col < ncol; ++col) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(long)col * nblk + i];
-        const double t = block_sum(s, sh);
-        if (threadIdx.x == 0) out[col] = t;
-        __syncthreads();
-    }
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(long)col * nblk + i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[col] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__ part, int nblk, int ncol,
+__global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__ part, int nblk,
                                                       double* __restrict__ out) {
     __shared__ double sh[kBlock / 64];
-    for (int col = 0; col < ncol; ++col) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) s = fmax(s, part[(long)col * nblk + i]);
-        const double t = block_max(s, sh);
-        if (threadIdx.x == 0) out[col] = t;
-        __syncthreads();
-    }
+    const int col = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s = fmax(s, part[(long)col * nblk + i]);
+    const double t = block_max(s, sh);
+    if (threadIdx.x == 0) out[col] = t;
 }
 
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
-    {
-        JFNK_PROF(KC_REDUCE, stream);
-        hipLaunchKernelGGL(k_final_sum, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
-    }
+    JFNK_PROF(KC_REDUCE, stream);
+    hipLaunchKernelGGL(k_final_sum, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
 }
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
-    {
-        JFNK_PROF(KC_REDUCE, stream);
-        hipLaunchKernelGGL(k_final_max, dim3(1), dim3(kBlock), 0, stream, part, nblk, ncol, out);
-    }
+    JFNK_PROF(KC_REDUCE, stream);
+    hipLaunchKernelGGL(k_final_max, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
 }
 
 // ---------------------------------------------------------------- sum of (x/S)^2 over a state-shaped vector
@@ -69,108 +63,164 @@ void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale
 }
 
 // ---------------------------------------------------------------- CGS2 passes
-// pass 1: h_i = V_i . w (i < k) and w . w in column k
-template <typename T, int KMAX>
-__global__ void __launch_bounds__(kBlock) k_mdot(const T* __restrict__ V, long ld, int k,
-                                                 const double* __restrict__ w, long n,
-                                                 double* __restrict__ part) {
-    double acc[KMAX + 1];
+// Every kernel is instantiated for the exact number K of basis vectors, so
+// the K loads of an element are issued together and all loops unroll.
+
+// per-block sums of K columns with one barrier: wave shuffles, then one
+// thread per column adds the waves' values in a fixed order
+template <int K>
+__device__ __forceinline__ void block_sum_cols(double (&acc)[K], double* __restrict__ part) {
+    __shared__ double sh[(kBlock / 64) * K];
 #pragma unroll
-    for (int i = 0; i <= KMAX; ++i) acc[i] = 0.0;
+    for (int i = 0; i < K; ++i)
+        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_down(acc[i], o, 64);
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) sh[wv * K + i] = acc[i];
+    }
+    __syncthreads();
+    if (t < K) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w * K + t];
+        part[(long)t * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// pass 1: h_i = V_i . w (i < K) and w . w in column K
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock) k_mdot(const T* __restrict__ V, long ld, const double* __restrict__ w,
+                                                 long n, double* __restrict__ part) {
+    double acc[K + 1];
+#pragma unroll
+    for (int i = 0; i <= K; ++i) acc[i] = 0.0;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        double vv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) vv[i] = (double)V[(long)i * ld + e];
         const double we = w[e];
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i)
-            if (i < k) acc[i] += (double)V[(long)i * ld + e] * we;
-        acc[KMAX] += we * we;
+        for (int i = 0; i < K; ++i) acc[i] += vv[i] * we;
+        acc[K] += we * we;
     }
-    __shared__ double sh[kBlock / 64];
-#pragma unroll
-    for (int i = 0; i <= KMAX; ++i) {
-        if (i < k || i == KMAX) {
-            const double t = block_sum(acc[i], sh);
-            const int col = i == KMAX ? k : i;
-            if (threadIdx.x == 0) part[(long)col * gridDim.x + blockIdx.x] = t;
-        }
-    }
+    block_sum_cols<K + 1>(acc, part);
 }
 
-// passes 2 and 3: w -= sum_i h_i V_i (in order of i), then either the new
-// dots V_i . w (column i) or |w|^2 (column 0)
-template <typename T, int KMAX>
-__global__ void __launch_bounds__(kBlock) k_update_mdot(const T* __restrict__ V, long ld, int k,
-                                                        const double* __restrict__ h,
-                                                        double* __restrict__ w, long n,
-                                                        double* __restrict__ part, int want_dots) {
-    double acc[KMAX];
-    double hh[KMAX];
+// passes 2 and 3: w -= sum_i h_i V_i (in order of i), then the new dots
+// V_i . w (DOTS) or |w|^2 in column 0
+template <typename T, int K, bool DOTS>
+__global__ void __launch_bounds__(kBlock) k_update(const T* __restrict__ V, long ld, const double* __restrict__ h,
+                                                   double* __restrict__ w, long n, double* __restrict__ part) {
+    constexpr int NC = DOTS ? K : 1;
+    double acc[NC];
+    double hh[K];
 #pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-        acc[i] = 0.0;
-        hh[i] = i < k ? h[i] : 0.0;
-    }
-    double nrm = 0.0;
+    for (int i = 0; i < NC; ++i) acc[i] = 0.0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) hh[i] = h[i];
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        double vv[KMAX];
+        double vv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) vv[i] = (double)V[(long)i * ld + e];
         double we = w[e];
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (i < k) {
-                vv[i] = (double)V[(long)i * ld + e];
-                we -= hh[i] * vv[i];
-            }
-        }
+        for (int i = 0; i < K; ++i) we -= hh[i] * vv[i];
         w[e] = we;
-        if (want_dots) {
+        if (DOTS) {
 #pragma unroll
-            for (int i = 0; i < KMAX; ++i)
-                if (i < k) acc[i] += vv[i] * we;
+            for (int i = 0; i < NC; ++i) acc[i] += vv[i] * we;
         } else {
-            nrm += we * we;
+            acc[0] += we * we;
         }
     }
-    __shared__ double sh[kBlock / 64];
-    if (want_dots) {
+    block_sum_cols<NC>(acc, part);
+}
+
+// t = sum_i y_i V_i, accumulated in order of i
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, long ld, const double* __restrict__ y,
+                                                    double* __restrict__ t, long n) {
+    double yy[K];
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i) {
-            if (i < k) {
-                const double t = block_sum(acc[i], sh);
-                if (threadIdx.x == 0) part[(long)i * gridDim.x + blockIdx.x] = t;
-            }
-        }
-    } else {
-        const double t = block_sum(nrm, sh);
-        if (threadIdx.x == 0) part[blockIdx.x] = t;
+    for (int i = 0; i < K; ++i) yy[i] = y[i];
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        double vv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) vv[i] = (double)V[(long)i * ld + e];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) s += yy[i] * vv[i];
+        t[e] = s;
     }
 }
 
+// blocks that fill the device once for a kernel (grid-stride loops take the
+// rest), capped by the partial-sum capacity
+template <typename Kern>
+static int resident_blocks(Kern kern) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    }
+    int per = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlock, 0) != hipSuccess || per <= 0) per = 1;
+    const int nb = cus * per;
+    return nb > kRedBlocks ? kRedBlocks : nb;
+}
+
+#define JFNK_K_CASES(X)                                                                                    \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) \
+        X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+
 template <typename T>
-void launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, int nblk,
-                 hipStream_t stream) {
+int launch_mdot(const T* V, long ld, int k, const double* w, long n, double* part, hipStream_t stream) {
     JFNK_PROFB(KC_MDOT, stream, (double)n * (k * sizeof(T) + 8));
-    if (k <= 8)
-        hipLaunchKernelGGL((k_mdot<T, 8>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, w, n, part);
-    else if (k <= 16)
-        hipLaunchKernelGGL((k_mdot<T, 16>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, w, n, part);
-    else if (k <= 32)
-        hipLaunchKernelGGL((k_mdot<T, 32>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, w, n, part);
-    else
-        hipLaunchKernelGGL((k_mdot<T, 64>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, w, n, part);
+    int nblk = 1;
+    switch (k) {
+#define C(K)                                                                                           \
+    case K: {                                                                                          \
+        static int nb = 0;                                                                             \
+        if (!nb) nb = resident_blocks(k_mdot<T, K>);                                                  \
+        nblk = std::min(nb, grid_blocks(n));                                                                                     \
+        hipLaunchKernelGGL((k_mdot<T, K>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, w, n, part); \
+        break;                                                                                         \
+    }
+        JFNK_K_CASES(C)
+#undef C
+        default:
+            break;
+    }
+    return nblk;
 }
 
 template <typename T>
-void launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
-                        int nblk, bool want_dots, hipStream_t stream) {
-    const int wd = want_dots ? 1 : 0;
-    JFNK_PROFB((wd ? KC_UPDATE_DOT : KC_UPDATE_NORM), stream, (double)n * (k * sizeof(T) + 16));
-    if (k <= 8)
-        hipLaunchKernelGGL((k_update_mdot<T, 8>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, h, w, n, part, wd);
-    else if (k <= 16)
-        hipLaunchKernelGGL((k_update_mdot<T, 16>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, h, w, n, part, wd);
-    else if (k <= 32)
-        hipLaunchKernelGGL((k_update_mdot<T, 32>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, h, w, n, part, wd);
-    else
-        hipLaunchKernelGGL((k_update_mdot<T, 64>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, k, h, w, n, part, wd);
+int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, long n, double* part,
+                       bool want_dots, hipStream_t stream) {
+    JFNK_PROFB((want_dots ? KC_UPDATE_DOT : KC_UPDATE_NORM), stream, (double)n * (k * sizeof(T) + 16));
+    int nblk = 1;
+    switch (k) {
+#define C(K)                                                                                                      \
+    case K: {                                                                                                     \
+        static int nbd = 0, nbn = 0;                                                                              \
+        if (want_dots) {                                                                                          \
+            if (!nbd) nbd = resident_blocks(k_update<T, K, true>);                                               \
+            nblk = std::min(nbd, grid_blocks(n));                                                                 \
+            hipLaunchKernelGGL((k_update<T, K, true>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
+        } else {                                                                                                  \
+            if (!nbn) nbn = resident_blocks(k_update<T, K, false>);                                              \
+            nblk = std::min(nbn, grid_blocks(n));                                                                 \
+            hipLaunchKernelGGL((k_update<T, K, false>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
+        }                                                                                                         \
+        break;                                                                                                    \
+    }
+        JFNK_K_CASES(C)
+#undef C
+        default:
+            break;
+    }
+    return nblk;
 }
 
 // v = w / hn (rounded to the basis type)
@@ -183,41 +233,24 @@ __global__ void __launch_bounds__(kBlock) k_store_scaled(const double* __restric
 
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream) {
-    {
-        JFNK_PROFB(KC_STORE, stream, (double)n * (8 + sizeof(T)));
-        hipLaunchKernelGGL((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
-    }
-}
-
-// t = sum_i y_i V_i, accumulated in order of i
-template <typename T, int KMAX>
-__global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, long ld, int k,
-                                                    const double* __restrict__ y, double* __restrict__ t,
-                                                    long n) {
-    double yy[KMAX];
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) yy[i] = i < k ? y[i] : 0.0;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < KMAX; ++i)
-            if (i < k) s += yy[i] * (double)V[(long)i * ld + e];
-        t[e] = s;
-    }
+    JFNK_PROFB(KC_STORE, stream, (double)n * (8 + sizeof(T)));
+    hipLaunchKernelGGL((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
 }
 
 template <typename T>
 void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, hipStream_t stream) {
     const int nb = grid_blocks(n, kBlock * 4);
     JFNK_PROFB(KC_COMBINE, stream, (double)n * (k * sizeof(T) + 8));
-    if (k <= 8)
-        hipLaunchKernelGGL((k_combine<T, 8>), dim3(nb), dim3(kBlock), 0, stream, V, ld, k, y, t, n);
-    else if (k <= 16)
-        hipLaunchKernelGGL((k_combine<T, 16>), dim3(nb), dim3(kBlock), 0, stream, V, ld, k, y, t, n);
-    else if (k <= 32)
-        hipLaunchKernelGGL((k_combine<T, 32>), dim3(nb), dim3(kBlock), 0, stream, V, ld, k, y, t, n);
-    else
-        hipLaunchKernelGGL((k_combine<T, 64>), dim3(nb), dim3(kBlock), 0, stream, V, ld, k, y, t, n);
+    switch (k) {
+#define C(K)                                                                                        \
+    case K:                                                                                         \
+        hipLaunchKernelGGL((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n); \
+        break;
+        JFNK_K_CASES(C)
+#undef C
+        default:
+            break;
+    }
 }
 
 // ---------------------------------------------------------------- small vector kernels
@@ -295,18 +328,19 @@ void launch_update_state(double* u, const double* x, const Grid& G, const double
 }
 
 // stored wall faces are not unknowns: force them to zero
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_zero_walls(double* __restrict__ u, Grid G) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    for (int d = 0; d < G.ndim; ++d)
+    for (int d = 0; d < ND; ++d)
         if (G.bc[d] == WALL && q.v[d] == 0) u[(long)(2 + d) * G.N + c] = 0.0;
 }
 void launch_zero_walls(double* u, const Grid& G, hipStream_t stream) {
     if (!G.has_wall) return;
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_zero_walls, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, u, G);
+        JFNK_LAUNCH_ND(G.ndim, k_zero_walls, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, u, G);
     }
 }
 
@@ -342,12 +376,12 @@ void launch_widen(const T* v, double* out, long n, hipStream_t stream) {
 // explicit instantiations
 template void launch_widen<double>(const double*, double*, long, hipStream_t);
 template void launch_widen<float>(const float*, double*, long, hipStream_t);
-template void launch_mdot<double>(const double*, long, int, const double*, long, double*, int, hipStream_t);
-template void launch_mdot<float>(const float*, long, int, const double*, long, double*, int, hipStream_t);
-template void launch_update_mdot<double>(const double*, long, int, const double*, double*, long, double*, int,
-                                         bool, hipStream_t);
-template void launch_update_mdot<float>(const float*, long, int, const double*, double*, long, double*, int,
-                                        bool, hipStream_t);
+template int launch_mdot<double>(const double*, long, int, const double*, long, double*, hipStream_t);
+template int launch_mdot<float>(const float*, long, int, const double*, long, double*, hipStream_t);
+template int launch_update_mdot<double>(const double*, long, int, const double*, double*, long, double*, bool,
+                                        hipStream_t);
+template int launch_update_mdot<float>(const float*, long, int, const double*, double*, long, double*, bool,
+                                       hipStream_t);
 template void launch_store_scaled<double>(const double*, double*, double, long, hipStream_t);
 template void launch_store_scaled<float>(const double*, float*, double, long, hipStream_t);
 template void launch_combine<double>(const double*, long, int, const double*, double*, long, hipStream_t);

@@ -16,13 +16,14 @@
 namespace jfnk {
 
 // ---------------------------------------------------------------- coefficients
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __restrict__ u, Prim P, PcCoef C,
                                                     double tau) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
     const double* E = u + G.N;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         double hf = 0.0, chif = 0.0;
         if (!(G.bc[d] == WALL && q.v[d] == 0)) {
             const long xl = shifted(G, q, d, -1);
@@ -43,7 +44,7 @@ void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef&
                     hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_BUILD, stream);
-        hipLaunchKernelGGL(k_pc_coef, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, u, P, C, 0.5 * dt);
+        JFNK_LAUNCH_ND(G.ndim, k_pc_coef, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, u, P, C, 0.5 * dt);
     }
 }
 
@@ -101,22 +102,22 @@ inline dim3 color_grid3(const int n[3]) {
     return dim3((half + kBx - 1) / kBx, (n[1] + kBy - 1) / kBy, n[2]);
 }
 
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_level0(Grid G, PcCoef C, int which, LevelT<R> L) {
     LIjk q;
     int c;
     if (!lcell(L, q, c)) return;
     L.sig[c] = which == 0 ? (R)1.0 : (R)(1.0 / C.W[c]);
-    for (int d = 0; d < G.ndim; ++d) L.a[d][c] = which == 0 ? (R)C.kap[d][c] : (R)C.beta[d][c];
+    for (int d = 0; d < ND; ++d) L.a[d][c] = which == 0 ? (R)C.kap[d][c] : (R)C.beta[d][c];
 }
 
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_level_diag(Grid G, LevelT<R> L) {
     LIjk q;
     int c;
     if (!lcell(L, q, c)) return;
     R den = L.sig[c];
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1);
         const R alo = L.a[d][c], ahi = up >= 0 ? L.a[d][up] : (R)0.0;
         den = den + alo;
@@ -128,28 +129,28 @@ __global__ void __launch_bounds__(kBlock) k_level_diag(Grid G, LevelT<R> L) {
 // coarse coefficients by re-discretisation: sig averaged over the children,
 // face couplings averaged over the fine faces of a coarse face and divided by
 // 4 (couplings scale as 1/dx^2)
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<R> Cl) {
     LIjk q;
     int c;
     if (!lcell(Cl, q, c)) return;
-    const int nch = 1 << G.ndim;
+    const int nch = 1 << ND;
     const R inv_ch = (R)(1.0 / nch), inv_face = (R)(1.0 / ((nch / 2) * 4));
-    const int kk = G.ndim > 2 ? 2 : 1;
+    const int kk = ND > 2 ? 2 : 1;
     R s = 0.0;
     for (int dk = 0; dk < kk; ++dk)
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di)
-                s = s + F.sig[lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2])];
+                s = s + F.sig[lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, ND > 2 ? 2 * q.v[2] + dk : q.v[2])];
     Cl.sig[c] = s * inv_ch;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         R t = 0.0;
         for (int dk = 0; dk < kk; ++dk)
             for (int dj = 0; dj < 2; ++dj)
                 for (int di = 0; di < 2; ++di) {
                     const int off[3] = {di, dj, dk};
                     if (off[d] != 0) continue;
-                    t = t + F.a[d][lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2])];
+                    t = t + F.a[d][lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, ND > 2 ? 2 * q.v[2] + dk : q.v[2])];
                 }
         Cl.a[d][c] = t * inv_face;
     }
@@ -158,17 +159,17 @@ __global__ void __launch_bounds__(kBlock) k_coarsen(Grid G, LevelT<R> F, LevelT<
 template <typename R>
 void launch_level0(const Grid& G, const PcCoef& C, int which, const LevelT<R>& L0, hipStream_t stream) {
     JFNK_PROF(KC_PC_BUILD, stream);
-    hipLaunchKernelGGL((k_level0<R>), cell_grid3(L0.n), dim3(kBx, kBy), 0, stream, G, C, which, L0);
+    JFNK_LAUNCH_RND(G.ndim, k_level0, R, cell_grid3(L0.n), dim3(kBx, kBy), 0, stream, G, C, which, L0);
 }
 template <typename R>
 void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream) {
     JFNK_PROF(KC_PC_BUILD, stream);
-    hipLaunchKernelGGL((k_coarsen<R>), cell_grid3(C.n), dim3(kBx, kBy), 0, stream, G, F, C);
+    JFNK_LAUNCH_RND(G.ndim, k_coarsen, R, cell_grid3(C.n), dim3(kBx, kBy), 0, stream, G, F, C);
 }
 template <typename R>
 void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
     JFNK_PROF(KC_PC_BUILD, stream);
-    hipLaunchKernelGGL((k_level_diag<R>), cell_grid3(L.n), dim3(kBx, kBy), 0, stream, G, L);
+    JFNK_LAUNCH_RND(G.ndim, k_level_diag, R, cell_grid3(L.n), dim3(kBx, kBy), 0, stream, G, L);
 }
 
 // ---------------------------------------------------------------- multigrid cell operations
@@ -176,11 +177,11 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 // coarse solver can keep them in LDS.
 
 // red-black Gauss-Seidel update of one cell (first: neighbours taken as 0)
-template <typename R>
+template <typename R, int ND>
 __device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
                                         bool first) {
     R num = b[c];
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
         if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : x[dn]);
         if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : x[up]);
@@ -189,12 +190,12 @@ __device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const
 }
 
 // residual of one fine cell
-template <typename R>
+template <typename R, int ND>
 __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
                                         int c) {
     const R xc = x[c];
     R acc = L.sig[c] * xc;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
         if (dn >= 0) acc = acc + L.a[d][c] * (xc - x[dn]);
         if (up >= 0) acc = acc + L.a[d][up] * (xc - x[up]);
@@ -203,10 +204,10 @@ __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const
 }
 
 // coarse right-hand side: mean of the children's residuals
-template <typename R>
+template <typename R, int ND>
 __device__ __forceinline__ R restrict_cell(const Grid& G, const LevelT<R>& F, const R* fb, const R* fx, LIjk q) {
-    const int kk = G.ndim > 2 ? 2 : 1;
-    const R inv_ch = (R)(1.0 / (1 << G.ndim));
+    const int kk = ND > 2 ? 2 : 1;
+    const R inv_ch = (R)(1.0 / (1 << ND));
     R s = 0.0;
     for (int dk = 0; dk < kk; ++dk)
         for (int dj = 0; dj < 2; ++dj)
@@ -214,22 +215,22 @@ __device__ __forceinline__ R restrict_cell(const Grid& G, const LevelT<R>& F, co
                 LIjk f;
                 f.v[0] = 2 * q.v[0] + di;
                 f.v[1] = 2 * q.v[1] + dj;
-                f.v[2] = G.ndim > 2 ? 2 * q.v[2] + dk : q.v[2];
-                s = s + resid_cell(G, F, fb, fx, f, lflat(F, f.v[0], f.v[1], f.v[2]));
+                f.v[2] = ND > 2 ? 2 * q.v[2] + dk : q.v[2];
+                s = s + resid_cell<R, ND>(G, F, fb, fx, f, lflat(F, f.v[0], f.v[1], f.v[2]));
             }
     return s * inv_ch;
 }
 
 // cell-centred (bi/tri)linear prolongation of the coarse correction, weights
 // 3/4 and 1/4 per axis; beyond a wall the parent value is reused
-template <typename R>
+template <typename R, int ND>
 __device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, const R* cx, LIjk f) {
-    const int P[3] = {f.v[0] / 2, f.v[1] / 2, G.ndim > 2 ? f.v[2] / 2 : f.v[2]};
+    const int P[3] = {f.v[0] / 2, f.v[1] / 2, ND > 2 ? f.v[2] / 2 : f.v[2]};
     R e = 0.0;
-    for (int m = 0; m < (1 << G.ndim); ++m) {
+    for (int m = 0; m < (1 << ND); ++m) {
         int qq[3] = {P[0], P[1], P[2]};
         R w = 1.0;
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             if (m & (1 << d)) {
                 const int off = (f.v[d] % 2 == 0) ? -1 : 1;
                 w = w * (R)0.25;
@@ -248,85 +249,112 @@ __device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, co
 }
 
 // ---------------------------------------------------------------- multigrid kernels (multi-block levels)
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color, int first) {
     LIjk q;
     int c;
     if (!lcell_color(L, color, q, c)) return;
-    gs_cell(G, L, L.b, L.x, q, c, first != 0);
+    gs_cell<R, ND>(G, L, L.b, L.x, q, c, first != 0);
 }
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
     LIjk q;
     int c;
     if (!lcell(Cl, q, c)) return;
-    Cl.b[c] = restrict_cell(G, F, F.b, F.x, q);
+    Cl.b[c] = restrict_cell<R, ND>(G, F, F.b, F.x, q);
 }
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
     LIjk q;
     int c;
     if (!lcell(F, q, c)) return;
-    F.x[c] = F.x[c] + prolong_cell(G, Cl, Cl.x, q);
+    F.x[c] = F.x[c] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
 }
 
-// The rest of the V-cycle, levels from..nlev-1, in one workgroup with x and
-// b of every level in LDS.
-constexpr int kCoarseThreads = 1024;
-
-template <typename R>
-__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, const R* b, R* x, int sweeps, bool first) {
+// The rest of the V-cycle, levels from..nlev-1 (at most kCoarseLdsCells cells
+// in all), in one workgroup with every array of those levels in LDS.  Level
+// descriptors come from device memory (Ld) so that the level loop may index
+// them at run time.
+constexpr int kCoarseThreads = 256;
+template <typename R, int ND>
+__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
                 const LIjk q = lcoords(L, c);
-                if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) gs_cell(G, L, b, x, q, c, first && s == 0 && color == 0);
+                if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color)
+                    gs_cell<R, ND>(G, L, L.b, L.x, q, c, first && s == 0 && color == 0);
             }
             __syncthreads();
         }
 }
-template <typename R>
-__global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, LevelSet<R> S, int from, int nlev,
-                                                                   int nu1, int nu2, int nuc, int first_top) {
-    __shared__ R xs[kCoarseLdsCells], bs[kCoarseLdsCells];
-    R* xl[kMaxLevels];
-    R* bl[kMaxLevels];
-    int off = 0;
-    for (int l = from; l < nlev; ++l) {
-        xl[l] = xs + off;
-        bl[l] = bs + off;
-        off += (int)S.L[l].N;
+template <typename R, int ND>
+__global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const LevelT<R>* __restrict__ Ld,
+                                                                   int from, int nlev, int nu1, int nu2, int nuc,
+                                                                   int first_top) {
+    __shared__ R sm[(4 + ND) * kCoarseLdsCells];
+    __shared__ LevelT<R> Ls[kMaxLevels];
+    if (threadIdx.x == 0) {
+        int off = 0;
+        for (int l = from; l < nlev; ++l) {
+            LevelT<R> L = Ld[l];
+            const int n = (int)L.N;
+            L.sig = sm + off;
+            off += n;
+            for (int d = 0; d < ND; ++d) {
+                L.a[d] = sm + off;
+                off += n;
+            }
+            L.D = sm + off;
+            off += n;
+            L.x = sm + off;
+            off += n;
+            L.b = sm + off;
+            off += n;
+            Ls[l] = L;
+        }
     }
+    __syncthreads();
     const bool top_first = first_top != 0;
-    for (int c = threadIdx.x; c < S.L[from].N; c += blockDim.x) {
-        bl[from][c] = S.L[from].b[c];
-        if (!top_first) xl[from][c] = S.L[from].x[c];
+    for (int l = from; l < nlev; ++l) {
+        const LevelT<R> gL = Ld[l];
+        const LevelT<R>& L = Ls[l];
+        for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+            L.sig[c] = gL.sig[c];
+            for (int d = 0; d < ND; ++d) L.a[d][c] = gL.a[d][c];
+            L.D[c] = gL.D[c];
+            if (l == from) {
+                L.b[c] = gL.b[c];
+                if (!top_first) L.x[c] = gL.x[c];
+            }
+        }
     }
     __syncthreads();
     for (int l = from; l < nlev - 1; ++l) {
         const bool first = l == from ? top_first : true;
-        lds_smooth(G, S.L[l], bl[l], xl[l], nu1, first);
-        for (int c = threadIdx.x; c < S.L[l + 1].N; c += blockDim.x)
-            bl[l + 1][c] = restrict_cell(G, S.L[l], bl[l], xl[l], lcoords(S.L[l + 1], c));
+        lds_smooth<R, ND>(G, Ls[l], nu1, first);
+        for (int c = threadIdx.x; c < Ls[l + 1].N; c += blockDim.x)
+            Ls[l + 1].b[c] = restrict_cell<R, ND>(G, Ls[l], Ls[l].b, Ls[l].x, lcoords(Ls[l + 1], c));
         __syncthreads();
     }
-    lds_smooth(G, S.L[nlev - 1], bl[nlev - 1], xl[nlev - 1], nuc, nlev - 1 == from ? top_first : true);
+    lds_smooth<R, ND>(G, Ls[nlev - 1], nuc, nlev - 1 == from ? top_first : true);
     for (int l = nlev - 2; l >= from; --l) {
-        for (int c = threadIdx.x; c < S.L[l].N; c += blockDim.x)
-            xl[l][c] = xl[l][c] + prolong_cell(G, S.L[l + 1], xl[l + 1], lcoords(S.L[l], c));
+        for (int c = threadIdx.x; c < Ls[l].N; c += blockDim.x)
+            Ls[l].x[c] = Ls[l].x[c] + prolong_cell<R, ND>(G, Ls[l + 1], Ls[l + 1].x, lcoords(Ls[l], c));
         __syncthreads();
-        lds_smooth(G, S.L[l], bl[l], xl[l], nu2, false);
+        lds_smooth<R, ND>(G, Ls[l], nu2, false);
     }
-    for (int c = threadIdx.x; c < S.L[from].N; c += blockDim.x) S.L[from].x[c] = xl[from][c];
+    const LevelT<R> gT = Ld[from];
+    for (int c = threadIdx.x; c < Ls[from].N; c += blockDim.x) gT.x[c] = Ls[from].x[c];
 }
 
 template <typename R>
-static void vcycle_level(const Grid& G, const LevelSet<R>& S, int l, int nlev, int coarse_from, int nu1,
-                         int nu2, int nuc, bool first, hipStream_t stream) {
+static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int l, int nlev,
+                         int coarse_from, int nu1, int nu2, int nuc, bool first, hipStream_t stream) {
     if (l >= coarse_from) {
         JFNK_PROF(KC_MG_COARSE, stream);
-        hipLaunchKernelGGL((k_coarse_vcycle<R>), dim3(1), dim3(kCoarseThreads), 0, stream, G, S, l, nlev, nu1, nu2,
-                           nuc, first ? 1 : 0);
+        JFNK_LAUNCH_RND(G.ndim, k_coarse_vcycle, R, dim3(1), dim3(kCoarseThreads), 0, stream, G, Ld, l, nlev, nu1,
+                        nu2, nuc, first ? 1 : 0);
         return;
     }
     const LevelT<R>& L = S.L[l];
@@ -335,42 +363,42 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, int l, int nlev, i
     for (int s = 0; s < nu1; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 1, 0);
+            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
         }
     }
     {
         JFNK_PROFB(KC_MG_RESTRICT, stream, (double)L.N * sizeof(R) * (3 + G.ndim) + (double)S.L[l + 1].N * sizeof(R));
-        hipLaunchKernelGGL((k_restrict<R>), cell_grid3(S.L[l + 1].n), bl, 0, stream, G, L, S.L[l + 1]);
+        JFNK_LAUNCH_RND(G.ndim, k_restrict, R, cell_grid3(S.L[l + 1].n), bl, 0, stream, G, L, S.L[l + 1]);
     }
-    vcycle_level(G, S, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
+    vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
     {
         JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) * 2 + (double)S.L[l + 1].N * sizeof(R));
-        hipLaunchKernelGGL((k_prolong<R>), cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1]);
+        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1]);
     }
     for (int s = 0; s < nu2; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 0, 0);
+            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, 0);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            hipLaunchKernelGGL((k_gs<R>), cg, bl, 0, stream, G, L, 1, 0);
+            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
         }
     }
 }
 
 template <typename R>
-void mg_vcycle(const Grid& G, const LevelSet<R>& S, int nlev, int coarse_from, int nu1, int nu2, int nuc,
-               bool first, hipStream_t stream) {
-    vcycle_level(G, S, 0, nlev, coarse_from, nu1, nu2, nuc, first, stream);
+void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
+               int nuc, bool first, hipStream_t stream) {
+    vcycle_level(G, S, Ld, 0, nlev, coarse_from, nu1, nu2, nuc, first, stream);
 }
 
 // ---------------------------------------------------------------- right-hand sides and back-substitution
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, R* __restrict__ rp) {
     Ijk q;
@@ -378,7 +406,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
     if (!cell_from_launch(G, q, c)) return;
     const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
     double acc = 0.0;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const double* vm = v + (long)(2 + d) * G.N;
         const double s = sc.v[2 + d];
         const double flo = C.hf[d][c] * (s * vm[c]);
@@ -392,7 +420,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
     rp[c] = (R)(G.gm1 * (re - C.tau * acc));
 }
 
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                          const R* __restrict__ s, Scales5 sc,
                                                          double* __restrict__ rE) {
@@ -401,7 +429,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
     if (!cell_from_launch(G, q, c)) return;
     double acc = sc.v[1] * v[G.N + c];
     const double sc0 = (double)s[c];
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
         const bool bot = G.bc[d] == WALL && q.v[d] == 0;
         double thi = 0.0, tlo = 0.0;
@@ -418,7 +446,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
     rE[c] = acc;
 }
 
-template <typename R>
+template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                     const double* __restrict__ rE, const R* __restrict__ dp,
                                                     Scales5 sc, double* __restrict__ z, double* __restrict__ part) {
@@ -431,7 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
         double dmlo[3], dmhi[3];
         bool top[3];
         long upi[3];
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             const double* vm = v + (long)(2 + d) * G.N;
             const double s = sc.v[2 + d];
             if (G.bc[d] == WALL && q.v[d] == 0) {
@@ -450,10 +478,10 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             }
         }
         double acc = 0.0;
-        for (int d = 0; d < G.ndim; ++d) acc = acc + (dmhi[d] - dmlo[d]) * G.idx[d];
+        for (int d = 0; d < ND; ++d) acc = acc + (dmhi[d] - dmlo[d]) * G.idx[d];
         const double drho = sc.v[0] * v[c] - C.tau * acc;
         acc = 0.0;
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             const double flo = C.hf[d][c] * dmlo[d];
             const double fhi = top[d] ? 0.0 : C.hf[d][upi[d]] * dmhi[d];
             acc = acc + (fhi - flo) * G.idx[d];
@@ -465,7 +493,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
         t = dE / sc.v[1];
         z[G.N + c] = t;
         ss += t * t;
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             t = dmlo[d] / sc.v[2 + d];
             z[(long)(2 + d) * G.N + c] = t;
             ss += t * t;
@@ -515,7 +543,7 @@ void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double
                    hipStream_t stream) {
     {
         JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (1 + 2 * G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        hipLaunchKernelGGL((k_pc_rhs<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, rp);
+        JFNK_LAUNCH_RND(G.ndim, k_pc_rhs, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, rp);
     }
 }
 template <typename R>
@@ -523,7 +551,7 @@ void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const 
                          hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
-        hipLaunchKernelGGL((k_pc_diff_back<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, s, sc, rE);
+        JFNK_LAUNCH_RND(G.ndim, k_pc_diff_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, s, sc, rE);
     }
 }
 template <typename R>
@@ -532,7 +560,7 @@ void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const doubl
     (void)nblk;
     {
         JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        hipLaunchKernelGGL((k_pc_back<R>), cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, sc, z,
+        JFNK_LAUNCH_RND(G.ndim, k_pc_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, sc, z,
                            part);
     }
 }
@@ -668,7 +696,8 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     template void launch_level0<R>(const Grid&, const PcCoef&, int, const LevelT<R>&, hipStream_t);          \
     template void launch_coarsen<R>(const Grid&, const LevelT<R>&, const LevelT<R>&, hipStream_t);           \
     template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
-    template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, int, int, int, int, int, bool, hipStream_t); \
+    template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, const LevelT<R>*, int, int, int, int, int,     \
+                               bool, hipStream_t);                                                           \
     template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5, R*,    \
                                    hipStream_t);                                                             \
     template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const R*, Scales5,       \

@@ -19,13 +19,14 @@ __device__ __forceinline__ double st(const StateView& s, int f, long c) {
 }
 
 // ---------------------------------------------------------------- sweep 1: primitives per cell
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
     const double rho = st(s, 0, c), E = st(s, 1, c);
     double qk = 0.0;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const bool wall = G.bc[d] == WALL;
         double a = 0.0, b = 0.0;
         if (!(wall && q.v[d] == 0)) {
@@ -75,11 +76,12 @@ __device__ __forceinline__ Ghost wall_ghost(const Grid& G, const Prim& P, long c
     return gh;
 }
 
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFlux W) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    for (int d = 0; d < G.ndim; ++d) {
+    for (int d = 0; d < ND; ++d) {
         const bool wall = G.bc[d] == WALL;
         const int id = q.v[d];
         if (wall && id == 0) {
@@ -198,6 +200,27 @@ __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const F
     return Gm * upstream(Gm, ub, sl, uc, sr);
 }
 
+// Momentum transport fluxes of the staggered control volumes, one per
+// (component, direction) and cell: cell-centred for d == e, at the lower
+// e-edge of the d-face otherwise (wall faces, which are not unknowns, get 0).
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_mflux(Grid G, Prim P, Flux Fx) {
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        Fx.phic[d][c] = phi_cell(G, P, Fx, q, d);
+        const bool wallface = G.bc[d] == WALL && q.v[d] == 0;
+#pragma unroll
+        for (int e = 0; e < ND; ++e) {
+            if (e == d) continue;
+            Fx.phie[d][e][c] = wallface ? 0.0 : phi_edge(G, P, Fx, q, d, e);
+        }
+    }
+}
+
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o) {
     Ijk q;
@@ -207,7 +230,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         double R[5];
         // mass and energy in the cell
         double ar = 0.0, ae = 0.0;
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             double frh, feh;
             if (top) {
@@ -221,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             ar = ar - (frh - Fx.fr[d][c]) * G.idx[d];
             ae = ae - (feh - Fx.fe[d][c]) * G.idx[d];
         }
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             if (G.g[d] == 0.0) continue;
             const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             const double mlo = st(s, 2 + d, c);
@@ -232,31 +255,31 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         R[0] = ar;
         R[1] = ae;
         // momentum on the lower faces
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             if (G.bc[d] == WALL && q.v[d] == 0) {
                 R[2 + d] = 0.0;
                 continue;
             }
             double a = 0.0;
-            for (int e = 0; e < G.ndim; ++e) {
+            const long cl = shifted(G, q, d, -1);
+#pragma unroll
+            for (int e = 0; e < ND; ++e) {
                 if (e == d) {
-                    Ijk lo = q;
-                    lo.v[d] = q.v[d] - 1;
-                    if (lo.v[d] < 0) lo.v[d] += G.n[d];
-                    a = a - (phi_cell(G, P, Fx, q, d) - phi_cell(G, P, Fx, lo, d)) * G.idx[d];
+                    a = a - (Fx.phic[d][c] - Fx.phic[d][cl]) * G.idx[d];
                 } else {
-                    Ijk up = q;
-                    up.v[e] = q.v[e] + 1;
-                    a = a - (phi_edge(G, P, Fx, up, d, e) - phi_edge(G, P, Fx, q, d, e)) * G.idx[e];
+                    // the edge above along e; on a wall of e it carries no flux
+                    const double up = (G.bc[e] == WALL && q.v[e] == G.n[e] - 1)
+                                          ? 0.0
+                                          : Fx.phie[d][e][shifted(G, q, e, 1)];
+                    a = a - (up - Fx.phie[d][e][c]) * G.idx[e];
                 }
             }
-            const long cl = shifted(G, q, d, -1);
             a = a - (P.p[c] - P.p[cl]) * G.idx[d];
             if (G.g[d] != 0.0) a = a + (0.5 * (P.rho[cl] + P.rho[c])) * G.g[d];
             R[2 + d] = a;
         }
         // consumers
-        const int nv = 2 + G.ndim;
+        const int nv = 2 + ND;
         for (int f = 0; f < nv; ++f) {
             const long x = (long)f * G.N + c;
             const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
@@ -294,6 +317,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
 }
 
 // ---------------------------------------------------------------- time step and scales (eqs. 5-7)
+template <int ND>
 __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const double* __restrict__ u,
                                                         double* __restrict__ part) {
     Ijk q;
@@ -303,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
         const double r = P.rho[c];
         const double cs = sqrt(G.gamma * P.p[c] / r);
         const double cp = G.gamma / G.gm1;
-        for (int d = 0; d < G.ndim; ++d) {
+        for (int d = 0; d < ND; ++d) {
             const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             const double a = fabs(P.uf[d][c]);
             const double b = top ? 0.0 : fabs(P.uf[d][shifted(G, q, d, 1)]);
@@ -340,35 +364,39 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     const double vec = 8.0 * G.nvec;
     const double b_prim = (s.v ? 2.0 : 1.0) * vec + prim_writes(G);
     const double b_flux = prim_writes(G) + 8.0 * G.N * 2 * G.ndim;
-    double b_out = 8.0 * G.N * (3 * G.ndim + 2 + (sbal ? 1 : 0)) + (s.v ? 2.0 : 1.0) * vec + vec;
+    double b_out = 8.0 * G.N * (2 * G.ndim + G.ndim * G.ndim + 2 + (sbal ? 1 : 0)) + (s.v ? 2.0 : 1.0) * vec + vec;
     if (o.mode == OUT_CN_OLD) b_out += vec;
     if (o.mode == OUT_RESIDUAL) b_out += vec;
     if (o.mode == OUT_JV) b_out += 2.0 * vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
-        hipLaunchKernelGGL(k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
+        JFNK_LAUNCH_ND(G.ndim, k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
     }
     {
         JFNK_PROFB(KC_FLUX, stream, b_flux);
-        hipLaunchKernelGGL(k_flux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx, W);
+        JFNK_LAUNCH_ND(G.ndim, k_flux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx, W);
+    }
+    {
+        JFNK_PROFB(KC_MFLUX, stream, 8.0 * G.N * (2 * G.ndim + G.ndim * G.ndim));
+        JFNK_LAUNCH_ND(G.ndim, k_mflux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx);
     }
     {
         JFNK_PROFB(KC_OUT, stream, b_out);
-        hipLaunchKernelGGL(k_out, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P, Fx, W, sbal, o);
+        JFNK_LAUNCH_ND(G.ndim, k_out, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P, Fx, W, sbal, o);
     }
 }
 
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));
-        hipLaunchKernelGGL(k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
+        JFNK_LAUNCH_ND(G.ndim, k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
     }
 }
 
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_dt_partial, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, u, part);
+        JFNK_LAUNCH_ND(G.ndim, k_dt_partial, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, u, part);
     }
 }
 

@@ -65,6 +65,11 @@ struct jfnk_problem {
     PcCoef C{};
     LevelSet<double> ac64{}, df64{};
     LevelSet<float> ac32{}, df32{};
+    // device copies of the level descriptors (for the single-workgroup solve)
+    LevelT<double>* dac64 = nullptr;
+    LevelT<double>* ddf64 = nullptr;
+    LevelT<float>* dac32 = nullptr;
+    LevelT<float>* ddf32 = nullptr;
     int nlev = 1, coarse_from = 0;
     double* rEd = nullptr;
     double* lines = nullptr;
@@ -167,12 +172,12 @@ int count_levels(const Grid& G, int n_out[][3]) {
     return L;
 }
 
-constexpr long kCoarseCells = 4096;  // levels at or below this size run in one workgroup (x, b in LDS)
+constexpr long kCoarseCells = 512;  // levels at or below this size run in one workgroup from LDS
 
 size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
 
 template <typename R>
-int alloc_levels(jfnk_problem* p, LevelSet<R>& S, int nl[][3]) {
+int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3]) {
     for (int l = 0; l < p->nlev; ++l) {
         LevelT<R>& L = S.L[l];
         for (int a = 0; a < 3; ++a) L.n[a] = nl[l][a];
@@ -187,6 +192,8 @@ int alloc_levels(jfnk_problem* p, LevelSet<R>& S, int nl[][3]) {
         L.x = blk + 5 * L.N;
         L.b = blk + 6 * L.N;
     }
+    CK(dalloc(p, dS, (size_t)kMaxLevels));
+    HIPCHK(hipMemcpy(*dS, S.L, sizeof(LevelT<R>) * kMaxLevels, hipMemcpyHostToDevice));
     return 0;
 }
 
@@ -318,11 +325,22 @@ int pc_build(jfnk_problem* p, const double* u, double dt) {
 }
 
 template <typename R>
+const LevelT<R>* dlevels(jfnk_problem* p, int which);
+template <>
+const LevelT<double>* dlevels<double>(jfnk_problem* p, int which) {
+    return which == 0 ? p->dac64 : p->ddf64;
+}
+template <>
+const LevelT<float>* dlevels<float>(jfnk_problem* p, int which) {
+    return which == 0 ? p->dac32 : p->ddf32;
+}
+
+template <typename R>
 void mg_solve(jfnk_problem* p, int which) {
     const LevelSet<R>& S = levels<R>(p, which);
     for (int c = 0; c < p->opts.mg_cycles; ++c)
-        mg_vcycle<R>(p->G, S, p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2, p->opts.mg_nuc, c == 0,
-                     p->stream);
+        mg_vcycle<R>(p->G, S, dlevels<R>(p, which), p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2,
+                     p->opts.mg_nuc, c == 0, p->stream);
 }
 
 // z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z
@@ -455,12 +473,12 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
             }
             pc_apply(p, vin, p->z);
             jv(p, u, p->F, p->b, dt, p->z, p->w);
-            launch_mdot<T>(V, n, j + 1, p->w, n, p->part, p->nred, p->stream);
-            launch_final_sum(p->part, p->nred, j + 2, p->dsum + D_H1, p->stream);
-            launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, p->w, n, p->part, p->nred, true, p->stream);
-            launch_final_sum(p->part, p->nred, j + 1, p->dsum + D_H2, p->stream);
-            launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, p->w, n, p->part, p->nred, false, p->stream);
-            launch_final_sum(p->part, p->nred, 1, p->dsum + D_HN, p->stream);
+            int nb = launch_mdot<T>(V, n, j + 1, p->w, n, p->part, p->stream);
+            launch_final_sum(p->part, nb, j + 2, p->dsum + D_H1, p->stream);
+            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, p->w, n, p->part, true, p->stream);
+            launch_final_sum(p->part, nb, j + 1, p->dsum + D_H2, p->stream);
+            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, p->w, n, p->part, false, p->stream);
+            launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream);
             HIPCHK(hipGetLastError());
             CK(read_scalars(p, 0, D_HN + 1, hb.data()));
             const double w0 = std::sqrt(hb[D_H1 + j + 1]);
@@ -699,7 +717,7 @@ size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
     size_t b = 13 * nv * 8;  // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);  // basis
-    b += 9 * N * 8 + 6 * N * 8;                                            // primitives, fluxes
+    b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;  // primitives, fluxes
     b += (3 * 3 + 1) * N * 8 + N * 8 + 4 * N * 8;                          // pc coefficients, rE, lines
     const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
     for (int l = 0; l < nlev; ++l) b += 2 * level_bytes((long)nl[l][0] * nl[l][1] * nl[l][2], rs);
@@ -819,10 +837,23 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     p->P.chi = prim + 7 * N;
     p->P.q = prim + 8 * N;
     double* flux = nullptr;
-    AL(flux, (size_t)6 * N);
-    for (int d = 0; d < 3; ++d) {
+    const int nphi = G.ndim * G.ndim;
+    AL(flux, (size_t)(2 * G.ndim + nphi) * N);
+    for (int d = 0; d < G.ndim; ++d) {
         p->Fx.fr[d] = flux + d * N;
-        p->Fx.fe[d] = flux + (3 + d) * N;
+        p->Fx.fe[d] = flux + (G.ndim + d) * N;
+    }
+    {
+        double* ph = flux + 2 * G.ndim * N;
+        for (int d = 0; d < G.ndim; ++d) {
+            p->Fx.phic[d] = ph;
+            ph += N;
+            for (int e = 0; e < G.ndim; ++e) {
+                if (e == d) continue;
+                p->Fx.phie[d][e] = ph;
+                ph += N;
+            }
+        }
     }
     for (int d = 0; d < G.ndim; ++d) {
         if (G.bc[d] == WALL && G.has_chi) {
@@ -846,11 +877,11 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     AL(p->rEd, N);
     AL(p->lines, (size_t)4 * N);
     if (opts->prec == JFNK_MIXED) {
-        if ((rc = alloc_levels<float>(p, p->ac32, nl))) return cleanup(rc);
-        if ((rc = alloc_levels<float>(p, p->df32, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl))) return cleanup(rc);
     } else {
-        if ((rc = alloc_levels<double>(p, p->ac64, nl))) return cleanup(rc);
-        if ((rc = alloc_levels<double>(p, p->df64, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl))) return cleanup(rc);
     }
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
@@ -1060,7 +1091,7 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
 }
 
 static const char* kClassNames[KC_COUNT] = {
-    "residual_prim", "residual_flux", "residual_out", "cgs2_dot", "cgs2_update_dot", "cgs2_update_norm",
+    "residual_prim", "residual_flux", "residual_mflux", "residual_out", "cgs2_dot", "cgs2_update_dot", "cgs2_update_norm",
     "basis_store", "basis_combine", "mg_smooth", "mg_restrict", "mg_prolong", "mg_coarse", "pc_rhs",
     "pc_back", "pc_build", "reduce", "adi_lines", "other"};
 
