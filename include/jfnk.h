@@ -66,8 +66,9 @@ typedef struct {
 } jfnk_problem_desc;
 
 /* Solver options.  Defaults (jfnk_default_opts): rtol 1e-8, atol 1e-14,
- * corr_tol 1e-12, newton_max 20, GMRES(30) x 10 cycles, eta 1e-4, acoustic
- * preconditioner with one multigrid V(2,2) cycle, FP64. */
+ * corr_tol 1e-12, newton_max 20, GMRES(30) x 10 cycles, eta 1e-2, acoustic
+ * preconditioner with one multigrid V(2,2) cycle (4 sweeps on the coarsest
+ * level), FP64. */
 typedef struct {
     double newton_rtol;     /* stop when |S^-1 F| <= max(rtol |S^-1 F0|, atol sqrt(N_unknowns)) */
     double newton_atol;

@@ -741,12 +741,12 @@ void jfnk_default_opts(jfnk_solver_opts* o) {
     o->newton_max = 20;
     o->gmres_restart = 30;
     o->gmres_max_cycles = 10;
-    o->gmres_eta = 1e-4;
+    o->gmres_eta = 1e-2;
     o->pc = JFNK_PC_ACOUSTIC;
     o->pc_solver = JFNK_PCS_MULTIGRID;
     o->mg_nu1 = 2;
     o->mg_nu2 = 2;
-    o->mg_nuc = 16;
+    o->mg_nuc = 4;
     o->mg_cycles = 1;
     o->prec = JFNK_FP64;
     o->cfl_hydro = 1.0;
