@@ -6,7 +6,10 @@ A step is one full implicit time step (time-step selection, Crank-Nicolson
 old-time term, Newton iterations with preconditioned GMRES).  The state is
 resident in HBM before the timed region.  Two forms are timed: plain FP64,
 and the mixed form (FP32 preconditioner and Krylov basis, FP64 residual,
-Jacobian-free differences and orthogonalisation).  Prints one JSON line.
+Jacobian-free differences and orthogonalisation).  A serving mix of
+independent simulations through the continuous-batching request loop is
+measured beside it (throughput and p50/p99 step latency).  Prints one JSON
+line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -70,6 +73,75 @@ def run_form(jfnk, torch, desc, opts, u0, steps, warmup, prof=True):
                 state=state)
 
 
+def serving_mix(nreq, steps_lo, steps_hi, seed):
+    """Requests of the serving workload: problem uniform over rt/kh/tg/rad,
+    2D size N uniform over 32, 48, 64, 96, 128, 192, 256, 384, 512 (rt N x 2N,
+    kh N x N, rad N x 4N; sizes of the form 2^j or 3 * 2^j coarsen to a few
+    cells per axis), 3D size uniform over 32/64/96/128, steps uniform over
+    [steps_lo, steps_hi], precision FP64 or mixed with equal probability."""
+    from workloads import PREC_FP64, PREC_MIXED
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nreq):
+        name = ["rt", "kh", "tg", "rad"][rng.integers(4)]
+        n = int(rng.choice([32, 64, 96, 128] if name == "tg" else [32, 48, 64, 96, 128, 192, 256, 384, 512]))
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        prec = PREC_MIXED if rng.integers(2) else PREC_FP64
+        out.append((name, n, steps, prec))
+    return out
+
+
+def run_serving(jfnk, mix, hbm_bytes, active, rate, seed):
+    """Submit the mix at Poisson arrivals of the given rate (requests/s;
+    0 = all at once) and wait for every request."""
+    from workloads import make_config
+    reqs = []
+    for name, n, steps, prec in mix:
+        d, o, u = make_config(name, n=n, prec=prec)
+        reqs.append((d, o, u, steps))
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0 / rate, len(reqs)) if rate > 0 else np.zeros(len(reqs))
+    srv = jfnk.Server(hbm_bytes, active)
+    t0 = time.perf_counter()
+    t_next = t0
+    ids = []
+    for (d, o, u, k), gap in zip(reqs, gaps):
+        t_next += gap
+        delay = t_next - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(d, o, u, k))
+    res = [srv.wait(i) for i in ids]
+    wall = time.perf_counter() - t0
+    srv.close()
+    step_ms = np.concatenate([r[2] for r in res])
+    cell_steps = sum(r[1]["cells"] * r[1]["steps_done"] for r in res)
+    lat = np.array([r[1]["t_done_ms"] - r[1]["t_submit_ms"] for r in res])
+    queue = np.array([r[1]["t_admit_ms"] - r[1]["t_submit_ms"] for r in res])
+    return dict(requests=len(res), failed=sum(1 for r in res if r[1]["status"] != 0), wall_s=wall,
+                cell_steps_per_s=cell_steps / wall, requests_per_s=len(res) / wall,
+                step_p50_ms=float(np.percentile(step_ms, 50)), step_p99_ms=float(np.percentile(step_ms, 99)),
+                request_p50_ms=float(np.percentile(lat, 50)), request_p99_ms=float(np.percentile(lat, 99)),
+                queue_p50_ms=float(np.percentile(queue, 50)), queue_p99_ms=float(np.percentile(queue, 99)),
+                steps=int(sum(r[1]["steps_done"] for r in res)))
+
+
+def serving(jfnk, args):
+    lo, hi = (int(x) for x in args.serve_steps.split(","))
+    mix = serving_mix(args.serve_requests, lo, hi, args.serve_seed)
+    hbm = int(args.serve_hbm_gb * (1 << 30))
+    log("serving: %d requests, saturated pass" % len(mix))
+    sat = run_serving(jfnk, mix, hbm, args.serve_active, 0.0, args.serve_seed)
+    rate = 0.8 * sat["requests_per_s"]
+    log("serving: Poisson arrivals at %.2f requests/s" % rate)
+    poi = run_serving(jfnk, mix, hbm, args.serve_active, rate, args.serve_seed)
+    poi["arrival_rate_per_s"] = rate
+    return {"workload": "serving mix: %d requests (rt/kh/tg/rad, 2D 32..512, 3D 32..128 cubed, %d..%d steps, "
+                        "FP64 or mixed), seed %d" % (len(mix), lo, hi, args.serve_seed),
+            "max_active": args.serve_active, "arena_gb": args.serve_hbm_gb,
+            "saturated": sat, "poisson_0.8x": poi}
+
+
 def cpu_baseline(n, steps):
     from oracle import Oracle
     from workloads import make_config
@@ -95,14 +167,19 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--cpu-n", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-steps", default="5,20", help="lo,hi implicit steps per request")
+    ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
+    ap.add_argument("--serve-seed", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the implicit step of one grid runs on one device here, and a "
-              "multi-GPU run would need the domain-decomposed path, which this build does not include.",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the implicit step of one grid runs on one device, and several "
+              "GPUs would need a domain-decomposed path, which is not implemented.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1610_10053_amd import jfnk
@@ -164,6 +241,8 @@ def main():
         sf.pop("kernels")
         sf["speedup_vs_%s" % main_form] = sf["value"] / s0["value"]
         out.setdefault("forms", {})[f] = sf
+    if not args.no_serve:
+        out["serving"] = serving(jfnk, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)

@@ -165,6 +165,47 @@ int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask);
 int jfnk_profile_read(jfnk_problem* p, double* ms, long long* count, double* bytes, int nclass);
 const char* jfnk_profile_class_name(int cls);
 
+/* ---- serving: continuous batching of independent simulations ----
+ * A server owns one device arena of hbm_bytes and max_active worker threads,
+ * each with its own non-blocking HIP stream.  Submitted requests (a problem,
+ * its initial state and a number of implicit steps) wait in arrival order; a
+ * free worker admits the oldest waiting request whose footprint
+ * (jfnk_footprint_bytes plus alignment) fits a free range of the arena, so
+ * requests arriving while others run are admitted as workers and memory free
+ * up.  An admitted request keeps its state and Krylov workspaces resident in
+ * its arena range until its last step; the work of concurrent requests
+ * overlaps on the device through their streams.  Each request runs exactly
+ * the kernels and host decisions it would run alone, so its result does not
+ * depend on the mix.  Times are host milliseconds since server creation. */
+typedef struct jfnk_server jfnk_server;
+
+typedef struct {
+    int status;            /* 0 ok; > 0 solver status of the step that failed; < 0 error */
+    int steps_done;        /* accepted implicit steps */
+    int newton_its, gmres_its, rejections;
+    int pad;
+    double cells;          /* cells of the grid */
+    double t_submit_ms, t_admit_ms, t_done_ms;
+    double sim_time;       /* simulated time reached */
+    double footprint_bytes;
+} jfnk_request_stats;
+
+/* hbm_bytes: arena size (> 0); max_active: concurrent requests (1..64). */
+int jfnk_server_create(size_t hbm_bytes, int max_active, jfnk_server** out);
+/* Queue a request.  u0 is host memory in the state layout above; the server
+ * copies it.  Fails with -1 if the request can never fit the arena. */
+int jfnk_server_submit(jfnk_server* s, const jfnk_problem_desc* desc, const jfnk_solver_opts* opts,
+                       const double* u0, int nsteps, long long* id);
+/* 0 waiting, 1 running, 2 finished; -1 unknown id. */
+int jfnk_server_poll(jfnk_server* s, long long id);
+/* Block until the request has finished; copy its final state (host, may be
+ * NULL) and statistics, and the wall time of each step (host milliseconds,
+ * up to cap values, count in *nsteps_out).  The request is then released. */
+int jfnk_server_wait(jfnk_server* s, long long id, double* u_out, jfnk_request_stats* st, double* step_ms,
+                     int cap, int* nsteps_out);
+/* Finish every admitted and queued request, stop the workers and free the arena. */
+int jfnk_server_destroy(jfnk_server* s);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* jfnk_last_error(void);
 

@@ -45,7 +45,7 @@
 typedef struct {
     int n[3];
     long N;
-    double *sig, *a[3], *D, *x, *b, *r;
+    double *sig, *a[3], *D, *x, *b, *r, *t;
 } Level;
 
 typedef struct {
@@ -647,7 +647,7 @@ static long lnb(const Or *o, const Level *L, int i, int j, int k, int d, int s) 
     for (int k = 0; k < (L)->n[2]; ++k) for (int j = 0; j < (L)->n[1]; ++j) for (int i = 0; i < (L)->n[0]; ++i)
 
 static void level_free(Level *L) {
-    free(L->sig); free(L->D); free(L->x); free(L->b); free(L->r);
+    free(L->sig); free(L->D); free(L->x); free(L->b); free(L->r); free(L->t);
     for (int d = 0; d < 3; ++d) free(L->a[d]);
     memset(L, 0, sizeof(*L));
 }
@@ -658,6 +658,7 @@ static void level_alloc(Level *L, const int n[3]) {
     L->sig = calloc(L->N, sizeof(double)); L->D = calloc(L->N, sizeof(double));
     L->x = calloc(L->N, sizeof(double)); L->b = calloc(L->N, sizeof(double));
     L->r = calloc(L->N, sizeof(double));
+    L->t = calloc(L->N, sizeof(double));
     for (int d = 0; d < 3; ++d) L->a[d] = calloc(L->N, sizeof(double));
 }
 
@@ -731,10 +732,15 @@ static void mg_build(Or *o, Level *lev, const double *sig, double *const *a) {
     }
 }
 
-/* red-black Gauss-Seidel: red cells (i+j+k even) first, then black */
+/* red-black Gauss-Seidel: red cells (i+j+k even) first, then black.  The
+ * cells of one colour are updated together from the values before their
+ * half-sweep.  While every periodic axis has even length no two cells of one
+ * colour are neighbours and this is the classical red-black sweep; on a
+ * coarsest level with an odd periodic axis the two cells facing each other
+ * across the wrap share a colour and see each other's previous values. */
 static void mg_smooth(const Or *o, Level *L, int sweeps) {
     for (int s = 0; s < sweeps; ++s)
-        for (int color = 0; color < 2; ++color)
+        for (int color = 0; color < 2; ++color) {
             FOR_LEVEL(L) {
                 if (((i + j + k) & 1) != color) continue;
                 long c = lidx(L, i, j, k);
@@ -744,8 +750,14 @@ static void mg_smooth(const Or *o, Level *L, int sweeps) {
                     if (dn >= 0) num = num + L->a[d][c] * L->x[dn];
                     if (up >= 0) num = num + L->a[d][up] * L->x[up];
                 }
-                L->x[c] = num / L->D[c];
+                L->t[c] = num / L->D[c];
             }
+            FOR_LEVEL(L) {
+                if (((i + j + k) & 1) != color) continue;
+                long c = lidx(L, i, j, k);
+                L->x[c] = L->t[c];
+            }
+        }
 }
 
 static void mg_residual(const Or *o, Level *L) {

@@ -111,6 +111,7 @@ struct LevelT {
     R* D;     // sig + sum of the cell's couplings
     R* x;
     R* b;
+    R* x2;  // second iterate buffer (coarsest level only, else null)
 };
 template <typename R>
 struct LevelSet {

@@ -3,6 +3,7 @@
 // basis combination and Newton update.  The basis may be stored in FP64 or
 // FP32; every dot product and update is accumulated in FP64.
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.hpp"
 
@@ -158,16 +159,24 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, lon
 // rest), capped by the partial-sum capacity
 template <typename Kern>
 static int resident_blocks(Kern kern) {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     int per = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, kBlock, 0) != hipSuccess || per <= 0) per = 1;
     const int nb = cus * per;
     return nb > kRedBlocks ? kRedBlocks : nb;
+}
+// resident_blocks computed once per kernel (the library drives one device
+// type; concurrent first calls compute the same value)
+template <typename Kern>
+static int cached_blocks(std::atomic<int>& slot, Kern kern) {
+    int v = slot.load(std::memory_order_relaxed);
+    if (!v) {
+        v = resident_blocks(kern);
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return v;
 }
 
 #define JFNK_K_CASES(X)                                                                                    \
@@ -181,9 +190,8 @@ int launch_mdot(const T* V, long ld, int k, const double* w, long n, double* par
     switch (k) {
 #define C(K)                                                                                           \
     case K: {                                                                                          \
-        static int nb = 0;                                                                             \
-        if (!nb) nb = resident_blocks(k_mdot<T, K>);                                                  \
-        nblk = std::min(nb, grid_blocks(n));                                                                                     \
+        static std::atomic<int> nb{0};                                                                 \
+        nblk = std::min(cached_blocks(nb, k_mdot<T, K>), grid_blocks(n));                              \
         hipLaunchKernelGGL((k_mdot<T, K>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, w, n, part); \
         break;                                                                                         \
     }
@@ -203,14 +211,12 @@ int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, l
     switch (k) {
 #define C(K)                                                                                                      \
     case K: {                                                                                                     \
-        static int nbd = 0, nbn = 0;                                                                              \
+        static std::atomic<int> nbd{0}, nbn{0};                                                                   \
         if (want_dots) {                                                                                          \
-            if (!nbd) nbd = resident_blocks(k_update<T, K, true>);                                               \
-            nblk = std::min(nbd, grid_blocks(n));                                                                 \
+            nblk = std::min(cached_blocks(nbd, k_update<T, K, true>), grid_blocks(n));                            \
             hipLaunchKernelGGL((k_update<T, K, true>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
         } else {                                                                                                  \
-            if (!nbn) nbn = resident_blocks(k_update<T, K, false>);                                              \
-            nblk = std::min(nbn, grid_blocks(n));                                                                 \
+            nblk = std::min(cached_blocks(nbn, k_update<T, K, false>), grid_blocks(n));                           \
             hipLaunchKernelGGL((k_update<T, K, false>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
         }                                                                                                         \
         break;                                                                                                    \

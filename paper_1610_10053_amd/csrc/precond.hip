@@ -176,17 +176,34 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 // x and b are read and written through pointers so that the single-workgroup
 // coarse solver can keep them in LDS.
 
-// red-black Gauss-Seidel update of one cell (first: neighbours taken as 0)
+// Gauss-Seidel value of one cell from its neighbours in x (first: neighbours
+// taken as 0)
 template <typename R, int ND>
-__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
-                                        bool first) {
+__device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c,
+                                      bool first) {
     R num = b[c];
     for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
         if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : x[dn]);
         if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : x[up]);
     }
-    x[c] = num / L.D[c];
+    return num / L.D[c];
+}
+// in-place red-black update of one cell: valid while no two cells of one
+// colour are neighbours, i.e. every periodic axis of the level has even length
+template <typename R, int ND>
+__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
+                                        bool first) {
+    x[c] = gs_value<R, ND>(G, L, b, x, q, c, first);
+}
+// a periodic axis of odd length (possible on the coarsest level only): the
+// two cells facing each other across the wrap share a colour, so a colour's
+// cells are updated together from the values before their half-sweep
+template <typename R>
+__device__ __forceinline__ bool odd_periodic(const Grid& G, const LevelT<R>& L) {
+    bool odd = false;
+    for (int d = 0; d < G.ndim; ++d) odd = odd || (G.bc[d] == PERIODIC && (L.n[d] & 1));
+    return odd;
 }
 
 // residual of one fine cell
@@ -256,6 +273,20 @@ __global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color, i
     if (!lcell_color(L, color, q, c)) return;
     gs_cell<R, ND>(G, L, L.b, L.x, q, c, first != 0);
 }
+// half-sweep of one colour from xin into xout (the other colour copied, or
+// zeroed on a first sweep): the update for levels with an odd periodic axis
+template <typename R, int ND>
+__global__ void __launch_bounds__(kBlock) k_gs_pp(Grid G, LevelT<R> L, int color, int first,
+                                                  const R* __restrict__ xin, R* __restrict__ xout) {
+    LIjk q;
+    int c;
+    if (!lcell(L, q, c)) return;
+    if (((q.v[0] + q.v[1] + q.v[2]) & 1) != color) {
+        xout[c] = first ? (R)0.0 : xin[c];
+        return;
+    }
+    xout[c] = gs_value<R, ND>(G, L, L.b, xin, q, c, first != 0);
+}
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
     LIjk q;
@@ -277,13 +308,27 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
 // them at run time.
 constexpr int kCoarseThreads = 256;
 template <typename R, int ND>
-__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
+__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first, R* tmp) {
+    const bool together = odd_periodic(G, L);
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
-            for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-                const LIjk q = lcoords(L, c);
-                if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color)
-                    gs_cell<R, ND>(G, L, L.b, L.x, q, c, first && s == 0 && color == 0);
+            const bool f = first && s == 0 && color == 0;
+            if (!together) {
+                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+                    const LIjk q = lcoords(L, c);
+                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) gs_cell<R, ND>(G, L, L.b, L.x, q, c, f);
+                }
+            } else {
+                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+                    const LIjk q = lcoords(L, c);
+                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) tmp[c] = gs_value<R, ND>(G, L, L.b, L.x, q, c, f);
+                }
+                __syncthreads();
+                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
+                    const LIjk q = lcoords(L, c);
+                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) L.x[c] = tmp[c];
+                    else if (f) L.x[c] = (R)0.0;
+                }
             }
             __syncthreads();
         }
@@ -293,6 +338,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
                                                                    int first_top) {
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
+    __shared__ R tmp[kCoarseLdsCells];
     __shared__ LevelT<R> Ls[kMaxLevels];
     if (threadIdx.x == 0) {
         int off = 0;
@@ -332,17 +378,17 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     __syncthreads();
     for (int l = from; l < nlev - 1; ++l) {
         const bool first = l == from ? top_first : true;
-        lds_smooth<R, ND>(G, Ls[l], nu1, first);
+        lds_smooth<R, ND>(G, Ls[l], nu1, first, tmp);
         for (int c = threadIdx.x; c < Ls[l + 1].N; c += blockDim.x)
             Ls[l + 1].b[c] = restrict_cell<R, ND>(G, Ls[l], Ls[l].b, Ls[l].x, lcoords(Ls[l + 1], c));
         __syncthreads();
     }
-    lds_smooth<R, ND>(G, Ls[nlev - 1], nuc, nlev - 1 == from ? top_first : true);
+    lds_smooth<R, ND>(G, Ls[nlev - 1], nuc, nlev - 1 == from ? top_first : true, tmp);
     for (int l = nlev - 2; l >= from; --l) {
         for (int c = threadIdx.x; c < Ls[l].N; c += blockDim.x)
             Ls[l].x[c] = Ls[l].x[c] + prolong_cell<R, ND>(G, Ls[l + 1], Ls[l + 1].x, lcoords(Ls[l], c));
         __syncthreads();
-        lds_smooth<R, ND>(G, Ls[l], nu2, false);
+        lds_smooth<R, ND>(G, Ls[l], nu2, false, tmp);
     }
     const LevelT<R> gT = Ld[from];
     for (int c = threadIdx.x; c < Ls[from].N; c += blockDim.x) gT.x[c] = Ls[from].x[c];
@@ -360,6 +406,38 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     const LevelT<R>& L = S.L[l];
     const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
     const double bs = (double)L.N * sizeof(R) * (2.5 + G.ndim);
+    if (l == nlev - 1) {
+        // coarsest level too large for the single-workgroup solve: the same
+        // nuc red-black sweeps as multi-block launches
+        bool odd = false;
+        for (int d = 0; d < G.ndim; ++d) odd = odd || (G.bc[d] == PERIODIC && (L.n[d] & 1));
+        if (odd) {
+            const dim3 fg = cell_grid3(L.n);
+            for (int s = 0; s < nuc; ++s) {
+                {
+                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                    JFNK_LAUNCH_RND(G.ndim, k_gs_pp, R, fg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0,
+                                    (const R*)L.x, L.x2);
+                }
+                {
+                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                    JFNK_LAUNCH_RND(G.ndim, k_gs_pp, R, fg, bl, 0, stream, G, L, 1, 0, (const R*)L.x2, L.x);
+                }
+            }
+            return;
+        }
+        for (int s = 0; s < nuc; ++s) {
+            {
+                JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+            }
+            {
+                JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
+            }
+        }
+        return;
+    }
     for (int s = 0; s < nu1; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);

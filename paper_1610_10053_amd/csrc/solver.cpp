@@ -15,6 +15,7 @@
 
 #include "../../include/jfnk.h"
 #include "kernels.hpp"
+#include "problem.hpp"
 
 using namespace jfnk;
 
@@ -53,6 +54,9 @@ struct jfnk_problem {
     jfnk_solver_opts opts{};
     hipStream_t stream = nullptr;
     Buffers buf;
+    // optional caller-provided device range that every buffer is carved from
+    char* slab = nullptr;
+    size_t slab_size = 0, slab_off = 0;
     // vectors of nvec doubles
     double *u = nullptr, *un = nullptr, *b = nullptr, *F = nullptr, *x = nullptr, *rhs = nullptr,
            *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
@@ -77,6 +81,7 @@ struct jfnk_problem {
     int npart = 0;
     double* dsum = nullptr;
     double* hpin = nullptr;
+    bool own_hpin = false;
     double scale[5] = {1, 1, 1, 1, 1};
     double t_now = 0.0;
     long nunk = 0;
@@ -85,14 +90,28 @@ struct jfnk_problem {
     double hyd = 0, adv = 0, rad = 0;
     Profiler prof;
     bool prof_on = false;
+    ~jfnk_problem() {
+        if (hpin && own_hpin) (void)hipHostFree(hpin);
+    }
 };
 
 namespace {
+
+constexpr size_t kSlabAlign = 256;
+constexpr size_t kSlabSlack = 128 * kSlabAlign;  // alignment of every carved buffer
 
 template <typename Tp>
 int dalloc(jfnk_problem* p, Tp** out, size_t count) {
     void* ptr = nullptr;
     const size_t bytes = count * sizeof(Tp);
+    if (p->slab) {
+        const size_t off = (p->slab_off + kSlabAlign - 1) / kSlabAlign * kSlabAlign;
+        if (off + bytes > p->slab_size) return fail(-2, "device range too small for the problem");
+        p->slab_off = off + bytes;
+        p->buf.bytes += bytes;
+        *out = (Tp*)(p->slab + off);
+        return 0;
+    }
     hipError_t e = hipMalloc(&ptr, bytes == 0 ? 8 : bytes);
     if (e != hipSuccess) return fail(-2, std::string("hipMalloc: ") + hipGetErrorString(e));
     p->buf.ptrs.push_back(ptr);
@@ -158,6 +177,8 @@ void make_grid(const jfnk_problem_desc& d, Grid& G) {
 }
 
 // multigrid depth: halve every active axis while all are even and >= 4
+// multigrid levels: every active axis halves while all are even and >= 4
+// (so only the coarsest level can have an odd axis)
 int count_levels(const Grid& G, int n_out[][3]) {
     int n[3] = {G.n[0], G.n[1], G.n[2]}, L = 0;
     for (;;) {
@@ -182,8 +203,9 @@ int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3]) {
         LevelT<R>& L = S.L[l];
         for (int a = 0; a < 3; ++a) L.n[a] = nl[l][a];
         L.N = (long)L.n[0] * L.n[1] * L.n[2];
+        const bool coarsest = l == p->nlev - 1;
         R* blk = nullptr;
-        CK(dalloc(p, &blk, (size_t)L.N * 7));
+        CK(dalloc(p, &blk, (size_t)L.N * (coarsest ? 8 : 7)));
         L.sig = blk;
         L.a[0] = blk + L.N;
         L.a[1] = blk + 2 * L.N;
@@ -191,9 +213,11 @@ int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3]) {
         L.D = blk + 4 * L.N;
         L.x = blk + 5 * L.N;
         L.b = blk + 6 * L.N;
+        L.x2 = coarsest ? blk + 7 * L.N : nullptr;
     }
     CK(dalloc(p, dS, (size_t)kMaxLevels));
-    HIPCHK(hipMemcpy(*dS, S.L, sizeof(LevelT<R>) * kMaxLevels, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpyAsync(*dS, S.L, sizeof(LevelT<R>) * kMaxLevels, hipMemcpyHostToDevice, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
     return 0;
 }
 
@@ -713,17 +737,22 @@ int freeze_sources(jfnk_problem* p) {
     return 0;
 }
 
+// device bytes create_problem requests (buffer for buffer)
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 13 * nv * 8;  // vectors
-    b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);  // basis
-    b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;  // primitives, fluxes
-    b += (3 * 3 + 1) * N * 8 + N * 8 + 4 * N * 8;                          // pc coefficients, rE, lines
+    size_t b = 13 * nv * 8;                                                       // vectors
+    b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
+    b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
+    for (int d = 0; d < G.ndim; ++d)                                              // frozen wall fluxes
+        if (G.bc[d] == WALL && G.has_chi) b += 2 * (size_t)G.n[(d + 1) % 3] * G.n[(d + 2) % 3] * 8;
+    if (G.heat_balance) b += N * 8;                                               // heat-balance source
+    b += 10 * N * 8 + N * 8 + 4 * N * 8;                                          // pc coefficients, rE, lines
     const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
     for (int l = 0; l < nlev; ++l) b += 2 * level_bytes((long)nl[l][0] * nl[l][1] * nl[l][2], rs);
-    const size_t nred = std::max<size_t>((size_t)grid_blocks((long)N), (size_t)kRedBlocks);
-    b += nred * (kMaxRestart + 2) * 8 + kDsum * 8;
-    if (G.has_chi) b += N * 8;
+    b += 2 * (size_t)nl[nlev - 1][0] * nl[nlev - 1][1] * nl[nlev - 1][2] * rs;  // coarsest second iterate
+    b += 2 * kMaxLevels * (o.prec == JFNK_MIXED ? sizeof(LevelT<float>) : sizeof(LevelT<double>));
+    const size_t npart = (size_t)std::max(cell_blocks(G.n), kRedBlocks) * (kMaxRestart + 2);
+    b += npart * 8 + kDsum * 8;
     return b;
 }
 
@@ -769,12 +798,28 @@ int jfnk_footprint_bytes(const jfnk_problem_desc* desc, const jfnk_solver_opts* 
 
 int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, const double* u0,
                         int on_device, void* hip_stream, jfnk_problem** out) {
+    return jfnk::create_problem_in(desc, opts, u0, on_device, hip_stream, nullptr, 0, nullptr, out);
+}
+}  // extern "C"
+
+namespace jfnk {
+size_t problem_range_bytes(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts) {
+    size_t b = 0;
+    if (jfnk_footprint_bytes(desc, opts, &b) != 0) return 0;
+    return b + kSlabSlack;
+}
+
+int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, const double* u0,
+                      int on_device, void* hip_stream, void* range, size_t range_bytes, void* pinned_host,
+                      jfnk_problem** out) {
     g_err.clear();
     int rc = validate(desc, opts);
     if (rc) return rc;
     if (!u0 || !out) return fail(-1, "null state or output pointer");
     jfnk_problem* p = new (std::nothrow) jfnk_problem();
     if (!p) return fail(-2, "host allocation failed");
+    p->slab = (char*)range;
+    p->slab_size = range ? range_bytes : 0;
     p->desc = *desc;
     p->opts = *opts;
     p->stream = (hipStream_t)hip_stream;
@@ -790,7 +835,9 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     int nl[kMaxLevels][3];
     p->nlev = count_levels(G, nl);
     // the coarse kernel takes the deepest levels whose cells fit in its LDS
-    p->coarse_from = p->nlev - 1;
+    // (none if the coarsest level alone does not: that level is then smoothed
+    // by multi-block sweeps)
+    p->coarse_from = p->nlev;
     {
         long tail = 0;
         for (int l = p->nlev - 1; l >= 0; --l) {
@@ -798,10 +845,6 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
             if (tail > kCoarseLdsCells || (long)nl[l][0] * nl[l][1] * nl[l][2] > kCoarseCells) break;
             p->coarse_from = l;
         }
-    }
-    if ((long)nl[p->nlev - 1][0] * nl[p->nlev - 1][1] * nl[p->nlev - 1][2] > kCoarseLdsCells) {
-        delete p;
-        return fail(-4, "coarsest multigrid level does not fit the coarse solver");
     }
     p->ncell_blk = cell_blocks(G.n);
     p->nred = std::min(kRedBlocks, grid_blocks(G.nvec));
@@ -886,9 +929,13 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
 #undef AL
-    {
+    static_assert(kPinnedBytes == sizeof(double) * kDsum, "read-back area size");
+    if (pinned_host) {
+        p->hpin = (double*)pinned_host;
+    } else {
         hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(double) * kDsum, hipHostMallocDefault);
         if (e != hipSuccess) return cleanup(fail(-2, "hipHostMalloc failed"));
+        p->own_hpin = true;
     }
     if (hipMemsetAsync(p->dsum, 0, sizeof(double) * kDsum, p->stream) != hipSuccess) return cleanup(fail(-3, "memset"));
     if ((rc = copy_in(p, p->u, u0, on_device))) return cleanup(rc);
@@ -897,12 +944,15 @@ int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* o
     *out = p;
     return 0;
 }
+int set_error(int code, const char* msg) { return fail(code, msg ? msg : ""); }
+}  // namespace jfnk
+
+extern "C" {
 
 int jfnk_destroy_problem(jfnk_problem* p) {
     if (!p) return 0;
     (void)hipStreamSynchronize(p->stream);
     p->prof.release();
-    if (p->hpin) (void)hipHostFree(p->hpin);
     delete p;
     return 0;
 }

@@ -46,11 +46,23 @@ class StepStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class RequestStats(C.Structure):
+    _fields_ = [("status", C.c_int), ("steps_done", C.c_int), ("newton_its", C.c_int), ("gmres_its", C.c_int),
+                ("rejections", C.c_int), ("pad", C.c_int), ("cells", C.c_double), ("t_submit_ms", C.c_double),
+                ("t_admit_ms", C.c_double), ("t_done_ms", C.c_double), ("sim_time", C.c_double),
+                ("footprint_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "jfnk_destroy_problem",
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
            "jfnk_eval_time_step", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
-           "jfnk_profile_enable", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_last_error")
+           "jfnk_profile_enable", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
+           "jfnk_server_submit", "jfnk_server_poll", "jfnk_server_wait", "jfnk_server_destroy",
+           "jfnk_last_error")
 
 _lib = None
 
@@ -93,6 +105,11 @@ def load():
         "jfnk_profile_enable": (ip, [vp, C.c_uint]),
         "jfnk_profile_read": (ip, [vp, dp, C.POINTER(C.c_longlong), dp, ip]),
         "jfnk_profile_class_name": (C.c_char_p, [ip]),
+        "jfnk_server_create": (ip, [C.c_size_t, ip, P(vp)]),
+        "jfnk_server_submit": (ip, [vp, P(ProblemDesc), P(SolverOpts), vp, ip, P(C.c_longlong)]),
+        "jfnk_server_poll": (ip, [vp, C.c_longlong]),
+        "jfnk_server_wait": (ip, [vp, C.c_longlong, vp, P(RequestStats), dp, ip, P(ip)]),
+        "jfnk_server_destroy": (ip, [vp]),
         "jfnk_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -346,3 +363,57 @@ def set_state(problem, u):
 
 def destroy_problem(problem):
     problem.close()
+
+
+class Server:
+    """Continuous-batching request loop on one device (jfnk_server_*).
+
+    submit() queues a simulation (host initial state, number of implicit
+    steps) and returns its id at once; the library's worker threads admit
+    waiting requests by device-memory footprint as workers and memory free
+    up.  wait(id) blocks (without the GIL) until the request is finished and
+    returns (final state, request statistics, per-step wall milliseconds)."""
+
+    def __init__(self, hbm_bytes, max_active):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.jfnk_server_create(int(hbm_bytes), int(max_active), C.byref(h)))
+        self._h = h
+        self._nvec = {}
+
+    def submit(self, desc, opts, u0, nsteps):
+        u0 = np.ascontiguousarray(u0, dtype=np.float64)
+        n = desc["n"]
+        nvec = (2 + desc["ndim"]) * n[0] * n[1] * n[2]
+        if u0.size != nvec:
+            raise ValueError("expected %d values, got %d" % (nvec, u0.size))
+        rid = C.c_longlong()
+        _check(_lib.jfnk_server_submit(self._h, C.byref(make_desc(desc)), C.byref(make_opts(opts)),
+                                       u0.ctypes.data, int(nsteps), C.byref(rid)))
+        self._nvec[rid.value] = (nvec, int(nsteps))
+        return rid.value
+
+    def poll(self, rid):
+        return _lib.jfnk_server_poll(self._h, rid)
+
+    def wait(self, rid):
+        nvec, nsteps = self._nvec.pop(rid)
+        u = np.empty(nvec)
+        st = RequestStats()
+        ms = np.empty(max(nsteps, 1))
+        cnt = C.c_int()
+        _check(_lib.jfnk_server_wait(self._h, rid, u.ctypes.data, C.byref(st),
+                                     ms.ctypes.data_as(C.POINTER(C.c_double)), len(ms), C.byref(cnt)))
+        return u, st.as_dict(), ms[:cnt.value].copy()
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.jfnk_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def server_create(hbm_bytes, max_active):
+    return Server(hbm_bytes, max_active)

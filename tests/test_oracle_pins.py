@@ -459,12 +459,16 @@ def _pc_case(kind):
         desc = desc2d(8, 8, gamma=5.0 / 3.0)
     elif kind == "walls":
         desc = desc2d(8, 8, bc=(BC_PERIODIC, BC_WALL), L=(1.0, 2.0))
+    elif kind == "periodic12":  # levels 12x12, 6x6 (3 would be odd across the wrap)
+        desc = desc2d(12, 12, gamma=5.0 / 3.0)
+    elif kind == "walls_odd":  # levels 12x10, 6x5 (odd along the walls)
+        desc = desc2d(12, 10, bc=(BC_PERIODIC, BC_WALL), L=(1.0, 2.0))
     else:
         desc = desc2d(8, 8, bc=(BC_PERIODIC, BC_WALL), chi0=0.4, gamma=5.0 / 3.0)
     return desc
 
 
-@pytest.mark.parametrize("kind", ["periodic", "walls", "diffusion"])
+@pytest.mark.parametrize("kind", ["periodic", "walls", "diffusion", "periodic12", "walls_odd"])
 def test_multigrid_preconditioner_converges_to_block_inverse(kind):
     """With many V-cycles the preconditioner is the exact inverse of the
     acoustic (+ diffusion) block system; with one it already removes most of
