@@ -154,14 +154,18 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
                        int on_device);
 
 /* ---- kernel-class timing ----
- * Record a HIP event pair around every launch of the kernel classes in
- * class_mask (bit c = class c; 0 disables) during later calls on p.  Events
- * are read at the host synchronisation points the solver already has.
- * jfnk_profile_read copies the accumulated milliseconds, launch counts and
- * compulsory bytes (every array a launch reads or writes counted once) of the
- * first nclass classes, resets them, and returns the number of classes.
+ * Time the launches of the kernel classes in class_mask (bit c = class c;
+ * 0 disables) during later calls on p, with a HIP event pair attached to the
+ * kernel dispatch itself (start and end of its execution).  Events are read
+ * at the host synchronisation points the solver already has.
+ * jfnk_profile_sample times one launch in every `period` of each class
+ * (default 1: all), which keeps the host cost of timing small.
+ * jfnk_profile_read copies the accumulated milliseconds, timed-launch counts
+ * and compulsory bytes (every array a launch reads or writes counted once) of
+ * the first nclass classes, resets them, and returns the number of classes.
  * jfnk_profile_class_name names class c ("residual_out", "cgs2_update_dot", ...). */
 int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask);
+int jfnk_profile_sample(jfnk_problem* p, int period);
 int jfnk_profile_read(jfnk_problem* p, double* ms, long long* count, double* bytes, int nclass);
 const char* jfnk_profile_class_name(int cls);
 

@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstddef>
 #include <cstdint>
@@ -57,15 +58,40 @@ inline int cell_blocks(const int n[3]) {
     const dim3 g = cell_grid3(n);
     return (int)(g.x * g.y * g.z);
 }
+// XCD-aware tile order.  The device hands the workgroups of a launch to its
+// 8 XCDs round-robin by flattened id, and each XCD has its own L2.  The
+// logical tile of a workgroup is chosen so that XCD x walks one contiguous
+// range of tiles (a slab of whole rows and planes): the halo rows and planes
+// a stencil reads are mostly tiles of the same XCD, found in its L2.
+constexpr unsigned kXcds = 8;
+struct Tile {
+    unsigned x, y, z, id;
+};
+__device__ __forceinline__ Tile xcd_tile() {
+    const unsigned gx = gridDim.x, gy = gridDim.y;
+    const unsigned total = gx * gy * gridDim.z;
+    const unsigned hw = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const unsigned q = total / kXcds, r = total % kXcds;
+    const unsigned xcd = hw % kXcds, slot = hw / kXcds;
+    Tile t;
+    t.id = xcd * q + (xcd < r ? xcd : r) + slot;
+    t.x = t.id % gx;
+    const unsigned rest = t.id / gx;
+    t.y = rest % gy;
+    t.z = rest / gy;
+    return t;
+}
 __device__ __forceinline__ bool cell_from_launch(const Grid& G, Ijk& q, long& c) {
-    q.v[0] = (int)(blockIdx.x * kBx + threadIdx.x);
-    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
-    q.v[2] = (int)blockIdx.z;
+    const Tile t = xcd_tile();
+    q.v[0] = (int)(t.x * kBx + threadIdx.x);
+    q.v[1] = (int)(t.y * kBy + threadIdx.y);
+    q.v[2] = (int)t.z;
     if (q.v[0] >= G.n[0] || q.v[1] >= G.n[1]) return false;
     c = flat(G, q.v[0], q.v[1], q.v[2]);
     return true;
 }
-__device__ __forceinline__ int lin_block() { return (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)); }
+// index of a workgroup's partial result (its logical tile)
+__device__ __forceinline__ int lin_block() { return (int)xcd_tile().id; }
 __device__ __forceinline__ int lin_thread() { return (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z)); }
 
 // Flat index of the cell shifted by s along axis d, with periodic wrap.
@@ -138,13 +164,13 @@ __device__ __forceinline__ double block_max(double v, double* sh) {
 // every loop over axes unrolls and all axis indices are compile-time
 #define JFNK_LAUNCH_ND(ndim, kern, ...)                                   \
     do {                                                                  \
-        if ((ndim) == 3) hipLaunchKernelGGL((kern<3>), __VA_ARGS__);     \
-        else hipLaunchKernelGGL((kern<2>), __VA_ARGS__);                  \
+        if ((ndim) == 3) JFNK_KLAUNCH((kern<3>), __VA_ARGS__);           \
+        else JFNK_KLAUNCH((kern<2>), __VA_ARGS__);                        \
     } while (0)
 #define JFNK_LAUNCH_RND(ndim, kern, R, ...)                               \
     do {                                                                  \
-        if ((ndim) == 3) hipLaunchKernelGGL((kern<R, 3>), __VA_ARGS__);  \
-        else hipLaunchKernelGGL((kern<R, 2>), __VA_ARGS__);               \
+        if ((ndim) == 3) JFNK_KLAUNCH((kern<R, 3>), __VA_ARGS__);        \
+        else JFNK_KLAUNCH((kern<R, 2>), __VA_ARGS__);                     \
     } while (0)
 
 inline int grid_blocks(long n, int block = kBlock) {
@@ -168,6 +194,8 @@ enum KClass : int {
 };
 struct Profiler {
     unsigned mask = 0;
+    unsigned period = 1;             // time one launch in every period of a class
+    long long seen[KC_COUNT] = {};   // launches of each selected class so far
     std::vector<hipEvent_t> pool;
     std::vector<int> cls;  // class of each recorded pair
     size_t used = 0;       // events in use (2 per pair)
@@ -175,25 +203,41 @@ struct Profiler {
     long long count[KC_COUNT] = {};
     double bytes[KC_COUNT] = {};  // compulsory bytes of the timed launches
     std::vector<double> pend;     // bytes of each recorded pair
-    int begin(int c, hipStream_t s, double b);
-    void end(int c, hipStream_t s, int token);
+    // arm an event pair for the next launch of class c (b: its bytes)
+    void begin(int c, double b);
+    void withdraw();  // drop the most recent pair
     void drain();  // caller has synchronised the stream
     void release();
 };
 extern thread_local Profiler* g_prof;
+// Event pair armed for the next kernel launch on this thread: the launch
+// macros attach it to the dispatch itself (hipExtLaunchKernelGGL), so it
+// brackets exactly the kernel's execution.
+extern thread_local hipEvent_t g_ev_start, g_ev_stop;
 
 struct ProfScope {
-    int c, token;
-    hipStream_t s;
-    ProfScope(int cls_, hipStream_t st, double b = 0.0) : c(cls_), token(-1), s(st) {
-        if (g_prof && (g_prof->mask >> cls_ & 1u)) token = g_prof->begin(cls_, st, b);
+    bool armed = false;
+    explicit ProfScope(int c, double b = 0.0) {
+        if (g_prof && (g_prof->mask >> c & 1u) && (g_prof->seen[c]++ % g_prof->period) == 0) {
+            g_prof->begin(c, b);
+            armed = g_ev_start != nullptr;
+        }
     }
     ~ProfScope() {
-        if (token >= 0 && g_prof) g_prof->end(c, s, token);
+        // a pair no launch consumed is withdrawn (its events were never recorded)
+        if (armed && g_ev_start && g_prof) g_prof->withdraw();
+        g_ev_start = g_ev_stop = nullptr;
     }
 };
 }  // namespace jfnk
 #define JFNK_CAT2(a, b) a##b
 #define JFNK_CAT(a, b) JFNK_CAT2(a, b)
-#define JFNK_PROF(cls, stream) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (stream))
-#define JFNK_PROFB(cls, stream, b) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (stream), (double)(b))
+#define JFNK_PROF(cls, stream) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls))
+#define JFNK_PROFB(cls, stream, b) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (double)(b))
+// kernel launch carrying the armed event pair, if any (then disarmed)
+#define JFNK_KLAUNCH(kern, grid, block, shm, stream, ...)                                          \
+    do {                                                                                          \
+        hipEvent_t jfnk_es_ = ::jfnk::g_ev_start, jfnk_ee_ = ::jfnk::g_ev_stop;                   \
+        ::jfnk::g_ev_start = ::jfnk::g_ev_stop = nullptr;                                         \
+        hipExtLaunchKernelGGL(kern, grid, block, shm, stream, jfnk_es_, jfnk_ee_, 0u, __VA_ARGS__); \
+    } while (0)

@@ -32,11 +32,11 @@ __global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__
 
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);
-    hipLaunchKernelGGL(k_final_sum, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
+    JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
 }
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);
-    hipLaunchKernelGGL(k_final_max, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
+    JFNK_KLAUNCH(k_final_max, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
 }
 
 // ---------------------------------------------------------------- sum of (x/S)^2 over a state-shaped vector
@@ -59,7 +59,7 @@ void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale
     for (int f = 0; f < 5; ++f) inv.v[f] = inv_scale5 ? inv_scale5[f] : 1.0;
     {
         JFNK_PROF(KC_REDUCE, stream);
-        hipLaunchKernelGGL(k_scaled_sumsq, dim3(nblk), dim3(kBlock), 0, stream, x, G.N, 2 + G.ndim, inv, part);
+        JFNK_KLAUNCH(k_scaled_sumsq, dim3(nblk), dim3(kBlock), 0, stream, x, G.N, 2 + G.ndim, inv, part);
     }
 }
 
@@ -192,7 +192,7 @@ int launch_mdot(const T* V, long ld, int k, const double* w, long n, double* par
     case K: {                                                                                          \
         static std::atomic<int> nb{0};                                                                 \
         nblk = std::min(cached_blocks(nb, k_mdot<T, K>), grid_blocks(n));                              \
-        hipLaunchKernelGGL((k_mdot<T, K>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, w, n, part); \
+        JFNK_KLAUNCH((k_mdot<T, K>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, w, n, part); \
         break;                                                                                         \
     }
         JFNK_K_CASES(C)
@@ -214,10 +214,10 @@ int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, l
         static std::atomic<int> nbd{0}, nbn{0};                                                                   \
         if (want_dots) {                                                                                          \
             nblk = std::min(cached_blocks(nbd, k_update<T, K, true>), grid_blocks(n));                            \
-            hipLaunchKernelGGL((k_update<T, K, true>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
+            JFNK_KLAUNCH((k_update<T, K, true>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
         } else {                                                                                                  \
             nblk = std::min(cached_blocks(nbn, k_update<T, K, false>), grid_blocks(n));                           \
-            hipLaunchKernelGGL((k_update<T, K, false>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
+            JFNK_KLAUNCH((k_update<T, K, false>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, h, w, n, part); \
         }                                                                                                         \
         break;                                                                                                    \
     }
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_store_scaled(const double* __restric
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream) {
     JFNK_PROFB(KC_STORE, stream, (double)n * (8 + sizeof(T)));
-    hipLaunchKernelGGL((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
+    JFNK_KLAUNCH((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
 }
 
 template <typename T>
@@ -250,7 +250,7 @@ void launch_combine(const T* V, long ld, int k, const double* y, double* t, long
     switch (k) {
 #define C(K)                                                                                        \
     case K:                                                                                         \
-        hipLaunchKernelGGL((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n); \
+        JFNK_KLAUNCH((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n); \
         break;
         JFNK_K_CASES(C)
 #undef C
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) k_add(double* __restrict__ x, const do
 void launch_add(double* x, const double* z, long n, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_add, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, x, z, n);
+        JFNK_KLAUNCH(k_add, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, x, z, n);
     }
 }
 
@@ -281,7 +281,7 @@ void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* 
     for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_neg_scaled, dim3(grid_blocks(G.nvec, kBlock * 4)), dim3(kBlock), 0, stream, F, r, G.N,
+        JFNK_KLAUNCH(k_neg_scaled, dim3(grid_blocks(G.nvec, kBlock * 4)), dim3(kBlock), 0, stream, F, r, G.N,
                            G.nvec, s);
     }
 }
@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a, co
 void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_sub, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, a, b, r, n);
+        JFNK_KLAUNCH(k_sub, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, a, b, r, n);
     }
 }
 
@@ -305,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) k_copy(double* __restrict__ d, const d
 void launch_copy(double* dst, const double* src, long n, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_copy, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, dst, src, n);
+        JFNK_KLAUNCH(k_copy, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, dst, src, n);
     }
 }
 
@@ -329,7 +329,7 @@ void launch_update_state(double* u, const double* x, const Grid& G, const double
     for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_update_state, dim3(nblk), dim3(kBlock), 0, stream, u, x, G.N, G.nvec, s, part);
+        JFNK_KLAUNCH(k_update_state, dim3(nblk), dim3(kBlock), 0, stream, u, x, G.N, G.nvec, s, part);
     }
 }
 
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kBlock) k_sum(const double* __restrict__ x, lo
 void launch_sum(const double* x, long n, double* part, int nblk, hipStream_t stream) {
     {
         JFNK_PROF(KC_REDUCE, stream);
-        hipLaunchKernelGGL(k_sum, dim3(nblk), dim3(kBlock), 0, stream, x, n, part);
+        JFNK_KLAUNCH(k_sum, dim3(nblk), dim3(kBlock), 0, stream, x, n, part);
     }
 }
 
@@ -375,7 +375,7 @@ template <typename T>
 void launch_widen(const T* v, double* out, long n, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL((k_widen<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, v, out, n);
+        JFNK_KLAUNCH((k_widen<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, v, out, n);
     }
 }
 

@@ -79,9 +79,10 @@ __device__ __forceinline__ int lnb(const Grid& G, const LevelT<R>& L, LIjk q, in
 // cell of a 3D launch over a level
 template <typename R>
 __device__ __forceinline__ bool lcell(const LevelT<R>& L, LIjk& q, int& c) {
-    q.v[0] = (int)(blockIdx.x * kBx + threadIdx.x);
-    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
-    q.v[2] = (int)blockIdx.z;
+    const Tile tl = xcd_tile();
+    q.v[0] = (int)(tl.x * kBx + threadIdx.x);
+    q.v[1] = (int)(tl.y * kBy + threadIdx.y);
+    q.v[2] = (int)tl.z;
     if (q.v[0] >= L.n[0] || q.v[1] >= L.n[1]) return false;
     c = lflat(L, q.v[0], q.v[1], q.v[2]);
     return true;
@@ -89,9 +90,10 @@ __device__ __forceinline__ bool lcell(const LevelT<R>& L, LIjk& q, int& c) {
 // cell of one colour (i + j + k parity) of a launch over half the x extent
 template <typename R>
 __device__ __forceinline__ bool lcell_color(const LevelT<R>& L, int color, LIjk& q, int& c) {
-    const int t = (int)(blockIdx.x * kBx + threadIdx.x);
-    q.v[1] = (int)(blockIdx.y * kBy + threadIdx.y);
-    q.v[2] = (int)blockIdx.z;
+    const Tile tl = xcd_tile();
+    const int t = (int)(tl.x * kBx + threadIdx.x);
+    q.v[1] = (int)(tl.y * kBy + threadIdx.y);
+    q.v[2] = (int)tl.z;
     q.v[0] = 2 * t + ((q.v[1] + q.v[2] + color) & 1);
     if (q.v[0] >= L.n[0] || q.v[1] >= L.n[1]) return false;
     c = lflat(L, q.v[0], q.v[1], q.v[2]);
@@ -646,20 +648,20 @@ template <typename R>
 void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
-        hipLaunchKernelGGL((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
+        JFNK_KLAUNCH((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
     }
 }
 void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        hipLaunchKernelGGL(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
+        JFNK_KLAUNCH(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
     }
 }
 void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
                    hipStream_t stream) {
     {
         JFNK_PROF(KC_REDUCE, stream);
-        hipLaunchKernelGGL(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
+        JFNK_KLAUNCH(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
     }
 }
 
@@ -764,7 +766,7 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     const long nl = (long)G.n[r1] * G.n[r2];
     {
         JFNK_PROF(KC_LINES, stream);
-        hipLaunchKernelGGL((k_line<R>), dim3(grid_blocks(nl)), dim3(kBlock), 0, stream, G, C, d, kind, x, scratch4,
+        JFNK_KLAUNCH((k_line<R>), dim3(grid_blocks(nl)), dim3(kBlock), 0, stream, G, C, d, kind, x, scratch4,
                            scratch4 + G.N, scratch4 + 2 * G.N, scratch4 + 3 * G.N);
     }
 }

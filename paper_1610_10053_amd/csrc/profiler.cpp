@@ -1,30 +1,35 @@
-// Kernel-class timing with HIP events (see jfnk_internal.hpp).
+// Kernel-class timing with HIP events attached to the dispatches of sampled
+// launches (see jfnk_internal.hpp).  A pair that no launch consumed is
+// withdrawn when its scope ends.
 #include "jfnk_internal.hpp"
 
 namespace jfnk {
 
 thread_local Profiler* g_prof = nullptr;
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
 
-int Profiler::begin(int c, hipStream_t s, double b) {
+void Profiler::begin(int c, double b) {
     if (used + 2 > pool.size()) {
         const size_t grow = pool.size() < 256 ? 256 : pool.size();
         for (size_t i = 0; i < grow; ++i) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return -1;
+            if (hipEventCreate(&e) != hipSuccess) return;
             pool.push_back(e);
         }
     }
-    const int token = (int)used;
+    const size_t token = used;
     used += 2;
     cls.push_back(c);
     pend.push_back(b);
-    (void)hipEventRecord(pool[token], s);
-    return token;
+    g_ev_start = pool[token];
+    g_ev_stop = pool[token + 1];
 }
 
-void Profiler::end(int c, hipStream_t s, int token) {
-    (void)c;
-    (void)hipEventRecord(pool[token + 1], s);
+void Profiler::withdraw() {
+    if (cls.empty()) return;
+    cls.pop_back();
+    pend.pop_back();
+    used -= 2;
 }
 
 void Profiler::drain() {

@@ -724,13 +724,13 @@ int freeze_sources(jfnk_problem* p) {
         const long nt = (long)G.n[r1] * G.n[r2];
         {
             JFNK_PROF(KC_OTHER, p->stream);
-            hipLaunchKernelGGL(k_wall_flux, dim3(grid_blocks(nt)), dim3(kBlock), 0, p->stream, G, p->P, d,
+            JFNK_KLAUNCH(k_wall_flux, dim3(grid_blocks(nt)), dim3(kBlock), 0, p->stream, G, p->P, d,
                                (double*)p->W.lo[d], (double*)p->W.hi[d]);
         }
     }
     {
         JFNK_PROF(KC_OTHER, p->stream);
-        if (p->sbal) hipLaunchKernelGGL(k_sbal, cell_grid3(G.n), dim3(kBx, kBy), 0, p->stream, G, p->P, p->W, p->sbal);
+        if (p->sbal) JFNK_KLAUNCH(k_sbal, cell_grid3(G.n), dim3(kBx, kBy), 0, p->stream, G, p->P, p->W, p->sbal);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(p->stream));
@@ -1153,7 +1153,15 @@ int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask) {
         p->prof.ms[c] = 0.0;
         p->prof.count[c] = 0;
         p->prof.bytes[c] = 0.0;
+        p->prof.seen[c] = 0;
     }
+    return 0;
+}
+
+int jfnk_profile_sample(jfnk_problem* p, int period) {
+    if (!p) return fail(-1, "null problem");
+    if (period < 1) return fail(-1, "sampling period must be >= 1");
+    p->prof.period = (unsigned)period;
     return 0;
 }
 

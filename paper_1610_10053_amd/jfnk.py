@@ -60,7 +60,7 @@ EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
            "jfnk_eval_time_step", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
-           "jfnk_profile_enable", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
+           "jfnk_profile_enable", "jfnk_profile_sample", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
            "jfnk_server_submit", "jfnk_server_poll", "jfnk_server_wait", "jfnk_server_destroy",
            "jfnk_last_error")
 
@@ -103,6 +103,7 @@ def load():
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_profile_enable": (ip, [vp, C.c_uint]),
+        "jfnk_profile_sample": (ip, [vp, ip]),
         "jfnk_profile_read": (ip, [vp, dp, C.POINTER(C.c_longlong), dp, ip]),
         "jfnk_profile_class_name": (C.c_char_p, [ip]),
         "jfnk_server_create": (ip, [C.c_size_t, ip, P(vp)]),
@@ -302,6 +303,10 @@ class Problem:
         for c in classes:
             mask |= 1 << (names.index(c) if isinstance(c, str) else int(c))
         _check(_lib.jfnk_profile_enable(self._h, mask))
+
+    def profile_sample(self, period):
+        """time one launch in every `period` of each enabled class"""
+        _check(_lib.jfnk_profile_sample(self._h, int(period)))
 
     def profile_read(self):
         """{class name: (milliseconds, launches, compulsory bytes)} since enable / last read."""
