@@ -111,7 +111,8 @@ struct LevelT {
     R* D;     // sig + sum of the cell's couplings
     R* x;
     R* b;
-    R* x2;  // second iterate buffer (coarsest level only, else null)
+    R* x2;         // second iterate buffer (coarsest level only, else null)
+    int unit_sig;  // sig == 1 on every cell (acoustic operator): D is formed from the couplings
 };
 template <typename R>
 struct LevelSet {

@@ -184,12 +184,16 @@ template <typename R, int ND>
 __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c,
                                       bool first) {
     R num = b[c];
+    R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
-        if (dn >= 0) num = num + L.a[d][c] * (first ? (R)0.0 : x[dn]);
-        if (up >= 0) num = num + L.a[d][up] * (first ? (R)0.0 : x[up]);
+        const R alo = L.a[d][c], ahi = up >= 0 ? L.a[d][up] : (R)0.0;
+        if (dn >= 0) num = num + alo * (first ? (R)0.0 : x[dn]);
+        if (up >= 0) num = num + ahi * (first ? (R)0.0 : x[up]);
+        den = den + alo;
+        den = den + ahi;
     }
-    return num / L.D[c];
+    return num / (L.unit_sig ? den : L.D[c]);
 }
 // in-place red-black update of one cell: valid while no two cells of one
 // colour are neighbours, i.e. every periodic axis of the level has even length
@@ -213,7 +217,7 @@ template <typename R, int ND>
 __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
                                         int c) {
     const R xc = x[c];
-    R acc = L.sig[c] * xc;
+    R acc = L.unit_sig ? xc : L.sig[c] * xc;
     for (int d = 0; d < ND; ++d) {
         const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
         if (dn >= 0) acc = acc + L.a[d][c] * (xc - x[dn]);
@@ -289,12 +293,48 @@ __global__ void __launch_bounds__(kBlock) k_gs_pp(Grid G, LevelT<R> L, int color
     }
     xout[c] = gs_value<R, ND>(G, L, L.b, xin, q, c, first != 0);
 }
+// Restriction of a multi-block level: one thread per fine cell computes its
+// residual, and the 2^ND children of each coarse cell (all in one workgroup)
+// are summed in LDS in the order of restrict_cell.  Workgroups are
+// kRx x kRy x kRz fine cells (kRz = 2 in 3D, 1 in 2D).
+constexpr int kRx = 32, kRy = 4;
+template <int ND>
+inline dim3 restrict_block() { return ND > 2 ? dim3(kRx, kRy, 2) : dim3(2 * kRx, kRy, 1); }
+template <int ND>
+inline dim3 restrict_grid(const int n[3]) {
+    const dim3 b = restrict_block<ND>();
+    return dim3((n[0] + b.x - 1) / b.x, (n[1] + b.y - 1) / b.y, ND > 2 ? (n[2] + 1) / 2 : n[2]);
+}
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    constexpr int BX = ND > 2 ? kRx : 2 * kRx, BZ = ND > 2 ? 2 : 1;
+    __shared__ R rs[BZ][kRy][BX];
+    const Tile t = xcd_tile();
+    LIjk f;
+    f.v[0] = (int)(t.x * BX + threadIdx.x);
+    f.v[1] = (int)(t.y * kRy + threadIdx.y);
+    f.v[2] = (int)(t.z * BZ + threadIdx.z);
+    R r = (R)0.0;
+    if (f.v[0] < F.n[0] && f.v[1] < F.n[1] && f.v[2] < F.n[2])
+        r = resid_cell<R, ND>(G, F, F.b, F.x, f, lflat(F, f.v[0], f.v[1], f.v[2]));
+    rs[threadIdx.z][threadIdx.y][threadIdx.x] = r;
+    __syncthreads();
+    // coarse cells of the tile: (BX/2) x (kRy/2) x 1
+    const int lt = (int)(threadIdx.x + BX * (threadIdx.y + kRy * threadIdx.z));
+    constexpr int CX = BX / 2, CY = kRy / 2;
+    if (lt >= CX * CY) return;
+    const int ci = lt % CX, cj = lt / CX;
     LIjk q;
-    int c;
-    if (!lcell(Cl, q, c)) return;
-    Cl.b[c] = restrict_cell<R, ND>(G, F, F.b, F.x, q);
+    q.v[0] = (int)(t.x * CX) + ci;
+    q.v[1] = (int)(t.y * CY) + cj;
+    q.v[2] = (int)t.z;
+    if (q.v[0] >= Cl.n[0] || q.v[1] >= Cl.n[1] || q.v[2] >= Cl.n[2]) return;
+    const R inv_ch = (R)(1.0 / (1 << ND));
+    R s = 0.0;
+    for (int dk = 0; dk < BZ; ++dk)
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) s = s + rs[dk][2 * cj + dj][2 * ci + di];
+    Cl.b[lflat(Cl, q.v[0], q.v[1], q.v[2])] = s * inv_ch;
 }
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
@@ -452,7 +492,10 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     }
     {
         JFNK_PROFB(KC_MG_RESTRICT, stream, (double)L.N * sizeof(R) * (3 + G.ndim) + (double)S.L[l + 1].N * sizeof(R));
-        JFNK_LAUNCH_RND(G.ndim, k_restrict, R, cell_grid3(S.L[l + 1].n), bl, 0, stream, G, L, S.L[l + 1]);
+        if (G.ndim == 3)
+            JFNK_KLAUNCH((k_restrict<R, 3>), restrict_grid<3>(L.n), restrict_block<3>(), 0, stream, G, L, S.L[l + 1]);
+        else
+            JFNK_KLAUNCH((k_restrict<R, 2>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
     }
     vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
     {

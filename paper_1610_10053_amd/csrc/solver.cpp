@@ -198,9 +198,10 @@ constexpr long kCoarseCells = 512;  // levels at or below this size run in one w
 size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
 
 template <typename R>
-int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3]) {
+int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3], bool unit_sig) {
     for (int l = 0; l < p->nlev; ++l) {
         LevelT<R>& L = S.L[l];
+        L.unit_sig = unit_sig ? 1 : 0;
         for (int a = 0; a < 3; ++a) L.n[a] = nl[l][a];
         L.N = (long)L.n[0] * L.n[1] * L.n[2];
         const bool coarsest = l == p->nlev - 1;
@@ -920,11 +921,11 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     AL(p->rEd, N);
     AL(p->lines, (size_t)4 * N);
     if (opts->prec == JFNK_MIXED) {
-        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl))) return cleanup(rc);
-        if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl, true))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl, false))) return cleanup(rc);
     } else {
-        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl))) return cleanup(rc);
-        if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, true))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl, false))) return cleanup(rc);
     }
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
