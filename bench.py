@@ -164,6 +164,41 @@ def serving(jfnk, args):
             "saturated": sat, "poisson_0.8x": poi}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tg128_fp64_hbm_traffic.md")
+
+
+def kernel_sources_sha():
+    """sha256 over the HIP kernel sources (csrc/*.hip, *.hpp, sorted by name)"""
+    import glob
+    import hashlib
+    d = os.path.join(ROOT, "paper_1610_10053_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(d, "*.hip")) + glob.glob(os.path.join(d, "*.hpp"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None when it is absent or was taken on other kernel sources"""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    sha = None
+    per = {}
+    for line in text.splitlines():
+        if line.startswith("sources_sha256="):
+            sha = line.split("=", 1)[1].strip()
+        elif line.startswith("traffic class="):
+            kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+            per[kv.get("class")] = float(kv["bytes_per_launch"])
+    if sha != kernel_sources_sha():
+        return None
+    return per.get(cls)
+
+
 def cpu_baseline(n, steps):
     from oracle import Oracle
     from workloads import make_config
@@ -253,7 +288,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": s0["dominant"], "achieved": s0["dominant_gbs"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": (s0["dominant_gbs"] / PEAK_HBM_GBS) if s0["dominant_gbs"] else None,
-                     "avg_launch_us": s0["dominant_avg_us"], "traffic": None},
+                     "avg_launch_us": s0["dominant_avg_us"], "traffic": measured_traffic(s0["dominant"]),
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"},
         "kernels": s0["kernels"],
     }
     for f in forms[1:]:
