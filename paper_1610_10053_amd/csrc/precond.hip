@@ -205,10 +205,11 @@ __device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const
 // a periodic axis of odd length (possible on the coarsest level only): the
 // two cells facing each other across the wrap share a colour, so a colour's
 // cells are updated together from the values before their half-sweep
-template <typename R>
+template <typename R, int ND>
 __device__ __forceinline__ bool odd_periodic(const Grid& G, const LevelT<R>& L) {
     bool odd = false;
-    for (int d = 0; d < G.ndim; ++d) odd = odd || (G.bc[d] == PERIODIC && (L.n[d] & 1));
+#pragma unroll
+    for (int d = 0; d < ND; ++d) odd = odd || (G.bc[d] == PERIODIC && (L.n[d] & 1));
     return odd;
 }
 
@@ -348,10 +349,11 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
 // in all), in one workgroup with every array of those levels in LDS.  Level
 // descriptors come from device memory (Ld) so that the level loop may index
 // them at run time.
-constexpr int kCoarseThreads = 256;
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseMaxLevelCells = 512;  // largest level the single-workgroup solve takes
 template <typename R, int ND>
-__device__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first, R* tmp) {
-    const bool together = odd_periodic(G, L);
+__device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first, R* tmp) {
+    const bool together = odd_periodic<R, ND>(G, L);
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             const bool f = first && s == 0 && color == 0;
@@ -375,38 +377,39 @@ __device__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool f
             __syncthreads();
         }
 }
+// LDS view of level l: its arrays at sm + base (sig, a[0..ND-1], D, x, b),
+// built in registers so that every access is a direct LDS access
+template <typename R, int ND>
+__device__ __forceinline__ LevelT<R> lds_level(const LevelT<R>& g, R* sm, int base) {
+    LevelT<R> L = g;
+    const int n = (int)g.N;
+    L.sig = sm + base;
+    for (int d = 0; d < 3; ++d) L.a[d] = d < ND ? sm + base + (1 + d) * n : nullptr;
+    L.D = sm + base + (1 + ND) * n;
+    L.x = sm + base + (2 + ND) * n;
+    L.b = sm + base + (3 + ND) * n;
+    return L;
+}
 template <typename R, int ND>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const LevelT<R>* __restrict__ Ld,
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
                                                                    int first_top) {
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
     __shared__ R tmp[kCoarseLdsCells];
-    __shared__ LevelT<R> Ls[kMaxLevels];
+    __shared__ R rbuf[kCoarseMaxLevelCells];  // residuals of the level being restricted
+    __shared__ int base[kMaxLevels];
     if (threadIdx.x == 0) {
         int off = 0;
         for (int l = from; l < nlev; ++l) {
-            LevelT<R> L = Ld[l];
-            const int n = (int)L.N;
-            L.sig = sm + off;
-            off += n;
-            for (int d = 0; d < ND; ++d) {
-                L.a[d] = sm + off;
-                off += n;
-            }
-            L.D = sm + off;
-            off += n;
-            L.x = sm + off;
-            off += n;
-            L.b = sm + off;
-            off += n;
-            Ls[l] = L;
+            base[l] = off;
+            off += (4 + ND) * (int)Ld[l].N;
         }
     }
     __syncthreads();
     const bool top_first = first_top != 0;
     for (int l = from; l < nlev; ++l) {
         const LevelT<R> gL = Ld[l];
-        const LevelT<R>& L = Ls[l];
+        const LevelT<R> L = lds_level<R, ND>(gL, sm, base[l]);
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
             L.sig[c] = gL.sig[c];
             for (int d = 0; d < ND; ++d) L.a[d][c] = gL.a[d][c];
@@ -420,20 +423,39 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     __syncthreads();
     for (int l = from; l < nlev - 1; ++l) {
         const bool first = l == from ? top_first : true;
-        lds_smooth<R, ND>(G, Ls[l], nu1, first, tmp);
-        for (int c = threadIdx.x; c < Ls[l + 1].N; c += blockDim.x)
-            Ls[l + 1].b[c] = restrict_cell<R, ND>(G, Ls[l], Ls[l].b, Ls[l].x, lcoords(Ls[l + 1], c));
+        const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
+        const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
+        lds_smooth<R, ND>(G, L, nu1, first, tmp);
+        // restriction: every fine residual once, then the children's sums in
+        // the order of restrict_cell
+        for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell<R, ND>(G, L, L.b, L.x, lcoords(L, c), c);
+        __syncthreads();
+        for (int c = threadIdx.x; c < C.N; c += blockDim.x) {
+            const LIjk q = lcoords(C, c);
+            const int kk = ND > 2 ? 2 : 1;
+            R sum = 0.0;
+            for (int dk = 0; dk < kk; ++dk)
+                for (int dj = 0; dj < 2; ++dj)
+                    for (int di = 0; di < 2; ++di)
+                        sum = sum + rbuf[lflat(L, 2 * q.v[0] + di, 2 * q.v[1] + dj, ND > 2 ? 2 * q.v[2] + dk : q.v[2])];
+            C.b[c] = sum * (R)(1.0 / (1 << ND));
+        }
         __syncthreads();
     }
-    lds_smooth<R, ND>(G, Ls[nlev - 1], nuc, nlev - 1 == from ? top_first : true, tmp);
+    {
+        const LevelT<R> L = lds_level<R, ND>(Ld[nlev - 1], sm, base[nlev - 1]);
+        lds_smooth<R, ND>(G, L, nuc, nlev - 1 == from ? top_first : true, tmp);
+    }
     for (int l = nlev - 2; l >= from; --l) {
-        for (int c = threadIdx.x; c < Ls[l].N; c += blockDim.x)
-            Ls[l].x[c] = Ls[l].x[c] + prolong_cell<R, ND>(G, Ls[l + 1], Ls[l + 1].x, lcoords(Ls[l], c));
+        const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
+        const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
+        for (int c = threadIdx.x; c < L.N; c += blockDim.x) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
-        lds_smooth<R, ND>(G, Ls[l], nu2, false, tmp);
+        lds_smooth<R, ND>(G, L, nu2, false, tmp);
     }
     const LevelT<R> gT = Ld[from];
-    for (int c = threadIdx.x; c < Ls[from].N; c += blockDim.x) gT.x[c] = Ls[from].x[c];
+    const LevelT<R> T = lds_level<R, ND>(gT, sm, base[from]);
+    for (int c = threadIdx.x; c < T.N; c += blockDim.x) gT.x[c] = T.x[c];
 }
 
 template <typename R>

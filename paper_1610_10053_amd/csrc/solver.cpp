@@ -194,6 +194,7 @@ int count_levels(const Grid& G, int n_out[][3]) {
 }
 
 constexpr long kCoarseCells = 512;  // levels at or below this size run in one workgroup from LDS
+                                     // (kCoarseMaxLevelCells of the coarse kernel)
 
 size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
 
