@@ -4,8 +4,8 @@
 // One device arena is allocated at creation and carved into per-request
 // ranges by a first-fit allocator with coalescing.  Worker threads, each
 // owning a non-blocking HIP stream and a pinned read-back area, take the
-// oldest waiting request whose range fits; a request that is passed over
-// repeatedly reserves the next free range for itself, so large requests are
+// oldest waiting request whose range fits; once a request has been passed
+// over 4 times per worker nothing passes it any more, so large requests are
 // not starved by a stream of small ones.  An admitted request creates its
 // problem inside its range (state, Krylov basis and preconditioner resident
 // for the request's life), runs its implicit steps on the worker's stream and
@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/jfnk.h"
+#include "admission.hpp"
 #include "problem.hpp"
 
 namespace {
@@ -35,44 +36,6 @@ constexpr size_t kRangeAlign = 4096;
 constexpr int kMaxActive = 64;
 // a waiting request passed over this many times (per worker) blocks later arrivals
 constexpr int kMaxSkipsPerWorker = 4;
-
-// first-fit allocator over [0, size) with coalescing of freed ranges
-class RangeAllocator {
-  public:
-    void init(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-    }
-    bool alloc(size_t bytes, size_t* off) {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            *off = it->first;
-            const size_t rest = it->second - bytes, start = it->first + bytes;
-            free_.erase(it);
-            if (rest) free_[start] = rest;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-
-  private:
-    std::map<size_t, size_t> free_;
-};
 
 enum { REQ_WAITING = 0, REQ_RUNNING = 1, REQ_DONE = 2 };
 
@@ -99,7 +62,7 @@ struct jfnk_server {
     int device = 0;
     char* arena = nullptr;
     size_t arena_bytes = 0;
-    RangeAllocator ranges;
+    jfnk::RangeAllocator ranges;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request*> waiting;
@@ -112,18 +75,7 @@ struct jfnk_server {
 
     // called with mu held: choose the request to admit and its range
     bool pick(Request** r, size_t* off) {
-        for (size_t i = 0; i < waiting.size(); ++i) {
-            Request* q = waiting[i];
-            if (ranges.alloc(q->bytes, off)) {
-                for (size_t j = 0; j < i; ++j) waiting[j]->skips++;
-                waiting.erase(waiting.begin() + (long)i);
-                *r = q;
-                return true;
-            }
-            // the oldest request has waited long enough: nothing passes it
-            if (q->skips >= kMaxSkipsPerWorker * nworkers) return false;
-        }
-        return false;
+        return jfnk::pick_request(waiting, ranges, kMaxSkipsPerWorker * nworkers, r, off);
     }
 
     void run(Request* r, void* range, hipStream_t stream, void* pinned) {
