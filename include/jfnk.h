@@ -153,6 +153,27 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
 int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z,
                        int on_device);
 
+/* ---- diagnostics (reductions over a state on the device) ----
+ * kinetic: sum over cells of (1/2) rho |v|^2 dV, |v|^2 of a cell being the
+ *   mean over each axis of the squared velocities of its two faces (the
+ *   kinetic energy of the Taylor-Green study, section 5.3; its rate of change
+ *   is the difference of successive values over dt);
+ * mass, energy: sum of rho dV and of E dV;
+ * max_mach: max over cells of |v| / c_s, c_s^2 = gamma p / rho;
+ * mix_width: mixing-region width of eqs. (12)-(14) along grid axis mix_axis,
+ *   X_H = (rho - rho_light)/(rho_heavy - rho_light), mean per layer normal to
+ *   the axis, X_M = 2 min(<X_H>, 1 - <X_H>), summed over layers times the
+ *   layer thickness; 0 when mix_axis < 0. */
+typedef struct {
+    double kinetic, mass, energy, max_mach, mix_width;
+} jfnk_diagnostics;
+
+/* u: a state in the layout above (host or device per on_device), or NULL for
+ * the problem's current state.  Errors: -1 bad axis or rho_heavy == rho_light
+ * with mix_axis >= 0. */
+int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, double rho_light, double rho_heavy,
+                          int mix_axis, jfnk_diagnostics* out);
+
 /* ---- kernel-class timing ----
  * Time the launches of the kernel classes in class_mask (bit c = class c;
  * 0 disables) during later calls on p, with a HIP event pair attached to the

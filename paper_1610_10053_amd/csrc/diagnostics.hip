@@ -1,0 +1,91 @@
+// Diagnostics of a state (reductions on the device): kinetic energy
+// sum (1/2) rho |v|^2 dV with |v|^2 of a cell the mean over each axis of the
+// squared velocities of its two faces (the Taylor-Green kinetic energy of
+// section 5.3), mass and total energy, the maximum Mach number (section 3.1),
+// and the mixing-region width of eqs. (12)-(14) along a vertical axis.
+#include "kernels.hpp"
+
+namespace jfnk {
+
+// per-block partials: sum kin dV-free, sum rho, sum E, max Mach
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_diag_cells(Grid G, Prim P, const double* __restrict__ u,
+                                                       double* __restrict__ part) {
+    Ijk q;
+    long c = 0;
+    double kin = 0.0, mass = 0.0, en = 0.0, mach = 0.0;
+    if (cell_from_launch(G, q, c)) {
+        double qk = 0.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+            const double a = P.uf[d][c];
+            const double b = top ? 0.0 : P.uf[d][shifted(G, q, d, 1)];
+            qk = qk + 0.5 * (a * a + b * b);
+        }
+        const double rho = P.rho[c];
+        kin = 0.5 * rho * qk;
+        mass = rho;
+        en = u[G.N + c];
+        mach = sqrt(qk) / sqrt(G.gamma * P.p[c] / rho);
+    }
+    __shared__ double sh[kBlock / 64];
+    const long nb = (long)gridDim.x * gridDim.y * gridDim.z;
+    const int b = lin_block();
+    double t = block_sum(kin, sh);
+    if (lin_thread() == 0) part[b] = t;
+    __syncthreads();
+    t = block_sum(mass, sh);
+    if (lin_thread() == 0) part[nb + b] = t;
+    __syncthreads();
+    t = block_sum(en, sh);
+    if (lin_thread() == 0) part[2 * nb + b] = t;
+    __syncthreads();
+    t = block_max(mach, sh);
+    if (lin_thread() == 0) part[3 * nb + b] = t;
+}
+
+// one workgroup per layer normal to `axis`: X_M of the layer's mean X_H
+__global__ void __launch_bounds__(kBlock) k_diag_layers(Grid G, Prim P, int axis, double rho_l, double rho_h,
+                                                        double* __restrict__ xm) {
+    const int j = (int)blockIdx.x;
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    const long n1 = G.n[a1], n2 = G.n[a2], nl = n1 * n2;
+    double s = 0.0;
+    for (long e = threadIdx.x; e < nl; e += blockDim.x) {
+        int v[3];
+        v[axis] = j;
+        v[a1] = (int)(e % n1);
+        v[a2] = (int)(e / n1);
+        const long c = flat(G, v[0], v[1], v[2]);
+        s += (P.rho[c] - rho_l) / (rho_h - rho_l);
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        const double mean = t / (double)nl;
+        xm[j] = mean <= 0.5 ? 2.0 * mean : 2.0 * (1.0 - mean);
+    }
+}
+
+int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,
+                       double* part, double* out5, hipStream_t stream) {
+    const int nb = cell_blocks(G.n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        JFNK_LAUNCH_ND(G.ndim, k_diag_cells, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, u, part);
+    }
+    launch_final_sum(part, nb, 3, out5, stream);
+    launch_final_max(part + 3L * nb, nb, 1, out5 + 3, stream);
+    if (axis >= 0) {
+        double* xm = part + 4L * nb;
+        {
+            JFNK_PROF(KC_OTHER, stream);
+            JFNK_KLAUNCH(k_diag_layers, dim3(G.n[axis]), dim3(kBlock), 0, stream, G, P, axis, rho_l, rho_h, xm);
+        }
+        launch_final_sum(xm, G.n[axis], 1, out5 + 4, stream);
+    }
+    return 0;
+}
+
+}  // namespace jfnk

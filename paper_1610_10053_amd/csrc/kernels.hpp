@@ -66,6 +66,11 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
                      const double* sbal, const OutSpec& o, hipStream_t stream);
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream);
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream);
+// diagnostics of the state whose primitives P hold: out5 = sum kin, sum rho,
+// sum E (per unit volume), max Mach, sum of the layers' X_M along axis (or
+// untouched when axis < 0); part needs 4 cell_blocks + n[axis] doubles
+int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,
+                       double* part, double* out5, hipStream_t stream);
 
 // krylov.hip: deterministic two-stage reductions and Krylov vector kernels
 // partial layout: part[col * nblk + block]

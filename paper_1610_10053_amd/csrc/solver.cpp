@@ -1102,6 +1102,36 @@ int jfnk_eval_time_step(jfnk_problem* p, const double* u, double* out9, int on_d
     return 0;
 }
 
+int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, double rho_light, double rho_heavy,
+                          int mix_axis, jfnk_diagnostics* out) {
+    if (!p || !out) return fail(-1, "null argument");
+    const Grid& G = p->G;
+    if (mix_axis >= G.ndim || mix_axis < -1) return fail(-1, "mix_axis must be -1 or a grid axis");
+    if (mix_axis >= 0 && !(rho_heavy != rho_light)) return fail(-1, "rho_heavy must differ from rho_light");
+    if (mix_axis >= 0 && 4L * p->ncell_blk + G.n[mix_axis] > (long)p->npart)
+        return fail(-4, "too many layers for the reduction buffer");
+    ProfGuard guard(p);
+    const double* src = p->u;
+    if (u) {
+        int rc = copy_in(p, p->s1, u, on_device);
+        if (rc) return rc;
+        src = p->s1;
+    }
+    launch_prim(G, view(p, src, nullptr), p->P, p->stream);
+    launch_diagnostics(G, p->P, src, mix_axis, rho_light, rho_heavy, p->part, p->dsum + D_TMP, p->stream);
+    HIPCHK(hipGetLastError());
+    double m[5] = {0, 0, 0, 0, 0};
+    CK(read_scalars(p, D_TMP, mix_axis >= 0 ? 5 : 4, m));
+    double dv = 1.0;
+    for (int d = 0; d < G.ndim; ++d) dv *= G.dx[d];
+    out->kinetic = m[0] * dv;
+    out->mass = m[1] * dv;
+    out->energy = m[2] * dv;
+    out->max_mach = m[3];
+    out->mix_width = mix_axis >= 0 ? m[4] * G.dx[mix_axis] : 0.0;
+    return 0;
+}
+
 int jfnk_set_scales(jfnk_problem* p, const double* s5) {
     if (!p || !s5) return fail(-1, "null argument");
     for (int f = 0; f < 5; ++f) {

@@ -46,6 +46,14 @@ class StepStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Diagnostics(C.Structure):
+    _fields_ = [("kinetic", C.c_double), ("mass", C.c_double), ("energy", C.c_double), ("max_mach", C.c_double),
+                ("mix_width", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class RequestStats(C.Structure):
     _fields_ = [("status", C.c_int), ("steps_done", C.c_int), ("newton_its", C.c_int), ("gmres_its", C.c_int),
                 ("rejections", C.c_int), ("pad", C.c_int), ("cells", C.c_double), ("t_submit_ms", C.c_double),
@@ -59,7 +67,7 @@ class RequestStats(C.Structure):
 EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "jfnk_destroy_problem",
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
-           "jfnk_eval_time_step", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
+           "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
            "jfnk_profile_enable", "jfnk_profile_sample", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
            "jfnk_server_submit", "jfnk_server_poll", "jfnk_server_wait", "jfnk_server_destroy",
            "jfnk_last_error")
@@ -99,6 +107,7 @@ def load():
         "jfnk_eval_cn_old": (ip, [vp, vp, C.c_double, vp, ip]),
         "jfnk_eval_residual": (ip, [vp, vp, vp, C.c_double, vp, ip]),
         "jfnk_eval_time_step": (ip, [vp, vp, dp, ip]),
+        "jfnk_eval_diagnostics": (ip, [vp, vp, ip, C.c_double, C.c_double, ip, P(Diagnostics)]),
         "jfnk_set_scales": (ip, [vp, dp]),
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
@@ -282,6 +291,19 @@ class Problem:
         pu, d, k1 = _ptr(u)
         _check(_lib.jfnk_eval_time_step(self._h, pu, out.ctypes.data_as(C.POINTER(C.c_double)), d))
         return dict(dt=out[0], hyd=out[1], adv=out[2], rad=out[3], scales=out[4:9].copy())
+
+    def eval_diagnostics(self, u=None, rho_light=0.0, rho_heavy=1.0, mix_axis=-1):
+        """kinetic energy, mass, energy, max Mach and mixing width (dict)"""
+        out = Diagnostics()
+        if u is None:
+            _check(_lib.jfnk_eval_diagnostics(self._h, None, 0, float(rho_light), float(rho_heavy), int(mix_axis),
+                                              C.byref(out)))
+        else:
+            pu, d, k1 = _ptr(u)
+            self._check_size(k1)
+            _check(_lib.jfnk_eval_diagnostics(self._h, pu, d, float(rho_light), float(rho_heavy), int(mix_axis),
+                                              C.byref(out)))
+        return out.as_dict()
 
     def set_scales(self, s):
         s = np.ascontiguousarray(list(s) + [1.0] * (5 - len(s)), dtype=np.float64)
