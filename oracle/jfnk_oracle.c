@@ -1040,6 +1040,7 @@ typedef struct {
 static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, double *x,
                   int m, int max_cycles, double eta, GmresInfo *info) {
     double *V = calloc((size_t)(m + 1) * n, sizeof(double));
+    double *Z = calloc((size_t)m * n, sizeof(double)); /* M^-1 v_j */
     double *H = calloc((size_t)(m + 1) * m, sizeof(double));
     double *cs = calloc(m, sizeof(double)), *sn = calloc(m, sizeof(double));
     double *gv = calloc(m + 1, sizeof(double)), *y = calloc(m, sizeof(double));
@@ -1060,9 +1061,9 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
         gv[0] = beta;
         int kdim = 0, conv = 0;
         for (int j = 0; j < m; ++j) {
-            double *vj = V + (long)j * n, *w = V + (long)(j + 1) * n;
-            Minv(ctx, vj, zt);
-            A(ctx, zt, w);
+            double *vj = V + (long)j * n, *w = V + (long)(j + 1) * n, *zj = Z + (long)j * n;
+            Minv(ctx, vj, zj);
+            A(ctx, zj, w);
             double w0 = norm2(n, w);
             for (int i = 0; i <= j; ++i) h1[i] = dot(n, V + (long)i * n, w);
             for (int i = 0; i <= j; ++i) {
@@ -1103,13 +1104,14 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
             for (int l = i + 1; l < kdim; ++l) s -= H[(long)i * m + l] * y[l];
             y[i] = s / H[(long)i * m + i];
         }
+        /* x += M^-1 V y = sum_i y_i M^-1 v_i (M^-1 is a fixed linear map), from
+         * the preconditioned vectors the Arnoldi process formed */
         for (long q = 0; q < n; ++q) t[q] = 0.0;
         for (int i = 0; i < kdim; ++i) {
-            const double *vi = V + (long)i * n;
-            for (long q = 0; q < n; ++q) t[q] += y[i] * vi[q];
+            const double *zi = Z + (long)i * n;
+            for (long q = 0; q < n; ++q) t[q] += y[i] * zi[q];
         }
-        Minv(ctx, t, zt);
-        for (long q = 0; q < n; ++q) x[q] += zt[q];
+        for (long q = 0; q < n; ++q) x[q] += t[q];
         if (conv) { info->converged = 1; break; }
         /* true residual for the restart */
         A(ctx, x, t);
@@ -1117,7 +1119,7 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
         info->res = norm2(n, r);
     }
 done:
-    free(V); free(H); free(cs); free(sn); free(gv); free(y); free(h1); free(h2);
+    free(V); free(Z); free(H); free(cs); free(sn); free(gv); free(y); free(h1); free(h2);
     free(r); free(zt); free(t);
 }
 

@@ -87,7 +87,7 @@ int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, l
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream);
 template <typename T>
-void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, hipStream_t stream);
+void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, bool acc, hipStream_t stream);
 void launch_add(double* x, const double* z, long n, hipStream_t stream);
 void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* scale5, hipStream_t stream);
 void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t stream);

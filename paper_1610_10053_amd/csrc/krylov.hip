@@ -137,10 +137,10 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* __restrict__ V, long
     block_sum_cols<NC>(acc, part);
 }
 
-// t = sum_i y_i V_i, accumulated in order of i
+// t = sum_i y_i V_i, accumulated in order of i (then added to t when acc)
 template <typename T, int K>
 __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, long ld, const double* __restrict__ y,
-                                                    double* __restrict__ t, long n) {
+                                                    double* __restrict__ t, long n, int acc) {
     double yy[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) yy[i] = y[i];
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, lon
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < K; ++i) s += yy[i] * vv[i];
-        t[e] = s;
+        t[e] = acc ? t[e] + s : s;
     }
 }
 
@@ -244,13 +244,13 @@ void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t s
 }
 
 template <typename T>
-void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, hipStream_t stream) {
+void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, bool acc, hipStream_t stream) {
     const int nb = grid_blocks(n, kBlock * 4);
-    JFNK_PROFB(KC_COMBINE, stream, (double)n * (k * sizeof(T) + 8));
+    JFNK_PROFB(KC_COMBINE, stream, (double)n * (k * sizeof(T) + (acc ? 16 : 8)));
     switch (k) {
 #define C(K)                                                                                        \
     case K:                                                                                         \
-        JFNK_KLAUNCH((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n); \
+        JFNK_KLAUNCH((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n, acc ? 1 : 0); \
         break;
         JFNK_K_CASES(C)
 #undef C
@@ -390,7 +390,7 @@ template int launch_update_mdot<float>(const float*, long, int, const double*, d
                                        hipStream_t);
 template void launch_store_scaled<double>(const double*, double*, double, long, hipStream_t);
 template void launch_store_scaled<float>(const double*, float*, double, long, hipStream_t);
-template void launch_combine<double>(const double*, long, int, const double*, double*, long, hipStream_t);
-template void launch_combine<float>(const float*, long, int, const double*, double*, long, hipStream_t);
+template void launch_combine<double>(const double*, long, int, const double*, double*, long, bool, hipStream_t);
+template void launch_combine<float>(const float*, long, int, const double*, double*, long, bool, hipStream_t);
 
 }  // namespace jfnk

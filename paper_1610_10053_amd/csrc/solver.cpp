@@ -62,6 +62,7 @@ struct jfnk_problem {
            *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
            *s2 = nullptr;
     void* V = nullptr;
+    double* Zb = nullptr;  // preconditioned basis vectors M^-1 v_j of a GMRES cycle
     Prim P{};
     Flux Fx{};
     WallFlux W{};
@@ -497,8 +498,9 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
                 launch_widen<T>(vj, p->vj, n, p->stream);
                 vin = p->vj;
             }
-            pc_apply(p, vin, p->z);
-            jv(p, u, p->F, p->b, dt, p->z, p->w);
+            double* zj = p->Zb + (long)j * n;
+            pc_apply(p, vin, zj);
+            jv(p, u, p->F, p->b, dt, zj, p->w);
             int nb = launch_mdot<T>(V, n, j + 1, p->w, n, p->part, p->stream);
             launch_final_sum(p->part, nb, j + 2, p->dsum + D_H1, p->stream);
             nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, p->w, n, p->part, true, p->stream);
@@ -544,9 +546,8 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
         }
         std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
         HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
-        launch_combine<T>(V, n, kdim, p->dsum + D_Y, p->t, n, p->stream);
-        pc_apply(p, p->t, p->z);
-        launch_add(p->x, p->z, n, p->stream);
+        // x += M^-1 V y, formed from the preconditioned vectors already at hand
+        launch_combine<double>(p->Zb, n, kdim, p->dsum + D_Y, p->x, n, true, p->stream);
         if (conv) {
             info->converged = 1;
             HIPCHK(hipStreamSynchronize(p->stream));
@@ -744,6 +745,7 @@ size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
     size_t b = 13 * nv * 8;                                                       // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
+    b += (size_t)o.gmres_restart * nv * 8;                                        // preconditioned basis
     b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
     for (int d = 0; d < G.ndim; ++d)                                              // frozen wall fluxes
         if (G.bc[d] == WALL && G.has_chi) b += 2 * (size_t)G.n[(d + 1) % 3] * G.n[(d + 2) % 3] * 8;
@@ -872,6 +874,7 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         AL(V, (size_t)(opts->gmres_restart + 1) * n);
         p->V = V;
     }
+    AL(p->Zb, (size_t)opts->gmres_restart * n);
     double* prim = nullptr;
     AL(prim, (size_t)9 * N);
     p->P.rho = prim;
