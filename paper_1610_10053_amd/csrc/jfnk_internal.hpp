@@ -53,6 +53,8 @@ __device__ __forceinline__ long flat(const Grid& G, int i, int j, int k) {
 // 3D launches of the cell sweeps: blocks of kBx x kBy threads (one wave per
 // row of kBx), grid (ceil(n0/kBx), ceil(n1/kBy), n2)
 constexpr int kBx = 64, kBy = 4;
+// threads of the single-workgroup final reductions (one workgroup per column)
+constexpr int kFinalThreads = 1024;
 inline dim3 cell_grid3(const int n[3]) { return dim3((n[0] + kBx - 1) / kBx, (n[1] + kBy - 1) / kBy, n[2]); }
 inline int cell_blocks(const int n[3]) {
     const dim3 g = cell_grid3(n);

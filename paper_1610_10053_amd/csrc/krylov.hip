@@ -10,9 +10,9 @@
 namespace jfnk {
 
 // ---------------------------------------------------------------- final reductions (one block per column, fixed order)
-__global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__ part, int nblk,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[kBlock / 64];
+__global__ void __launch_bounds__(kFinalThreads) k_final_sum(const double* __restrict__ part, int nblk,
+                                                             double* __restrict__ out) {
+    __shared__ double sh[kFinalThreads / 64];
     const int col = blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(long)col * nblk + i];
@@ -20,9 +20,9 @@ __global__ void __launch_bounds__(kBlock) k_final_sum(const double* __restrict__
     if (threadIdx.x == 0) out[col] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__ part, int nblk,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[kBlock / 64];
+__global__ void __launch_bounds__(kFinalThreads) k_final_max(const double* __restrict__ part, int nblk,
+                                                             double* __restrict__ out) {
+    __shared__ double sh[kFinalThreads / 64];
     const int col = blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) s = fmax(s, part[(long)col * nblk + i]);
@@ -32,11 +32,11 @@ __global__ void __launch_bounds__(kBlock) k_final_max(const double* __restrict__
 
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);
-    JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
+    JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kFinalThreads), 0, stream, part, nblk, out);
 }
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);
-    JFNK_KLAUNCH(k_final_max, dim3(ncol), dim3(kBlock), 0, stream, part, nblk, out);
+    JFNK_KLAUNCH(k_final_max, dim3(ncol), dim3(kFinalThreads), 0, stream, part, nblk, out);
 }
 
 // ---------------------------------------------------------------- sum of (x/S)^2 over a state-shaped vector

@@ -669,10 +669,10 @@ __global__ void __launch_bounds__(kBlock) k_copy_sumsq(const double* __restrict_
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_jv_eps(const double* __restrict__ usumsq,
-                                                   const double* __restrict__ part, int nblk, double nunk,
-                                                   double* __restrict__ eps) {
-    __shared__ double sh[kBlock / 64];
+__global__ void __launch_bounds__(kFinalThreads) k_jv_eps(const double* __restrict__ usumsq,
+                                                          const double* __restrict__ part, int nblk, double nunk,
+                                                          double* __restrict__ eps) {
+    __shared__ double sh[kFinalThreads / 64];
     double s = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[i];
     const double vs = block_sum(s, sh);
@@ -726,7 +726,7 @@ void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double 
                    hipStream_t stream) {
     {
         JFNK_PROF(KC_REDUCE, stream);
-        JFNK_KLAUNCH(k_jv_eps, dim3(1), dim3(kBlock), 0, stream, usumsq, part_v, nblk, nunk, eps);
+        JFNK_KLAUNCH(k_jv_eps, dim3(1), dim3(kFinalThreads), 0, stream, usumsq, part_v, nblk, nunk, eps);
     }
 }
 

@@ -461,8 +461,8 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
     const double eta = p->opts.gmres_eta;
     T* V = (T*)p->V;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
-    HIPCHK(hipMemsetAsync(p->x, 0, sizeof(double) * n, p->stream));
-    launch_copy(p->r, p->rhs, n, p->stream);
+    // x starts at 0: the first cycle's correction is written, later ones added;
+    // the residual of the first cycle is the right-hand side itself
     double beta0;
     CK(plain_norm(p, p->rhs, &beta0));
     info->its = 0;
@@ -472,6 +472,7 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
     info->beta0 = beta0;
     if (beta0 == 0.0) {
         info->converged = 1;
+        HIPCHK(hipMemsetAsync(p->x, 0, sizeof(double) * n, p->stream));
         return 0;
     }
     std::vector<double> hb(D_HN + 1);
@@ -484,7 +485,7 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
             break;
         }
         info->cycles++;
-        launch_store_scaled<T>(p->r, V, beta, n, p->stream);
+        launch_store_scaled<T>(cyc == 0 ? p->rhs : p->r, V, beta, n, p->stream);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int kdim = 0;
@@ -547,7 +548,7 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
         std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
         HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
         // x += M^-1 V y, formed from the preconditioned vectors already at hand
-        launch_combine<double>(p->Zb, n, kdim, p->dsum + D_Y, p->x, n, true, p->stream);
+        launch_combine<double>(p->Zb, n, kdim, p->dsum + D_Y, p->x, n, cyc > 0, p->stream);
         if (conv) {
             info->converged = 1;
             HIPCHK(hipStreamSynchronize(p->stream));
