@@ -76,11 +76,46 @@ __device__ __forceinline__ Ghost wall_ghost(const Grid& G, const Prim& P, long c
     return gh;
 }
 
+// In-plane tile of the flux sweep in LDS: the workgroup's kBx x kBy cells
+// with the halo the reconstruction reads along x and y (2 below, 1 above);
+// out-of-domain entries beyond a wall are never read.
+constexpr int kFhx = kBx + 3, kFhy = kBy + 3;
+struct FluxTile {
+    double rho[kFhy][kFhx], eps[kFhy][kFhx], p[kFhy][kFhx], T[kFhy][kFhx], chi[kFhy][kFhx];
+};
+
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFlux W) {
+    __shared__ FluxTile sm;
+    const Tile tl = xcd_tile();
+    const int i0 = (int)tl.x * kBx, j0 = (int)tl.y * kBy, k = (int)tl.z;
+    const int tid = (int)(threadIdx.x + kBx * threadIdx.y);
+    for (int e = tid; e < kFhx * kFhy; e += kBlock) {
+        const int hx = e % kFhx, hy = e / kFhx;
+        int i = i0 - 2 + hx, j = j0 - 2 + hy;
+        if (i < 0 || i >= G.n[0]) {
+            if (G.bc[0] == WALL) continue;
+            i = i < 0 ? i + G.n[0] : i - G.n[0];
+        }
+        if (j < 0 || j >= G.n[1]) {
+            if (G.bc[1] == WALL) continue;
+            j = j < 0 ? j + G.n[1] : j - G.n[1];
+        }
+        if (i < 0 || i >= G.n[0] || j < 0 || j >= G.n[1]) continue;  // tile wider than the grid
+        const long c = flat(G, i, j, k);
+        sm.rho[hy][hx] = P.rho[c];
+        sm.eps[hy][hx] = P.eps[c];
+        sm.p[hy][hx] = P.p[c];
+        if (G.has_chi) {
+            sm.T[hy][hx] = P.T[c];
+            sm.chi[hy][hx] = P.chi[c];
+        }
+    }
+    __syncthreads();
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
+    const int tx = (int)threadIdx.x + 2, ty = (int)threadIdx.y + 2;
     for (int d = 0; d < ND; ++d) {
         const bool wall = G.bc[d] == WALL;
         const int id = q.v[d];
@@ -89,27 +124,29 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
             Fx.fe[d][c] = W.lo[d] ? W.lo[d][transverse(G, q, d)] : 0.0;
             continue;
         }
+        // neighbour s along d: LDS for the in-plane axes, memory along z
+        const int ox = d == 0 ? 1 : 0, oy = d == 1 ? 1 : 0;
+        auto rho_at = [&](int s) { return d < 2 ? sm.rho[ty + s * oy][tx + s * ox] : P.rho[shifted(G, q, d, s)]; };
+        auto eps_at = [&](int s) { return d < 2 ? sm.eps[ty + s * oy][tx + s * ox] : P.eps[shifted(G, q, d, s)]; };
         const long L = shifted(G, q, d, -1);
         const double v = P.uf[d][c];
-        const double rc = P.rho[c], rL = P.rho[L], ec = P.eps[c], eL = P.eps[L];
+        const double rc = rho_at(0), rL = rho_at(-1), ec = eps_at(0), eL = eps_at(-1);
         double rLL, eLL, rR, eR;
         if (wall && id == 1) {
             const Ghost gh = wall_ghost(G, P, L, c, d, false);
             rLL = gh.rho;
             eLL = gh.eps;
         } else {
-            const long LL = shifted(G, q, d, -2);
-            rLL = P.rho[LL];
-            eLL = P.eps[LL];
+            rLL = rho_at(-2);
+            eLL = eps_at(-2);
         }
         if (wall && id == G.n[d] - 1) {
             const Ghost gh = wall_ghost(G, P, c, L, d, true);
             rR = gh.rho;
             eR = gh.eps;
         } else {
-            const long R = shifted(G, q, d, 1);
-            rR = P.rho[R];
-            eR = P.eps[R];
+            rR = rho_at(1);
+            eR = eps_at(1);
         }
         const double sl = van_leer(rc - rL, rL - rLL);
         const double sr = van_leer(rR - rc, rc - rL);
@@ -118,9 +155,12 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
         const double er = van_leer(eR - ec, ec - eL);
         const double ef = upstream(v, eL, el, ec, er);
         const double f_rho = v * rf;
-        double f_e = f_rho * ef + v * (0.5 * (P.p[L] + P.p[c]));
+        const double pL = d < 2 ? sm.p[ty - oy][tx - ox] : P.p[L], pc = d < 2 ? sm.p[ty][tx] : P.p[c];
+        double f_e = f_rho * ef + v * (0.5 * (pL + pc));
         if (G.has_chi) {
-            f_e = f_e + ((-0.5 * (P.chi[L] + P.chi[c])) * (P.T[c] - P.T[L])) * G.idx[d];
+            const double chiL = d < 2 ? sm.chi[ty - oy][tx - ox] : P.chi[L], chic = d < 2 ? sm.chi[ty][tx] : P.chi[c];
+            const double TL = d < 2 ? sm.T[ty - oy][tx - ox] : P.T[L], Tc = d < 2 ? sm.T[ty][tx] : P.T[c];
+            f_e = f_e + ((-0.5 * (chiL + chic)) * (Tc - TL)) * G.idx[d];
         }
         Fx.fr[d][c] = f_rho;
         Fx.fe[d][c] = f_e;
