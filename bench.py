@@ -28,7 +28,10 @@ if ROOT not in sys.path:
 
 METRIC = "implicit cell-steps/s at Newton rtol 1e-8 (3D TG 128^3) + % HBM peak; p50/p99"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-SAMPLE = 7  # timed-region launch sampling period of the dominant class (coprime to the V-cycle's 32 launches)
+# timed-region kernel timing: events on every launch in the first 4 of each 31
+# launches, the dominant class counted after a window's first launch (31 is
+# prime, so the windows walk through every position of the launch pattern)
+SAMPLE_PERIOD, SAMPLE_BURST = 31, 4
 
 
 def log(*a):
@@ -55,10 +58,10 @@ def run_form(jfnk, torch, desc, opts, u0, steps, warmup, prof=True):
     timed = {k: v for k, v in table.items() if v[2] > 0}
     dominant = max(timed, key=lambda k: timed[k][0]) if timed else "mg_smooth"
     # timed run: steps 1..K from t = 0 on a fresh instance; events on the
-    # dispatches of every SAMPLE-th launch of the dominant class only
+    # dispatches of sampled launch windows, the dominant class counted
     prob = jfnk.Problem(desc, opts, dev)
     prob.profile_enable([dominant] if prof else [])
-    prob.profile_sample(SAMPLE)
+    prob.profile_sample(SAMPLE_PERIOD, SAMPLE_BURST)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     stats = []
@@ -228,8 +231,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-steps", default="5,20", help="lo,hi implicit steps per request")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", default="10,60", help="lo,hi implicit steps per request")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
@@ -280,7 +283,7 @@ def main():
         "vs_baseline": None, "dtype": "f64" if main_form == "fp64" else "f64+f32", "data": "synthetic",
         "config": {"workload": "taylor_green_%d^3" % args.n, "cells": cells, "grid": desc["n"],
                    "cfl_hydro": opts["cfl_hydro"], "newton_rtol": opts["newton_rtol"],
-                   "gmres_restart": opts["gmres_restart"], "preconditioner": "acoustic, multigrid V(2,2)",
+                   "gmres_restart": opts["gmres_restart"], "preconditioner": "acoustic, %d multigrid V(2,2) cycle(s)" % opts["mg_cycles"],
                    "form": main_form, "timed_steps": "steps 1..%d of the run from t=0 (warm-up on a "
                    "separate instance)" % args.steps},
         "p50_ms": s0["p50_ms"], "p99_ms": s0["p99_ms"], "first_step_ms": s0["first_step_ms"],

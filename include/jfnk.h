@@ -179,14 +179,20 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
  * 0 disables) during later calls on p, with a HIP event pair attached to the
  * kernel dispatch itself (start and end of its execution).  Events are read
  * at the host synchronisation points the solver already has.
- * jfnk_profile_sample times one launch in every `period` of each class
- * (default 1: all), which keeps the host cost of timing small.
+ * jfnk_profile_sample(p, period, burst) keeps the host cost of timing small:
+ * with burst = 1 one launch in every `period` of each selected class is timed
+ * (default period 1: all); with burst > 1 every launch of any class in the
+ * first `burst` of each `period` launches carries events, and only the
+ * selected classes' launches after the first of such a window are counted,
+ * so every counted kernel follows one that also carried events (an event
+ * pair on a kernel that follows one without events can open before that
+ * kernel has drained and read long).
  * jfnk_profile_read copies the accumulated milliseconds, timed-launch counts
  * and compulsory bytes (every array a launch reads or writes counted once) of
  * the first nclass classes, resets them, and returns the number of classes.
  * jfnk_profile_class_name names class c ("residual_out", "cgs2_update_dot", ...). */
 int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask);
-int jfnk_profile_sample(jfnk_problem* p, int period);
+int jfnk_profile_sample(jfnk_problem* p, int period, int burst);
 int jfnk_profile_read(jfnk_problem* p, double* ms, long long* count, double* bytes, int nclass);
 const char* jfnk_profile_class_name(int cls);
 

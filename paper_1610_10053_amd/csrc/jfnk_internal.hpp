@@ -196,8 +196,14 @@ enum KClass : int {
 };
 struct Profiler {
     unsigned mask = 0;
-    unsigned period = 1;             // time one launch in every period of a class
+    // sampling: with burst == 1, one launch in every `period` of each selected
+    // class is timed; with burst > 1, every launch (of any class) in the first
+    // `burst` of each `period` launches carries events, and the selected
+    // classes' launches in such a window after its first one are counted, so
+    // each counted kernel follows a kernel that carried events too
+    unsigned period = 1, burst = 1;
     long long seen[KC_COUNT] = {};   // launches of each selected class so far
+    long long gseen = 0;             // launches of any class so far
     std::vector<hipEvent_t> pool;
     std::vector<int> cls;  // class of each recorded pair
     size_t used = 0;       // events in use (2 per pair)
@@ -220,8 +226,18 @@ extern thread_local hipEvent_t g_ev_start, g_ev_stop;
 struct ProfScope {
     bool armed = false;
     explicit ProfScope(int c, double b = 0.0) {
-        if (g_prof && (g_prof->mask >> c & 1u) && (g_prof->seen[c]++ % g_prof->period) == 0) {
-            g_prof->begin(c, b);
+        if (!g_prof || !g_prof->mask) return;
+        const bool sel = (g_prof->mask >> c & 1u) != 0;
+        if (g_prof->burst <= 1) {
+            if (sel && (g_prof->seen[c]++ % g_prof->period) == 0) {
+                g_prof->begin(c, b);
+                armed = g_ev_start != nullptr;
+            }
+            return;
+        }
+        const long long pos = g_prof->gseen++ % g_prof->period;
+        if (pos < g_prof->burst) {
+            g_prof->begin(sel && pos > 0 ? c : -1, b);  // -1: events only, not counted
             armed = g_ev_start != nullptr;
         }
     }

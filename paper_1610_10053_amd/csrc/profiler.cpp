@@ -35,7 +35,7 @@ void Profiler::withdraw() {
 void Profiler::drain() {
     for (size_t i = 0; i < cls.size(); ++i) {
         float t = 0.0f;
-        if (hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) {
+        if (cls[i] >= 0 && hipEventElapsedTime(&t, pool[2 * i], pool[2 * i + 1]) == hipSuccess) {
             ms[cls[i]] += t;
             count[cls[i]] += 1;
             bytes[cls[i]] += pend[i];

@@ -1191,13 +1191,16 @@ int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask) {
         p->prof.bytes[c] = 0.0;
         p->prof.seen[c] = 0;
     }
+    p->prof.gseen = 0;
     return 0;
 }
 
-int jfnk_profile_sample(jfnk_problem* p, int period) {
+int jfnk_profile_sample(jfnk_problem* p, int period, int burst) {
     if (!p) return fail(-1, "null problem");
-    if (period < 1) return fail(-1, "sampling period must be >= 1");
+    if (period < 1 || burst < 1 || burst > period) return fail(-1, "need 1 <= burst <= period");
     p->prof.period = (unsigned)period;
+    p->prof.burst = (unsigned)burst;
+    p->prof.gseen = 0;
     return 0;
 }
 

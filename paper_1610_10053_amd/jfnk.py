@@ -112,7 +112,7 @@ def load():
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_profile_enable": (ip, [vp, C.c_uint]),
-        "jfnk_profile_sample": (ip, [vp, ip]),
+        "jfnk_profile_sample": (ip, [vp, ip, ip]),
         "jfnk_profile_read": (ip, [vp, dp, C.POINTER(C.c_longlong), dp, ip]),
         "jfnk_profile_class_name": (C.c_char_p, [ip]),
         "jfnk_server_create": (ip, [C.c_size_t, ip, P(vp)]),
@@ -326,9 +326,11 @@ class Problem:
             mask |= 1 << (names.index(c) if isinstance(c, str) else int(c))
         _check(_lib.jfnk_profile_enable(self._h, mask))
 
-    def profile_sample(self, period):
-        """time one launch in every `period` of each enabled class"""
-        _check(_lib.jfnk_profile_sample(self._h, int(period)))
+    def profile_sample(self, period, burst=1):
+        """burst 1: time one launch in every `period` of each enabled class;
+        burst > 1: events on every launch in the first `burst` of each
+        `period` launches, enabled classes counted after a window's first"""
+        _check(_lib.jfnk_profile_sample(self._h, int(period), int(burst)))
 
     def profile_read(self):
         """{class name: (milliseconds, launches, compulsory bytes)} since enable / last read."""

@@ -54,6 +54,15 @@ DEFAULT_STEPS = {"rt": 10, "kh": 200, "tg": 100, "rad": 50}
 # 0.2 and 0.3 all converge every step; 0.2 and 0.3 take the least time).
 LINEAR_TOL = {"rt": 1e-2, "kh": 3e-2, "tg": 2e-1, "rad": 5e-3}
 
+# Multigrid V-cycles per preconditioner application, from the same kind of
+# runs on the GPU: one cycle solves the stiff conduction block of the
+# radiative layer too loosely (at 512 x 2048 GMRES stagnates and every step is
+# halved; 128 x 512: 18.9 ms/step with one cycle, 12.7 with three; 512 x 2048:
+# 811, 32 and 26 ms/step with one, two and three); two cycles take 3 % off the
+# Taylor-Green step (GMRES 47 -> 35 iterations per step); one is best for
+# the shear layer and the Rayleigh-Taylor problem.
+MG_CYCLES = {"rt": 1, "kh": 1, "tg": 2, "rad": 3}
+
 
 def default_opts(**over):
     """Solver options: Newton relative tolerance 1e-8, GMRES(30) to a
@@ -196,7 +205,7 @@ def _rt(n, seed, noise, perturb):
     mx = np.zeros_like(rho3)
     E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
-    opts = default_opts(cfl_hydro=5.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["rt"])
+    opts = default_opts(cfl_hydro=5.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["rt"], mg_cycles=MG_CYCLES["rt"])
     return desc, opts, u
 
 
@@ -226,7 +235,7 @@ def _kh(n, seed, noise, perturb):
     my = _face_avg_rho(rho3, 1, False) * vy3
     E = _energy(p3, rho3, desc["gamma"], [ux3, vy3], bc)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
-    opts = default_opts(cfl_hydro=10.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["kh"])
+    opts = default_opts(cfl_hydro=10.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["kh"], mg_cycles=MG_CYCLES["kh"])
     return desc, opts, u
 
 
@@ -261,7 +270,7 @@ def _tg(n, seed, noise, perturb):
     mz = _face_avg_rho(rho, 0, False) * uz
     E = _energy(p, rho, gamma, [ux, uy, uz], bc)
     u = join_state(dict(rho=rho, E=E, mx=mx, my=my, mz=mz), desc)
-    opts = default_opts(cfl_hydro=20.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["tg"])
+    opts = default_opts(cfl_hydro=20.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["tg"], mg_cycles=MG_CYCLES["tg"])
     return desc, opts, u
 
 
@@ -298,7 +307,8 @@ def _rad(n, seed, noise, perturb):
     my = _face_avg_rho(rho3, 1, True) * vy3
     E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
-    opts = default_opts(cfl_hydro=10.0, cfl_rad_max=1000.0, pc=PC_ACOUSTIC_DIFFUSION, gmres_eta=LINEAR_TOL["rad"])
+    opts = default_opts(cfl_hydro=10.0, cfl_rad_max=1000.0, pc=PC_ACOUSTIC_DIFFUSION,
+                        gmres_eta=LINEAR_TOL["rad"], mg_cycles=MG_CYCLES["rad"])
     return desc, opts, u
 
 
