@@ -351,28 +351,52 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
 // them at run time.
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseMaxLevelCells = 512;  // largest level the single-workgroup solve takes
+// Sweeps of a level held in LDS by the single workgroup: every cell has its
+// own thread (levels of at most kCoarseMaxLevelCells <= kCoarseThreads
+// cells), whose coordinates, colour and neighbour indices are found once per
+// call; the update is gs_value's, operation for operation.
 template <typename R, int ND>
-__device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first, R* tmp) {
+__device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
     const bool together = odd_periodic<R, ND>(G, L);
+    const int c = (int)threadIdx.x;
+    const bool mine = c < L.N;
+    int up[ND], dn[ND], colour = -1;
+    R alo[ND], ahi[ND], den = (R)1.0, bc = (R)0.0, Dc = (R)1.0;
+    if (mine) {
+        const LIjk q = lcoords(L, c);
+        colour = (q.v[0] + q.v[1] + q.v[2]) & 1;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            up[d] = lnb(G, L, q, d, 1);
+            dn[d] = lnb(G, L, q, d, -1);
+            alo[d] = L.a[d][c];
+            ahi[d] = up[d] >= 0 ? L.a[d][up[d]] : (R)0.0;
+            den = den + alo[d];
+            den = den + ahi[d];
+        }
+        bc = L.b[c];
+        if (!L.unit_sig) Dc = L.D[c];
+    }
+    const R dv = L.unit_sig ? den : Dc;
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             const bool f = first && s == 0 && color == 0;
+            R val = (R)0.0;
+            if (colour == color) {
+                R num = bc;
+#pragma unroll
+                for (int d = 0; d < ND; ++d) {
+                    if (dn[d] >= 0) num = num + alo[d] * (f ? (R)0.0 : L.x[dn[d]]);
+                    if (up[d] >= 0) num = num + ahi[d] * (f ? (R)0.0 : L.x[up[d]]);
+                }
+                val = num / dv;
+            }
             if (!together) {
-                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-                    const LIjk q = lcoords(L, c);
-                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) gs_cell<R, ND>(G, L, L.b, L.x, q, c, f);
-                }
+                if (colour == color) L.x[c] = val;
             } else {
-                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-                    const LIjk q = lcoords(L, c);
-                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) tmp[c] = gs_value<R, ND>(G, L, L.b, L.x, q, c, f);
-                }
                 __syncthreads();
-                for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-                    const LIjk q = lcoords(L, c);
-                    if (((q.v[0] + q.v[1] + q.v[2]) & 1) == color) L.x[c] = tmp[c];
-                    else if (f) L.x[c] = (R)0.0;
-                }
+                if (colour == color) L.x[c] = val;
+                else if (f && mine) L.x[c] = (R)0.0;
             }
             __syncthreads();
         }
@@ -395,7 +419,6 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
                                                                    int first_top) {
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
-    __shared__ R tmp[kCoarseLdsCells];
     __shared__ R rbuf[kCoarseMaxLevelCells];  // residuals of the level being restricted
     __shared__ int base[kMaxLevels];
     if (threadIdx.x == 0) {
@@ -425,7 +448,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         const bool first = l == from ? top_first : true;
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
-        lds_smooth<R, ND>(G, L, nu1, first, tmp);
+        lds_smooth<R, ND>(G, L, nu1, first);
         // restriction: every fine residual once, then the children's sums in
         // the order of restrict_cell
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell<R, ND>(G, L, L.b, L.x, lcoords(L, c), c);
@@ -444,14 +467,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     }
     {
         const LevelT<R> L = lds_level<R, ND>(Ld[nlev - 1], sm, base[nlev - 1]);
-        lds_smooth<R, ND>(G, L, nuc, nlev - 1 == from ? top_first : true, tmp);
+        lds_smooth<R, ND>(G, L, nuc, nlev - 1 == from ? top_first : true);
     }
     for (int l = nlev - 2; l >= from; --l) {
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
-        lds_smooth<R, ND>(G, L, nu2, false, tmp);
+        lds_smooth<R, ND>(G, L, nu2, false);
     }
     const LevelT<R> gT = Ld[from];
     const LevelT<R> T = lds_level<R, ND>(gT, sm, base[from]);
