@@ -97,6 +97,7 @@ typedef struct {
     double f0, f;         /* initial and final |S^-1 F| */
     int newton_its, gmres_its, rejections, status;
     double wall_ms;       /* host wall time of the call */
+    int scalar_newton_its, scalar_gmres_its;  /* passive-scalar solve of the accepted attempt */
 } jfnk_step_stats;
 
 typedef struct jfnk_problem jfnk_problem;
@@ -129,6 +130,22 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out);
 /* One Crank-Nicolson step at the given dt with no retry.  On failure the
  * state is restored to u^n. */
 int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out);
+
+/* ---- passive scalars (section 2.2) ----
+ * nscal scalars given as partial densities s_k = c_k rho (nscal * N doubles,
+ * scalar k at [k*N, (k+1)*N), cell order as rho), advanced by every later
+ * step: after the flow's Newton solve has converged they take a
+ * Crank-Nicolson step of d s_k/dt = -div(c_k rho u) with the mass fluxes of
+ * u^n and u^{n+1} (face concentration reconstructed upstream with the van
+ * Leer limiter, mirror image beyond walls), solved by Jacobian-free
+ * Newton-Krylov without a preconditioner to the flow's tolerances; with
+ * renormalize = 1 (and nscal > 1) the concentrations are then scaled to sum
+ * to one in every cell.  A failed scalar solve fails the step like a failed
+ * flow solve (state and scalars restored, dt halved).  nscal = 0 detaches
+ * them.  Not available for problems created inside a caller-provided device
+ * range (-4). */
+int jfnk_set_scalars(jfnk_problem* p, int nscal, int renormalize, const double* s, int on_device);
+int jfnk_get_scalars(jfnk_problem* p, double* s, int on_device);
 
 /* ---- component entry points (operate on caller buffers of nvec doubles) ---- */
 

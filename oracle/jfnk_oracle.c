@@ -83,6 +83,10 @@ typedef struct {
     double st_dt, st_cfl_h, st_cfl_a, st_cfl_r, st_rel_res, st_max_rel_corr, st_mass_drift,
         st_energy_drift, st_f0, st_f;
     int st_newton, st_gmres, st_rejections, st_status, st_gmres_fail;
+    /* passive scalars (section 2.2): nscal partial densities s_k = c_k rho */
+    int nscal, renorm;
+    double *sc, *sc_n;
+    int st_sc_newton, st_sc_gmres;
 } Or;
 
 /* ------------------------------------------------------------------ indexing */
@@ -1215,6 +1219,158 @@ static int newton(Or *o, double dt) {
     return status;
 }
 
+/* ------------------------------------------------------------------ passive scalars (section 2.2)
+ * Each scalar is a concentration c_k carried by the flow, advanced in its
+ * conservative form d(c_k rho)/dt = -div(c_k rho u): the face flux is the
+ * face mass flux of the hydrodynamic solution times the concentration
+ * reconstructed on the face like the other cell quantities (upstream linear
+ * extrapolation with the van Leer limiter; beyond a wall the mirror-image
+ * cell).  After a converged hydrodynamic step the scalars take their own
+ * Crank-Nicolson step with the mass fluxes of u^n and u^{n+1}, solved by
+ * Jacobian-free Newton-Krylov without a preconditioner, and are
+ * re-normalised so that the concentrations sum to one in every cell. */
+
+/* density and lower-face mass fluxes of state u, cell-indexed (0 on walls) */
+static void mass_flux_cells(Or *o, const double *u, double *rho, double *fr) {
+    primitives(o, u);
+    fluxes(o);
+    FOR_CELLS(o) {
+        long c = cidx(o, i, j, k), pc = pidx(o, i, j, k);
+        rho[c] = o->rho[pc];
+        for (int d = 0; d < o->ndim; ++d) fr[(long)d * o->N + c] = o->fr[d][pc];
+    }
+}
+
+/* concentration of the cell at offset a along d from (i, j, k) */
+static double conc(const Or *o, const double *s, const double *rho, int i, int j, int k, int d, int a) {
+    int x[3] = {i, j, k};
+    int n = o->n[d], v = x[d] + a;
+    if (v < 0 || v >= n) {
+        if (o->bc[d] == BC_WALL) v = v < 0 ? -1 - v : 2 * n - 1 - v;
+        else v = (v % n + n) % n;
+    }
+    x[d] = v;
+    long c = cidx(o, x[0], x[1], x[2]);
+    return s[c] / rho[c];
+}
+
+/* scalar flux through the lower face of cell (i, j, k) along d */
+static double scalar_flux(const Or *o, const double *s, const double *rho, const double *fr, int i, int j, int k,
+                          int d) {
+    int id = coord(d, i, j, k);
+    if (o->bc[d] == BC_WALL && id == 0) return 0.0;
+    double f = fr[(long)d * o->N + cidx(o, i, j, k)];
+    double cLL = conc(o, s, rho, i, j, k, d, -2), cL = conc(o, s, rho, i, j, k, d, -1);
+    double cc = conc(o, s, rho, i, j, k, d, 0), cR = conc(o, s, rho, i, j, k, d, 1);
+    double sl = vanleer(cc - cL, cL - cLL);
+    double sr = vanleer(cR - cc, cc - cL);
+    return f * upstream(f, cL, sl, cc, sr);
+}
+
+/* R_k = -div(c_k rho u) for every scalar */
+static void scalar_rhs(const Or *o, const double *s, const double *rho, const double *fr, double *R) {
+    for (int q = 0; q < o->nscal; ++q) {
+        const double *sq = s + (long)q * o->N;
+        FOR_CELLS(o) {
+            double r = 0.0;
+            for (int d = 0; d < o->ndim; ++d) {
+                int x[3] = {i, j, k};
+                double lo = scalar_flux(o, sq, rho, fr, i, j, k, d), hi = 0.0;
+                if (!(o->bc[d] == BC_WALL && x[d] == o->n[d] - 1)) {
+                    x[d] = (x[d] + 1) % o->n[d];
+                    hi = scalar_flux(o, sq, rho, fr, x[0], x[1], x[2], d);
+                }
+                r = r - (hi - lo) * o->idx[d];
+            }
+            R[(long)q * o->N + cidx(o, i, j, k)] = r;
+        }
+    }
+}
+
+typedef struct { Or *o; const double *s, *Gs, *b, *rho, *fr; double h, srms; double *sp, *R; } SCtx;
+
+/* G(s) = (s - b) - h R(s) */
+static void scalar_residual(SCtx *c, const double *s, double *G) {
+    long n = (long)c->o->nscal * c->o->N;
+    scalar_rhs(c->o, s, c->rho, c->fr, c->R);
+    for (long q = 0; q < n; ++q) G[q] = (s[q] - c->b[q]) - c->h * c->R[q];
+}
+static void op_sjv(void *ctx, const double *v, double *w) {
+    SCtx *c = ctx;
+    long n = (long)c->o->nscal * c->o->N;
+    double vrms = norm2(n, v) / sqrt((double)n);
+    if (vrms == 0.0) { memset(w, 0, sizeof(double) * n); return; }
+    double eps = sqrt(2.220446049250313e-16) * (1.0 + c->srms) / vrms;
+    for (long q = 0; q < n; ++q) c->sp[q] = c->s[q] + eps * v[q];
+    scalar_residual(c, c->sp, w);
+    for (long q = 0; q < n; ++q) w[q] = (w[q] - c->Gs[q]) / eps;
+}
+static void op_copy(void *ctx, const double *x, double *y) {
+    SCtx *c = ctx;
+    memcpy(y, x, sizeof(double) * (long)c->o->nscal * c->o->N);
+}
+
+/* Crank-Nicolson step of the scalars from u^n (o->un) to u^{n+1} (o->u) */
+static int scalar_step(Or *o, double dt) {
+    long N = o->N, n = (long)o->nscal * N;
+    double *rho0 = calloc(N, sizeof(double)), *rho1 = calloc(N, sizeof(double));
+    double *fr0 = calloc(3 * N, sizeof(double)), *fr1 = calloc(3 * N, sizeof(double));
+    double *b = calloc(n, sizeof(double)), *G = calloc(n, sizeof(double)), *R = calloc(n, sizeof(double));
+    double *x = calloc(n, sizeof(double)), *rhs = calloc(n, sizeof(double)), *sp = calloc(n, sizeof(double));
+    mass_flux_cells(o, o->un, rho0, fr0);
+    mass_flux_cells(o, o->u, rho1, fr1);
+    double *s = o->sc;
+    memcpy(o->sc_n, s, sizeof(double) * n);
+    double h = 0.5 * dt;
+    scalar_rhs(o, s, rho0, fr0, R);
+    for (long q = 0; q < n; ++q) b[q] = s[q] + h * R[q];
+    SCtx ctx = {o, s, G, b, rho1, fr1, h, 0.0, sp, R};
+    scalar_residual(&ctx, s, G);
+    double g0 = norm2(n, G), g = g0;
+    double tol = o->rtol * g0, floor_ = o->atol * sqrt((double)n);
+    if (floor_ > tol) tol = floor_;
+    int status = 0, its = 0, gits = 0;
+    if (!isfinite(g0)) status = 3;
+    while (status == 0 && g > tol) {
+        if (its >= o->newton_max) { status = 1; break; }
+        ctx.srms = norm2(n, s) / sqrt((double)n);
+        for (long q = 0; q < n; ++q) rhs[q] = -G[q];
+        GmresInfo gi;
+        gmres(n, op_sjv, op_copy, &ctx, rhs, x, o->restart, o->max_cycles, o->eta, &gi);
+        gits += gi.its;
+        if (!gi.converged && gi.res >= 0.999 * gi.beta0) { status = 2; break; }
+        for (long q = 0; q < n; ++q) s[q] = s[q] + x[q];
+        scalar_residual(&ctx, s, G);
+        g = norm2(n, G);
+        its++;
+        if (!isfinite(g)) { status = 3; break; }
+    }
+    if (status == 0 && o->renorm && o->nscal > 1) {
+        for (long c = 0; c < N; ++c) {
+            double tot = 0.0;
+            for (int q = 0; q < o->nscal; ++q) tot = tot + s[(long)q * N + c];
+            if (tot > 0.0)
+                for (int q = 0; q < o->nscal; ++q) s[(long)q * N + c] = s[(long)q * N + c] * (rho1[c] / tot);
+        }
+    }
+    if (status != 0) memcpy(s, o->sc_n, sizeof(double) * n);
+    o->st_sc_newton = its;
+    o->st_sc_gmres = gits;
+    free(rho0); free(rho1); free(fr0); free(fr1); free(b); free(G); free(R); free(x); free(rhs); free(sp);
+    return status;
+}
+
+/* one Crank-Nicolson step of the flow and then of the scalars; on failure
+ * the state (and the scalars) are those of u^n */
+static int step_at(Or *o, double dt) {
+    int s = newton(o, dt);
+    if (s == 0 && o->nscal > 0) {
+        s = scalar_step(o, dt);
+        if (s != 0) memcpy(o->u, o->un, sizeof(double) * o->nvec);
+    }
+    return s;
+}
+
 /* ------------------------------------------------------------------ public entry points */
 
 static void or_free(Or *o) {
@@ -1230,6 +1386,7 @@ static void or_free(Or *o) {
         for (int e = 0; e < 3; ++e) free(o->phic[d][e]);
     }
     for (int l = 0; l < MAXLEV; ++l) { level_free(&o->mg_ac[l]); level_free(&o->mg_df[l]); }
+    free(o->sc); free(o->sc_n);
     free(o);
 }
 
@@ -1352,7 +1509,7 @@ static void fill_stats(Or *o, double *st) {
 int or_newton_solve(void *h, double dt, double *stats) {
     Or *o = h;
     o->st_rejections = 0;
-    int s = newton(o, dt);
+    int s = step_at(o, dt);
     if (s == 0) o->t += dt;
     double hy, ad, ra;
     time_step(o, o->un, &hy, &ad, &ra);
@@ -1368,7 +1525,7 @@ int or_implicit_step(void *h, double *stats) {
     double dt = time_step(o, o->u, &hy, &ad, &ra);
     int rej = 0, s = 0;
     for (;;) {
-        s = newton(o, dt);
+        s = step_at(o, dt);
         if (s == 0 || rej >= o->max_halvings) break;
         rej++;
         dt = 0.5 * dt;
@@ -1379,6 +1536,26 @@ int or_implicit_step(void *h, double *stats) {
     fill_stats(o, stats);
     return s;
 }
+
+/* passive scalars: nscal partial densities s_k = c_k rho (nscal * N values) */
+void or_set_scalars(void *h, int nscal, int renorm, const double *s) {
+    Or *o = h;
+    free(o->sc); free(o->sc_n);
+    o->nscal = nscal;
+    o->renorm = renorm;
+    o->sc = calloc((long)nscal * o->N + 1, sizeof(double));
+    o->sc_n = calloc((long)nscal * o->N + 1, sizeof(double));
+    memcpy(o->sc, s, sizeof(double) * (long)nscal * o->N);
+}
+void or_get_scalars(void *h, double *s) { Or *o = h; memcpy(s, o->sc, sizeof(double) * (long)o->nscal * o->N); }
+void or_scalar_rhs(void *h, const double *u, const double *s, double *R) {
+    Or *o = h;
+    double *rho = calloc(o->N, sizeof(double)), *fr = calloc(3 * o->N, sizeof(double));
+    mass_flux_cells(o, u, rho, fr);
+    scalar_rhs(o, s, rho, fr, R);
+    free(rho); free(fr);
+}
+int or_scalar_its(void *h, int *out) { Or *o = h; out[0] = o->st_sc_newton; out[1] = o->st_sc_gmres; return 0; }
 
 /* frozen wall fluxes and heat-balance source: for tests */
 void or_get_sources(void *h, double *sbal) { Or *o = h; memcpy(sbal, o->sbal, sizeof(double) * o->N); }

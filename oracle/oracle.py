@@ -39,6 +39,10 @@ def _load():
         "or_newton_solve": (C.c_int, [vp, C.c_double, _dp]),
         "or_implicit_step": (C.c_int, [vp, _dp]),
         "or_get_sources": (None, [vp, _dp]),
+        "or_set_scalars": (None, [vp, C.c_int, C.c_int, _dp]),
+        "or_get_scalars": (None, [vp, _dp]),
+        "or_scalar_rhs": (None, [vp, _dp, _dp, _dp]),
+        "or_scalar_its": (C.c_int, [vp, _ip]),
         "or_tridiag": (None, [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_int]),
         "or_gmres_dense": (None, [C.c_long, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_double, _dp]),
     }
@@ -151,6 +155,29 @@ class Oracle:
         s = np.empty(self.N)
         _lib.or_get_sources(self._h, _d(s))
         return s
+
+    # passive scalars (partial densities s_k = c_k rho, nscal * N values)
+    def set_scalars(self, s, nscal, renormalize=True):
+        s = _arr(s, nscal * self.N)
+        self.nscal = int(nscal)
+        _lib.or_set_scalars(self._h, self.nscal, 1 if renormalize else 0, _d(s))
+
+    def get_scalars(self):
+        out = np.empty(self.nscal * self.N)
+        _lib.or_get_scalars(self._h, _d(out))
+        return out
+
+    def scalar_rhs(self, u, s):
+        u = _arr(u, self.nvec)
+        s = _arr(s)
+        out = np.empty(s.size)
+        _lib.or_scalar_rhs(self._h, _d(u), _d(s), _d(out))
+        return out
+
+    def scalar_its(self):
+        out = (C.c_int * 2)()
+        _lib.or_scalar_its(self._h, out)
+        return int(out[0]), int(out[1])
 
     # solver
     def newton_solve(self, dt):

@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libjfnk.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["residual.hip", "krylov.hip", "precond.hip", "diagnostics.hip", "solver.cpp", "profiler.cpp",
-           "server.cpp"]
+SOURCES = ["residual.hip", "krylov.hip", "precond.hip", "diagnostics.hip", "scalars.hip", "solver.cpp",
+           "profiler.cpp", "server.cpp"]
 ARCH = os.environ.get("JFNK_OFFLOAD_ARCH", "gfx950")
 
 # FP64 kernels follow a fixed evaluation order (no contraction into FMA) so

@@ -66,6 +66,29 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
                      const double* sbal, const OutSpec& o, hipStream_t stream);
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream);
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream);
+// passive scalars: residual consumers of s_k = c_k rho under the mass fluxes
+// fr and density rho of a flow state (modes OUT_CN_OLD, OUT_RESIDUAL, OUT_JV)
+struct ScalarArgs {
+    int ns;
+    const double* rho;
+    const double* fr[3];
+    const double* s;
+    const double* v;    // direction (OUT_JV) or null
+    const double* eps;  // device scalar (OUT_JV)
+    const double* b;    // old-time term (OUT_RESIDUAL, OUT_JV)
+    const double* Gs;   // G(s) (OUT_JV)
+    double h;
+    int mode;
+    double* out;
+    double* partial;    // block sums of out^2 (OUT_RESIDUAL) or null
+};
+void launch_scalar_out(const Grid& G, const ScalarArgs& A, hipStream_t stream);
+void launch_scalar_renorm(double* s, const double* rho, int ns, long N, hipStream_t stream);
+void launch_negate(const double* in, double* out, long n, hipStream_t stream);
+// primitives and lower-face fluxes of a state (the first two residual sweeps)
+void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                      hipStream_t stream);
+
 // diagnostics of the state whose primitives P hold: out5 = sum kin, sum rho,
 // sum E (per unit volume), max Mach, sum of the layers' X_M along axis (or
 // untouched when axis < 0); part needs 4 cell_blocks + n[axis] doubles

@@ -426,6 +426,15 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     }
 }
 
+void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                      hipStream_t stream) {
+    launch_prim(G, s, P, stream);
+    {
+        JFNK_PROFB(KC_FLUX, stream, prim_writes(G) + 8.0 * G.N * 2 * G.ndim);
+        JFNK_LAUNCH_ND(G.ndim, k_flux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx, W);
+    }
+}
+
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));

@@ -36,7 +36,8 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kDsum = 512;  // device scalar area
 // offsets in the device scalar area
-constexpr int D_H1 = 0, D_H2 = 80, D_HN = 160, D_Y = 170, D_USQ = 250, D_EPS = 251, D_TMP = 260;
+constexpr int D_H1 = 0, D_H2 = 80, D_HN = 160, D_Y = 170, D_USQ = 250, D_EPS = 251, D_TMP = 260, D_SUSQ = 300,
+              D_SEPS = 301;
 
 struct Buffers {
     std::vector<void*> ptrs;
@@ -91,6 +92,14 @@ struct jfnk_problem {
     double hyd = 0, adv = 0, rad = 0;
     Profiler prof;
     bool prof_on = false;
+    // passive scalars: ns partial densities (ns x N), their Krylov workspace
+    // and the density and mass fluxes of u^n and u^{n+1}
+    int nscal = 0, renorm = 0;
+    Buffers sbuf;
+    double *sc = nullptr, *sc_n = nullptr, *sb = nullptr, *sG = nullptr, *sx = nullptr, *srhs = nullptr,
+           *sr = nullptr, *sw = nullptr, *stmp = nullptr, *sV = nullptr;
+    double *srho0 = nullptr, *srho1 = nullptr, *sfr0 = nullptr, *sfr1 = nullptr;
+    int sc_newton = 0, sc_gmres = 0;
     ~jfnk_problem() {
         if (hpin && own_hpin) (void)hipHostFree(hpin);
     }
@@ -453,18 +462,25 @@ struct GmresInfo {
 };
 
 // ---------------------------------------------------------------- GMRES(m), right preconditioned, CGS2
-template <typename T>
-int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
-    const Grid& G = p->G;
-    const long n = G.nvec;
+// Restarted GMRES on vectors of n doubles: basis V (T), classical
+// Gram-Schmidt applied twice on the device, Givens rotations and the
+// triangular solve on the host (one read-back per iteration).
+//   norm(v, &out): the 2-norm of v (synchronises);
+//   pc(j, v, z):   z_j = M^-1 v_j into Zb column j (not called when Zb is null:
+//                  no preconditioner, the basis vectors themselves are used);
+//   op(z, w):      w = A z for a preconditioned basis vector;
+//   opx(x, t):     t = A x for the restart residual.
+// x += M^-1 V y is formed from the kept preconditioned vectors.
+template <typename T, class Norm, class Pc, class Op, class OpX>
+int gmres_core(jfnk_problem* p, long n, T* V, double* Zb, const double* rhs, double* x, double* r, double* w,
+               double* t, double* vtmp, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info) {
     const int m = p->opts.gmres_restart;
     const double eta = p->opts.gmres_eta;
-    T* V = (T*)p->V;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
     // x starts at 0: the first cycle's correction is written, later ones added;
     // the residual of the first cycle is the right-hand side itself
     double beta0;
-    CK(plain_norm(p, p->rhs, &beta0));
+    CK(norm(rhs, &beta0));
     info->its = 0;
     info->cycles = 0;
     info->converged = 0;
@@ -472,20 +488,20 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
     info->beta0 = beta0;
     if (beta0 == 0.0) {
         info->converged = 1;
-        HIPCHK(hipMemsetAsync(p->x, 0, sizeof(double) * n, p->stream));
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, p->stream));
         return 0;
     }
     std::vector<double> hb(D_HN + 1);
     for (int cyc = 0; cyc < p->opts.gmres_max_cycles; ++cyc) {
         double beta = beta0;
-        if (cyc > 0) CK(plain_norm(p, p->r, &beta));
+        if (cyc > 0) CK(norm(r, &beta));
         info->res = beta;
         if (beta <= eta * beta0) {
             info->converged = 1;
             break;
         }
         info->cycles++;
-        launch_store_scaled<T>(cyc == 0 ? p->rhs : p->r, V, beta, n, p->stream);
+        launch_store_scaled<T>(cyc == 0 ? rhs : r, V, beta, n, p->stream);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int kdim = 0;
@@ -496,17 +512,20 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
             if (sizeof(T) == sizeof(double)) {
                 vin = (const double*)vj;
             } else {
-                launch_widen<T>(vj, p->vj, n, p->stream);
-                vin = p->vj;
+                launch_widen<T>(vj, vtmp, n, p->stream);
+                vin = vtmp;
             }
-            double* zj = p->Zb + (long)j * n;
-            pc_apply(p, vin, zj);
-            jv(p, u, p->F, p->b, dt, zj, p->w);
-            int nb = launch_mdot<T>(V, n, j + 1, p->w, n, p->part, p->stream);
+            const double* zj = vin;
+            if (Zb) {
+                pc(j, vin, Zb + (long)j * n);
+                zj = Zb + (long)j * n;
+            }
+            op(zj, w);
+            int nb = launch_mdot<T>(V, n, j + 1, w, n, p->part, p->stream);
             launch_final_sum(p->part, nb, j + 2, p->dsum + D_H1, p->stream);
-            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, p->w, n, p->part, true, p->stream);
+            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, w, n, p->part, true, p->stream);
             launch_final_sum(p->part, nb, j + 1, p->dsum + D_H2, p->stream);
-            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, p->w, n, p->part, false, p->stream);
+            nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, w, n, p->part, false, p->stream);
             launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream);
             HIPCHK(hipGetLastError());
             CK(read_scalars(p, 0, D_HN + 1, hb.data()));
@@ -534,7 +553,7 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
                 conv = true;
                 break;
             }
-            launch_store_scaled<T>(p->w, V + (long)(j + 1) * n, hn, n, p->stream);
+            launch_store_scaled<T>(w, V + (long)(j + 1) * n, hn, n, p->stream);
             if (info->res <= eta * beta0) {
                 conv = true;
                 break;
@@ -548,19 +567,33 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
         std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
         HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
         // x += M^-1 V y, formed from the preconditioned vectors already at hand
-        launch_combine<double>(p->Zb, n, kdim, p->dsum + D_Y, p->x, n, cyc > 0, p->stream);
+        if (Zb) launch_combine<double>(Zb, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
+        else launch_combine<T>(V, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
         if (conv) {
             info->converged = 1;
             HIPCHK(hipStreamSynchronize(p->stream));
             break;
         }
-        eps_for(p, p->x);
-        jv(p, u, p->F, p->b, dt, p->x, p->t);
-        launch_sub(p->rhs, p->t, p->r, n, p->stream);
-        CK(plain_norm(p, p->r, &info->res));
+        opx(x, t);
+        launch_sub(rhs, t, r, n, p->stream);
+        CK(norm(r, &info->res));
     }
     HIPCHK(hipGetLastError());
     return 0;
+}
+
+// the flow's linear system in scaled variables, with the physics-based preconditioner
+template <typename T>
+int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
+    const long n = p->G.nvec;
+    auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
+    auto pc = [&](int, const double* v, double* z) { pc_apply(p, v, z); };
+    auto op = [&](const double* z, double* w) { jv(p, u, p->F, p->b, dt, z, w); };
+    auto opx = [&](const double* x, double* t) {
+        eps_for(p, x);
+        jv(p, u, p->F, p->b, dt, x, t);
+    };
+    return gmres_core<T>(p, n, (T*)p->V, p->Zb, p->rhs, p->x, p->r, p->w, p->t, p->vj, norm, pc, op, opx, info);
 }
 
 // Newton-Raphson from u^n at dt; on failure the state is restored
@@ -628,6 +661,130 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
     if (status != 0) launch_copy(p->u, p->un, n, p->stream);
     HIPCHK(hipGetLastError());
     return status;
+}
+
+// ---------------------------------------------------------------- passive scalars (section 2.2)
+// After a converged step of the flow the scalars take a Crank-Nicolson step
+// with the mass fluxes of u^n and u^{n+1}, solved by Jacobian-free
+// Newton-Krylov without a preconditioner (the same tolerances as the flow),
+// then are re-normalised so that the concentrations sum to one per cell.
+ScalarArgs scalar_args(jfnk_problem* p, int mode, const double* rho, const double* fr, const double* s,
+                       double* out, double h) {
+    ScalarArgs A;
+    A.ns = p->nscal;
+    A.rho = rho;
+    for (int d = 0; d < 3; ++d) A.fr[d] = d < p->G.ndim ? fr + (long)d * p->G.N : nullptr;
+    A.s = s;
+    A.v = nullptr;
+    A.eps = p->dsum + D_SEPS;
+    A.b = p->sb;
+    A.Gs = p->sG;
+    A.h = h;
+    A.mode = mode;
+    A.out = out;
+    A.partial = mode == OUT_RESIDUAL ? p->part : nullptr;
+    return A;
+}
+
+// 2-norm of a vector of n doubles
+int vec_norm(jfnk_problem* p, const double* v, long n, double* out) {
+    const int nb = launch_mdot<double>(v, n, 1, v, n, p->part, p->stream);
+    launch_final_sum(p->part, nb, 1, p->dsum + D_TMP, p->stream);
+    double s2;
+    CK(read_scalars(p, D_TMP, 1, &s2));
+    *out = std::sqrt(s2);
+    return 0;
+}
+
+int scalar_step(jfnk_problem* p, double dt) {
+    const Grid& G = p->G;
+    const long N = G.N, n = (long)p->nscal * N;
+    const jfnk_solver_opts& o = p->opts;
+    // density and mass fluxes of u^n and u^{n+1}
+    launch_prim_flux(G, view(p, p->un, nullptr), p->P, p->Fx, p->W, p->stream);
+    HIPCHK(hipMemcpyAsync(p->srho0, p->P.rho, sizeof(double) * N, hipMemcpyDeviceToDevice, p->stream));
+    for (int d = 0; d < G.ndim; ++d)
+        HIPCHK(hipMemcpyAsync(p->sfr0 + (long)d * N, p->Fx.fr[d], sizeof(double) * N, hipMemcpyDeviceToDevice,
+                              p->stream));
+    launch_prim_flux(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->stream);
+    HIPCHK(hipMemcpyAsync(p->srho1, p->P.rho, sizeof(double) * N, hipMemcpyDeviceToDevice, p->stream));
+    for (int d = 0; d < G.ndim; ++d)
+        HIPCHK(hipMemcpyAsync(p->sfr1 + (long)d * N, p->Fx.fr[d], sizeof(double) * N, hipMemcpyDeviceToDevice,
+                              p->stream));
+    launch_copy(p->sc_n, p->sc, n, p->stream);
+    const double h = 0.5 * dt;
+    launch_scalar_out(G, scalar_args(p, OUT_CN_OLD, p->srho0, p->sfr0, p->sc, p->sb, h), p->stream);
+    auto residual = [&](double* g) {
+        launch_scalar_out(G, scalar_args(p, OUT_RESIDUAL, p->srho1, p->sfr1, p->sc, p->sG, h), p->stream);
+        launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
+        double g2;
+        CK(read_scalars(p, D_TMP, 1, &g2));
+        *g = std::sqrt(g2);
+        return 0;
+    };
+    double g0;
+    CK(residual(&g0));
+    double g = g0, tol = o.newton_rtol * g0;
+    const double floor_ = o.newton_atol * std::sqrt((double)n);
+    if (floor_ > tol) tol = floor_;
+    int status = 0, its = 0, gits = 0;
+    if (!std::isfinite(g0)) status = 3;
+    auto norm = [&](const double* v, double* out) { return vec_norm(p, v, n, out); };
+    auto pc = [&](int, const double*, double*) {};
+    // w = (G(s + eps v) - G(s)) / eps, eps = sqrt(2^-52)(1 + rms(s))/rms(v)
+    auto op = [&](const double* v, double* w) {
+        const int nb = launch_mdot<double>(v, n, 1, v, n, p->part, p->stream);
+        launch_jv_eps(p->dsum + D_SUSQ, p->part, nb, (double)n, p->dsum + D_SEPS, p->stream);
+        ScalarArgs A = scalar_args(p, OUT_JV, p->srho1, p->sfr1, p->sc, w, h);
+        A.v = v;
+        launch_scalar_out(G, A, p->stream);
+    };
+    while (status == 0 && g > tol) {
+        if (its >= o.newton_max) {
+            status = 1;
+            break;
+        }
+        const int nb = launch_mdot<double>(p->sc, n, 1, p->sc, n, p->part, p->stream);
+        launch_final_sum(p->part, nb, 1, p->dsum + D_SUSQ, p->stream);
+        launch_negate(p->sG, p->srhs, n, p->stream);
+        GmresInfo gi;
+        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, nullptr, norm, pc, op, op,
+                              &gi));
+        gits += gi.its;
+        if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
+            status = 2;
+            break;
+        }
+        launch_add(p->sc, p->sx, n, p->stream);
+        CK(residual(&g));
+        its++;
+        if (!std::isfinite(g)) {
+            status = 3;
+            break;
+        }
+    }
+    if (status == 0 && p->renorm && p->nscal > 1) launch_scalar_renorm(p->sc, p->srho1, p->nscal, N, p->stream);
+    if (status != 0) launch_copy(p->sc, p->sc_n, n, p->stream);
+    p->sc_newton = its;
+    p->sc_gmres = gits;
+    HIPCHK(hipGetLastError());
+    return status;
+}
+
+// a step of the flow and then of the scalars at dt; on failure both are at u^n
+int step_at(jfnk_problem* p, double dt, jfnk_step_stats* st) {
+    int rc = newton(p, dt, st);
+    p->sc_newton = p->sc_gmres = 0;
+    if (rc == 0 && p->nscal > 0) {
+        rc = scalar_step(p, dt);
+        if (rc != 0) launch_copy(p->u, p->un, p->G.nvec, p->stream);
+        if (rc > 0 && st) st->status = rc;
+    }
+    if (st) {
+        st->scalar_newton_its = p->sc_newton;
+        st->scalar_gmres_its = p->sc_gmres;
+    }
+    return rc;
 }
 
 // sums of rho and E (drift report), two-stage device reduction
@@ -977,6 +1134,49 @@ int jfnk_get_state(jfnk_problem* p, double* u, int on_device) {
     return copy_out(p, u, p->u, on_device);
 }
 
+int jfnk_set_scalars(jfnk_problem* p, int nscal, int renormalize, const double* s, int on_device) {
+    if (!p || nscal < 0 || (nscal > 0 && !s)) return fail(-1, "bad scalar arguments");
+    if (p->slab) return fail(-4, "passive scalars need their own device memory (not a caller-provided range)");
+    HIPCHK(hipStreamSynchronize(p->stream));
+    for (void* q : p->sbuf.ptrs) (void)hipFree(q);
+    p->sbuf.ptrs.clear();
+    p->sbuf.bytes = 0;
+    p->nscal = 0;
+    if (nscal == 0) return 0;
+    const long N = p->G.N, n = (long)nscal * N;
+    const int m = p->opts.gmres_restart;
+    auto al = [&](double** out, size_t count) {
+        void* q = nullptr;
+        if (hipMalloc(&q, count * sizeof(double)) != hipSuccess) return fail(-2, "hipMalloc (scalars)");
+        p->sbuf.ptrs.push_back(q);
+        p->sbuf.bytes += count * sizeof(double);
+        *out = (double*)q;
+        return 0;
+    };
+    double** vecs[] = {&p->sc, &p->sc_n, &p->sb, &p->sG, &p->sx, &p->srhs, &p->sr, &p->sw, &p->stmp};
+    for (double** v : vecs) CK(al(v, (size_t)n));
+    CK(al(&p->sV, (size_t)(m + 1) * n));
+    CK(al(&p->srho0, (size_t)N));
+    CK(al(&p->srho1, (size_t)N));
+    CK(al(&p->sfr0, (size_t)3 * N));
+    CK(al(&p->sfr1, (size_t)3 * N));
+    HIPCHK(hipMemcpyAsync(p->sc, s, sizeof(double) * n, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->nscal = nscal;
+    p->renorm = renormalize ? 1 : 0;
+    return 0;
+}
+
+int jfnk_get_scalars(jfnk_problem* p, double* s, int on_device) {
+    if (!p || !s) return fail(-1, "null argument");
+    if (p->nscal == 0) return 0;
+    HIPCHK(hipMemcpyAsync(s, p->sc, sizeof(double) * (long)p->nscal * p->G.N,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    return 0;
+}
+
 int jfnk_set_time(jfnk_problem* p, double t) {
     if (!p) return fail(-1, "null problem");
     p->t_now = t;
@@ -1003,7 +1203,7 @@ int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out) {
     double m0, e0;
     int rc = field_sums(p, p->u, &m0, &e0);
     if (rc) return rc;
-    rc = newton(p, dt, &st);
+    rc = step_at(p, dt, &st);
     if (rc < 0) return rc;
     if (rc == 0) {
         p->t_now += dt;
@@ -1035,7 +1235,7 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
     const double hyd = p->hyd, adv = p->adv, rad = p->rad;
     int rej = 0;
     for (;;) {
-        rc = newton(p, dt, &st);
+        rc = step_at(p, dt, &st);
         if (rc < 0) return rc;
         if (rc == 0 || rej >= p->opts.max_halvings) break;
         rej++;

@@ -40,7 +40,8 @@ class StepStats(C.Structure):
                 ("cfl_rad", C.c_double), ("rel_res", C.c_double), ("max_rel_corr", C.c_double),
                 ("mass_drift", C.c_double), ("energy_drift", C.c_double), ("f0", C.c_double),
                 ("f", C.c_double), ("newton_its", C.c_int), ("gmres_its", C.c_int),
-                ("rejections", C.c_int), ("status", C.c_int), ("wall_ms", C.c_double)]
+                ("rejections", C.c_int), ("status", C.c_int), ("wall_ms", C.c_double),
+                ("scalar_newton_its", C.c_int), ("scalar_gmres_its", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -65,7 +66,8 @@ class RequestStats(C.Structure):
 
 
 EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "jfnk_destroy_problem",
-           "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_implicit_step",
+           "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_set_scalars",
+           "jfnk_get_scalars", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
            "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
            "jfnk_profile_enable", "jfnk_profile_sample", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
@@ -100,6 +102,8 @@ def load():
         "jfnk_set_state": (ip, [vp, vp, ip]),
         "jfnk_get_state": (ip, [vp, vp, ip]),
         "jfnk_set_time": (ip, [vp, C.c_double]),
+        "jfnk_set_scalars": (ip, [vp, ip, ip, vp, ip]),
+        "jfnk_get_scalars": (ip, [vp, vp, ip]),
         "jfnk_set_opts": (ip, [vp, P(SolverOpts)]),
         "jfnk_implicit_step": (ip, [vp, P(StepStats)]),
         "jfnk_newton_solve": (ip, [vp, C.c_double, P(StepStats)]),
@@ -243,6 +247,21 @@ class Problem:
         p, d, keep = _ptr(out)
         self._check_size(keep)
         _check(_lib.jfnk_get_state(self._h, p, d))
+        return out
+
+    def set_scalars(self, s, nscal, renormalize=True):
+        """attach nscal passive scalars (partial densities c_k rho, nscal * N values)"""
+        p, d, keep = _ptr(s)
+        size = keep.size if isinstance(keep, np.ndarray) else keep.numel()
+        if size != nscal * self.N:
+            raise ValueError("expected %d values, got %d" % (nscal * self.N, size))
+        _check(_lib.jfnk_set_scalars(self._h, int(nscal), 1 if renormalize else 0, p, d))
+        self.nscal = int(nscal)
+
+    def get_scalars(self, out=None):
+        out = np.empty(self.nscal * self.N) if out is None else out
+        p, d, keep = _ptr(out)
+        _check(_lib.jfnk_get_scalars(self._h, p, d))
         return out
 
     def set_time(self, t):

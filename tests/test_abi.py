@@ -32,7 +32,7 @@ def test_struct_layouts_match_header_sizes():
     from paper_1610_10053_amd import jfnk
     assert C.sizeof(jfnk.ProblemDesc) == 128
     assert C.sizeof(jfnk.SolverOpts) == 120
-    assert C.sizeof(jfnk.StepStats) == 112
+    assert C.sizeof(jfnk.StepStats) == 120
     assert C.sizeof(jfnk.RequestStats) == 72
     assert C.sizeof(jfnk.Diagnostics) == 40
 
