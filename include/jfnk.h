@@ -180,9 +180,13 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
  * mix_width: mixing-region width of eqs. (12)-(14) along grid axis mix_axis,
  *   X_H = (rho - rho_light)/(rho_heavy - rho_light), mean per layer normal to
  *   the axis, X_M = 2 min(<X_H>, 1 - <X_H>), summed over layers times the
- *   layer thickness; 0 when mix_axis < 0. */
+ *   layer thickness; 0 when mix_axis < 0;
+ * mix_width_scalars: the same width from the first two passive scalars,
+ *   eq. (16): X_M = 2 min(<c1>, <c2>) of the layer means of c_k = s_k / rho
+ *   (0 unless the problem's own state is evaluated, it carries two or more
+ *   scalars and mix_axis >= 0). */
 typedef struct {
-    double kinetic, mass, energy, max_mach, mix_width;
+    double kinetic, mass, energy, max_mach, mix_width, mix_width_scalars;
 } jfnk_diagnostics;
 
 /* u: a state in the layout above (host or device per on_device), or NULL for

@@ -13,7 +13,9 @@ Definitions, written out from the paper:
   - mixing-region width, eqs. (12)-(14): X_H = (rho - rho_L)/(rho_H - rho_L)
     per cell, <X_H> its mean over each layer normal to the vertical axis,
     X_M = 2<X_H> if <X_H> <= 1/2 else 2(1 - <X_H>), and h = sum over layers
-    of X_M dy (the integral of eq. 14 as a midpoint sum over the layers).
+    of X_M dy (the integral of eq. 14 as a midpoint sum over the layers);
+  - the same width from two passive scalars, eq. (16): X_M = 2 min(<c1>, <c2>)
+    of the layer means of the concentrations c_k = s_k / rho.
 """
 import numpy as np
 
@@ -99,5 +101,19 @@ def mixing_width(u, desc, rho_light, rho_heavy, axis):
     other = tuple(a for a in range(3) if a != ax)
     mean = xh.mean(axis=other)
     xm = np.where(mean <= 0.5, 2.0 * mean, 2.0 * (1.0 - mean))
+    dy = (desc["hi"][axis] - desc["lo"][axis]) / desc["n"][axis]
+    return float(np.sum(xm) * dy)
+
+
+def mixing_width_scalars(u, s, desc, axis):
+    """eq. (16) with eq. (14): layer means of c1 = s1/rho and c2 = s2/rho"""
+    rho, E, m = _fields(u, desc)
+    nx, ny, nz = desc["n"]
+    N = nx * ny * nz
+    c1 = s[:N].reshape(nz, ny, nx) / rho
+    c2 = s[N:2 * N].reshape(nz, ny, nx) / rho
+    ax = _axis(axis)
+    other = tuple(a for a in range(3) if a != ax)
+    xm = 2.0 * np.minimum(c1.mean(axis=other), c2.mean(axis=other))
     dy = (desc["hi"][axis] - desc["lo"][axis]) / desc["n"][axis]
     return float(np.sum(xm) * dy)

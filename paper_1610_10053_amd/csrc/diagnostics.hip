@@ -68,8 +68,35 @@ __global__ void __launch_bounds__(kBlock) k_diag_layers(Grid G, Prim P, int axis
     }
 }
 
+// one workgroup per layer normal to `axis`: 2 min(<c1>, <c2>) of the layer
+// means of the concentrations of two passive scalars
+__global__ void __launch_bounds__(kBlock) k_diag_layers_scalars(Grid G, Prim P, const double* __restrict__ s,
+                                                                int axis, double* __restrict__ xm) {
+    const int j = (int)blockIdx.x;
+    const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+    const long n1 = G.n[a1], n2 = G.n[a2], nl = n1 * n2;
+    double s1 = 0.0, s2 = 0.0;
+    for (long e = threadIdx.x; e < nl; e += blockDim.x) {
+        int v[3];
+        v[axis] = j;
+        v[a1] = (int)(e % n1);
+        v[a2] = (int)(e / n1);
+        const long c = flat(G, v[0], v[1], v[2]);
+        s1 += s[c] / P.rho[c];
+        s2 += s[G.N + c] / P.rho[c];
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t1 = block_sum(s1, sh);
+    __syncthreads();
+    const double t2 = block_sum(s2, sh);
+    if (threadIdx.x == 0) {
+        const double m1 = t1 / (double)nl, m2 = t2 / (double)nl;
+        xm[j] = 2.0 * (m1 < m2 ? m1 : m2);
+    }
+}
+
 int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,
-                       double* part, double* out5, hipStream_t stream) {
+                       const double* scal, double* part, double* out5, hipStream_t stream) {
     const int nb = cell_blocks(G.n);
     {
         JFNK_PROF(KC_OTHER, stream);
@@ -84,6 +111,13 @@ int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, 
             JFNK_KLAUNCH(k_diag_layers, dim3(G.n[axis]), dim3(kBlock), 0, stream, G, P, axis, rho_l, rho_h, xm);
         }
         launch_final_sum(xm, G.n[axis], 1, out5 + 4, stream);
+        if (scal) {
+            {
+                JFNK_PROF(KC_OTHER, stream);
+                JFNK_KLAUNCH(k_diag_layers_scalars, dim3(G.n[axis]), dim3(kBlock), 0, stream, G, P, scal, axis, xm);
+            }
+            launch_final_sum(xm, G.n[axis], 1, out5 + 5, stream);
+        }
     }
     return 0;
 }

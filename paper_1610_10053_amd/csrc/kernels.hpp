@@ -91,9 +91,11 @@ void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Fl
 
 // diagnostics of the state whose primitives P hold: out5 = sum kin, sum rho,
 // sum E (per unit volume), max Mach, sum of the layers' X_M along axis (or
-// untouched when axis < 0); part needs 4 cell_blocks + n[axis] doubles
+// untouched when axis < 0), and with two passive scalars scal (or null) the
+// sum of their layers' 2 min(<c1>, <c2>); part needs 4 cell_blocks + n[axis]
+// doubles
 int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,
-                       double* part, double* out5, hipStream_t stream);
+                       const double* scal, double* part, double* out5, hipStream_t stream);
 
 // krylov.hip: deterministic two-stage reductions and Krylov vector kernels
 // partial layout: part[col * nblk + block]

@@ -1322,10 +1322,11 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
         src = p->s1;
     }
     launch_prim(G, view(p, src, nullptr), p->P, p->stream);
-    launch_diagnostics(G, p->P, src, mix_axis, rho_light, rho_heavy, p->part, p->dsum + D_TMP, p->stream);
+    const double* scal = (!u && p->nscal >= 2) ? p->sc : nullptr;  // the scalars belong to the problem's state
+    launch_diagnostics(G, p->P, src, mix_axis, rho_light, rho_heavy, scal, p->part, p->dsum + D_TMP, p->stream);
     HIPCHK(hipGetLastError());
-    double m[5] = {0, 0, 0, 0, 0};
-    CK(read_scalars(p, D_TMP, mix_axis >= 0 ? 5 : 4, m));
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    CK(read_scalars(p, D_TMP, mix_axis < 0 ? 4 : (scal ? 6 : 5), m));
     double dv = 1.0;
     for (int d = 0; d < G.ndim; ++d) dv *= G.dx[d];
     out->kinetic = m[0] * dv;
@@ -1333,6 +1334,7 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
     out->energy = m[2] * dv;
     out->max_mach = m[3];
     out->mix_width = mix_axis >= 0 ? m[4] * G.dx[mix_axis] : 0.0;
+    out->mix_width_scalars = (mix_axis >= 0 && scal) ? m[5] * G.dx[mix_axis] : 0.0;
     return 0;
 }
 

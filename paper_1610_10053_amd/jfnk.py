@@ -49,7 +49,7 @@ class StepStats(C.Structure):
 
 class Diagnostics(C.Structure):
     _fields_ = [("kinetic", C.c_double), ("mass", C.c_double), ("energy", C.c_double), ("max_mach", C.c_double),
-                ("mix_width", C.c_double)]
+                ("mix_width", C.c_double), ("mix_width_scalars", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

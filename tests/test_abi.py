@@ -34,7 +34,7 @@ def test_struct_layouts_match_header_sizes():
     assert C.sizeof(jfnk.SolverOpts) == 120
     assert C.sizeof(jfnk.StepStats) == 120
     assert C.sizeof(jfnk.RequestStats) == 72
-    assert C.sizeof(jfnk.Diagnostics) == 40
+    assert C.sizeof(jfnk.Diagnostics) == 48
 
 
 def test_default_opts_and_footprint_are_host_only():

@@ -95,6 +95,18 @@ def test_mixing_width_averages_each_layer_before_mixing():
     assert dg.mixing_width(u, desc, 1.0, 2.0, 1) == pytest.approx(1.0, rel=1e-14)
 
 
+def test_scalar_mixing_width_limits():
+    desc = desc2d(8, 16, bc=(BC_PERIODIC, BC_WALL), L=(1.0, 2.0))
+    N = 8 * 16
+    rho = np.linspace(1.0, 2.0, N)
+    u = np.concatenate([rho, np.full(N, 3.0), np.zeros(2 * N)])
+    below = (np.arange(N) // 8 < 8).astype(float)
+    sharp = np.concatenate([below * rho, (1.0 - below) * rho])
+    assert dg.mixing_width_scalars(u, sharp, desc, 1) == 0.0
+    mixed = np.concatenate([0.5 * rho, 0.5 * rho])
+    assert dg.mixing_width_scalars(u, mixed, desc, 1) == pytest.approx(2.0, rel=1e-14)
+
+
 # ---------------------------------------------------------------- GPU against the oracle
 @pytest.mark.gpu
 @pytest.mark.parametrize("name,n,steps,axis", [("rt", None, 5, 1), ("kh", 64, 3, 1), ("tg", 32, 2, -1),

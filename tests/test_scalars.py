@@ -127,3 +127,8 @@ def test_gpu_scalars_match_oracle(name, n, steps, renorm):
         assert plain.implicit_step()[0] == 0
     # the scalars do not touch the flow: bit for bit the run without them
     assert np.array_equal(g.get_state(), plain.get_state())
+    # mixing width from the scalars, eq. (16), against the oracle's definition
+    from oracle import diagnostics as dg
+    d = g.eval_diagnostics(None, 1.0, 2.0, 1)
+    ref = dg.mixing_width_scalars(g.get_state(), g.get_scalars(), desc, 1)
+    assert d["mix_width_scalars"] == pytest.approx(ref, rel=1e-12, abs=1e-15)
