@@ -143,7 +143,19 @@ struct LevelT {
     R* b;
     R* x2;         // second iterate buffer (coarsest level only, else null)
     int unit_sig;  // sig == 1 on every cell (acoustic operator): D is formed from the couplings
+    // x, b and x2 of a multi-block level are stored split by colour: the cells
+    // of colour (i+j+k)&1 together, x-pairs merged (H entries per colour,
+    // hn0 per row), so that a half-sweep reads and writes them contiguously
+    int split, hn0, H;
 };
+// index of cell (i, j, k) in a level's x, b and x2 arrays (levels hold fewer
+// than 2^30 cells)
+template <typename R>
+__device__ __forceinline__ int xbi(const LevelT<R>& L, int i, int j, int k) {
+    const int row = j + L.n[1] * k;
+    if (!L.split) return i + L.n[0] * row;
+    return ((i + j + k) & 1) * L.H + (i >> 1) + L.hn0 * row;
+}
 template <typename R>
 struct LevelSet {
     LevelT<R> L[kMaxLevels];
@@ -173,20 +185,23 @@ void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nle
 
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>
-void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc, R* rp,
-                   hipStream_t stream);
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc,
+                   const LevelT<R>& L0, hipStream_t stream);
 // conduction block: rE = S_E v_E + tau D(chi_f G s)
 template <typename R>
-void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const R* s, Scales5 sc, double* rE,
-                         hipStream_t stream);
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const LevelT<R>& L0, Scales5 sc,
+                         double* rE, hipStream_t stream);
 // dm = r_m - tau G dp, drho = r_rho - tau D dm, dE = r_E - tau D(h_f dm),
 // z = S^-1 delta and per-block |z|^2
 template <typename R>
-void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp, Scales5 sc,
-                    double* z, double* part, int nblk, hipStream_t stream);
+void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp,
+                    const LevelT<R>& L0, Scales5 sc, double* z, double* part, int nblk, hipStream_t stream);
 // out = s * v[off : off + N] in precision R
 template <typename R>
 void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream);
+// L0.b = s * v (a cell field) in precision R, in the level's x/b order
+template <typename R>
+void launch_field_to_level(const Grid& G, const double* v, double s, const LevelT<R>& L0, hipStream_t stream);
 // z = v and per-block |z|^2 (no preconditioner)
 void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream);
 // eps of the Jacobian-free product from sum (S^-1 u)^2 and sum v^2

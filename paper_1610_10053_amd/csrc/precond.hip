@@ -65,16 +65,28 @@ template <typename R>
 __device__ __forceinline__ int lflat(const LevelT<R>& L, int i, int j, int k) {
     return i + L.n[0] * (j + L.n[1] * k);
 }
-// neighbour along d on a level: periodic wrap, -1 beyond a wall
+// coordinates of the neighbour along d on a level: periodic wrap, false
+// beyond a wall
 template <typename R>
-__device__ __forceinline__ int lnb(const Grid& G, const LevelT<R>& L, LIjk q, int d, int s) {
+__device__ __forceinline__ bool lnbq(const Grid& G, const LevelT<R>& L, LIjk& q, int d, int s) {
     int a = q.v[d] + s;
     if (a < 0 || a >= L.n[d]) {
-        if (G.bc[d] == WALL) return -1;
+        if (G.bc[d] == WALL) return false;
         a = a < 0 ? a + L.n[d] : a - L.n[d];
     }
     q.v[d] = a;
+    return true;
+}
+// neighbour along d on a level (coefficient index): -1 beyond a wall
+template <typename R>
+__device__ __forceinline__ int lnb(const Grid& G, const LevelT<R>& L, LIjk q, int d, int s) {
+    if (!lnbq(G, L, q, d, s)) return -1;
     return lflat(L, q.v[0], q.v[1], q.v[2]);
+}
+// index of a cell in the level's x, b and x2 arrays
+template <typename R>
+__device__ __forceinline__ int xbq(const LevelT<R>& L, const LIjk& q) {
+    return xbi(L, q.v[0], q.v[1], q.v[2]);
 }
 // cell of a 3D launch over a level
 template <typename R>
@@ -176,20 +188,22 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 
 // ---------------------------------------------------------------- multigrid cell operations
 // x and b are read and written through pointers so that the single-workgroup
-// coarse solver can keep them in LDS.
+// coarse solver can keep them in LDS.  c is the cell's index in the
+// coefficient arrays (natural order); x and b are indexed by xbq.
 
 // Gauss-Seidel value of one cell from its neighbours in x (first: neighbours
 // taken as 0)
 template <typename R, int ND>
 __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c,
                                       bool first) {
-    R num = b[c];
+    R num = b[xbq(L, q)];
     R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
-        const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
-        const R alo = L.a[d][c], ahi = up >= 0 ? L.a[d][up] : (R)0.0;
-        if (dn >= 0) num = num + alo * (first ? (R)0.0 : x[dn]);
-        if (up >= 0) num = num + ahi * (first ? (R)0.0 : x[up]);
+        LIjk qu = q, qd = q;
+        const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
+        const R alo = L.a[d][c], ahi = hu ? L.a[d][lflat(L, qu.v[0], qu.v[1], qu.v[2])] : (R)0.0;
+        if (hd) num = num + alo * (first ? (R)0.0 : x[xbq(L, qd)]);
+        if (hu) num = num + ahi * (first ? (R)0.0 : x[xbq(L, qu)]);
         den = den + alo;
         den = den + ahi;
     }
@@ -200,7 +214,7 @@ __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R
 template <typename R, int ND>
 __device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
                                         bool first) {
-    x[c] = gs_value<R, ND>(G, L, b, x, q, c, first);
+    x[xbq(L, q)] = gs_value<R, ND>(G, L, b, x, q, c, first);
 }
 // a periodic axis of odd length (possible on the coarsest level only): the
 // two cells facing each other across the wrap share a colour, so a colour's
@@ -217,14 +231,15 @@ __device__ __forceinline__ bool odd_periodic(const Grid& G, const LevelT<R>& L) 
 template <typename R, int ND>
 __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
                                         int c) {
-    const R xc = x[c];
+    const R xc = x[xbq(L, q)];
     R acc = L.unit_sig ? xc : L.sig[c] * xc;
     for (int d = 0; d < ND; ++d) {
-        const int up = lnb(G, L, q, d, 1), dn = lnb(G, L, q, d, -1);
-        if (dn >= 0) acc = acc + L.a[d][c] * (xc - x[dn]);
-        if (up >= 0) acc = acc + L.a[d][up] * (xc - x[up]);
+        LIjk qu = q, qd = q;
+        const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
+        if (hd) acc = acc + L.a[d][c] * (xc - x[xbq(L, qd)]);
+        if (hu) acc = acc + L.a[d][lflat(L, qu.v[0], qu.v[1], qu.v[2])] * (xc - x[xbq(L, qu)]);
     }
-    return b[c] - acc;
+    return b[xbq(L, q)] - acc;
 }
 
 // coarse right-hand side: mean of the children's residuals
@@ -267,7 +282,7 @@ __device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, co
                 w = w * (R)0.75;
             }
         }
-        e = e + w * cx[lflat(Cl, qq[0], qq[1], qq[2])];
+        e = e + w * cx[xbi(Cl, qq[0], qq[1], qq[2])];
     }
     return e;
 }
@@ -288,11 +303,12 @@ __global__ void __launch_bounds__(kBlock) k_gs_pp(Grid G, LevelT<R> L, int color
     LIjk q;
     int c;
     if (!lcell(L, q, c)) return;
+    const int e = xbq(L, q);
     if (((q.v[0] + q.v[1] + q.v[2]) & 1) != color) {
-        xout[c] = first ? (R)0.0 : xin[c];
+        xout[e] = first ? (R)0.0 : xin[e];
         return;
     }
-    xout[c] = gs_value<R, ND>(G, L, L.b, xin, q, c, first != 0);
+    xout[e] = gs_value<R, ND>(G, L, L.b, xin, q, c, first != 0);
 }
 // Restriction of a multi-block level: one thread per fine cell computes its
 // residual, and the 2^ND children of each coarse cell (all in one workgroup)
@@ -335,14 +351,20 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT
     for (int dk = 0; dk < BZ; ++dk)
         for (int dj = 0; dj < 2; ++dj)
             for (int di = 0; di < 2; ++di) s = s + rs[dk][2 * cj + dj][2 * ci + di];
-    Cl.b[lflat(Cl, q.v[0], q.v[1], q.v[2])] = s * inv_ch;
+    Cl.b[xbq(Cl, q)] = s * inv_ch;
 }
+// Prolongation of the coarse correction onto the cells of one colour (color
+// 0 or 1), or onto every cell (color < 0).  When post-smoothing follows, only
+// colour 1 needs it: the colour-0 half-sweep that comes next overwrites every
+// colour-0 value without reading it, so the result is the same as correcting
+// every cell.
 template <typename R, int ND>
-__global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
+__global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<R> Cl, int color) {
     LIjk q;
     int c;
-    if (!lcell(F, q, c)) return;
-    F.x[c] = F.x[c] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
+    if (color < 0 ? !lcell(F, q, c) : !lcell_color(F, color, q, c)) return;
+    const int e = xbq(F, q);
+    F.x[e] = F.x[e] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
 }
 
 // The rest of the V-cycle, levels from..nlev-1 (at most kCoarseLdsCells cells
@@ -544,8 +566,11 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     }
     vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
     {
-        JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) * 2 + (double)S.L[l + 1].N * sizeof(R));
-        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1]);
+        const bool half = nu2 > 0;
+        JFNK_PROFB(KC_MG_PROLONG, stream,
+                   (double)L.N * sizeof(R) * (half ? 1 : 2) + (double)S.L[l + 1].N * sizeof(R));
+        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, half ? cg : cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1],
+                        half ? 1 : -1);
     }
     for (int s = 0; s < nu2; ++s) {
         {
@@ -566,9 +591,20 @@ void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nle
 }
 
 // ---------------------------------------------------------------- right-hand sides and back-substitution
+// x/b index on the finest level of the cell one step along d from q (periodic
+// wrap; the caller excludes steps through a wall)
+template <typename R>
+__device__ __forceinline__ int xb_shifted(const LevelT<R>& L, const Ijk& q, int d, int s) {
+    int v[3] = {q.v[0], q.v[1], q.v[2]};
+    int a = v[d] + s;
+    if (a < 0) a += L.n[d];
+    else if (a >= L.n[d]) a -= L.n[d];
+    v[d] = a;
+    return xbi(L, v[0], v[1], v[2]);
+}
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
-                                                   const double* __restrict__ rE, Scales5 sc, R* __restrict__ rp) {
+                                                   const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
@@ -585,30 +621,27 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
         }
         acc = acc + (fhi - flo) * G.idx[d];
     }
-    rp[c] = (R)(G.gm1 * (re - C.tau * acc));
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)(G.gm1 * (re - C.tau * acc));
 }
 
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const double* __restrict__ v,
-                                                         const R* __restrict__ s, Scales5 sc,
-                                                         double* __restrict__ rE) {
+                                                         LevelT<R> L0, Scales5 sc, double* __restrict__ rE) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
+    const R* __restrict__ s = L0.x;
     double acc = sc.v[1] * v[G.N + c];
-    const double sc0 = (double)s[c];
+    const double sc0 = (double)s[xbi(L0, q.v[0], q.v[1], q.v[2])];
     for (int d = 0; d < ND; ++d) {
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
         const bool bot = G.bc[d] == WALL && q.v[d] == 0;
         double thi = 0.0, tlo = 0.0;
         if (!top) {
             const long up = shifted(G, q, d, 1);
-            thi = C.beta[d][up] * ((double)s[up] - sc0);
+            thi = C.beta[d][up] * ((double)s[xb_shifted(L0, q, d, 1)] - sc0);
         }
-        if (!bot) {
-            const long dn = shifted(G, q, d, -1);
-            tlo = C.beta[d][c] * (sc0 - (double)s[dn]);
-        }
+        if (!bot) tlo = C.beta[d][c] * (sc0 - (double)s[xb_shifted(L0, q, d, -1)]);
         acc = acc + (thi - tlo);
     }
     rE[c] = acc;
@@ -617,13 +650,14 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                     const double* __restrict__ rE, const R* __restrict__ dp,
-                                                    Scales5 sc, double* __restrict__ z, double* __restrict__ part) {
+                                                    LevelT<R> L0, Scales5 sc, double* __restrict__ z,
+                                                    double* __restrict__ part) {
     Ijk q;
     long c = 0;
     double ss = 0.0;
     if (cell_from_launch(G, q, c)) {
         const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
-        const double dpc = (double)dp[c];
+        const double dpc = (double)dp[xbi(L0, q.v[0], q.v[1], q.v[2])];
         double dmlo[3], dmhi[3];
         bool top[3];
         long upi[3];
@@ -633,8 +667,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             if (G.bc[d] == WALL && q.v[d] == 0) {
                 dmlo[d] = 0.0;
             } else {
-                const long lo = shifted(G, q, d, -1);
-                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[lo]) * G.idx[d]);
+                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * G.idx[d]);
             }
             top[d] = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             dmhi[d] = 0.0;
@@ -642,7 +675,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             if (!top[d]) {
                 const long up = shifted(G, q, d, 1);
                 upi[d] = up;
-                dmhi[d] = s * vm[up] - C.tau * (((double)dp[up] - dpc) * G.idx[d]);
+                dmhi[d] = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * G.idx[d]);
             }
         }
         double acc = 0.0;
@@ -679,6 +712,15 @@ __global__ void __launch_bounds__(kBlock) k_field_scaled(const double* __restric
     if (c < N) out[c] = (R)(s * v[c]);
 }
 
+template <typename R, int ND>
+__global__ void __launch_bounds__(kBlock) k_field_to_level(Grid G, const double* __restrict__ v, double s,
+                                                           LevelT<R> L0) {
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)(s * v[c]);
+}
+
 __global__ void __launch_bounds__(kBlock) k_copy_sumsq(const double* __restrict__ v, double* __restrict__ z,
                                                        long n, double* __restrict__ part) {
     double ss = 0.0;
@@ -707,29 +749,29 @@ __global__ void __launch_bounds__(kFinalThreads) k_jv_eps(const double* __restri
 }
 
 template <typename R>
-void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc, R* rp,
-                   hipStream_t stream) {
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc,
+                   const LevelT<R>& L0, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (1 + 2 * G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        JFNK_LAUNCH_RND(G.ndim, k_pc_rhs, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, rp);
+        JFNK_LAUNCH_RND(G.ndim, k_pc_rhs, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, L0);
     }
 }
 template <typename R>
-void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const R* s, Scales5 sc, double* rE,
-                         hipStream_t stream) {
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const LevelT<R>& L0, Scales5 sc,
+                         double* rE, hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
-        JFNK_LAUNCH_RND(G.ndim, k_pc_diff_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, s, sc, rE);
+        JFNK_LAUNCH_RND(G.ndim, k_pc_diff_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, L0, sc, rE);
     }
 }
 template <typename R>
-void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp, Scales5 sc,
-                    double* z, double* part, int nblk, hipStream_t stream) {
+void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp,
+                    const LevelT<R>& L0, Scales5 sc, double* z, double* part, int nblk, hipStream_t stream) {
     (void)nblk;
     {
         JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        JFNK_LAUNCH_RND(G.ndim, k_pc_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, sc, z,
-                           part);
+        JFNK_LAUNCH_RND(G.ndim, k_pc_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, L0, sc,
+                        z, part);
     }
 }
 template <typename R>
@@ -737,6 +779,13 @@ void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t 
     {
         JFNK_PROF(KC_PC_RHS, stream);
         JFNK_KLAUNCH((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
+    }
+}
+template <typename R>
+void launch_field_to_level(const Grid& G, const double* v, double s, const LevelT<R>& L0, hipStream_t stream) {
+    {
+        JFNK_PROF(KC_PC_RHS, stream);
+        JFNK_LAUNCH_RND(G.ndim, k_field_to_level, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, v, s, L0);
     }
 }
 void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream) {
@@ -866,13 +915,14 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
     template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, const LevelT<R>*, int, int, int, int, int,     \
                                bool, hipStream_t);                                                           \
-    template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5, R*,    \
-                                   hipStream_t);                                                             \
-    template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const R*, Scales5,       \
-                                         double*, hipStream_t);                                              \
+    template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5,        \
+                                   const LevelT<R>&, hipStream_t);                                           \
+    template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const LevelT<R>&,        \
+                                         Scales5, double*, hipStream_t);                                     \
     template void launch_pc_back<R>(const Grid&, const PcCoef&, const double*, const double*, const R*,      \
-                                    Scales5, double*, double*, int, hipStream_t);                            \
+                                    const LevelT<R>&, Scales5, double*, double*, int, hipStream_t);          \
     template void launch_field_scaled<R>(const double*, double, R*, long, hipStream_t);                      \
+    template void launch_field_to_level<R>(const Grid&, const double*, double, const LevelT<R>&, hipStream_t); \
     template void launch_line_solve<R>(const Grid&, const PcCoef&, int, int, R*, double*, hipStream_t);
 INST(double)
 INST(float)

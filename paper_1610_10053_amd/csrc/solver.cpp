@@ -206,26 +206,40 @@ int count_levels(const Grid& G, int n_out[][3]) {
 constexpr long kCoarseCells = 512;  // levels at or below this size run in one workgroup from LDS
                                      // (kCoarseMaxLevelCells of the coarse kernel)
 
-size_t level_bytes(long N, size_t rsize) { return (size_t)N * rsize * 7; }
+// entries of a level's x, b and x2 arrays: room for the colour-split order
+// (x-pairs merged, one slot per colour), which holds every natural index too
+long level_xb_len(const int n[3]) { return 2L * ((n[0] + 1) / 2) * n[1] * n[2]; }
+// a level's arrays: sig, a[0..2], D (N each), x and b (and x2 on the coarsest)
+constexpr int kLevelCoefArrays = 5;
+size_t level_bytes(const int n[3], bool coarsest, size_t rsize) {
+    const long N = (long)n[0] * n[1] * n[2];
+    return ((size_t)kLevelCoefArrays * N + (size_t)(coarsest ? 3 : 2) * level_xb_len(n)) * rsize;
+}
 
+// split: store x, b and x2 of the multi-block levels in colour-split order
 template <typename R>
-int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3], bool unit_sig) {
+int alloc_levels(jfnk_problem* p, LevelSet<R>& S, LevelT<R>** dS, int nl[][3], bool unit_sig, bool split) {
     for (int l = 0; l < p->nlev; ++l) {
         LevelT<R>& L = S.L[l];
         L.unit_sig = unit_sig ? 1 : 0;
         for (int a = 0; a < 3; ++a) L.n[a] = nl[l][a];
         L.N = (long)L.n[0] * L.n[1] * L.n[2];
+        // the single-workgroup coarse kernel takes its levels in natural order
+        L.split = split && l < p->coarse_from ? 1 : 0;
+        L.hn0 = (L.n[0] + 1) / 2;
+        L.H = L.hn0 * L.n[1] * L.n[2];
         const bool coarsest = l == p->nlev - 1;
+        const long xb = level_xb_len(L.n);
         R* blk = nullptr;
-        CK(dalloc(p, &blk, (size_t)L.N * (coarsest ? 8 : 7)));
+        CK(dalloc(p, &blk, level_bytes(L.n, coarsest, sizeof(R)) / sizeof(R)));
         L.sig = blk;
         L.a[0] = blk + L.N;
         L.a[1] = blk + 2 * L.N;
         L.a[2] = blk + 3 * L.N;
         L.D = blk + 4 * L.N;
-        L.x = blk + 5 * L.N;
-        L.b = blk + 6 * L.N;
-        L.x2 = coarsest ? blk + 7 * L.N : nullptr;
+        L.x = blk + kLevelCoefArrays * L.N;
+        L.b = L.x + xb;
+        L.x2 = coarsest ? L.b + xb : nullptr;
     }
     CK(dalloc(p, dS, (size_t)kMaxLevels));
     HIPCHK(hipMemcpyAsync(*dS, S.L, sizeof(LevelT<R>) * kMaxLevels, hipMemcpyHostToDevice, p->stream));
@@ -390,9 +404,9 @@ void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
     if (p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION) {
         if (mg) {
             LevelSet<R>& S = levels<R>(p, 1);
-            launch_field_scaled<R>(v + G.N, sc.v[1], S.L[0].b, G.N, p->stream);
+            launch_field_to_level<R>(G, v + G.N, sc.v[1], S.L[0], p->stream);
             mg_solve<R>(p, 1);
-            launch_pc_diff_back<R>(G, p->C, v, S.L[0].x, sc, p->rEd, p->stream);
+            launch_pc_diff_back<R>(G, p->C, v, S.L[0], sc, p->rEd, p->stream);
         } else {
             launch_field_scaled<double>(v + G.N, sc.v[1], p->rEd, G.N, p->stream);
             for (int d = 0; d < G.ndim; ++d) launch_line_solve<double>(G, p->C, d, 1, p->rEd, p->lines, p->stream);
@@ -400,7 +414,7 @@ void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
         rE = p->rEd;
     }
     LevelSet<R>& A = levels<R>(p, 0);
-    launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0].b, p->stream);
+    launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0], p->stream);
     const R* dp;
     if (mg) {
         mg_solve<R>(p, 0);
@@ -409,7 +423,7 @@ void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
         for (int d = 0; d < G.ndim; ++d) launch_line_solve<R>(G, p->C, d, 0, A.L[0].b, p->lines, p->stream);
         dp = A.L[0].b;
     }
-    launch_pc_back<R>(G, p->C, v, rE, dp, sc, z, p->part, p->ncell_blk, p->stream);
+    launch_pc_back<R>(G, p->C, v, rE, dp, A.L[0], sc, z, p->part, p->ncell_blk, p->stream);
 }
 
 void pc_apply(jfnk_problem* p, const double* v, double* z) {
@@ -910,8 +924,7 @@ size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]
     if (G.heat_balance) b += N * 8;                                               // heat-balance source
     b += 10 * N * 8 + N * 8 + 4 * N * 8;                                          // pc coefficients, rE, lines
     const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
-    for (int l = 0; l < nlev; ++l) b += 2 * level_bytes((long)nl[l][0] * nl[l][1] * nl[l][2], rs);
-    b += 2 * (size_t)nl[nlev - 1][0] * nl[nlev - 1][1] * nl[nlev - 1][2] * rs;  // coarsest second iterate
+    for (int l = 0; l < nlev; ++l) b += 2 * level_bytes(nl[l], l == nlev - 1, rs);  // two operators
     b += 2 * kMaxLevels * (o.prec == JFNK_MIXED ? sizeof(LevelT<float>) : sizeof(LevelT<double>));
     const size_t npart = (size_t)std::max(cell_blocks(G.n), kRedBlocks) * (kMaxRestart + 2);
     b += npart * 8 + kDsum * 8;
@@ -1082,12 +1095,13 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     p->C.W = pcb + 9 * N;
     AL(p->rEd, N);
     AL(p->lines, (size_t)4 * N);
+    const bool split = opts->pc_solver == JFNK_PCS_MULTIGRID;
     if (opts->prec == JFNK_MIXED) {
-        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl, true))) return cleanup(rc);
-        if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl, false))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl, true, split))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl, false, split))) return cleanup(rc);
     } else {
-        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, true))) return cleanup(rc);
-        if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl, false))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, true, split))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl, false, split))) return cleanup(rc);
     }
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
