@@ -9,9 +9,12 @@
  * the GPU path.
  *
  * Passages followed:
- *   - governing equations: section 2, eqs. (1)-(3), discretised in the
- *     total-energy conservative form (a reading: eq. 2 is written for internal
- *     energy, but the conservation checks need a flux form for E);
+ *   - governing equations: section 2, eqs. (1)-(3), discretised by default in
+ *     the total-energy conservative form (a reading: eq. 2 is written for
+ *     internal energy, but the conservation checks need a flux form for E),
+ *     or, as an option, with the energy variable rho e of eq. (2) as written:
+ *     advective flux of rho e, the -p div u term at cell centres, no
+ *     gravitational work;
  *   - ideal-gas closure and conductivity: section 2 (eq. 4 replaced by the
  *     synthetic chi = chi0 T^3);
  *   - staggered grid, upstream linear reconstruction with the van Leer
@@ -51,6 +54,7 @@ typedef struct {
 typedef struct {
     /* problem */
     int ndim, n[3], bc[3], heat_balance;
+    int internal; /* energy variable rho e (eq. 2) instead of total energy E */
     double lo[3], hi[3], dx[3], idx[3], gamma, g[3], chi0;
     /* solver */
     double rtol, atol, eta, cfl_hydro, cfl_adv_max, cfl_rad_max, dt_max;
@@ -160,9 +164,10 @@ static double upstream(double vel, double ql, double sl, double qr, double sr) {
 
 static double *field(const Or *o, const double *u, int f) { return (double *)u + (long)f * o->N; }
 
-/* Velocities on faces, pressure, specific total energy, temperature,
- * conductivity, with ghosts.  Section 2: scalars at cell centres, velocity
- * components on faces; ideal gas p = (gamma-1) rho e, with p = rho T. */
+/* Velocities on faces, pressure, specific energy of the energy variable
+ * (total E/rho, or internal e), temperature, conductivity, with ghosts.
+ * Section 2: scalars at cell centres, velocity components on faces; ideal gas
+ * p = (gamma-1) rho e, with p = rho T. */
 static void primitives(Or *o, const double *u) {
     const double *rho_c = field(o, u, 0), *E_c = field(o, u, 1);
     fill_nan(o, o->rho);
@@ -234,7 +239,8 @@ static void primitives(Or *o, const double *u) {
         }
         double r = o->rho[pc], E = E_c[cidx(o, i, j, k)];
         double kin = 0.5 * r * q;
-        double p = (o->gamma - 1.0) * (E - kin);
+        /* E holds rho e in the internal-energy form */
+        double p = o->internal ? (o->gamma - 1.0) * E : (o->gamma - 1.0) * (E - kin);
         double T = p / r;
         o->q[pc] = q;
         o->p[pc] = p;
@@ -260,7 +266,7 @@ static void primitives(Or *o, const double *u) {
                 double Tg = 2.0 * o->T[c0] - o->T[c1];
                 double rg = o->rho[c0] * (o->T[c0] - hg) / (Tg + hg);
                 o->T[cg] = Tg; o->rho[cg] = rg;
-                o->eps[cg] = Tg / (o->gamma - 1.0) + 0.5 * o->q[c0];
+                o->eps[cg] = o->internal ? Tg / (o->gamma - 1.0) : Tg / (o->gamma - 1.0) + 0.5 * o->q[c0];
                 o->chi[cg] = o->chi0 * (Tg * Tg * Tg);
                 x[d] = n - 1; c0 = pidx(o, x[0], x[1], x[2]);
                 x[d] = n - 2; c1 = pidx(o, x[0], x[1], x[2]);
@@ -268,7 +274,7 @@ static void primitives(Or *o, const double *u) {
                 Tg = 2.0 * o->T[c0] - o->T[c1];
                 rg = o->rho[c0] * (o->T[c0] + hg) / (Tg - hg);
                 o->T[cg] = Tg; o->rho[cg] = rg;
-                o->eps[cg] = Tg / (o->gamma - 1.0) + 0.5 * o->q[c0];
+                o->eps[cg] = o->internal ? Tg / (o->gamma - 1.0) : Tg / (o->gamma - 1.0) + 0.5 * o->q[c0];
                 o->chi[cg] = o->chi0 * (Tg * Tg * Tg);
             }
     }
@@ -279,8 +285,10 @@ static double diff_flux(const Or *o, long l, long r, int d) {
     return ((-0.5 * (o->chi[l] + o->chi[r])) * (o->T[r] - o->T[l])) * o->idx[d];
 }
 
-/* Mass and total-energy fluxes on every lower face (section 2: upstream
- * linear extrapolation of rho and of E/rho, limited by van Leer). */
+/* Mass and energy fluxes on every lower face (section 2: upstream linear
+ * extrapolation of rho and of the specific energy, limited by van Leer): the
+ * total-energy flux carries the pressure work p u, the internal-energy flux
+ * of eq. (2) only rho e u. */
 static void fluxes(Or *o) {
     for (int d = 0; d < o->ndim; ++d) {
         double *fr = o->fr[d], *fe = o->fe[d];
@@ -300,7 +308,7 @@ static void fluxes(Or *o) {
             double er = vanleer(o->eps[R] - o->eps[c], o->eps[c] - o->eps[L]);
             double ef = upstream(v, o->eps[L], el, o->eps[c], er);
             double f_rho = v * rf;
-            double f_e = f_rho * ef + v * (0.5 * (o->p[L] + o->p[c]));
+            double f_e = o->internal ? f_rho * ef : f_rho * ef + v * (0.5 * (o->p[L] + o->p[c]));
             if (o->chi0 != 0.0) f_e = f_e + diff_flux(o, L, c, d);
             fr[c] = f_rho;
             fe[c] = f_e;
@@ -380,8 +388,11 @@ static void momentum_fluxes(Or *o) {
         }
 }
 
-/* R(u): the right-hand side of eqs. (1)-(3) in total-energy form with
- * gravity as a body force and the heat-balance source, on the staggered grid. */
+/* R(u): the right-hand side of eqs. (1)-(3) with gravity as a body force and
+ * the heat-balance source, on the staggered grid.  Total-energy form: the
+ * energy equation gains the work of gravity, rho u . g; internal-energy form
+ * (eq. 2): it gains -p div u, with p at the cell centre and div u from the
+ * cell's face velocities. */
 static void rhs(Or *o, const double *u, double *R) {
     primitives(o, u);
     fluxes(o);
@@ -396,8 +407,12 @@ static void rhs(Or *o, const double *u, double *R) {
             ae = ae - (o->fe[d][x + s] - o->fe[d][x]) * o->idx[d];
         }
         for (int d = 0; d < o->ndim; ++d) {
-            if (o->g[d] == 0.0) continue;
             long s = pstride(o, d);
+            if (o->internal) {
+                ae = ae - o->p[x] * ((o->uf[d][x + s] - o->uf[d][x]) * o->idx[d]);
+                continue;
+            }
+            if (o->g[d] == 0.0) continue;
             ae = ae + o->g[d] * (0.5 * (o->m[d][x] + o->m[d][x + s]));
         }
         if (o->heat_balance && o->sources_frozen) ae = ae + o->sbal[c];
@@ -861,6 +876,9 @@ static void pc_build(Or *o, const double *u, double dt) {
                 if (d == 1) jj = (j + o->n[1] - 1) % o->n[1];
                 if (d == 2) kk = (k + o->n[2] - 1) % o->n[2];
                 cl = cidx(o, ii, jj, kk);
+                /* (E + p)/rho of the energy variable: in the internal-energy
+                 * form the enthalpy, i.e. the p div u term is linearised in dm
+                 * as the divergence of (p/rho)_f dm */
                 double hl = (Ec[cl] + o->p[xl]) / o->rho[xl];
                 double hr = (Ec[c] + o->p[x]) / o->rho[x];
                 hf = 0.5 * (hl + hr);
@@ -1391,7 +1409,8 @@ static void or_free(Or *o) {
 }
 
 /* ip: ndim, n0, n1, n2, bc0, bc1, bc2, heat_balance, newton_max, restart,
- *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles
+ *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles,
+ *     energy form (0 total, 1 internal)
  * dp: lo0..2, hi0..2, gamma, g0..2, chi0, rtol, atol, eta, cfl_hydro,
  *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol */
 void *or_create(const int *ip, const double *dp, const double *u0) {
@@ -1401,6 +1420,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->heat_balance = ip[7]; o->newton_max = ip[8]; o->restart = ip[9]; o->max_cycles = ip[10];
     o->pc = ip[11]; o->max_halvings = ip[12];
     o->pc_solver = ip[13]; o->mg_nu1 = ip[14]; o->mg_nu2 = ip[15]; o->mg_nuc = ip[16]; o->mg_cycles = ip[17];
+    o->internal = ip[18];
     o->corr_tol = dp[18];
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];

@@ -9,15 +9,15 @@ from workloads import (BC_PERIODIC, BC_WALL, default_opts, join_state, n_vars,
 
 
 def desc2d(nx, ny, L=(1.0, 1.0), bc=(BC_PERIODIC, BC_PERIODIC), gamma=1.4, g=(0.0, 0.0),
-           chi0=0.0, heat_balance=0):
+           chi0=0.0, heat_balance=0, energy_form=0):
     return dict(ndim=2, n=[nx, ny, 1], lo=[0.0, 0.0, 0.0], hi=[L[0], L[1], 1.0],
                 bc=[bc[0], bc[1], BC_PERIODIC], gamma=gamma, g=[g[0], g[1], 0.0],
-                chi0=chi0, heat_balance=heat_balance)
+                chi0=chi0, heat_balance=heat_balance, energy_form=energy_form)
 
 
-def desc3d(n, L=2 * math.pi, gamma=5.0 / 3.0):
+def desc3d(n, L=2 * math.pi, gamma=5.0 / 3.0, energy_form=0):
     return dict(ndim=3, n=[n, n, n], lo=[0.0] * 3, hi=[L] * 3, bc=[BC_PERIODIC] * 3,
-                gamma=gamma, g=[0.0] * 3, chi0=0.0, heat_balance=0)
+                gamma=gamma, g=[0.0] * 3, chi0=0.0, heat_balance=0, energy_form=energy_form)
 
 
 def centres(desc):
@@ -32,7 +32,8 @@ def centres(desc):
 
 def state_from_primitive(desc, rho_fn, vel_fns, p_fn):
     """Conserved state from smooth primitive fields sampled at the right
-    positions; E = p/(gamma-1) + rho |v_c|^2/2 (v_c = mean of the face values).
+    positions; E = p/(gamma-1) + rho |v_c|^2/2 (v_c = mean of the face values),
+    or rho e = p/(gamma-1) when desc selects the internal-energy variable.
     vel_fns[d](x, y, z) is sampled on the lower faces along d."""
     nx, ny, nz = desc["n"]
     X, Y, Z, c, f, dx = centres(desc)
@@ -58,7 +59,10 @@ def state_from_primitive(desc, rho_fn, vel_fns, p_fn):
             vu[tuple(idx)] = 0.0
         ke += (0.5 * (v + vu)) ** 2
         fields[names[d]] = rf * v
-    fields["E"] = p / (desc["gamma"] - 1.0) + 0.5 * rho * ke
+    if desc.get("energy_form", 0) == 1:
+        fields["E"] = p / (desc["gamma"] - 1.0)
+    else:
+        fields["E"] = p / (desc["gamma"] - 1.0) + 0.5 * rho * ke
     return join_state(fields, desc)
 
 

@@ -41,6 +41,10 @@ PREC_MIXED = 1
 PCS_MULTIGRID = 0
 PCS_ADI = 1
 
+# energy variable of the state: total energy E, or internal energy rho e (eq. 2)
+ENERGY_TOTAL = 0
+ENERGY_INTERNAL = 1
+
 CONFIG_NAMES = ("rt", "kh", "tg", "rad")
 
 # implicit steps each benchmark problem runs
@@ -132,7 +136,7 @@ def mirror_x(u, desc):
     return join_state(out, desc)
 
 
-def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0):
+def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0, energy_form=ENERGY_TOTAL):
     n = list(n) + [1] * (3 - len(n))
     lo = list(lo) + [0.0] * (3 - len(lo))
     hi = list(hi) + [1.0] * (3 - len(hi))
@@ -141,7 +145,7 @@ def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0):
     return dict(ndim=ndim, n=[int(v) for v in n], lo=[float(v) for v in lo],
                 hi=[float(v) for v in hi], bc=[int(v) for v in bc],
                 gamma=float(gamma), g=[float(v) for v in g], chi0=float(chi0),
-                heat_balance=int(heat_balance))
+                heat_balance=int(heat_balance), energy_form=int(energy_form))
 
 
 def _face_avg_rho(rho, axis, wall):
@@ -165,8 +169,11 @@ def _upper(a, axis, wall):
     return up
 
 
-def _energy(p, rho, gamma, vel, bc):
-    """E = p/(gamma-1) + rho |v_c|^2 / 2 with v_c the mean of a cell's two faces."""
+def _energy(p, rho, gamma, vel, bc, internal=False):
+    """E = p/(gamma-1) + rho |v_c|^2 / 2 with v_c the mean of a cell's two
+    faces, or rho e = p/(gamma-1) for the internal-energy variable."""
+    if internal:
+        return p / (gamma - 1.0)
     ke = np.zeros_like(p)
     for d, v in enumerate(vel):
         axis = 2 - d
@@ -175,7 +182,7 @@ def _energy(p, rho, gamma, vel, bc):
     return p / (gamma - 1.0) + 0.5 * rho * ke
 
 
-def _rt(n, seed, noise, perturb):
+def _rt(n, seed, noise, perturb, internal):
     nx, ny = (32, 64) if n is None else (int(n), 2 * int(n))
     if nx % 2:
         raise ValueError("rt needs an even nx for the mirror-symmetric set-up")
@@ -203,13 +210,13 @@ def _rt(n, seed, noise, perturb):
     bc = desc["bc"]
     my = _face_avg_rho(rho3, 1, True) * vy3
     mx = np.zeros_like(rho3)
-    E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc)
+    E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc, internal)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
     opts = default_opts(cfl_hydro=5.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["rt"], mg_cycles=MG_CYCLES["rt"])
     return desc, opts, u
 
 
-def _kh(n, seed, noise, perturb):
+def _kh(n, seed, noise, perturb, internal):
     nn = 256 if n is None else int(n)
     desc = _desc(2, (nn, nn), (0.0, 0.0), (1.0, 1.0), (BC_PERIODIC, BC_PERIODIC),
                  5.0 / 3.0, (0.0, 0.0))
@@ -233,13 +240,13 @@ def _kh(n, seed, noise, perturb):
     bc = desc["bc"]
     mx = _face_avg_rho(rho3, 2, False) * ux3
     my = _face_avg_rho(rho3, 1, False) * vy3
-    E = _energy(p3, rho3, desc["gamma"], [ux3, vy3], bc)
+    E = _energy(p3, rho3, desc["gamma"], [ux3, vy3], bc, internal)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
     opts = default_opts(cfl_hydro=10.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["kh"], mg_cycles=MG_CYCLES["kh"])
     return desc, opts, u
 
 
-def _tg(n, seed, noise, perturb):
+def _tg(n, seed, noise, perturb, internal):
     nn = 128 if n is None else int(n)
     L = 2.0 * math.pi
     desc = _desc(3, (nn, nn, nn), (0.0, 0.0, 0.0), (L, L, L),
@@ -268,7 +275,7 @@ def _tg(n, seed, noise, perturb):
     mx = _face_avg_rho(rho, 2, False) * ux
     my = _face_avg_rho(rho, 1, False) * uy
     mz = _face_avg_rho(rho, 0, False) * uz
-    E = _energy(p, rho, gamma, [ux, uy, uz], bc)
+    E = _energy(p, rho, gamma, [ux, uy, uz], bc, internal)
     u = join_state(dict(rho=rho, E=E, mx=mx, my=my, mz=mz), desc)
     opts = default_opts(cfl_hydro=20.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["tg"], mg_cycles=MG_CYCLES["tg"])
     return desc, opts, u
@@ -277,7 +284,7 @@ def _tg(n, seed, noise, perturb):
 RAD_CHI0 = 0.6304
 
 
-def _rad(n, seed, noise, perturb):
+def _rad(n, seed, noise, perturb, internal):
     nx = 128 if n is None else int(n)
     ny = 4 * nx
     d = 1.0 / ny
@@ -305,7 +312,7 @@ def _rad(n, seed, noise, perturb):
     bc = desc["bc"]
     mx = _face_avg_rho(rho3, 2, False) * vx3
     my = _face_avg_rho(rho3, 1, True) * vy3
-    E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc)
+    E = _energy(p3, rho3, desc["gamma"], [vx3, vy3], bc, internal)
     u = join_state(dict(rho=rho3, E=E, mx=mx, my=my), desc)
     opts = default_opts(cfl_hydro=10.0, cfl_rad_max=1000.0, pc=PC_ACOUSTIC_DIFFUSION,
                         gmres_eta=LINEAR_TOL["rad"], mg_cycles=MG_CYCLES["rad"])
@@ -315,15 +322,19 @@ def _rad(n, seed, noise, perturb):
 _BUILDERS = {"rt": (_rt, 0), "kh": (_kh, 1), "tg": (_tg, 2), "rad": (_rad, 3)}
 
 
-def make_config(name, n=None, seed=None, noise=True, perturb=True, **opt_over):
+def make_config(name, n=None, seed=None, noise=True, perturb=True, energy_form=ENERGY_TOTAL, **opt_over):
     """Return (desc, opts, u0) for one of ``rt``, ``kh``, ``tg``, ``rad``.
 
     ``n`` rescales the grid keeping each problem's aspect ratio (rt: n x 2n,
     kh: n x n, tg: n^3, rad: n x 4n).  ``noise``/``perturb`` switch off the
     seeded noise or the deterministic velocity perturbation.
+    ``energy_form`` selects the energy variable (ENERGY_TOTAL or
+    ENERGY_INTERNAL); the same pressure field gives the initial state.
     """
     fn, default_seed = _BUILDERS[name]
-    desc, opts, u = fn(n, default_seed if seed is None else seed, noise, perturb)
+    internal = energy_form == ENERGY_INTERNAL
+    desc, opts, u = fn(n, default_seed if seed is None else seed, noise, perturb, internal)
+    desc["energy_form"] = int(energy_form)
     for k, v in opt_over.items():
         if k not in opts:
             raise KeyError(k)
