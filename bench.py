@@ -4,9 +4,10 @@ GMRES(30), multigrid physics-based preconditioner), on one MI355X.
 
 A step is one full implicit time step (time-step selection, Crank-Nicolson
 old-time term, Newton iterations with preconditioned GMRES).  The state is
-resident in HBM before the timed region.  Two forms are timed: plain FP64,
-and the mixed form (FP32 preconditioner and Krylov basis, FP64 residual,
-Jacobian-free differences and orthogonalisation).  A serving mix of
+resident in HBM before the timed region.  Three forms are timed: plain FP64,
+the mixed form (FP32 preconditioner and Krylov basis, FP64 residual,
+Jacobian-free differences and orthogonalisation), and FP64 with the
+internal-energy variable of eq. (2) as written.  A serving mix of
 independent simulations through the continuous-batching request loop is
 measured beside it (throughput and p50/p99 step latency).  Prints one JSON
 line.
@@ -225,7 +226,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=128)
-    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--forms", default="fp64,mixed,internal",
+                    help="fp64, mixed (FP32 preconditioner and basis), internal (FP64, energy variable rho e)")
     ap.add_argument("--cpu-n", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -243,7 +245,7 @@ def main():
         sys.exit(2)
     import torch
     from paper_1610_10053_amd import jfnk
-    from workloads import make_config, PREC_FP64, PREC_MIXED
+    from workloads import make_config, ENERGY_INTERNAL, PREC_FP64, PREC_MIXED
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -255,6 +257,10 @@ def main():
     res = {}
     for f in forms:
         log("form", f)
+        if f == "internal":
+            d_i, o_i, u_i = make_config("tg", n=args.n, energy_form=ENERGY_INTERNAL)
+            res[f] = run_form(jfnk, torch, d_i, o_i, u_i, args.steps, args.warmup, prof=not args.no_prof)
+            continue
         o = dict(opts, prec=PREC_MIXED if f == "mixed" else PREC_FP64)
         res[f] = run_form(jfnk, torch, desc, o, u0, args.steps, args.warmup, prof=not args.no_prof)
 
@@ -298,7 +304,14 @@ def main():
     for f in forms[1:]:
         sf = summary(res[f])
         a, b = res[f]["state"], res[main_form]["state"]
-        sf["state_rel_l2_vs_%s" % main_form] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        if f == "internal" or main_form == "internal":
+            # the energy fields hold different variables: compare rho and m
+            N = cells
+            a = np.concatenate([a[:N], a[2 * N:]])
+            b = np.concatenate([b[:N], b[2 * N:]])
+            sf["rho_m_rel_l2_vs_%s" % main_form] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        else:
+            sf["state_rel_l2_vs_%s" % main_form] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
         sf.pop("kernels")
         sf["speedup_vs_%s" % main_form] = sf["value"] / s0["value"]
         out.setdefault("forms", {})[f] = sf

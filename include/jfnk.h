@@ -6,7 +6,8 @@
  * Newton-Krylov with a physics-based preconditioner, after Goffrey et al.,
  * "Benchmarking the Multi-dimensional Stellar Implicit Code MUSIC"
  * (arXiv:1610.10053), section 2:
- *   - equations (1)-(3) (discretised in total-energy conservative form),
+ *   - equations (1)-(3), discretised in total-energy conservative form or,
+ *     on request, with the internal-energy variable of eq. (2) as written;
  *     ideal-gas closure, conductivity chi = chi0 T^3 (stand-in for eq. 4);
  *   - staggered grid: rho and E at cell centres, momentum on cell faces;
  *     upstream linear reconstruction limited by van Leer;
@@ -26,7 +27,7 @@
  *     -3 HIP runtime error, -4 unsupported configuration).  jfnk_last_error()
  *     returns a thread-local message describing the last failure.
  *   - State layout: one array of (2 + ndim) * N doubles, N = n[0]*n[1]*n[2]:
- *     rho, E, m_x, m_y (, m_z) one after another, each in C order with x
+ *     rho, E (or rho e), m_x, m_y (, m_z) one after another, each in C order with x
  *     fastest (index i + n0*(j + n1*k)).  m_d at index c is the momentum on
  *     the lower face of cell c along d.  Along a wall direction the face with
  *     i_d = 0 is the wall: its entry must be 0, stays 0 and is not an unknown.
@@ -51,6 +52,7 @@ enum { JFNK_BC_PERIODIC = 0, JFNK_BC_WALL = 1 };
 enum { JFNK_PC_NONE = 0, JFNK_PC_ACOUSTIC = 1, JFNK_PC_ACOUSTIC_DIFFUSION = 2 };
 enum { JFNK_PCS_MULTIGRID = 0, JFNK_PCS_ADI = 1 };
 enum { JFNK_FP64 = 0, JFNK_MIXED = 1 };
+enum { JFNK_ENERGY_TOTAL = 0, JFNK_ENERGY_INTERNAL = 1 };
 
 /* Problem: grid, boundaries, gas and forces (section 2). */
 typedef struct {
@@ -63,6 +65,10 @@ typedef struct {
     double chi0;       /* conductivity chi = chi0 T^3 (0: no conduction) */
     int heat_balance;  /* 1: add the time-independent source that cancels the
                           conductive divergence of the creation state */
+    int energy_form;   /* JFNK_ENERGY_TOTAL: energy variable E, total-energy
+                          conservative form; JFNK_ENERGY_INTERNAL: rho e,
+                          eq. (2) as written (flux rho e u, -p div u at cell
+                          centres, no gravitational work) */
 } jfnk_problem_desc;
 
 /* Solver options.  Defaults (jfnk_default_opts): rtol 1e-8, atol 1e-14,

@@ -29,6 +29,7 @@ struct Grid {
     double gamma, gm1, g[3], chi0;
     int heat_balance;
     int has_wall, has_chi;
+    int internal;  // energy variable rho e (eq. 2 as written) instead of E
 };
 
 // Cell coordinates from a flat index.

@@ -1,7 +1,9 @@
 // Residual of the Crank-Nicolson system on the staggered grid (section 2 of
-// Goffrey et al. 2016): R(u) of eqs. (1)-(3) in total-energy form with
-// gravity as a body force and conduction chi = chi0 T^3, upstream linear
-// extrapolation with the van Leer limiter, and the three consumers
+// Goffrey et al. 2016): R(u) of eqs. (1)-(3) in total-energy form (or with the
+// internal-energy variable of eq. 2: flux rho e u, -p div u at cell centres,
+// no gravitational work) with gravity as a body force and conduction
+// chi = chi0 T^3, upstream linear extrapolation with the van Leer limiter, and
+// the three consumers
 //   b = u + dt/2 R(u)                 (old-time half of Crank-Nicolson)
 //   F = (u - b) - dt/2 R(u)           (residual)
 //   w = (F(u + eps S v) - F(u)) / (eps S)   (Jacobian-free product)
@@ -44,7 +46,7 @@ __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
         P.uf[d][c] = a;
     }
     const double kin = 0.5 * rho * qk;
-    const double p = G.gm1 * (E - kin);
+    const double p = G.internal ? G.gm1 * E : G.gm1 * (E - kin);  // E holds rho e in the internal form
     P.rho[c] = rho;
     P.p[c] = p;
     P.eps[c] = E / rho;
@@ -60,8 +62,9 @@ __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
 
 // Ghost-cell values one layer beyond a wall: temperature extrapolated
 // linearly, density from the discrete hydrostatic balance across the wall
-// face, specific energy from the ghost temperature and the mirrored kinetic
-// energy (section 3.1).  c0 is the wall cell, c1 its inner neighbour.
+// face, specific energy from the ghost temperature (plus the mirrored kinetic
+// energy in the total-energy form) (section 3.1).  c0 is the wall cell, c1
+// its inner neighbour.
 struct Ghost {
     double rho, eps;
 };
@@ -72,7 +75,7 @@ __device__ __forceinline__ Ghost wall_ghost(const Grid& G, const Prim& P, long c
     const double Tg = 2.0 * T0 - T1;
     Ghost gh;
     gh.rho = top ? P.rho[c0] * (T0 + hg) / (Tg - hg) : P.rho[c0] * (T0 - hg) / (Tg + hg);
-    gh.eps = Tg / G.gm1 + 0.5 * P.q[c0];
+    gh.eps = G.internal ? Tg / G.gm1 : Tg / G.gm1 + 0.5 * P.q[c0];
     return gh;
 }
 
@@ -156,7 +159,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
         const double ef = upstream(v, eL, el, ec, er);
         const double f_rho = v * rf;
         const double pL = d < 2 ? sm.p[ty - oy][tx - ox] : P.p[L], pc = d < 2 ? sm.p[ty][tx] : P.p[c];
-        double f_e = f_rho * ef + v * (0.5 * (pL + pc));
+        double f_e = G.internal ? f_rho * ef : f_rho * ef + v * (0.5 * (pL + pc));
         if (G.has_chi) {
             const double chiL = d < 2 ? sm.chi[ty - oy][tx - ox] : P.chi[L], chic = d < 2 ? sm.chi[ty][tx] : P.chi[c];
             const double TL = d < 2 ? sm.T[ty - oy][tx - ox] : P.T[L], Tc = d < 2 ? sm.T[ty][tx] : P.T[c];
@@ -284,12 +287,23 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             ar = ar - (frh - Fx.fr[d][c]) * G.idx[d];
             ae = ae - (feh - Fx.fe[d][c]) * G.idx[d];
         }
-        for (int d = 0; d < ND; ++d) {
-            if (G.g[d] == 0.0) continue;
-            const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
-            const double mlo = st(s, 2 + d, c);
-            const double mhi = top ? 0.0 : st(s, 2 + d, shifted(G, q, d, 1));
-            ae = ae + G.g[d] * (0.5 * (mlo + mhi));
+        if (G.internal) {
+            // -p div u with the cell's face velocities
+            const double pc = P.p[c];
+            for (int d = 0; d < ND; ++d) {
+                const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+                const double ulo = P.uf[d][c];
+                const double uhi = top ? 0.0 : P.uf[d][shifted(G, q, d, 1)];
+                ae = ae - pc * ((uhi - ulo) * G.idx[d]);
+            }
+        } else {
+            for (int d = 0; d < ND; ++d) {
+                if (G.g[d] == 0.0) continue;
+                const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+                const double mlo = st(s, 2 + d, c);
+                const double mhi = top ? 0.0 : st(s, 2 + d, shifted(G, q, d, 1));
+                ae = ae + G.g[d] * (0.5 * (mlo + mhi));
+            }
         }
         if (G.heat_balance && sbal) ae = ae + sbal[c];
         R[0] = ar;

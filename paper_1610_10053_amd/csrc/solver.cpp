@@ -148,6 +148,8 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (d->ndim == 2 && d->n[2] != 1) return fail(-1, "2D problems need n[2] = 1");
     if (!(d->gamma > 1.0)) return fail(-1, "gamma must exceed 1");
     if (d->chi0 < 0.0) return fail(-1, "chi0 must be >= 0");
+    if (d->energy_form != JFNK_ENERGY_TOTAL && d->energy_form != JFNK_ENERGY_INTERNAL)
+        return fail(-1, "unknown energy_form");
     if (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart) return fail(-1, "gmres_restart out of range");
     if (o->gmres_max_cycles < 0 || o->newton_max < 0) return fail(-1, "negative iteration limits");
     if (o->pc < JFNK_PC_NONE || o->pc > JFNK_PC_ACOUSTIC_DIFFUSION) return fail(-1, "unknown preconditioner");
@@ -184,6 +186,7 @@ void make_grid(const jfnk_problem_desc& d, Grid& G) {
     G.chi0 = d.chi0;
     G.has_chi = d.chi0 != 0.0;
     G.heat_balance = d.heat_balance && d.chi0 != 0.0;
+    G.internal = d.energy_form == JFNK_ENERGY_INTERNAL ? 1 : 0;
 }
 
 // multigrid depth: halve every active axis while all are even and >= 4

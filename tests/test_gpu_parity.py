@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 from _helpers import exact_sum, rel_l2
-from workloads import (PC_ACOUSTIC, PC_ACOUSTIC_DIFFUSION, PC_NONE, PCS_ADI, make_config, mirror_x,
-                       split_state, unknown_mask)
+from workloads import (ENERGY_INTERNAL, PC_ACOUSTIC, PC_ACOUSTIC_DIFFUSION, PC_NONE, PCS_ADI, PREC_MIXED,
+                       make_config, mirror_x, split_state, unknown_mask)
 
 pytestmark = pytest.mark.gpu
 
@@ -159,6 +159,59 @@ def test_adi_and_unpreconditioned_paths(torch_cuda, name, n):
         assert rg == ro
         if rg == 0:
             assert rel_l2(g.get_state(), o.get_state()) <= 1e-10
+
+
+# ---------------------------------------------------------------- internal-energy form (eq. 2 as written)
+
+@pytest.mark.parametrize("name,n", CASES + [("rad", None)])
+def test_internal_energy_form_components(torch_cuda, name, n):
+    """residual, time step and preconditioner bit for bit, Jv to 1e-9"""
+    desc, opts, u, g, o = _pair(name, n, energy_form=ENERGY_INTERNAL)
+    assert np.array_equal(g.eval_rhs(u), o.rhs(u))
+    tg, to = g.eval_time_step(u), o.time_step(u)
+    assert tg["dt"] == to["dt"] and np.array_equal(tg["scales"], to["scales"])
+    dt = to["dt"]
+    b = o.cn_old(u, dt)
+    assert np.array_equal(g.eval_cn_old(u, dt), b)
+    u1 = u + 1e-3 * np.abs(u) * _direction(desc, 8)
+    assert np.array_equal(g.eval_residual(u1, b, dt), o.residual(u1, b, dt))
+    v = _direction(desc, 9)
+    assert rel_l2(g.apply_jv(u1, b, dt, v), o.jv(u1, b, dt, v)) < 1e-9
+    assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
+
+
+@pytest.mark.parametrize("name,n,steps", [("rt", None, 4), ("kh", 32, 3), ("tg", 16, 3), ("rad", 32, 3)])
+def test_internal_energy_form_steps(torch_cuda, name, n, steps):
+    """implicit steps of the internal-energy form from identical states:
+    same dt, same iteration counts, states within 1e-10"""
+    desc, opts, u, g, o = _pair(name, n, energy_form=ENERGY_INTERNAL)
+    for k in range(steps):
+        o.set_state(g.get_state())
+        rg, sg = g.implicit_step()
+        ro, so = o.implicit_step()
+        assert rg == 0 and ro == 0
+        assert sg["dt"] == so["dt"]
+        assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+        e = rel_l2(g.get_state(), o.get_state())
+        print("step", k, sg["newton_its"], sg["gmres_its"], e, flush=True)
+        assert e <= 1e-10
+
+
+def test_internal_energy_form_mixed_precision(torch_cuda):
+    """the mixed form of the internal-energy variable converges to the
+    FP64 form's answer within the Newton tolerance"""
+    jfnk = _lib()
+    desc, opts, u = make_config("tg", n=32, energy_form=ENERGY_INTERNAL)
+    out = []
+    for prec in (0, PREC_MIXED):
+        opts["prec"] = prec
+        p = jfnk.Problem(desc, opts, u)
+        for _ in range(2):
+            rc, st = p.implicit_step()
+            assert rc == 0
+        out.append(p.get_state())
+        p.close()
+    assert rel_l2(out[1], out[0]) <= 1e-8
 
 
 # ---------------------------------------------------------------- invariants on the GPU path
