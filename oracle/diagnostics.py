@@ -9,13 +9,18 @@ Definitions, written out from the paper:
     mean of the two cells sharing face f (0 on wall faces);
   - mass and total energy: sum of rho dV and E dV;
   - maximum Mach number: max over cells of |v| / c_s, c_s^2 = gamma p / rho,
-    p = (gamma - 1)(E - (1/2) rho |v|^2) (section 3.1 quotes it);
+    p = (gamma - 1)(E - (1/2) rho |v|^2), or (gamma - 1) rho e when the energy
+    variable is the internal energy of eq. (2) (section 3.1 quotes it);
   - mixing-region width, eqs. (12)-(14): X_H = (rho - rho_L)/(rho_H - rho_L)
     per cell, <X_H> its mean over each layer normal to the vertical axis,
     X_M = 2<X_H> if <X_H> <= 1/2 else 2(1 - <X_H>), and h = sum over layers
     of X_M dy (the integral of eq. 14 as a midpoint sum over the layers);
   - the same width from two passive scalars, eq. (16): X_M = 2 min(<c1>, <c2>)
-    of the layer means of the concentrations c_k = s_k / rho.
+    of the layer means of the concentrations c_k = s_k / rho;
+  - the relative error of eq. (17) between a solution and a higher-resolution
+    one: the velocity component of a cell is the mean of its two face
+    velocities, the high-resolution field is volume averaged onto the coarse
+    cells (section 4.3), and eps = sum |v_low - avg v_high| / sum |avg v_high|.
 """
 import numpy as np
 
@@ -89,7 +94,7 @@ def max_mach(u, desc):
     rho, E, m = _fields(u, desc)
     q = speed_squared(u, desc)
     g = desc["gamma"]
-    p = (g - 1.0) * (E - 0.5 * rho * q)
+    p = (g - 1.0) * E if desc.get("energy_form", 0) == 1 else (g - 1.0) * (E - 0.5 * rho * q)
     return float(np.max(np.sqrt(q) / np.sqrt(g * p / rho)))
 
 
@@ -117,3 +122,33 @@ def mixing_width_scalars(u, s, desc, axis):
     xm = 2.0 * np.minimum(c1.mean(axis=other), c2.mean(axis=other))
     dy = (desc["hi"][axis] - desc["lo"][axis]) / desc["n"][axis]
     return float(np.sum(xm) * dy)
+
+
+def cell_velocity(u, desc, axis):
+    """component `axis` of the velocity per cell: the mean of its lower and
+    upper face velocities (the face beyond a top wall is the wall, 0)"""
+    v = face_velocities(u, desc)[axis]
+    ax = _axis(axis)
+    up = np.roll(v, -1, axis=ax)
+    if desc["bc"][axis] == 1:
+        idx = [slice(None)] * 3
+        idx[ax] = -1
+        up[tuple(idx)] = 0.0
+    return 0.5 * (v + up)
+
+
+def velocity_error(u_low, desc_low, u_high, desc_high, axis):
+    """eq. (17): relative L1 error of velocity component `axis` of u_low
+    against u_high volume averaged onto the low-resolution grid (every active
+    axis of the high-resolution grid r times finer; equal cell volumes make
+    the volume average the mean over the r^ndim fine cells)"""
+    nd = desc_low["ndim"]
+    r = desc_high["n"][0] // desc_low["n"][0]
+    for d in range(nd):
+        assert desc_high["n"][d] == r * desc_low["n"][d]
+    vl = cell_velocity(u_low, desc_low, axis)
+    vh = cell_velocity(u_high, desc_high, axis)
+    nx, ny, nz = desc_low["n"]
+    rz = r if nd == 3 else 1
+    avg = vh.reshape(nz, rz, ny, r, nx, r).mean(axis=(1, 3, 5))
+    return float(np.sum(np.abs(vl - avg)) / np.sum(np.abs(avg)))
