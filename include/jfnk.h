@@ -201,6 +201,21 @@ typedef struct {
 int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, double rho_light, double rho_heavy,
                           int mix_axis, jfnk_diagnostics* out);
 
+/* Relative error of eq. (17) (section 4.3) of velocity component `axis`
+ * between a solution and a higher-resolution one of the same problem:
+ * eps = sum |v_low - <v_high>| / sum |<v_high>| over the cells of this
+ * problem's grid, where the velocity of a cell is the mean of the velocities
+ * m / rho_f on its two faces along the axis and <v_high> is the volume
+ * average of the high-resolution cell velocities over the ratio^ndim cells
+ * that make up the cell.  u_low: a state of this problem's grid, or NULL
+ * for the problem's current state; u_high: a state on the grid ratio times
+ * finer on every active axis (same domain and boundaries), host or device
+ * per on_device (a host u_high is staged through a temporary device buffer).
+ * *out = 0 when the averaged field is zero.  Errors: -1 bad ratio or axis,
+ * -2 no device memory for staging, -4 high-resolution grid too large. */
+int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_high, int on_device, int ratio,
+                        int axis, double* out);
+
 /* ---- kernel-class timing ----
  * Time the launches of the kernel classes in class_mask (bit c = class c;
  * 0 disables) during later calls on p, with a HIP event pair attached to the

@@ -2,7 +2,8 @@
 // sum (1/2) rho |v|^2 dV with |v|^2 of a cell the mean over each axis of the
 // squared velocities of its two faces (the Taylor-Green kinetic energy of
 // section 5.3), mass and total energy, the maximum Mach number (section 3.1),
-// and the mixing-region width of eqs. (12)-(14) along a vertical axis.
+// the mixing-region width of eqs. (12)-(14) along a vertical axis, and the
+// relative velocity error of eq. (17) against a higher-resolution solution.
 #include "kernels.hpp"
 
 namespace jfnk {
@@ -93,6 +94,70 @@ __global__ void __launch_bounds__(kBlock) k_diag_layers_scalars(Grid G, Prim P, 
         const double m1 = t1 / (double)nl, m2 = t2 / (double)nl;
         xm[j] = 2.0 * (m1 < m2 ? m1 : m2);
     }
+}
+
+// Velocity component `axis` of cell q of state u on grid G: the mean of the
+// velocities m / rho_f of its two faces along the axis (rho_f the mean of the
+// two cells of a face; 0 on wall faces).
+__device__ __forceinline__ double cell_velocity(const Grid& G, const double* __restrict__ u, const Ijk& q, long c,
+                                                int axis) {
+    const double* m = u + (long)(2 + axis) * G.N;
+    const bool wall = G.bc[axis] == WALL;
+    double a = 0.0, b = 0.0;
+    if (!(wall && q.v[axis] == 0)) a = m[c] / (0.5 * (u[shifted(G, q, axis, -1)] + u[c]));
+    if (!(wall && q.v[axis] == G.n[axis] - 1)) {
+        const long cu = shifted(G, q, axis, 1);
+        b = m[cu] / (0.5 * (u[c] + u[cu]));
+    }
+    return 0.5 * (a + b);
+}
+
+// eq. (17): per block, sum over low-resolution cells of |v_low - <v_high>|
+// and of |<v_high>|, <.> the mean over the r^ND cells of the high-resolution
+// grid Gh that make up the low cell (equal volumes: the volume average)
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_vel_error(Grid Gl, Grid Gh, const double* __restrict__ ul,
+                                                      const double* __restrict__ uh, int r, int axis,
+                                                      double* __restrict__ part) {
+    Ijk q;
+    long c = 0;
+    double e = 0.0, a = 0.0;
+    if (cell_from_launch(Gl, q, c)) {
+        const double vl = cell_velocity(Gl, ul, q, c, axis);
+        const int rz = ND > 2 ? r : 1;
+        double s = 0.0;
+        for (int dk = 0; dk < rz; ++dk)
+            for (int dj = 0; dj < r; ++dj)
+                for (int di = 0; di < r; ++di) {
+                    Ijk f;
+                    f.v[0] = q.v[0] * r + di;
+                    f.v[1] = q.v[1] * r + dj;
+                    f.v[2] = ND > 2 ? q.v[2] * r + dk : 0;
+                    s += cell_velocity(Gh, uh, f, flat(Gh, f.v[0], f.v[1], f.v[2]), axis);
+                }
+        const double avg = s / (double)(r * r * rz);
+        e = fabs(vl - avg);
+        a = fabs(avg);
+    }
+    __shared__ double sh[kBlock / 64];
+    const long nb = (long)gridDim.x * gridDim.y * gridDim.z;
+    const int b = lin_block();
+    double t = block_sum(e, sh);
+    if (lin_thread() == 0) part[b] = t;
+    __syncthreads();
+    t = block_sum(a, sh);
+    if (lin_thread() == 0) part[nb + b] = t;
+}
+
+void launch_vel_error(const Grid& Gl, const Grid& Gh, const double* ul, const double* uh, int r, int axis,
+                      double* part, double* out2, hipStream_t stream) {
+    const int nb = cell_blocks(Gl.n);
+    {
+        JFNK_PROF(KC_OTHER, stream);
+        JFNK_LAUNCH_ND(Gl.ndim, k_vel_error, cell_grid3(Gl.n), dim3(kBx, kBy), 0, stream, Gl, Gh, ul, uh, r, axis,
+                       part);
+    }
+    launch_final_sum(part, nb, 2, out2, stream);
 }
 
 int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,

@@ -96,6 +96,11 @@ void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Fl
 // doubles
 int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,
                        const double* scal, double* part, double* out5, hipStream_t stream);
+// eq. (17) sums for velocity component axis: out2 = sum |v_low - <v_high>|,
+// sum |<v_high>| over the cells of Gl; Gh is r times finer on every active
+// axis; part needs 2 cell_blocks(Gl.n) doubles
+void launch_vel_error(const Grid& Gl, const Grid& Gh, const double* ul, const double* uh, int r, int axis,
+                      double* part, double* out2, hipStream_t stream);
 
 // krylov.hip: deterministic two-stage reductions and Krylov vector kernels
 // partial layout: part[col * nblk + block]

@@ -1355,6 +1355,46 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
     return 0;
 }
 
+int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_high, int on_device, int ratio,
+                        int axis, double* out) {
+    if (!p || !u_high || !out) return fail(-1, "null argument");
+    const Grid& G = p->G;
+    if (ratio < 1 || ratio > 1024) return fail(-1, "ratio must lie in 1..1024");
+    if (axis < 0 || axis >= G.ndim) return fail(-1, "axis must be a grid axis");
+    Grid Gh = G;
+    Gh.N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < G.ndim) Gh.n[d] = G.n[d] * ratio;
+        Gh.N *= Gh.n[d];
+    }
+    Gh.nvec = (long)(2 + G.ndim) * Gh.N;
+    if (Gh.nvec >= (1L << 31)) return fail(-4, "high-resolution grid too large for 32-bit cell indexing");
+    ProfGuard guard(p);
+    const double* lo = p->u;
+    if (u_low) {
+        int rc = copy_in(p, p->s1, u_low, on_device);
+        if (rc) return rc;
+        lo = p->s1;
+    }
+    const double* hi = u_high;
+    double* tmp = nullptr;
+    if (!on_device) {
+        if (hipMalloc(&tmp, sizeof(double) * Gh.nvec) != hipSuccess) return fail(-2, "hipMalloc (high-resolution state)");
+        if (hipMemcpyAsync(tmp, u_high, sizeof(double) * Gh.nvec, hipMemcpyHostToDevice, p->stream) != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(-3, "copy of the high-resolution state");
+        }
+        hi = tmp;
+    }
+    launch_vel_error(G, Gh, lo, hi, ratio, axis, p->part, p->dsum + D_TMP, p->stream);
+    double r[2] = {0.0, 0.0};
+    int rc = hipGetLastError() == hipSuccess ? read_scalars(p, D_TMP, 2, r) : fail(-3, "vel_error launch");
+    if (tmp) (void)hipFree(tmp);
+    if (rc) return rc;
+    *out = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+    return 0;
+}
+
 int jfnk_set_scales(jfnk_problem* p, const double* s5) {
     if (!p || !s5) return fail(-1, "null argument");
     for (int f = 0; f < 5; ++f) {

@@ -135,3 +135,124 @@ def test_gpu_diagnostics_match_oracle(name, n, steps, axis):
         assert d["mix_width"] == pytest.approx(dg.mixing_width(s, desc, rl, rh, axis), rel=1e-12, abs=1e-15)
     else:
         assert d["mix_width"] == 0.0
+
+
+# ---------------------------------------------------------------- eq. (17): error against a finer solution
+
+def _shear_state(desc, vfun, axis):
+    """uniform rho and p, velocity component `axis` = vfun(coordinate array
+    of its faces), other components 0"""
+    nx, ny, nz = desc["n"]
+    shape = (nz, ny, nx)
+    dx = [(desc["hi"][d] - desc["lo"][d]) / desc["n"][d] for d in range(3)]
+    cz, cy, cx = [(np.arange(desc["n"][d]) + 0.5) * dx[d] for d in (2, 1, 0)]
+    Z, Y, X = np.meshgrid(cz, cy, cx, indexing="ij")
+    P = [X, Y, Z]
+    P[axis] = P[axis] - 0.5 * dx[axis]
+    vel = [np.zeros(shape) for _ in range(desc["ndim"])]
+    vel[axis] = vfun(*P)
+    return _state(desc, np.full(shape, 1.3), vel, np.full(shape, 2.0))
+
+
+def test_velocity_error_against_itself_and_uniform_fields():
+    desc = desc2d(16, 8)
+    u = _shear_state(desc, lambda x, y, z: np.sin(6.0 * y) + x, 0)
+    assert dg.velocity_error(u, desc, u, desc, 0) == 0.0
+    fine = desc2d(32, 16)
+    one = _shear_state(fine, lambda x, y, z: 1.0 + 0 * x, 1)
+    two = _shear_state(desc, lambda x, y, z: 2.0 + 0 * x, 1)
+    assert dg.velocity_error(two, desc, one, fine, 1) == pytest.approx(1.0, rel=1e-14)
+
+
+@pytest.mark.parametrize("r", [2, 4, 8])
+def test_velocity_error_of_a_sine_is_the_dirichlet_kernel(r):
+    """v_x = sin(2 pi y): the mean of the r fine cell values over a coarse
+    cell is sin(2 pi y_c) D, D = sin(pi r h)/(r sin(pi h)) with h the fine
+    spacing, so eps = |1 - D| / D"""
+    n = 16
+    lo, hi = desc2d(n, n), desc2d(n * r, n * r)
+    f = lambda x, y, z: np.sin(2.0 * np.pi * y)
+    h = 1.0 / (n * r)
+    D = np.sin(np.pi * r * h) / (r * np.sin(np.pi * h))
+    eps = dg.velocity_error(_shear_state(lo, f, 0), lo, _shear_state(hi, f, 0), hi, 0)
+    assert eps == pytest.approx(abs(1.0 - D) / D, rel=1e-10)
+
+
+def test_velocity_error_dirichlet_kernel_3d():
+    n, r = 8, 2
+    lo, hi = desc3d(n, L=1.0), desc3d(n * r, L=1.0)
+    f = lambda x, y, z: np.cos(2.0 * np.pi * x) + 0.25
+    h = 1.0 / (n * r)
+    D = np.sin(np.pi * r * h) / (r * np.sin(np.pi * h))
+    xc = (np.arange(n) + 0.5) / n
+    ref = np.sum(np.abs(np.cos(2 * np.pi * xc) * (1 - D))) / np.sum(np.abs(np.cos(2 * np.pi * xc) * D + 0.25))
+    eps = dg.velocity_error(_shear_state(lo, f, 2), lo, _shear_state(hi, f, 2), hi, 2)
+    assert eps == pytest.approx(ref, rel=1e-10)
+
+
+def test_velocity_error_of_a_linear_profile_between_walls_is_zero():
+    """the volume average of a linear field is its value at the centre"""
+    lo = desc2d(8, 8, bc=(BC_PERIODIC, BC_WALL))
+    hi = desc2d(32, 32, bc=(BC_PERIODIC, BC_WALL))
+    f = lambda x, y, z: 0.5 + y
+    eps = dg.velocity_error(_shear_state(lo, f, 0), lo, _shear_state(hi, f, 0), hi, 0)
+    assert eps <= 1e-14
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name,n,axis", [("kh", 32, 1), ("rt", 16, 1), ("tg", 8, 0)])
+def test_gpu_velocity_error_matches_oracle(name, n, axis):
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_10053_amd import jfnk
+    jfnk.load()
+    d_lo, o_lo, u_lo = make_config(name, n=n)
+    d_hi, o_hi, u_hi = make_config(name, n=2 * n)
+    g_lo, g_hi = jfnk.Problem(d_lo, o_lo, u_lo), jfnk.Problem(d_hi, o_hi, u_hi)
+    for _ in range(2):
+        assert g_lo.implicit_step()[0] == 0
+        assert g_hi.implicit_step()[0] == 0
+    s_lo, s_hi = g_lo.get_state(), g_hi.get_state()
+    ref = dg.velocity_error(s_lo, d_lo, s_hi, d_hi, axis)
+    assert ref > 0
+    e_host = g_lo.velocity_error(s_hi, 2, axis)
+    e_dev = g_lo.velocity_error(torch.from_numpy(s_hi).cuda(), 2, axis)
+    e_given = g_hi.velocity_error(s_hi, 1, axis, u_low=s_hi)
+    print(name, n, axis, ref, e_host, e_dev, flush=True)
+    assert e_host == pytest.approx(ref, rel=1e-12)
+    assert e_dev == e_host
+    assert e_given == 0.0
+    g_lo.close()
+    g_hi.close()
+
+
+def test_max_mach_of_the_internal_energy_variable():
+    """with the internal-energy variable p = (gamma - 1) rho e, whatever the
+    velocity"""
+    desc = desc2d(8, 8, gamma=1.4, energy_form=1)
+    shape = (1, 8, 8)
+    rho = np.full(shape, 1.3)
+    v = [np.full(shape, 0.3), np.full(shape, -0.4)]
+    m = [0.5 * (np.roll(rho, 1, axis=2 - d) + rho) * v[d] for d in range(2)]
+    rhoe = np.full(shape, 2.0 / 0.4)
+    u = np.concatenate([rho.ravel(), rhoe.ravel()] + [a.ravel() for a in m])
+    assert dg.max_mach(u, desc) == pytest.approx(0.5 / np.sqrt(1.4 * 2.0 / 1.3), rel=1e-14)
+
+
+@pytest.mark.gpu
+def test_gpu_diagnostics_internal_energy_form():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1610_10053_amd import jfnk
+    jfnk.load()
+    desc, opts, u = make_config("kh", n=64, energy_form=1)
+    g = jfnk.Problem(desc, opts, u)
+    for _ in range(2):
+        assert g.implicit_step()[0] == 0
+    s = g.get_state()
+    d = g.eval_diagnostics(None)
+    assert d["max_mach"] == dg.max_mach(s, desc)
+    assert d["kinetic"] == pytest.approx(dg.kinetic_energy(s, desc), rel=1e-12)
+    g.close()
