@@ -22,7 +22,12 @@
  *   - Crank-Nicolson, Newton-Raphson, GMRES, Jacobian-free products: section 2;
  *   - physics-based preconditioner (sound waves and optionally thermal
  *     diffusion implicit): section 2, last paragraph, and section 6;
- *   - time-step choice from CFL numbers: section 2.1, eqs. (5)-(7).
+ *   - time-step choice from CFL numbers: section 2.1, eqs. (5)-(7);
+ *   - two-dimensional spherical geometry (r, theta) with azimuthal symmetry
+ *     and radial gravity (section 2: constant or radial gravity as a body
+ *     force; section 6: the radiative envelope in 2D spherical geometry):
+ *     finite volumes with the cell volumes and face areas of the sphere, the
+ *     momentum equations with their geometric terms.
  * Every detail the paper leaves open is a documented reading; the readings
  * are listed with the design notes of the repository.
  *
@@ -55,12 +60,22 @@ typedef struct {
     /* problem */
     int ndim, n[3], bc[3], heat_balance;
     int internal; /* energy variable rho e (eq. 2) instead of total energy E */
+    int sph;      /* 2D spherical: axis 0 = r, axis 1 = colatitude theta */
     double lo[3], hi[3], dx[3], idx[3], gamma, g[3], chi0;
     /* solver */
     double rtol, atol, eta, cfl_hydro, cfl_adv_max, cfl_rad_max, dt_max;
     int newton_max, restart, max_cycles, pc, max_halvings;
     int pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles;
     double corr_tol;
+    /* spherical metric, per radial index i and colatitude index j:
+     *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
+     *   (cell volume Vr Vt per radian of azimuth); r2f[i] = r_{i-1/2}^2 and
+     *   hr2[i] = (r_{i+1/2}^2 - r_{i-1/2}^2)/2 (face areas r2f Vt and hr2 stf);
+     *   stf[j] = sin th_{j-1/2}; rc[i] cell-centre radius; ith[i] = 1/(rc dth);
+     *   momentum control volumes: Vrc[i] = (rc_i^3 - rc_{i-1}^3)/3,
+     *   r2c[i] = rc_i^2, hr2c[i] = (rc_i^2 - rc_{i-1}^2)/2,
+     *   Vtc[j] = cos thc_{j-1} - cos thc_j, stc[j] = sin thc_j */
+    double *Vr, *Vt, *r2f, *hr2, *stf, *rfa, *rc, *ith, *Vrc, *r2c, *hr2c, *Vtc, *stc;
     /* sizes */
     int gh[3], pn[3];  /* ghost layers per axis, padded extents */
     long N, P, nvar, nvec, nunk;
@@ -163,6 +178,52 @@ static double upstream(double vel, double ql, double sl, double qr, double sr) {
 /* ------------------------------------------------------------------ state -> primitives */
 
 static double *field(const Or *o, const double *u, int f) { return (double *)u + (long)f * o->N; }
+
+/* ---- spherical metric (section 6 geometry) ---- */
+static void sph_tables(Or *o) {
+    int nr = o->n[0], nt = o->n[1];
+    double dr = o->dx[0], dth = o->dx[1];
+    o->Vr = calloc(nr, sizeof(double)); o->rc = calloc(nr, sizeof(double)); o->ith = calloc(nr, sizeof(double));
+    o->r2f = calloc(nr + 1, sizeof(double)); o->rfa = calloc(nr + 1, sizeof(double));
+    o->hr2 = calloc(nr, sizeof(double));
+    o->Vrc = calloc(nr, sizeof(double)); o->r2c = calloc(nr, sizeof(double)); o->hr2c = calloc(nr, sizeof(double));
+    o->Vt = calloc(nt, sizeof(double)); o->stf = calloc(nt + 1, sizeof(double));
+    o->Vtc = calloc(nt, sizeof(double)); o->stc = calloc(nt, sizeof(double));
+    for (int i = 0; i <= nr; ++i) {
+        double r = o->lo[0] + i * dr;
+        o->rfa[i] = r;
+        o->r2f[i] = r * r;
+    }
+    for (int i = 0; i < nr; ++i) {
+        double a = o->rfa[i], b = o->rfa[i + 1];
+        o->Vr[i] = (b * b * b - a * a * a) / 3.0;
+        o->hr2[i] = 0.5 * (b * b - a * a);
+        o->rc[i] = o->lo[0] + (i + 0.5) * dr;
+        o->ith[i] = 1.0 / (o->rc[i] * dth);
+        o->r2c[i] = o->rc[i] * o->rc[i];
+    }
+    for (int i = 1; i < nr; ++i) {
+        double a = o->rc[i - 1], b = o->rc[i];
+        o->Vrc[i] = (b * b * b - a * a * a) / 3.0;
+        o->hr2c[i] = 0.5 * (b * b - a * a);
+    }
+    for (int j = 0; j <= nt; ++j) o->stf[j] = sin(o->lo[1] + j * dth);
+    for (int j = 0; j < nt; ++j) {
+        o->Vt[j] = cos(o->lo[1] + j * dth) - cos(o->lo[1] + (j + 1) * dth);
+        o->stc[j] = sin(o->lo[1] + (j + 0.5) * dth);
+    }
+    for (int j = 1; j < nt; ++j)
+        o->Vtc[j] = cos(o->lo[1] + (j - 0.5) * dth) - cos(o->lo[1] + (j + 0.5) * dth);
+}
+static double sph_vol(const Or *o, int i, int j) { return o->Vr[i] * o->Vt[j]; }
+/* area of the lower face of cell (i, j) along d (i may be n0, j may be n1) */
+static double sph_area(const Or *o, int d, int i, int j) {
+    return d == 0 ? o->r2f[i] * o->Vt[j] : o->hr2[i] * o->stf[j];
+}
+/* inverse distance between the two cells of a face along d in row i */
+static double face_ids(const Or *o, int d, int i) {
+    return (o->sph && d == 1) ? o->ith[i] : o->idx[d];
+}
 
 /* Velocities on faces, pressure, specific energy of the energy variable
  * (total E/rho, or internal e), temperature, conductivity, with ghosts.
@@ -280,9 +341,10 @@ static void primitives(Or *o, const double *u) {
     }
 }
 
-/* diffusive flux -chi_f dT/dx on the face between padded cells l and r */
-static double diff_flux(const Or *o, long l, long r, int d) {
-    return ((-0.5 * (o->chi[l] + o->chi[r])) * (o->T[r] - o->T[l])) * o->idx[d];
+/* diffusive flux -chi_f dT/ds on the face between padded cells l and r,
+ * ids the inverse distance of their centres */
+static double diff_flux(const Or *o, long l, long r, double ids) {
+    return ((-0.5 * (o->chi[l] + o->chi[r])) * (o->T[r] - o->T[l])) * ids;
 }
 
 /* Mass and energy fluxes on every lower face (section 2: upstream linear
@@ -309,7 +371,7 @@ static void fluxes(Or *o) {
             double ef = upstream(v, o->eps[L], el, o->eps[c], er);
             double f_rho = v * rf;
             double f_e = o->internal ? f_rho * ef : f_rho * ef + v * (0.5 * (o->p[L] + o->p[c]));
-            if (o->chi0 != 0.0) f_e = f_e + diff_flux(o, L, c, d);
+            if (o->chi0 != 0.0) f_e = f_e + diff_flux(o, L, c, face_ids(o, d, i));
             fr[c] = f_rho;
             fe[c] = f_e;
         }
@@ -388,6 +450,42 @@ static void momentum_fluxes(Or *o) {
         }
 }
 
+/* Momentum right-hand side in 2D spherical geometry on the staggered control
+ * volume of the lower d-face of cell (i, j): transport fluxes through the
+ * volume's sides times their areas over its volume, the pressure gradient
+ * across the face, gravity (radial), and the geometric terms of the
+ * spherical momentum equations, +rho u_th^2/r for the radial and
+ * -rho u_r u_th/r for the polar component (u_phi = 0), with the face density
+ * and the mean of the other component over the four faces around the face. */
+static double sph_momentum(const Or *o, int d, int i, int j, long x) {
+    long s0 = pstride(o, 0), s1 = pstride(o, 1);
+    double a = 0.0;
+    if (d == 0) {
+        double rf = 0.5 * (o->rho[x - s0] + o->rho[x]);
+        double V = o->Vrc[i] * o->Vt[j];
+        double Ahi = o->r2c[i] * o->Vt[j], Alo = o->r2c[i - 1] * o->Vt[j];
+        a = a - (Ahi * o->phic[0][0][x] - Alo * o->phic[0][0][x - s0]) / V;
+        double Bhi = o->hr2c[i] * o->stf[j + 1], Blo = o->hr2c[i] * o->stf[j];
+        a = a - (Bhi * o->phic[0][1][x + s1] - Blo * o->phic[0][1][x]) / V;
+        a = a - (o->p[x] - o->p[x - s0]) * o->idx[0];
+        if (o->g[0] != 0.0) a = a + rf * o->g[0];
+        double u1 = o->uf[1][x - s0], u2 = o->uf[1][x - s0 + s1], u3 = o->uf[1][x], u4 = o->uf[1][x + s1];
+        double ut2 = 0.25 * (((u1 * u1 + u2 * u2) + u3 * u3) + u4 * u4);
+        a = a + rf * ut2 / o->rfa[i];
+    } else {
+        double rf = 0.5 * (o->rho[x - s1] + o->rho[x]);
+        double V = o->Vr[i] * o->Vtc[j];
+        double Ahi = o->r2f[i + 1] * o->Vtc[j], Alo = o->r2f[i] * o->Vtc[j];
+        a = a - (Ahi * o->phic[1][0][x + s0] - Alo * o->phic[1][0][x]) / V;
+        double Bhi = o->hr2[i] * o->stc[j], Blo = o->hr2[i] * o->stc[j - 1];
+        a = a - (Bhi * o->phic[1][1][x] - Blo * o->phic[1][1][x - s1]) / V;
+        a = a - (o->p[x] - o->p[x - s1]) * o->ith[i];
+        double ur = 0.25 * (((o->uf[0][x - s1] + o->uf[0][x - s1 + s0]) + o->uf[0][x]) + o->uf[0][x + s0]);
+        a = a - rf * ur * o->uf[1][x] / o->rc[i];
+    }
+    return a;
+}
+
 /* R(u): the right-hand side of eqs. (1)-(3) with gravity as a body force and
  * the heat-balance source, on the staggered grid.  Total-energy form: the
  * energy equation gains the work of gravity, rho u . g; internal-energy form
@@ -403,12 +501,26 @@ static void rhs(Or *o, const double *u, double *R) {
         double ar = 0.0, ae = 0.0;
         for (int d = 0; d < o->ndim; ++d) {
             long s = pstride(o, d);
+            if (o->sph) {
+                /* (1/V) sum of area-weighted face fluxes */
+                double V = sph_vol(o, i, j);
+                double Alo = sph_area(o, d, i, j), Ahi = sph_area(o, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+                ar = ar - (Ahi * o->fr[d][x + s] - Alo * o->fr[d][x]) / V;
+                ae = ae - (Ahi * o->fe[d][x + s] - Alo * o->fe[d][x]) / V;
+                continue;
+            }
             ar = ar - (o->fr[d][x + s] - o->fr[d][x]) * o->idx[d];
             ae = ae - (o->fe[d][x + s] - o->fe[d][x]) * o->idx[d];
         }
         for (int d = 0; d < o->ndim; ++d) {
             long s = pstride(o, d);
             if (o->internal) {
+                if (o->sph) {
+                    double V = sph_vol(o, i, j);
+                    double Alo = sph_area(o, d, i, j), Ahi = sph_area(o, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+                    ae = ae - o->p[x] * ((Ahi * o->uf[d][x + s] - Alo * o->uf[d][x]) / V);
+                    continue;
+                }
                 ae = ae - o->p[x] * ((o->uf[d][x + s] - o->uf[d][x]) * o->idx[d]);
                 continue;
             }
@@ -425,6 +537,7 @@ static void rhs(Or *o, const double *u, double *R) {
         FOR_CELLS(o) {
             long x = pidx(o, i, j, k), c = cidx(o, i, j, k);
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) { Rm[c] = 0.0; continue; }
+            if (o->sph) { Rm[c] = sph_momentum(o, d, i, j, x); continue; }
             double a = 0.0;
             for (int e = 0; e < o->ndim; ++e) {
                 long se = pstride(o, e);
@@ -462,9 +575,9 @@ static void freeze_sources(Or *o, const double *u) {
                 x[r1] = a1; x[r2] = b;
                 long t = (long)a1 + (long)o->n[r1] * b;
                 x[d] = 0; long c = pidx(o, x[0], x[1], x[2]);
-                o->qwall[d][0][t] = diff_flux(o, c - s, c, d);
+                o->qwall[d][0][t] = diff_flux(o, c - s, c, face_ids(o, d, x[0]));
                 x[d] = n; c = pidx(o, x[0], x[1], x[2]);
-                o->qwall[d][1][t] = diff_flux(o, c - s, c, d);
+                o->qwall[d][1][t] = diff_flux(o, c - s, c, face_ids(o, d, x[0]));
             }
     }
     memset(o->sbal, 0, sizeof(double) * o->N);
@@ -477,7 +590,7 @@ static void freeze_sources(Or *o, const double *u) {
             FOR_CELLS(o) {
                 long c = pidx(o, i, j, k);
                 if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) continue;
-                f[c] = diff_flux(o, c - s, c, d);
+                f[c] = diff_flux(o, c - s, c, face_ids(o, d, i));
             }
             if (o->bc[d] == BC_WALL) {
                 int n = o->n[d], r1 = (d + 1) % 3, r2 = (d + 2) % 3;
@@ -497,7 +610,13 @@ static void freeze_sources(Or *o, const double *u) {
             double acc = 0.0;
             for (int d = 0; d < o->ndim; ++d) {
                 long s = pstride(o, d);
-                acc = acc + (o->fe[d][x + s] - o->fe[d][x]) * o->idx[d];
+                if (o->sph) {
+                    int ih = d == 0 ? i + 1 : i, jh = d == 1 ? j + 1 : j;
+                    acc = acc + (sph_area(o, d, ih, jh) * o->fe[d][x + s] - sph_area(o, d, i, j) * o->fe[d][x]) /
+                                    sph_vol(o, i, j);
+                } else {
+                    acc = acc + (o->fe[d][x + s] - o->fe[d][x]) * o->idx[d];
+                }
             }
             o->sbal[cidx(o, i, j, k)] = acc;
         }
@@ -565,13 +684,14 @@ static double time_step(Or *o, const double *u, double *hyd_out, double *adv_out
         for (int d = 0; d < o->ndim; ++d) {
             double a = fabs(o->uf[d][x]), b = fabs(o->uf[d][x + pstride(o, d)]);
             double ud = a > b ? a : b;
-            double h = (ud + cs) * o->idx[d];
-            double v = ud * o->idx[d];
+            double ids = face_ids(o, d, i);
+            double h = (ud + cs) * ids;
+            double v = ud * ids;
             if (h > hyd) hyd = h;
             if (v > adv) adv = v;
             if (o->chi0 != 0.0) {
                 double D = o->chi[x] / (r * cp);
-                double z = D * (o->idx[d] * o->idx[d]);
+                double z = D * (ids * ids);
                 if (z > rad) rad = z;
             }
         }
@@ -885,17 +1005,23 @@ static void pc_build(Or *o, const double *u, double dt) {
                 chif = 0.5 * (o->chi[xl] + o->chi[x]);
             }
             o->pc_hf[d][c] = hf;
-            o->pc_kap[d][c] = ((tau * tau) * gm1) * hf * (o->idx[d] * o->idx[d]);
-            o->pc_beta[d][c] = (tau * chif) * (o->idx[d] * o->idx[d]);
+            /* couplings per unit volume, or, in spherical geometry, of the
+             * volume-weighted system: area over centre distance */
+            double w = o->sph ? sph_area(o, d, i, j) * face_ids(o, d, i) : o->idx[d] * o->idx[d];
+            o->pc_kap[d][c] = ((tau * tau) * gm1) * hf * w;
+            o->pc_beta[d][c] = (tau * chif) * w;
         }
     }
     FOR_CELLS(o) o->pc_W[cidx(o, i, j, k)] = gm1 / o->rho[pidx(o, i, j, k)];
     if (o->pc_solver == PCS_MULTIGRID && o->pc != PC_NONE) {
         double *sig = calloc(o->N, sizeof(double));
-        for (long c = 0; c < o->N; ++c) sig[c] = 1.0;
+        FOR_CELLS(o) sig[cidx(o, i, j, k)] = o->sph ? sph_vol(o, i, j) : 1.0;
         mg_build(o, o->mg_ac, sig, o->pc_kap);
         if (o->pc == PC_ACOUSTIC_DIFFUSION) {
-            for (long c = 0; c < o->N; ++c) sig[c] = 1.0 / o->pc_W[c];
+            FOR_CELLS(o) {
+                long c = cidx(o, i, j, k);
+                sig[c] = o->sph ? sph_vol(o, i, j) / o->pc_W[c] : 1.0 / o->pc_W[c];
+            }
             mg_build(o, o->mg_df, sig, o->pc_beta);
         }
         free(sig);
@@ -971,6 +1097,11 @@ static void div_faces(Or *o, const double *const *mf, int weighted, double *out)
                 flo = o->pc_hf[d][c] * flo;
                 fhi = up >= 0 ? o->pc_hf[d][up] * fhi : 0.0;
             }
+            if (o->sph) {
+                double Alo = sph_area(o, d, i, j), Ahi = sph_area(o, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+                acc = acc + (Ahi * fhi - Alo * flo) / sph_vol(o, i, j);
+                continue;
+            }
             acc = acc + (fhi - flo) * o->idx[d];
         }
         out[c] = acc;
@@ -1006,18 +1137,19 @@ static void pc_apply(Or *o, const double *v, double *z) {
              * dE = r_E + tau D(chi_f G s), which keeps sum(dE) = sum(r_E) */
             double *sv = o->w2;
             memcpy(sv, rE, sizeof(double) * N);
+            if (o->sph) FOR_CELLS(o) sv[cidx(o, i, j, k)] *= sph_vol(o, i, j);  /* volume-weighted system */
             mg_solve(o, o->mg_df, sv);
             double *y = o->w2 + N;
             FOR_CELLS(o) {
                 long c = cidx(o, i, j, k);
-                double acc = rE[c];
+                double acc = o->sph ? 0.0 : rE[c];
                 for (int d = 0; d < o->ndim; ++d) {
                     long up = nb(o, i, j, k, d, 1), dn = nb(o, i, j, k, d, -1);
                     double thi = up >= 0 ? o->pc_beta[d][up] * (sv[up] - sv[c]) : 0.0;
                     double tlo = dn >= 0 ? o->pc_beta[d][c] * (sv[c] - sv[dn]) : 0.0;
                     acc = acc + (thi - tlo);
                 }
-                y[c] = acc;
+                y[c] = o->sph ? rE[c] + acc / sph_vol(o, i, j) : acc;
             }
             memcpy(rE, y, sizeof(double) * N);
         }
@@ -1025,6 +1157,7 @@ static void pc_apply(Or *o, const double *v, double *z) {
     double *dp = o->w2;
     div_faces(o, rm, 1, dp);
     for (long c = 0; c < N; ++c) dp[c] = gm1 * (rE[c] - tau * dp[c]);
+    if (o->sph) FOR_CELLS(o) dp[cidx(o, i, j, k)] *= sph_vol(o, i, j);  /* volume-weighted system */
     if (o->pc_solver == PCS_ADI) {
         for (int d = 0; d < o->ndim; ++d) line_solve(o, d, 0, dp);
     } else {
@@ -1036,7 +1169,7 @@ static void pc_apply(Or *o, const double *v, double *z) {
             long c = cidx(o, i, j, k);
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) { dm[d][c] = 0.0; continue; }
             long lo = nb(o, i, j, k, d, -1);
-            dm[d][c] = rm[d][c] - tau * ((dp[c] - dp[lo]) * o->idx[d]);
+            dm[d][c] = rm[d][c] - tau * ((dp[c] - dp[lo]) * face_ids(o, d, i));
         }
     }
     double *tmp = dp; /* dp no longer needed */
@@ -1393,7 +1526,8 @@ static int step_at(Or *o, double dt) {
 
 static void or_free(Or *o) {
     if (!o) return;
-    double **ptrs[] = {&o->u, &o->un, &o->sbal, &o->rho, &o->eps, &o->p, &o->T, &o->chi, &o->q,
+    double **ptrs[] = {&o->u, &o->un, &o->sbal, &o->Vr, &o->Vt, &o->r2f, &o->hr2, &o->stf, &o->rfa, &o->rc,
+                       &o->ith, &o->Vrc, &o->r2c, &o->hr2c, &o->Vtc, &o->stc, &o->rho, &o->eps, &o->p, &o->T, &o->chi, &o->q,
                        &o->b, &o->F, &o->w1, &o->w2, &o->R1, &o->pc_W, &o->la, &o->lb, &o->lc,
                        &o->ld, &o->lx, &o->lt1, &o->lt2};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(*ptrs[i]);
@@ -1410,7 +1544,7 @@ static void or_free(Or *o) {
 
 /* ip: ndim, n0, n1, n2, bc0, bc1, bc2, heat_balance, newton_max, restart,
  *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles,
- *     energy form (0 total, 1 internal)
+ *     energy form (0 total, 1 internal), geometry (0 Cartesian, 1 2D spherical)
  * dp: lo0..2, hi0..2, gamma, g0..2, chi0, rtol, atol, eta, cfl_hydro,
  *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol */
 void *or_create(const int *ip, const double *dp, const double *u0) {
@@ -1421,6 +1555,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->pc = ip[11]; o->max_halvings = ip[12];
     o->pc_solver = ip[13]; o->mg_nu1 = ip[14]; o->mg_nu2 = ip[15]; o->mg_nuc = ip[16]; o->mg_cycles = ip[17];
     o->internal = ip[18];
+    o->sph = ip[19];
     o->corr_tol = dp[18];
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];
@@ -1433,6 +1568,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
         o->pn[d] = o->n[d] + 2 * o->gh[d];
     }
     o->N = (long)o->n[0] * o->n[1] * o->n[2];
+    if (o->sph) sph_tables(o);
     o->nlev = count_levels(o);
     o->P = (long)o->pn[0] * o->pn[1] * o->pn[2];
     o->nvar = 2 + o->ndim;

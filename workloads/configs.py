@@ -20,6 +20,9 @@ the paper relies on data that is not available:
 * ``rad`` a stratified layer in discrete hydrostatic equilibrium with a
   radiative conductivity chi = chi0 T^3 (a synthetic stand-in for the stellar
   envelope of paper section 6).
+* ``srad`` the same layer as a spherical shell segment in 2D spherical
+  geometry (r in [1, 2], a 0.25 rad wedge about the equator, walls on every
+  side, constant radial gravity), the geometry of paper section 6.
 
 Random numbers come from numpy's PCG64 generator with a fixed seed per
 problem; every draw is uniform on [-1, 1).
@@ -44,6 +47,11 @@ PCS_ADI = 1
 # energy variable of the state: total energy E, or internal energy rho e (eq. 2)
 ENERGY_TOTAL = 0
 ENERGY_INTERNAL = 1
+
+# grid geometry: Cartesian, or 2D spherical (axis 0 = radius r, axis 1 =
+# colatitude theta, azimuthal symmetry)
+GEOM_CARTESIAN = 0
+GEOM_SPHERICAL = 1
 
 CONFIG_NAMES = ("rt", "kh", "tg", "rad")
 
@@ -136,7 +144,8 @@ def mirror_x(u, desc):
     return join_state(out, desc)
 
 
-def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0, energy_form=ENERGY_TOTAL):
+def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0, energy_form=ENERGY_TOTAL,
+          geometry=GEOM_CARTESIAN):
     n = list(n) + [1] * (3 - len(n))
     lo = list(lo) + [0.0] * (3 - len(lo))
     hi = list(hi) + [1.0] * (3 - len(hi))
@@ -145,7 +154,7 @@ def _desc(ndim, n, lo, hi, bc, gamma, g, chi0=0.0, heat_balance=0, energy_form=E
     return dict(ndim=ndim, n=[int(v) for v in n], lo=[float(v) for v in lo],
                 hi=[float(v) for v in hi], bc=[int(v) for v in bc],
                 gamma=float(gamma), g=[float(v) for v in g], chi0=float(chi0),
-                heat_balance=int(heat_balance), energy_form=int(energy_form))
+                heat_balance=int(heat_balance), energy_form=int(energy_form), geometry=int(geometry))
 
 
 def _face_avg_rho(rho, axis, wall):
@@ -319,14 +328,51 @@ def _rad(n, seed, noise, perturb, internal):
     return desc, opts, u
 
 
-_BUILDERS = {"rt": (_rt, 0), "kh": (_kh, 1), "tg": (_tg, 2), "rad": (_rad, 3)}
+def _srad(n, seed, noise, perturb, internal):
+    nt = 128 if n is None else int(n)
+    nr = 4 * nt
+    r0, r1 = 1.0, 2.0
+    dr = (r1 - r0) / nr
+    th0, th1 = 0.5 * math.pi - 0.125, 0.5 * math.pi + 0.125
+    T = 1.0 + (10.0 ** (-4.0 / 3.0) - 1.0) * np.arange(nr) / (nr - 1)
+    g = -3.25 * (T[0] - T[-1]) / ((nr - 1) * dr)
+    desc = _desc(2, (nr, nt), (r0, th0), (r1, th1), (BC_WALL, BC_WALL), 5.0 / 3.0, (g, 0.0),
+                 chi0=RAD_CHI0, heat_balance=1, geometry=GEOM_SPHERICAL)
+    # radial two-cell hydrostatic balance, face density the mean of its cells
+    hg = 0.5 * abs(g) * dr
+    rho1 = np.empty(nr)
+    rho1[0] = 1.0
+    for i in range(nr - 1):
+        rho1[i + 1] = rho1[i] * (T[i] - hg) / (T[i + 1] + hg)
+    rho = np.ones((nt, 1)) * rho1[None, :]          # (theta, r) = (axis 1, axis 0)
+    p = rho * T[None, :]
+    vr = np.zeros((nt, nr))
+    vt = np.zeros((nt, nr))
+    if noise:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        vr = 1e-10 * rng.uniform(-1.0, 1.0, size=(nt, nr))
+        vt = 1e-10 * rng.uniform(-1.0, 1.0, size=(nt, nr))
+    vr[:, 0] = 0.0
+    vt[0, :] = 0.0
+    rho3, p3, vr3, vt3 = rho[None], p[None], vr[None], vt[None]
+    bc = desc["bc"]
+    mr = _face_avg_rho(rho3, 2, True) * vr3
+    mt = _face_avg_rho(rho3, 1, True) * vt3
+    E = _energy(p3, rho3, desc["gamma"], [vr3, vt3], bc, internal)
+    u = join_state(dict(rho=rho3, E=E, mx=mr, my=mt), desc)
+    opts = default_opts(cfl_hydro=10.0, cfl_rad_max=1000.0, pc=PC_ACOUSTIC_DIFFUSION,
+                        gmres_eta=LINEAR_TOL["rad"], mg_cycles=MG_CYCLES["rad"])
+    return desc, opts, u
+
+
+_BUILDERS = {"rt": (_rt, 0), "kh": (_kh, 1), "tg": (_tg, 2), "rad": (_rad, 3), "srad": (_srad, 5)}
 
 
 def make_config(name, n=None, seed=None, noise=True, perturb=True, energy_form=ENERGY_TOTAL, **opt_over):
     """Return (desc, opts, u0) for one of ``rt``, ``kh``, ``tg``, ``rad``.
 
     ``n`` rescales the grid keeping each problem's aspect ratio (rt: n x 2n,
-    kh: n x n, tg: n^3, rad: n x 4n).  ``noise``/``perturb`` switch off the
+    kh: n x n, tg: n^3, rad: n x 4n, srad: 4n radial x n polar cells).  ``noise``/``perturb`` switch off the
     seeded noise or the deterministic velocity perturbation.
     ``energy_form`` selects the energy variable (ENERGY_TOTAL or
     ENERGY_INTERNAL); the same pressure field gives the initial state.
