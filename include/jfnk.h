@@ -53,6 +53,7 @@ enum { JFNK_PC_NONE = 0, JFNK_PC_ACOUSTIC = 1, JFNK_PC_ACOUSTIC_DIFFUSION = 2 };
 enum { JFNK_PCS_MULTIGRID = 0, JFNK_PCS_ADI = 1 };
 enum { JFNK_FP64 = 0, JFNK_MIXED = 1 };
 enum { JFNK_ENERGY_TOTAL = 0, JFNK_ENERGY_INTERNAL = 1 };
+enum { JFNK_GEOM_CARTESIAN = 0, JFNK_GEOM_SPHERICAL = 1 };
 
 /* Problem: grid, boundaries, gas and forces (section 2). */
 typedef struct {
@@ -69,6 +70,14 @@ typedef struct {
                           conservative form; JFNK_ENERGY_INTERNAL: rho e,
                           eq. (2) as written (flux rho e u, -p div u at cell
                           centres, no gravitational work) */
+    int geometry;      /* JFNK_GEOM_CARTESIAN, or JFNK_GEOM_SPHERICAL: 2D
+                          (r, theta) with azimuthal symmetry (section 6):
+                          axis 0 the radius, axis 1 the colatitude (radians),
+                          walls on both axes, 0 < lo[0], 0 < theta < pi,
+                          radial gravity g[0] only, multigrid preconditioner
+                          only; volumes and areas per radian of azimuth.
+                          Passive scalars, the diagnostics and the eq. (17)
+                          error are Cartesian only (-4) */
 } jfnk_problem_desc;
 
 /* Solver options.  Defaults (jfnk_default_opts): rtol 1e-8, atol 1e-14,

@@ -17,6 +17,23 @@ constexpr int kRedBlocks = 2048;   // most blocks of a multi-dot reduction
 
 enum Bc : int { PERIODIC = 0, WALL = 1 };
 
+// Metric tables of a 2D spherical grid (axis 0 = radius r, axis 1 =
+// colatitude theta, azimuthal symmetry), in device memory, per radial index i
+// and colatitude index j, per radian of azimuth:
+//   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
+//     (cell volume Vr Vt);
+//   r2f[i] = r_{i-1/2}^2 (lower r-face area r2f Vt), rfa[i] = r_{i-1/2};
+//   hr2[i] = (r_{i+1/2}^2 - r_{i-1/2}^2)/2, stf[j] = sin th_{j-1/2}
+//     (lower theta-face area hr2 stf);
+//   rc[i] cell-centre radius, ith[i] = 1/(rc[i] dth);
+//   momentum control volumes: Vrc[i] = (rc_i^3 - rc_{i-1}^3)/3,
+//   r2c[i] = rc_i^2, hr2c[i] = (rc_i^2 - rc_{i-1}^2)/2,
+//   Vtc[j] = cos thc_{j-1} - cos thc_j, stc[j] = sin thc_j.
+struct SphMet {
+    const double *Vr, *rc, *ith, *hr2, *Vrc, *r2c, *hr2c, *r2f, *rfa;
+    const double *Vt, *Vtc, *stc, *stf;
+};
+
 // Geometry and physics constants passed by value to every kernel.
 struct Grid {
     int ndim;
@@ -30,7 +47,21 @@ struct Grid {
     int heat_balance;
     int has_wall, has_chi;
     int internal;  // energy variable rho e (eq. 2 as written) instead of E
+    int sph;       // 2D spherical geometry (metric tables M)
+    SphMet M;
 };
+
+// inverse distance between the centres of the two cells of a lower face
+// along d in radial row i (r dtheta along theta on spherical grids)
+__device__ __forceinline__ double face_ids(const Grid& G, int d, int i) {
+    return (G.sph && d == 1) ? G.M.ith[i] : G.idx[d];
+}
+// spherical cell volume and lower-face area along d of cell (i, j) (i may
+// be n0 and j n1 for the upper wall faces)
+__device__ __forceinline__ double sph_vol(const Grid& G, int i, int j) { return G.M.Vr[i] * G.M.Vt[j]; }
+__device__ __forceinline__ double sph_area(const Grid& G, int d, int i, int j) {
+    return d == 0 ? G.M.r2f[i] * G.M.Vt[j] : G.M.hr2[i] * G.M.stf[j];
+}
 
 // Cell coordinates from a flat index.
 struct Ijk {

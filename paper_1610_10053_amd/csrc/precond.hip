@@ -32,7 +32,9 @@ __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __rest
             hf = 0.5 * (hl + hr);
             if (G.has_chi) chif = 0.5 * (P.chi[xl] + P.chi[c]);
         }
-        const double i2 = G.idx[d] * G.idx[d];
+        // couplings per unit volume, or, on spherical grids, of the
+        // volume-weighted system: face area over centre distance
+        const double i2 = G.sph ? sph_area(G, d, q.v[0], q.v[1]) * face_ids(G, d, q.v[0]) : G.idx[d] * G.idx[d];
         C.hf[d][c] = hf;
         C.kap[d][c] = ((tau * tau) * G.gm1) * hf * i2;
         C.beta[d][c] = (tau * chif) * i2;
@@ -121,7 +123,12 @@ __global__ void __launch_bounds__(kBlock) k_level0(Grid G, PcCoef C, int which, 
     LIjk q;
     int c;
     if (!lcell(L, q, c)) return;
-    L.sig[c] = which == 0 ? (R)1.0 : (R)(1.0 / C.W[c]);
+    if (G.sph) {  // volume-weighted system: sigma = V (acoustic) or V / W (conduction)
+        const double V = sph_vol(G, q.v[0], q.v[1]);
+        L.sig[c] = which == 0 ? (R)V : (R)(V / C.W[c]);
+    } else {
+        L.sig[c] = which == 0 ? (R)1.0 : (R)(1.0 / C.W[c]);
+    }
     for (int d = 0; d < ND; ++d) L.a[d][c] = which == 0 ? (R)C.kap[d][c] : (R)C.beta[d][c];
 }
 
@@ -619,9 +626,17 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
             const long up = shifted(G, q, d, 1);
             fhi = C.hf[d][up] * (s * vm[up]);
         }
-        acc = acc + (fhi - flo) * G.idx[d];
+        if (G.sph) {
+            const int i = q.v[0], j = q.v[1];
+            const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+            acc = acc + (Ahi * fhi - Alo * flo) / sph_vol(G, i, j);
+        } else {
+            acc = acc + (fhi - flo) * G.idx[d];
+        }
     }
-    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)(G.gm1 * (re - C.tau * acc));
+    double rp = G.gm1 * (re - C.tau * acc);
+    if (G.sph) rp = rp * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)rp;
 }
 
 template <typename R, int ND>
@@ -631,7 +646,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
     long c;
     if (!cell_from_launch(G, q, c)) return;
     const R* __restrict__ s = L0.x;
-    double acc = sc.v[1] * v[G.N + c];
+    double acc = G.sph ? 0.0 : sc.v[1] * v[G.N + c];
     const double sc0 = (double)s[xbi(L0, q.v[0], q.v[1], q.v[2])];
     for (int d = 0; d < ND; ++d) {
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
@@ -644,7 +659,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
         if (!bot) tlo = C.beta[d][c] * (sc0 - (double)s[xb_shifted(L0, q, d, -1)]);
         acc = acc + (thi - tlo);
     }
-    rE[c] = acc;
+    rE[c] = G.sph ? sc.v[1] * v[G.N + c] + acc / sph_vol(G, q.v[0], q.v[1]) : acc;
 }
 
 template <typename R, int ND>
@@ -667,7 +682,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             if (G.bc[d] == WALL && q.v[d] == 0) {
                 dmlo[d] = 0.0;
             } else {
-                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * G.idx[d]);
+                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * face_ids(G, d, q.v[0]));
             }
             top[d] = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             dmhi[d] = 0.0;
@@ -675,17 +690,25 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             if (!top[d]) {
                 const long up = shifted(G, q, d, 1);
                 upi[d] = up;
-                dmhi[d] = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * G.idx[d]);
+                dmhi[d] = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * face_ids(G, d, q.v[0]));
             }
         }
+        // divergence of face values: (hi - lo)/dx, or on spherical grids
+        // (A_hi hi - A_lo lo)/V
+        auto divterm = [&](int d, double hi, double lo) {
+            if (!G.sph) return (hi - lo) * G.idx[d];
+            const int i = q.v[0], j = q.v[1];
+            const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+            return (Ahi * hi - Alo * lo) / sph_vol(G, i, j);
+        };
         double acc = 0.0;
-        for (int d = 0; d < ND; ++d) acc = acc + (dmhi[d] - dmlo[d]) * G.idx[d];
+        for (int d = 0; d < ND; ++d) acc = acc + divterm(d, dmhi[d], dmlo[d]);
         const double drho = sc.v[0] * v[c] - C.tau * acc;
         acc = 0.0;
         for (int d = 0; d < ND; ++d) {
             const double flo = C.hf[d][c] * dmlo[d];
             const double fhi = top[d] ? 0.0 : C.hf[d][upi[d]] * dmhi[d];
-            acc = acc + (fhi - flo) * G.idx[d];
+            acc = acc + divterm(d, fhi, flo);
         }
         const double dE = re - C.tau * acc;
         double t = drho / sc.v[0];
@@ -718,7 +741,9 @@ __global__ void __launch_bounds__(kBlock) k_field_to_level(Grid G, const double*
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)(s * v[c]);
+    double b = s * v[c];
+    if (G.sph) b = b * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)b;
 }
 
 __global__ void __launch_bounds__(kBlock) k_copy_sumsq(const double* __restrict__ v, double* __restrict__ z,

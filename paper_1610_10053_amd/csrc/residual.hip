@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
         if (G.has_chi) {
             const double chiL = d < 2 ? sm.chi[ty - oy][tx - ox] : P.chi[L], chic = d < 2 ? sm.chi[ty][tx] : P.chi[c];
             const double TL = d < 2 ? sm.T[ty - oy][tx - ox] : P.T[L], Tc = d < 2 ? sm.T[ty][tx] : P.T[c];
-            f_e = f_e + ((-0.5 * (chiL + chic)) * (Tc - TL)) * G.idx[d];
+            f_e = f_e + ((-0.5 * (chiL + chic)) * (Tc - TL)) * face_ids(G, d, q.v[0]);
         }
         Fx.fr[d][c] = f_rho;
         Fx.fe[d][c] = f_e;
@@ -263,6 +263,53 @@ __global__ void __launch_bounds__(kBlock) k_mflux(Grid G, Prim P, Flux Fx) {
     }
 }
 
+// Momentum right-hand side on a 2D spherical grid, on the staggered control
+// volume of the lower d-face of cell q (not a wall face): transport fluxes
+// through the volume's sides times their areas over its volume, the pressure
+// gradient across the face, radial gravity, and the geometric terms
+// +rho u_th^2 / r (radial) and -rho u_r u_th / r (polar) with the face
+// density and the other component's mean over the four faces around.
+__device__ __forceinline__ double sph_momentum(const Grid& G, const Prim& P, const Flux& Fx, const Ijk& q, long c,
+                                               int d) {
+    const SphMet& M = G.M;
+    const int i = q.v[0], j = q.v[1];
+    const long n0 = G.n[0];
+    double a = 0.0;
+    if (d == 0) {
+        const long cl = c - 1;  // i - 1 (i >= 1: the wall face is excluded)
+        const bool topj = j == G.n[1] - 1;
+        const double rf = 0.5 * (P.rho[cl] + P.rho[c]);
+        const double V = M.Vrc[i] * M.Vt[j];
+        const double Ahi = M.r2c[i] * M.Vt[j], Alo = M.r2c[i - 1] * M.Vt[j];
+        a = a - (Ahi * Fx.phic[0][c] - Alo * Fx.phic[0][cl]) / V;
+        const double Bhi = M.hr2c[i] * M.stf[j + 1], Blo = M.hr2c[i] * M.stf[j];
+        const double ehi = topj ? 0.0 : Fx.phie[0][1][c + n0];
+        a = a - (Bhi * ehi - Blo * Fx.phie[0][1][c]) / V;
+        a = a - (P.p[c] - P.p[cl]) * G.idx[0];
+        if (G.g[0] != 0.0) a = a + rf * G.g[0];
+        const double u1 = P.uf[1][cl], u2 = topj ? 0.0 : P.uf[1][cl + n0];
+        const double u3 = P.uf[1][c], u4 = topj ? 0.0 : P.uf[1][c + n0];
+        const double ut2 = 0.25 * (((u1 * u1 + u2 * u2) + u3 * u3) + u4 * u4);
+        a = a + rf * ut2 / M.rfa[i];
+    } else {
+        const long cl = c - n0;  // j - 1 (j >= 1)
+        const bool topi = i == G.n[0] - 1;
+        const double rf = 0.5 * (P.rho[cl] + P.rho[c]);
+        const double V = M.Vr[i] * M.Vtc[j];
+        const double Ahi = M.r2f[i + 1] * M.Vtc[j], Alo = M.r2f[i] * M.Vtc[j];
+        const double ehi = topi ? 0.0 : Fx.phie[1][0][c + 1];
+        a = a - (Ahi * ehi - Alo * Fx.phie[1][0][c]) / V;
+        const double Bhi = M.hr2[i] * M.stc[j], Blo = M.hr2[i] * M.stc[j - 1];
+        a = a - (Bhi * Fx.phic[1][c] - Blo * Fx.phic[1][cl]) / V;
+        a = a - (P.p[c] - P.p[cl]) * M.ith[i];
+        const double ua = P.uf[0][cl], ub = topi ? 0.0 : P.uf[0][cl + 1];
+        const double uc = P.uf[0][c], ud = topi ? 0.0 : P.uf[0][c + 1];
+        const double ur = 0.25 * (((ua + ub) + uc) + ud);
+        a = a - rf * ur * P.uf[1][c] / M.rc[i];
+    }
+    return a;
+}
+
 template <int ND>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o) {
@@ -284,6 +331,15 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 frh = Fx.fr[d][cu];
                 feh = Fx.fe[d][cu];
             }
+            if (G.sph) {
+                // (1/V) sum of area-weighted face fluxes
+                const int i = q.v[0], j = q.v[1];
+                const double V = sph_vol(G, i, j);
+                const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+                ar = ar - (Ahi * frh - Alo * Fx.fr[d][c]) / V;
+                ae = ae - (Ahi * feh - Alo * Fx.fe[d][c]) / V;
+                continue;
+            }
             ar = ar - (frh - Fx.fr[d][c]) * G.idx[d];
             ae = ae - (feh - Fx.fe[d][c]) * G.idx[d];
         }
@@ -294,6 +350,13 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
                 const double ulo = P.uf[d][c];
                 const double uhi = top ? 0.0 : P.uf[d][shifted(G, q, d, 1)];
+                if (G.sph) {
+                    const int i = q.v[0], j = q.v[1];
+                    const double V = sph_vol(G, i, j);
+                    const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+                    ae = ae - pc * ((Ahi * uhi - Alo * ulo) / V);
+                    continue;
+                }
                 ae = ae - pc * ((uhi - ulo) * G.idx[d]);
             }
         } else {
@@ -312,6 +375,10 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         for (int d = 0; d < ND; ++d) {
             if (G.bc[d] == WALL && q.v[d] == 0) {
                 R[2 + d] = 0.0;
+                continue;
+            }
+            if (G.sph) {
+                R[2 + d] = sph_momentum(G, P, Fx, q, c, d);
                 continue;
             }
             double a = 0.0;
@@ -386,11 +453,12 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
             const double a = fabs(P.uf[d][c]);
             const double b = top ? 0.0 : fabs(P.uf[d][shifted(G, q, d, 1)]);
             const double ud = a > b ? a : b;
-            hyd = fmax(hyd, (ud + cs) * G.idx[d]);
-            adv = fmax(adv, ud * G.idx[d]);
+            const double ids = face_ids(G, d, q.v[0]);
+            hyd = fmax(hyd, (ud + cs) * ids);
+            adv = fmax(adv, ud * ids);
             if (G.has_chi) {
                 const double D = P.chi[c] / (r * cp);
-                rad = fmax(rad, D * (G.idx[d] * G.idx[d]));
+                rad = fmax(rad, D * (ids * ids));
             }
         }
         rmax = r;

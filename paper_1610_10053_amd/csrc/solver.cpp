@@ -150,6 +150,19 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (d->chi0 < 0.0) return fail(-1, "chi0 must be >= 0");
     if (d->energy_form != JFNK_ENERGY_TOTAL && d->energy_form != JFNK_ENERGY_INTERNAL)
         return fail(-1, "unknown energy_form");
+    if (d->geometry != JFNK_GEOM_CARTESIAN && d->geometry != JFNK_GEOM_SPHERICAL)
+        return fail(-1, "unknown geometry");
+    if (d->geometry == JFNK_GEOM_SPHERICAL) {
+        if (d->ndim != 2) return fail(-4, "spherical geometry is two-dimensional (r, theta)");
+        if (d->bc[0] != JFNK_BC_WALL || d->bc[1] != JFNK_BC_WALL)
+            return fail(-4, "spherical geometry needs walls on both axes");
+        if (!(d->lo[0] > 0.0)) return fail(-1, "spherical geometry needs r > 0");
+        if (!(d->lo[1] > 0.0) || !(d->hi[1] < 3.141592653589793))
+            return fail(-1, "spherical geometry needs 0 < theta < pi");
+        if (d->g[1] != 0.0) return fail(-4, "spherical geometry takes radial gravity only (g[1] = 0)");
+        if (o->pc_solver != JFNK_PCS_MULTIGRID)
+            return fail(-4, "spherical geometry supports the multigrid preconditioner only");
+    }
     if (o->gmres_restart < 1 || o->gmres_restart > kMaxRestart) return fail(-1, "gmres_restart out of range");
     if (o->gmres_max_cycles < 0 || o->newton_max < 0) return fail(-1, "negative iteration limits");
     if (o->pc < JFNK_PC_NONE || o->pc > JFNK_PC_ACOUSTIC_DIFFUSION) return fail(-1, "unknown preconditioner");
@@ -187,6 +200,70 @@ void make_grid(const jfnk_problem_desc& d, Grid& G) {
     G.has_chi = d.chi0 != 0.0;
     G.heat_balance = d.heat_balance && d.chi0 != 0.0;
     G.internal = d.energy_form == JFNK_ENERGY_INTERNAL ? 1 : 0;
+    G.sph = d.geometry == JFNK_GEOM_SPHERICAL ? 1 : 0;
+}
+
+// entries of the spherical metric tables (SphMet): seven of n0, two of
+// n0 + 1, three of n1, one of n1 + 1
+long sph_table_len(const Grid& G) { return 7L * G.n[0] + 2L * (G.n[0] + 1) + 3L * G.n[1] + (G.n[1] + 1); }
+
+// the metric tables on the host, in the order of SphMet's members
+void sph_tables(const jfnk_problem_desc& d, const Grid& G, std::vector<double>& t) {
+    const int nr = G.n[0], nt = G.n[1];
+    const double dr = G.dx[0], dth = G.dx[1], r0 = d.lo[0], t0 = d.lo[1];
+    std::vector<double> Vr(nr), rc(nr), ith(nr), hr2(nr), Vrc(nr, 0.0), r2c(nr), hr2c(nr, 0.0), r2f(nr + 1),
+        rfa(nr + 1), Vt(nt), Vtc(nt, 0.0), stc(nt), stf(nt + 1);
+    for (int i = 0; i <= nr; ++i) {
+        const double r = r0 + i * dr;
+        rfa[i] = r;
+        r2f[i] = r * r;
+    }
+    for (int i = 0; i < nr; ++i) {
+        const double a = rfa[i], b = rfa[i + 1];
+        Vr[i] = (b * b * b - a * a * a) / 3.0;
+        hr2[i] = 0.5 * (b * b - a * a);
+        rc[i] = r0 + (i + 0.5) * dr;
+        ith[i] = 1.0 / (rc[i] * dth);
+        r2c[i] = rc[i] * rc[i];
+    }
+    for (int i = 1; i < nr; ++i) {
+        const double a = rc[i - 1], b = rc[i];
+        Vrc[i] = (b * b * b - a * a * a) / 3.0;
+        hr2c[i] = 0.5 * (b * b - a * a);
+    }
+    for (int j = 0; j <= nt; ++j) stf[j] = std::sin(t0 + j * dth);
+    for (int j = 0; j < nt; ++j) {
+        Vt[j] = std::cos(t0 + j * dth) - std::cos(t0 + (j + 1) * dth);
+        stc[j] = std::sin(t0 + (j + 0.5) * dth);
+    }
+    for (int j = 1; j < nt; ++j) Vtc[j] = std::cos(t0 + (j - 0.5) * dth) - std::cos(t0 + (j + 0.5) * dth);
+    t.clear();
+    for (const std::vector<double>* v : {&Vr, &rc, &ith, &hr2, &Vrc, &r2c, &hr2c, &r2f, &rfa, &Vt, &Vtc, &stc, &stf})
+        t.insert(t.end(), v->begin(), v->end());
+}
+
+// point G.M into a device copy of the tables at dev (sph_table_len entries)
+void sph_bind(Grid& G, const double* dev) {
+    const long n0 = G.n[0], n1 = G.n[1];
+    const double* q = dev;
+    auto take = [&](long n) {
+        const double* r = q;
+        q += n;
+        return r;
+    };
+    G.M.Vr = take(n0);
+    G.M.rc = take(n0);
+    G.M.ith = take(n0);
+    G.M.hr2 = take(n0);
+    G.M.Vrc = take(n0);
+    G.M.r2c = take(n0);
+    G.M.hr2c = take(n0);
+    G.M.r2f = take(n0 + 1);
+    G.M.rfa = take(n0 + 1);
+    G.M.Vt = take(n1);
+    G.M.Vtc = take(n1);
+    G.M.stc = take(n1);
+    G.M.stf = take(n1 + 1);
 }
 
 // multigrid depth: halve every active axis while all are even and >= 4
@@ -856,17 +933,18 @@ __global__ void k_wall_flux(Grid G, Prim P, int d, double* lo, double* hi) {
     const long c1 = flat(G, q.v[0], q.v[1], q.v[2]);
     double Tg = 2.0 * P.T[c0] - P.T[c1];
     double chig = G.chi0 * (Tg * Tg * Tg);
-    lo[t] = ((-0.5 * (chig + P.chi[c0])) * (P.T[c0] - Tg)) * G.idx[d];
+    lo[t] = ((-0.5 * (chig + P.chi[c0])) * (P.T[c0] - Tg)) * face_ids(G, d, q.v[0]);
     q.v[d] = G.n[d] - 1;
     const long cn = flat(G, q.v[0], q.v[1], q.v[2]);
     q.v[d] = G.n[d] - 2;
     const long cm = flat(G, q.v[0], q.v[1], q.v[2]);
     Tg = 2.0 * P.T[cn] - P.T[cm];
     chig = G.chi0 * (Tg * Tg * Tg);
-    hi[t] = ((-0.5 * (P.chi[cn] + chig)) * (Tg - P.T[cn])) * G.idx[d];
+    hi[t] = ((-0.5 * (P.chi[cn] + chig)) * (Tg - P.T[cn])) * face_ids(G, d, q.v[0]);
 }
 
-// heat-balance source: + sum_d (f_T(up) - f_T(lo)) / dx of the conductive flux
+// heat-balance source: + the divergence of the conductive flux, sum_d
+// (f_T(up) - f_T(lo)) / dx (spherical: area-weighted over the cell volume)
 __global__ void k_sbal(Grid G, Prim P, WallFlux W, double* sbal) {
     Ijk q;
     long c;
@@ -878,15 +956,21 @@ __global__ void k_sbal(Grid G, Prim P, WallFlux W, double* sbal) {
             flo = W.lo[d] ? W.lo[d][transverse(G, q, d)] : 0.0;
         } else {
             const long l = shifted(G, q, d, -1);
-            flo = ((-0.5 * (P.chi[l] + P.chi[c])) * (P.T[c] - P.T[l])) * G.idx[d];
+            flo = ((-0.5 * (P.chi[l] + P.chi[c])) * (P.T[c] - P.T[l])) * face_ids(G, d, q.v[0]);
         }
         if (G.bc[d] == WALL && q.v[d] == G.n[d] - 1) {
             fhi = W.hi[d] ? W.hi[d][transverse(G, q, d)] : 0.0;
         } else {
             const long up = shifted(G, q, d, 1);
-            fhi = ((-0.5 * (P.chi[c] + P.chi[up])) * (P.T[up] - P.T[c])) * G.idx[d];
+            fhi = ((-0.5 * (P.chi[c] + P.chi[up])) * (P.T[up] - P.T[c])) * face_ids(G, d, q.v[0]);
         }
-        acc = acc + (fhi - flo) * G.idx[d];
+        if (G.sph) {
+            const int i = q.v[0], j = q.v[1];
+            const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
+            acc = acc + (Ahi * fhi - Alo * flo) / sph_vol(G, i, j);
+        } else {
+            acc = acc + (fhi - flo) * G.idx[d];
+        }
     }
     sbal[c] = acc;
 }
@@ -925,6 +1009,7 @@ size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]
     for (int d = 0; d < G.ndim; ++d)                                              // frozen wall fluxes
         if (G.bc[d] == WALL && G.has_chi) b += 2 * (size_t)G.n[(d + 1) % 3] * G.n[(d + 2) % 3] * 8;
     if (G.heat_balance) b += N * 8;                                               // heat-balance source
+    if (G.sph) b += (size_t)sph_table_len(G) * 8;                                 // spherical metric
     b += 10 * N * 8 + N * 8 + 4 * N * 8;                                          // pc coefficients, rE, lines
     const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
     for (int l = 0; l < nlev; ++l) b += 2 * level_bytes(nl[l], l == nlev - 1, rs);  // two operators
@@ -1088,6 +1173,17 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         }
     }
     if (G.heat_balance) AL(p->sbal, N);
+    if (G.sph) {
+        double* met = nullptr;
+        AL(met, (size_t)sph_table_len(G));
+        std::vector<double> tab;
+        sph_tables(*desc, G, tab);
+        if (hipMemcpyAsync(met, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice, p->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(p->stream) != hipSuccess)
+            return cleanup(fail(-3, "copy of the spherical metric"));
+        sph_bind(p->G, met);
+    }
     double* pcb = nullptr;
     AL(pcb, (size_t)10 * N);
     for (int d = 0; d < 3; ++d) {
@@ -1100,10 +1196,10 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     AL(p->lines, (size_t)4 * N);
     const bool split = opts->pc_solver == JFNK_PCS_MULTIGRID;
     if (opts->prec == JFNK_MIXED) {
-        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl, true, split))) return cleanup(rc);
+        if ((rc = alloc_levels<float>(p, p->ac32, &p->dac32, nl, !G.sph, split))) return cleanup(rc);
         if ((rc = alloc_levels<float>(p, p->df32, &p->ddf32, nl, false, split))) return cleanup(rc);
     } else {
-        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, true, split))) return cleanup(rc);
+        if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, !G.sph, split))) return cleanup(rc);
         if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl, false, split))) return cleanup(rc);
     }
     AL(p->part, (size_t)p->npart);
@@ -1154,6 +1250,7 @@ int jfnk_get_state(jfnk_problem* p, double* u, int on_device) {
 int jfnk_set_scalars(jfnk_problem* p, int nscal, int renormalize, const double* s, int on_device) {
     if (!p || nscal < 0 || (nscal > 0 && !s)) return fail(-1, "bad scalar arguments");
     if (p->slab) return fail(-4, "passive scalars need their own device memory (not a caller-provided range)");
+    if (p->G.sph && nscal > 0) return fail(-4, "passive scalars are for Cartesian grids");
     HIPCHK(hipStreamSynchronize(p->stream));
     for (void* q : p->sbuf.ptrs) (void)hipFree(q);
     p->sbuf.ptrs.clear();
@@ -1327,6 +1424,7 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
                           int mix_axis, jfnk_diagnostics* out) {
     if (!p || !out) return fail(-1, "null argument");
     const Grid& G = p->G;
+    if (G.sph) return fail(-4, "diagnostics are for Cartesian grids");
     if (mix_axis >= G.ndim || mix_axis < -1) return fail(-1, "mix_axis must be -1 or a grid axis");
     if (mix_axis >= 0 && !(rho_heavy != rho_light)) return fail(-1, "rho_heavy must differ from rho_light");
     if (mix_axis >= 0 && 4L * p->ncell_blk + G.n[mix_axis] > (long)p->npart)
@@ -1359,6 +1457,7 @@ int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_hi
                         int axis, double* out) {
     if (!p || !u_high || !out) return fail(-1, "null argument");
     const Grid& G = p->G;
+    if (G.sph) return fail(-4, "the eq. (17) error is for Cartesian grids");
     if (ratio < 1 || ratio > 1024) return fail(-1, "ratio must lie in 1..1024");
     if (axis < 0 || axis >= G.ndim) return fail(-1, "axis must be a grid axis");
     Grid Gh = G;

@@ -23,7 +23,7 @@ FP64, MIXED = 0, 1
 class ProblemDesc(C.Structure):
     _fields_ = [("ndim", C.c_int), ("n", C.c_int * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
                 ("bc", C.c_int * 3), ("gamma", C.c_double), ("g", C.c_double * 3), ("chi0", C.c_double),
-                ("heat_balance", C.c_int), ("energy_form", C.c_int)]
+                ("heat_balance", C.c_int), ("energy_form", C.c_int), ("geometry", C.c_int)]
 
 
 class SolverOpts(C.Structure):
@@ -153,7 +153,7 @@ def default_opts():
 
 def make_desc(d):
     """ProblemDesc from a dict with keys ndim, n, lo, hi, bc, gamma, g, chi0, heat_balance
-    (and optionally energy_form)."""
+    (and optionally energy_form, geometry)."""
     pd = ProblemDesc()
     pd.ndim = d["ndim"]
     for a in range(3):
@@ -166,6 +166,7 @@ def make_desc(d):
     pd.chi0 = d["chi0"]
     pd.heat_balance = d["heat_balance"]
     pd.energy_form = d.get("energy_form", 0)
+    pd.geometry = d.get("geometry", 0)
     return pd
 
 

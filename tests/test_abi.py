@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_header_sizes():
     import ctypes as C
     from paper_1610_10053_amd import jfnk
-    assert C.sizeof(jfnk.ProblemDesc) == 128
+    assert C.sizeof(jfnk.ProblemDesc) == 136
     assert C.sizeof(jfnk.SolverOpts) == 120
     assert C.sizeof(jfnk.StepStats) == 120
     assert C.sizeof(jfnk.RequestStats) == 72

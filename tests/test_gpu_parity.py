@@ -214,6 +214,93 @@ def test_internal_energy_form_mixed_precision(torch_cuda):
     assert rel_l2(out[1], out[0]) <= 1e-8
 
 
+# ---------------------------------------------------------------- 2D spherical geometry
+
+def _sph_flow(n, internal=False):
+    """a spherical wedge (r in [1, 2], theta in [pi/4, 3pi/4], walls) with a
+    smooth flow, radial gravity and conduction: every geometric term active"""
+    import math
+    from _helpers import state_from_primitive
+    from workloads import default_opts
+    desc = dict(ndim=2, n=[n, n, 1], lo=[1.0, math.pi / 4, 0.0], hi=[2.0, 3 * math.pi / 4, 1.0],
+                bc=[1, 1, 0], gamma=5.0 / 3.0, g=[-0.7, 0.0, 0.0], chi0=0.05, heat_balance=0,
+                energy_form=ENERGY_INTERNAL if internal else 0, geometry=1)
+    rho = lambda x, y, z: 1.0 + 0.2 * np.sin(2.0 * x) * np.cos(2.0 * y)
+    ur = lambda x, y, z: 0.02 + 0.01 * np.sin(3.0 * x) * np.cos(y)
+    ut = lambda x, y, z: -0.015 + 0.01 * np.cos(2.0 * x) * np.sin(3.0 * y)
+    p = lambda x, y, z: 1.0 + 0.1 * np.cos(2.0 * x - y)
+    u = np.where(unknown_mask(desc), state_from_primitive(desc, rho, (ur, ut), p), 0.0)
+    opts = default_opts(cfl_hydro=4.0, pc=PC_ACOUSTIC_DIFFUSION, gmres_eta=1e-2)
+    return desc, opts, u
+
+
+def _sph_pair(kind, n):
+    from oracle import Oracle
+    jfnk = _lib()
+    if kind == "srad":
+        desc, opts, u = make_config("srad", n=n)
+    else:
+        desc, opts, u = _sph_flow(n, internal=(kind == "flow_internal"))
+    print("case", kind, n, flush=True)
+    return desc, opts, u, jfnk.Problem(desc, opts, u), Oracle(desc, opts, u)
+
+
+@pytest.mark.parametrize("kind,n", [("srad", 8), ("srad", 32), ("flow", 16), ("flow", 48), ("flow_internal", 16)])
+def test_spherical_components(torch_cuda, kind, n):
+    """residual, time step and preconditioner bit for bit, Jv to 1e-9"""
+    desc, opts, u, g, o = _sph_pair(kind, n)
+    assert np.array_equal(g.eval_rhs(u), o.rhs(u))
+    tg, to = g.eval_time_step(u), o.time_step(u)
+    assert tg["dt"] == to["dt"] and np.array_equal(tg["scales"], to["scales"])
+    dt = to["dt"]
+    b = o.cn_old(u, dt)
+    assert np.array_equal(g.eval_cn_old(u, dt), b)
+    u1 = u + 1e-3 * np.abs(u) * _direction(desc, 10)
+    assert np.array_equal(g.eval_residual(u1, b, dt), o.residual(u1, b, dt))
+    v = _direction(desc, 11)
+    assert rel_l2(g.apply_jv(u1, b, dt, v), o.jv(u1, b, dt, v)) < 1e-9
+    assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
+
+
+@pytest.mark.parametrize("kind,n,steps", [("srad", 16, 3), ("flow", 32, 3), ("flow_internal", 16, 2)])
+def test_spherical_steps(torch_cuda, kind, n, steps):
+    """implicit steps from identical states: same dt and iteration counts,
+    states within 1e-10"""
+    desc, opts, u, g, o = _sph_pair(kind, n)
+    for k in range(steps):
+        o.set_state(g.get_state())
+        rg, sg = g.implicit_step()
+        ro, so = o.implicit_step()
+        assert rg == 0 and ro == 0
+        assert sg["dt"] == so["dt"]
+        assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+        e = rel_l2(g.get_state(), o.get_state())
+        print("step", k, sg["newton_its"], sg["gmres_its"], e, flush=True)
+        assert e <= 1e-10
+
+
+def test_spherical_mixed_precision_and_rejections(torch_cuda):
+    """the mixed form converges to the FP64 answer; Cartesian-only calls
+    refuse a spherical problem"""
+    jfnk = _lib()
+    desc, opts, u = make_config("srad", n=16)
+    out = []
+    for prec in (0, PREC_MIXED):
+        opts["prec"] = prec
+        p = jfnk.Problem(desc, opts, u)
+        for _ in range(2):
+            rc, st = p.implicit_step()
+            assert rc == 0
+        out.append(p.get_state())
+        if prec == 0:
+            with pytest.raises(jfnk.JfnkError):
+                p.eval_diagnostics(None)
+            with pytest.raises(jfnk.JfnkError):
+                p.set_scalars(np.ones(p.N), 1)
+        p.close()
+    assert rel_l2(out[1], out[0]) <= 1e-8
+
+
 # ---------------------------------------------------------------- invariants on the GPU path
 
 @pytest.mark.parametrize("name,n", [("kh", 64), ("tg", 16)])
