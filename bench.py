@@ -233,6 +233,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-geometries", action="store_true",
+                    help="skip the radiative layer in Cartesian and spherical geometry")
+    ap.add_argument("--geo-steps", type=int, default=20)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", default="10,60", help="lo,hi implicit steps per request")
     ap.add_argument("--serve-active", type=int, default=8)
@@ -315,6 +318,21 @@ def main():
         sf.pop("kernels")
         sf["speedup_vs_%s" % main_form] = sf["value"] / s0["value"]
         out.setdefault("forms", {})[f] = sf
+    if not args.no_geometries:
+        # the radiative layer (conduction block in the preconditioner) as a
+        # Cartesian box and as a spherical shell segment of the same cell count
+        geo = {}
+        for name in ("rad", "srad"):
+            log("geometry", name)
+            d_g, o_g, u_g = make_config(name)
+            r = run_form(jfnk, torch, d_g, o_g, u_g, args.geo_steps, 1, prof=False)
+            nc = d_g["n"][0] * d_g["n"][1] * d_g["n"][2]
+            geo[name] = dict(grid=d_g["n"][:2], geometry="spherical (r, theta)" if name == "srad" else "cartesian",
+                             steps=args.geo_steps, ms_per_step=1e3 * r["wall"] / args.geo_steps,
+                             value=nc * args.geo_steps / r["wall"], unit="cell-steps/s",
+                             newton_its_per_step=float(np.mean([st["newton_its"] for st in r["stats"]])),
+                             gmres_its_per_step=float(np.mean([st["gmres_its"] for st in r["stats"]])))
+        out["radiative_layer"] = geo
     if not args.no_serve:
         out["serving"] = serving(jfnk, args)
     if not args.no_cpu_baseline:
