@@ -66,6 +66,7 @@ typedef struct {
     double rtol, atol, eta, cfl_hydro, cfl_adv_max, cfl_rad_max, dt_max;
     int newton_max, restart, max_cycles, pc, max_halvings;
     int pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles;
+    int mg_light; /* levels of at most this many cells: one pre- and one post-sweep (0: off) */
     double corr_tol;
     /* spherical metric, per radial index i and colatitude index j:
      *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
@@ -916,7 +917,8 @@ static void mg_residual(const Or *o, Level *L) {
 static void mg_vcycle(Or *o, Level *lev, int l) {
     Level *L = &lev[l];
     if (l == o->nlev - 1) { mg_smooth(o, L, o->mg_nuc); return; }
-    mg_smooth(o, L, o->mg_nu1);
+    int light = o->mg_light > 0 && L->N <= o->mg_light;
+    mg_smooth(o, L, light ? 1 : o->mg_nu1);
     mg_residual(o, L);
     Level *C = &lev[l + 1];
     int nch = 1 << o->ndim;
@@ -958,7 +960,7 @@ static void mg_vcycle(Or *o, Level *lev, int l) {
         }
         L->x[lidx(L, i, j, k)] = L->x[lidx(L, i, j, k)] + e;
     }
-    mg_smooth(o, L, o->mg_nu2);
+    mg_smooth(o, L, light ? 1 : o->mg_nu2);
 }
 
 /* approximate solve of M x = b by V-cycles from x = 0 (a fixed linear map) */
@@ -1544,7 +1546,8 @@ static void or_free(Or *o) {
 
 /* ip: ndim, n0, n1, n2, bc0, bc1, bc2, heat_balance, newton_max, restart,
  *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles,
- *     energy form (0 total, 1 internal), geometry (0 Cartesian, 1 2D spherical)
+ *     energy form (0 total, 1 internal), geometry (0 Cartesian, 1 2D spherical),
+ *     mg_light (levels of at most this many cells take V(1,1), 0 = off)
  * dp: lo0..2, hi0..2, gamma, g0..2, chi0, rtol, atol, eta, cfl_hydro,
  *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol */
 void *or_create(const int *ip, const double *dp, const double *u0) {
@@ -1556,6 +1559,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->pc_solver = ip[13]; o->mg_nu1 = ip[14]; o->mg_nu2 = ip[15]; o->mg_nuc = ip[16]; o->mg_cycles = ip[17];
     o->internal = ip[18];
     o->sph = ip[19];
+    o->mg_light = ip[20];
     o->corr_tol = dp[18];
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];

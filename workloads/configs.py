@@ -75,6 +75,12 @@ LINEAR_TOL = {"rt": 1e-2, "kh": 3e-2, "tg": 2e-1, "rad": 5e-3}
 # the shear layer and the Rayleigh-Taylor problem.
 MG_CYCLES = {"rt": 1, "kh": 1, "tg": 2, "rad": 3}
 
+# Levels of at most this many cells take one pre- and one post-smoothing sweep
+# instead of two (0: none), from GPU runs like the cycles: for TG 128^3 the
+# 32^3 level and below (54.5 -> 52.6 ms/step, GMRES 34.8 -> 35.3 per step;
+# including the 64^3 level: 53.5; V(1,0) there: 52.8).
+MG_LIGHT_CELLS = {"rt": 0, "kh": 0, "tg": 32768, "rad": 0}
+
 
 def default_opts(**over):
     """Solver options: Newton relative tolerance 1e-8, GMRES(30) to a
@@ -85,7 +91,7 @@ def default_opts(**over):
              pc=PC_ACOUSTIC, prec=PREC_FP64, cfl_hydro=1.0,
              cfl_adv_max=0.0, cfl_rad_max=0.0, dt_max=0.0, max_halvings=5,
              pc_solver=PCS_MULTIGRID, mg_nu1=2, mg_nu2=2, mg_nuc=4, mg_cycles=1,
-             newton_corr_tol=1e-12)
+             newton_corr_tol=1e-12, mg_light_cells=0)
     for k, v in over.items():
         if k not in o:
             raise KeyError(k)
@@ -286,7 +292,8 @@ def _tg(n, seed, noise, perturb, internal):
     mz = _face_avg_rho(rho, 0, False) * uz
     E = _energy(p, rho, gamma, [ux, uy, uz], bc, internal)
     u = join_state(dict(rho=rho, E=E, mx=mx, my=my, mz=mz), desc)
-    opts = default_opts(cfl_hydro=20.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["tg"], mg_cycles=MG_CYCLES["tg"])
+    opts = default_opts(cfl_hydro=20.0, pc=PC_ACOUSTIC, gmres_eta=LINEAR_TOL["tg"], mg_cycles=MG_CYCLES["tg"],
+                        mg_light_cells=MG_LIGHT_CELLS["tg"])
     return desc, opts, u
 
 
