@@ -101,6 +101,8 @@ typedef struct {
     double cfl_rad_max;     /* eq. (7) cap with D = chi/(rho c_P), 0 = off */
     double dt_max;          /* 0 = off */
     int max_halvings;       /* step retries at dt/2 after a failed Newton solve */
+    int mg_light_cells;     /* multigrid levels of at most this many cells (not the coarsest) take one
+                               pre- and one post-smoothing sweep; 0: every level takes mg_nu1/mg_nu2 */
 } jfnk_solver_opts;
 
 /* Statistics of the last step. */

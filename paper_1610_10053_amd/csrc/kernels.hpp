@@ -183,10 +183,11 @@ template <typename R>
 void launch_coarsen(const Grid& G, const LevelT<R>& F, const LevelT<R>& C, hipStream_t stream);
 template <typename R>
 void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream);
-// V-cycles on b of level 0; levels >= coarse_from run in one single-block kernel
+// V-cycles on b of level 0; levels >= coarse_from run in one single-block
+// kernel; levels (not the coarsest) of at most `light` cells take V(1,1)
 template <typename R>
 void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
-               int nuc, bool first, hipStream_t stream);
+               int nuc, int light, bool first, hipStream_t stream);
 
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>

@@ -446,7 +446,7 @@ __device__ __forceinline__ LevelT<R> lds_level(const LevelT<R>& g, R* sm, int ba
 template <typename R, int ND>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const LevelT<R>* __restrict__ Ld,
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
-                                                                   int first_top) {
+                                                                   int first_top, int light) {
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
     __shared__ R rbuf[kCoarseMaxLevelCells];  // residuals of the level being restricted
     __shared__ int base[kMaxLevels];
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         const bool first = l == from ? top_first : true;
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
-        lds_smooth<R, ND>(G, L, nu1, first);
+        lds_smooth<R, ND>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
         // restriction: every fine residual once, then the children's sums in
         // the order of restrict_cell
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell<R, ND>(G, L, L.b, L.x, lcoords(L, c), c);
@@ -503,23 +503,26 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
-        lds_smooth<R, ND>(G, L, nu2, false);
+        lds_smooth<R, ND>(G, L, (light > 0 && L.N <= light) ? 1 : nu2, false);
     }
     const LevelT<R> gT = Ld[from];
     const LevelT<R> T = lds_level<R, ND>(gT, sm, base[from]);
     for (int c = threadIdx.x; c < T.N; c += blockDim.x) gT.x[c] = T.x[c];
 }
 
+// light: levels (not the coarsest) of at most this many cells take one pre-
+// and one post-smoothing sweep (0: none)
 template <typename R>
 static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int l, int nlev,
-                         int coarse_from, int nu1, int nu2, int nuc, bool first, hipStream_t stream) {
+                         int coarse_from, int nu1, int nu2, int nuc, int light, bool first, hipStream_t stream) {
     if (l >= coarse_from) {
         JFNK_PROF(KC_MG_COARSE, stream);
         JFNK_LAUNCH_RND(G.ndim, k_coarse_vcycle, R, dim3(1), dim3(kCoarseThreads), 0, stream, G, Ld, l, nlev, nu1,
-                        nu2, nuc, first ? 1 : 0);
+                        nu2, nuc, first ? 1 : 0, light);
         return;
     }
     const LevelT<R>& L = S.L[l];
+    if (light > 0 && L.N <= light) nu1 = nu2 = 1;
     const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
     const double bs = (double)L.N * sizeof(R) * (2.5 + G.ndim);
     if (l == nlev - 1) {
@@ -571,7 +574,7 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         else
             JFNK_KLAUNCH((k_restrict<R, 2>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
     }
-    vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, true, stream);
+    vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, light, true, stream);
     {
         const bool half = nu2 > 0;
         JFNK_PROFB(KC_MG_PROLONG, stream,
@@ -593,8 +596,8 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
 
 template <typename R>
 void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
-               int nuc, bool first, hipStream_t stream) {
-    vcycle_level(G, S, Ld, 0, nlev, coarse_from, nu1, nu2, nuc, first, stream);
+               int nuc, int light, bool first, hipStream_t stream) {
+    vcycle_level(G, S, Ld, 0, nlev, coarse_from, nu1, nu2, nuc, light, first, stream);
 }
 
 // ---------------------------------------------------------------- right-hand sides and back-substitution
@@ -939,7 +942,7 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     template void launch_coarsen<R>(const Grid&, const LevelT<R>&, const LevelT<R>&, hipStream_t);           \
     template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
     template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, const LevelT<R>*, int, int, int, int, int,     \
-                               bool, hipStream_t);                                                           \
+                               int, bool, hipStream_t);                                                      \
     template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5,        \
                                    const LevelT<R>&, hipStream_t);                                           \
     template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const LevelT<R>&,        \

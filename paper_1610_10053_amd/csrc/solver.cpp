@@ -167,8 +167,8 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (o->gmres_max_cycles < 0 || o->newton_max < 0) return fail(-1, "negative iteration limits");
     if (o->pc < JFNK_PC_NONE || o->pc > JFNK_PC_ACOUSTIC_DIFFUSION) return fail(-1, "unknown preconditioner");
     if (o->pc_solver != JFNK_PCS_MULTIGRID && o->pc_solver != JFNK_PCS_ADI) return fail(-1, "unknown pc_solver");
-    if (o->mg_nu1 < 1 || o->mg_nu2 < 0 || o->mg_nuc < 1 || o->mg_cycles < 1)
-        return fail(-1, "multigrid sweeps: nu1 >= 1, nu2 >= 0, nuc >= 1, cycles >= 1");
+    if (o->mg_nu1 < 1 || o->mg_nu2 < 0 || o->mg_nuc < 1 || o->mg_cycles < 1 || o->mg_light_cells < 0)
+        return fail(-1, "multigrid sweeps: nu1 >= 1, nu2 >= 0, nuc >= 1, cycles >= 1, light cells >= 0");
     if (o->prec != JFNK_FP64 && o->prec != JFNK_MIXED) return fail(-1, "unknown precision");
     if (o->prec == JFNK_MIXED && o->pc_solver == JFNK_PCS_ADI)
         return fail(-4, "the mixed-precision form supports the multigrid preconditioner only");
@@ -470,7 +470,7 @@ void mg_solve(jfnk_problem* p, int which) {
     const LevelSet<R>& S = levels<R>(p, which);
     for (int c = 0; c < p->opts.mg_cycles; ++c)
         mg_vcycle<R>(p->G, S, dlevels<R>(p, which), p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2,
-                     p->opts.mg_nuc, c == 0, p->stream);
+                     p->opts.mg_nuc, p->opts.mg_light_cells, c == 0, p->stream);
 }
 
 // z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z
