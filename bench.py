@@ -29,10 +29,11 @@ if ROOT not in sys.path:
 
 METRIC = "implicit cell-steps/s at Newton rtol 1e-8 (3D TG 128^3) + % HBM peak; p50/p99"
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-# timed-region kernel timing: events on every launch in the first 4 of each 251
-# launches, the dominant class counted after a window's first launch (251 is
-# prime, so the windows walk through every position of the launch pattern).
-# An evented launch costs about 5 us more than a plain one, so the windows are
+# timed-region kernel timing: windows of 4 consecutive launches carry events,
+# a window opening at a launch with probability 1/251 (a fixed pseudo-random
+# sequence, so the windows do not alias with the solver's periodic launch
+# pattern), the dominant class counted after a window's first launch.  An
+# evented launch costs about 5 us more than a plain one, so the windows are
 # kept sparse: about 60 evented launches per step (< 1 % of the step time)
 SAMPLE_PERIOD, SAMPLE_BURST = 251, 4
 

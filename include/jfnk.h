@@ -234,9 +234,11 @@ int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_hi
  * at the host synchronisation points the solver already has.
  * jfnk_profile_sample(p, period, burst) keeps the host cost of timing small:
  * with burst = 1 one launch in every `period` of each selected class is timed
- * (default period 1: all); with burst > 1 every launch of any class in the
- * first `burst` of each `period` launches carries events, and only the
- * selected classes' launches after the first of such a window are counted,
+ * (default period 1: all); with burst > 1 windows of `burst` consecutive
+ * launches of any class carry events, a window opening at a launch with
+ * probability 1/period (a fixed pseudo-random sequence, which does not alias
+ * with the solver's periodic launch pattern), and only the selected classes'
+ * launches after the first of a window are counted,
  * so every counted kernel follows one that also carried events (an event
  * pair on a kernel that follows one without events can open before that
  * kernel has drained and read long).

@@ -229,13 +229,17 @@ enum KClass : int {
 struct Profiler {
     unsigned mask = 0;
     // sampling: with burst == 1, one launch in every `period` of each selected
-    // class is timed; with burst > 1, every launch (of any class) in the first
-    // `burst` of each `period` launches carries events, and the selected
-    // classes' launches in such a window after its first one are counted, so
-    // each counted kernel follows a kernel that carried events too
+    // class is timed; with burst > 1, windows of `burst` consecutive launches
+    // (of any class) carry events, and the selected classes' launches in a
+    // window after its first one are counted, so each counted kernel follows
+    // a kernel that carried events too.  Outside a window each launch opens
+    // one with probability 1/period, drawn from a fixed 64-bit linear
+    // congruential sequence, so the windows do not alias with the periodic
+    // launch pattern of the solver.
     unsigned period = 1, burst = 1;
     long long seen[KC_COUNT] = {};   // launches of each selected class so far
-    long long gseen = 0;             // launches of any class so far
+    unsigned left = 0;               // launches left in the open window
+    unsigned long long lcg = 0;      // state of the window draw
     std::vector<hipEvent_t> pool;
     std::vector<int> cls;  // class of each recorded pair
     size_t used = 0;       // events in use (2 per pair)
@@ -267,9 +271,14 @@ struct ProfScope {
             }
             return;
         }
-        const long long pos = g_prof->gseen++ % g_prof->period;
-        if (pos < g_prof->burst) {
-            g_prof->begin(sel && pos > 0 ? c : -1, b);  // -1: events only, not counted
+        if (g_prof->left == 0) {
+            g_prof->lcg = g_prof->lcg * 6364136223846793005ULL + 1442695040888963407ULL;
+            if ((g_prof->lcg >> 33) % g_prof->period == 0) g_prof->left = g_prof->burst;
+        }
+        if (g_prof->left > 0) {
+            const bool opening = g_prof->left == g_prof->burst;
+            g_prof->left--;
+            g_prof->begin(sel && !opening ? c : -1, b);  // -1: events only, not counted
             armed = g_ev_start != nullptr;
         }
     }

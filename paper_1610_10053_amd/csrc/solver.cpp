@@ -1549,7 +1549,8 @@ int jfnk_profile_enable(jfnk_problem* p, unsigned class_mask) {
         p->prof.bytes[c] = 0.0;
         p->prof.seen[c] = 0;
     }
-    p->prof.gseen = 0;
+    p->prof.left = 0;
+    p->prof.lcg = 0;
     return 0;
 }
 
@@ -1558,7 +1559,8 @@ int jfnk_profile_sample(jfnk_problem* p, int period, int burst) {
     if (period < 1 || burst < 1 || burst > period) return fail(-1, "need 1 <= burst <= period");
     p->prof.period = (unsigned)period;
     p->prof.burst = (unsigned)burst;
-    p->prof.gseen = 0;
+    p->prof.left = 0;
+    p->prof.lcg = 0;
     return 0;
 }
 
