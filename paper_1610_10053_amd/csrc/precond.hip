@@ -524,7 +524,12 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     const LevelT<R>& L = S.L[l];
     if (light > 0 && L.N <= light) nu1 = nu2 = 1;
     const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
-    const double bs = (double)L.N * sizeof(R) * (2.5 + G.ndim);
+    // compulsory bytes of a half-sweep: the couplings of every face (ndim per
+    // cell), b (and D without unit sigma) and the other colour's x for half
+    // the cells, this colour's x written; the two-buffer sweep of an odd
+    // periodic coarsest level also writes the other colour's copy
+    const double bs = (double)L.N * sizeof(R) * (G.ndim + 1.5 + (L.unit_sig ? 0.0 : 0.5));
+    const double bs_pp = bs + 0.5 * (double)L.N * sizeof(R);
     if (l == nlev - 1) {
         // coarsest level too large for the single-workgroup solve: the same
         // nuc red-black sweeps as multi-block launches
@@ -534,12 +539,12 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
             const dim3 fg = cell_grid3(L.n);
             for (int s = 0; s < nuc; ++s) {
                 {
-                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs_pp);
                     JFNK_LAUNCH_RND(G.ndim, k_gs_pp, R, fg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0,
                                     (const R*)L.x, L.x2);
                 }
                 {
-                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
+                    JFNK_PROFB(KC_MG_SMOOTH, stream, bs_pp);
                     JFNK_LAUNCH_RND(G.ndim, k_gs_pp, R, fg, bl, 0, stream, G, L, 1, 0, (const R*)L.x2, L.x);
                 }
             }
@@ -568,7 +573,9 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         }
     }
     {
-        JFNK_PROFB(KC_MG_RESTRICT, stream, (double)L.N * sizeof(R) * (3 + G.ndim) + (double)S.L[l + 1].N * sizeof(R));
+        // fine x, b, couplings (and sigma) read once, coarse b written
+        JFNK_PROFB(KC_MG_RESTRICT, stream,
+                   (double)L.N * sizeof(R) * (2 + G.ndim + (L.unit_sig ? 0 : 1)) + (double)S.L[l + 1].N * sizeof(R));
         if (G.ndim == 3)
             JFNK_KLAUNCH((k_restrict<R, 3>), restrict_grid<3>(L.n), restrict_block<3>(), 0, stream, G, L, S.L[l + 1]);
         else

@@ -486,7 +486,14 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     const double vec = 8.0 * G.nvec;
     const double b_prim = (s.v ? 2.0 : 1.0) * vec + prim_writes(G);
     const double b_flux = prim_writes(G) + 8.0 * G.N * 2 * G.ndim;
-    double b_out = 8.0 * G.N * (2 * G.ndim + G.ndim * G.ndim + 2 + (sbal ? 1 : 0)) + (s.v ? 2.0 : 1.0) * vec + vec;
+    // fluxes, momentum fluxes, p, rho (with gravity), the face velocities
+    // (internal-energy form), the heat-balance source, the state, the output
+    bool gravity = false;
+    for (int d = 0; d < G.ndim; ++d) gravity = gravity || G.g[d] != 0.0;
+    double b_out = 8.0 * G.N *
+                       (2 * G.ndim + G.ndim * G.ndim + 1 + (gravity ? 1 : 0) + (G.internal ? G.ndim : 0) +
+                        (sbal ? 1 : 0)) +
+                   (s.v ? 2.0 : 1.0) * vec + vec;
     if (o.mode == OUT_CN_OLD) b_out += vec;
     if (o.mode == OUT_RESIDUAL) b_out += vec;
     if (o.mode == OUT_JV) b_out += 2.0 * vec;
