@@ -317,7 +317,36 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
     long c = 0;
     double part = 0.0;
     if (cell_from_launch(G, q, c)) {
-        double R[5];
+        // consumer of field f's right-hand side Rf, called field by field in
+        // order (each value is written as soon as it is formed)
+        auto emit = [&](int f, double Rf) {
+            const long x = (long)f * G.N + c;
+            const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
+            if (o.mode == OUT_RHS) {
+                o.out[x] = Rf;
+            } else if (o.mode == OUT_CN_OLD) {
+                const double u0 = s.u[x];
+                const double b = u0 + o.h * Rf;
+                o.out[x] = b;
+                const double F = wallface ? 0.0 : (u0 - b) - o.h * Rf;
+                o.out2[x] = F;
+                const double t = F / o.scale[f];
+                part += t * t;
+            } else if (o.mode == OUT_RESIDUAL) {
+                const double F = wallface ? 0.0 : (st(s, f, c) - o.b[x]) - o.h * Rf;
+                o.out[x] = F;
+                const double t = F / o.scale[f];
+                part += t * t;
+            } else {  // OUT_JV
+                double w = 0.0;
+                const double e = s.eps[0];
+                if (!wallface && e != 0.0) {
+                    const double F = (st(s, f, c) - o.b[x]) - o.h * Rf;
+                    w = (F - o.Fu[x]) / (e * s.scale[f]);
+                }
+                o.out[x] = w;
+            }
+        };
         // mass and energy in the cell
         double ar = 0.0, ae = 0.0;
         for (int d = 0; d < ND; ++d) {
@@ -369,16 +398,16 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             }
         }
         if (G.heat_balance && sbal) ae = ae + sbal[c];
-        R[0] = ar;
-        R[1] = ae;
+        emit(0, ar);
+        emit(1, ae);
         // momentum on the lower faces
         for (int d = 0; d < ND; ++d) {
             if (G.bc[d] == WALL && q.v[d] == 0) {
-                R[2 + d] = 0.0;
+                emit(2 + d, 0.0);
                 continue;
             }
             if (G.sph) {
-                R[2 + d] = sph_momentum(G, P, Fx, q, c, d);
+                emit(2 + d, sph_momentum(G, P, Fx, q, c, d));
                 continue;
             }
             double a = 0.0;
@@ -397,37 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             }
             a = a - (P.p[c] - P.p[cl]) * G.idx[d];
             if (G.g[d] != 0.0) a = a + (0.5 * (P.rho[cl] + P.rho[c])) * G.g[d];
-            R[2 + d] = a;
-        }
-        // consumers
-        const int nv = 2 + ND;
-        for (int f = 0; f < nv; ++f) {
-            const long x = (long)f * G.N + c;
-            const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
-            if (o.mode == OUT_RHS) {
-                o.out[x] = R[f];
-            } else if (o.mode == OUT_CN_OLD) {
-                const double u0 = s.u[x];
-                const double b = u0 + o.h * R[f];
-                o.out[x] = b;
-                const double F = wallface ? 0.0 : (u0 - b) - o.h * R[f];
-                o.out2[x] = F;
-                const double t = F / o.scale[f];
-                part += t * t;
-            } else if (o.mode == OUT_RESIDUAL) {
-                const double F = wallface ? 0.0 : (st(s, f, c) - o.b[x]) - o.h * R[f];
-                o.out[x] = F;
-                const double t = F / o.scale[f];
-                part += t * t;
-            } else {  // OUT_JV
-                double w = 0.0;
-                const double e = s.eps[0];
-                if (!wallface && e != 0.0) {
-                    const double F = (st(s, f, c) - o.b[x]) - o.h * R[f];
-                    w = (F - o.Fu[x]) / (e * s.scale[f]);
-                }
-                o.out[x] = w;
-            }
+            emit(2 + d, a);
         }
     }
     if (o.partial) {
