@@ -77,3 +77,43 @@ def test_server_arguments_are_rejected_on_host():
         with pytest.raises(jfnk.JfnkError) as e:
             jfnk.Server(hbm, act)
         assert e.value.code == -1
+
+
+def test_geometry_energy_and_light_options_are_checked_on_host():
+    """spherical grids need 2D, walls on both axes, 0 < r, 0 < theta < pi,
+    radial gravity and the multigrid preconditioner; unknown enum values and
+    negative light-level sizes are bad arguments"""
+    from paper_1610_10053_amd import jfnk
+    from workloads import make_config
+    if not os.path.exists(jfnk.LIB_PATH):
+        pytest.skip("libjfnk.so not built")
+    desc, opts, u = make_config("srad", n=8)
+    assert jfnk.footprint_bytes(desc, opts) > 0
+    cases = [(dict(desc, bc=[1, 0, 0]), opts, -4), (dict(desc, lo=[0.0, 0.5, 0.0]), opts, -1),
+             (dict(desc, hi=[2.0, 3.2, 1.0]), opts, -1), (dict(desc, g=[-1.0, 0.5, 0.0]), opts, -4),
+             (desc, dict(opts, pc_solver=jfnk.PCS_ADI), -4), (dict(desc, geometry=2), opts, -1),
+             (dict(desc, energy_form=2), opts, -1), (desc, dict(opts, mg_light_cells=-1), -1)]
+    d3, o3, _ = make_config("tg", n=8)
+    cases.append((dict(d3, geometry=1), o3, -4))
+    for d, o, code in cases:
+        with pytest.raises(jfnk.JfnkError) as e:
+            jfnk.footprint_bytes(d, o)
+        assert e.value.code == code, (d, e.value)
+
+
+def test_grid_beyond_32_bit_indexing_is_refused_before_any_allocation():
+    """the size check precedes every device call, so it runs on the host"""
+    import ctypes as C
+    import numpy as np
+    from paper_1610_10053_amd import jfnk
+    from workloads import make_config
+    if not os.path.exists(jfnk.LIB_PATH):
+        pytest.skip("libjfnk.so not built")
+    lib = jfnk.load()
+    desc, opts, u = make_config("tg", n=8)
+    big = dict(desc, n=[1024, 1024, 1024])
+    one = np.zeros(1)
+    h = C.c_void_p()
+    rc = lib.jfnk_create_problem(C.byref(jfnk.make_desc(big)), C.byref(jfnk.make_opts(opts)),
+                                 one.ctypes.data, 0, None, C.byref(h))
+    assert rc == -4 and not h.value

@@ -200,15 +200,16 @@ def test_velocity_error_of_a_linear_profile_between_walls_is_zero():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("name,n,axis", [("kh", 32, 1), ("rt", 16, 1), ("tg", 8, 0)])
-def test_gpu_velocity_error_matches_oracle(name, n, axis):
+@pytest.mark.parametrize("name,n,axis,r", [("kh", 32, 1, 2), ("rt", 16, 1, 2), ("tg", 8, 0, 2), ("kh", 16, 0, 4),
+                                           ("rad", 8, 1, 3)])
+def test_gpu_velocity_error_matches_oracle(name, n, axis, r):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1610_10053_amd import jfnk
     jfnk.load()
     d_lo, o_lo, u_lo = make_config(name, n=n)
-    d_hi, o_hi, u_hi = make_config(name, n=2 * n)
+    d_hi, o_hi, u_hi = make_config(name, n=r * n)
     g_lo, g_hi = jfnk.Problem(d_lo, o_lo, u_lo), jfnk.Problem(d_hi, o_hi, u_hi)
     for _ in range(2):
         assert g_lo.implicit_step()[0] == 0
@@ -216,8 +217,8 @@ def test_gpu_velocity_error_matches_oracle(name, n, axis):
     s_lo, s_hi = g_lo.get_state(), g_hi.get_state()
     ref = dg.velocity_error(s_lo, d_lo, s_hi, d_hi, axis)
     assert ref > 0
-    e_host = g_lo.velocity_error(s_hi, 2, axis)
-    e_dev = g_lo.velocity_error(torch.from_numpy(s_hi).cuda(), 2, axis)
+    e_host = g_lo.velocity_error(s_hi, r, axis)
+    e_dev = g_lo.velocity_error(torch.from_numpy(s_hi).cuda(), r, axis)
     e_given = g_hi.velocity_error(s_hi, 1, axis, u_low=s_hi)
     print(name, n, axis, ref, e_host, e_dev, flush=True)
     assert e_host == pytest.approx(ref, rel=1e-12)

@@ -163,7 +163,7 @@ def test_adi_and_unpreconditioned_paths(torch_cuda, name, n):
 
 # ---------------------------------------------------------------- internal-energy form (eq. 2 as written)
 
-@pytest.mark.parametrize("name,n", CASES + [("rad", None)])
+@pytest.mark.parametrize("name,n", CASES + [("rad", None), ("kh", 54), ("rt", 20)])
 def test_internal_energy_form_components(torch_cuda, name, n):
     """residual, time step and preconditioner bit for bit, Jv to 1e-9"""
     desc, opts, u, g, o = _pair(name, n, energy_form=ENERGY_INTERNAL)
@@ -245,7 +245,8 @@ def _sph_pair(kind, n):
     return desc, opts, u, jfnk.Problem(desc, opts, u), Oracle(desc, opts, u)
 
 
-@pytest.mark.parametrize("kind,n", [("srad", 8), ("srad", 32), ("flow", 16), ("flow", 48), ("flow_internal", 16)])
+@pytest.mark.parametrize("kind,n", [("srad", 8), ("srad", 12), ("srad", 32), ("flow", 16), ("flow", 20), ("flow", 48),
+                                    ("flow_internal", 16)])
 def test_spherical_components(torch_cuda, kind, n):
     """residual, time step and preconditioner bit for bit, Jv to 1e-9"""
     desc, opts, u, g, o = _sph_pair(kind, n)
