@@ -91,6 +91,7 @@ typedef struct {
     double *rho, *eps, *p, *T, *chi, *q, *uf[3], *m[3], *fr[3], *fe[3], *phic[3][3];
     /* residual / Krylov workspace (nvec entries) */
     double *b, *F, *w1, *w2, *R1;
+    double *Ru; /* R at the current Newton iterate (Jacobian-free products) */
     /* scaling */
     double scale[5];
     /* preconditioner coefficients (cells N, faces per direction N) */
@@ -718,14 +719,24 @@ static double time_step(Or *o, const double *u, double *hyd_out, double *adv_out
 
 /* J v ~ (F(u + eps S v) - F(u)) / eps in scaled variables (section 2: the
  * matrix-vector products GMRES needs are approximated from residuals). */
-static void jv(Or *o, const double *u, const double *Fu, const double *b, double dt,
-               double urms, const double *v, double *w) {
+/* Jacobian-free product (section 2) in scaled variables.  F(u) = (u - b) -
+ * h R(u) is linear in u apart from R, so the difference quotient
+ * (F(u + e S v) - F(u)) / (e S) equals v - h (R(u + e S v) - R(u)) / (e S):
+ * only R is differenced, the identity part is applied exactly (reading R27).
+ * Ru = R(u); wall faces, which are not unknowns, give 0. */
+static void jv(Or *o, const double *u, const double *Ru, double dt, double urms, const double *v, double *w) {
     double vn = norm2(o->nvec, v) / sqrt((double)o->nunk);
     if (vn == 0.0) { memset(w, 0, sizeof(double) * o->nvec); return; }
     double e = sqrt(2.220446049250313e-16) * (1.0 + urms) / vn;
     for (long x = 0; x < o->nvec; ++x) o->w2[x] = u[x] + (e * scale_of(o, x)) * v[x];
-    cn_residual(o, o->w2, b, dt, o->w1);
-    for (long x = 0; x < o->nvec; ++x) w[x] = (o->w1[x] - Fu[x]) / (e * scale_of(o, x));
+    rhs(o, o->w2, o->R1);
+    double h = 0.5 * dt;
+    for (long x = 0; x < o->nvec; ++x) w[x] = v[x] - (h * (o->R1[x] - Ru[x])) / (e * scale_of(o, x));
+    for (int d = 0; d < o->ndim; ++d) {
+        if (o->bc[d] != BC_WALL) continue;
+        double *wm = w + (long)(2 + d) * o->N;
+        FOR_CELLS(o) if (coord(d, i, j, k) == 0) wm[cidx(o, i, j, k)] = 0.0;
+    }
 }
 
 /* ------------------------------------------------------------------ tridiagonal lines */
@@ -1282,11 +1293,11 @@ done:
 
 /* ------------------------------------------------------------------ Newton */
 
-typedef struct { Or *o; const double *u, *Fu, *b; double dt, urms; } JCtx;
+typedef struct { Or *o; const double *u, *Ru; double dt, urms; } JCtx;
 
 static void op_jv(void *ctx, const double *x, double *y) {
     JCtx *c = ctx;
-    jv(c->o, c->u, c->Fu, c->b, c->dt, c->urms, x, y);
+    jv(c->o, c->u, c->Ru, c->dt, c->urms, x, y);
 }
 static void op_pc(void *ctx, const double *x, double *y) {
     JCtx *c = ctx;
@@ -1322,6 +1333,7 @@ static int newton(Or *o, double dt) {
     time_step(o, u, NULL, NULL, NULL); /* scales from u^n */
     cn_old(o, u, dt, b);
     cn_residual(o, u, b, dt, F);
+    memcpy(o->Ru, o->R1, sizeof(double) * nv);
     double f0 = snorm2(o, F), f = f0;
     double tol = o->rtol * f0;
     double floor_ = o->atol * sqrt((double)o->nunk);
@@ -1335,7 +1347,7 @@ static int newton(Or *o, double dt) {
         pc_build(o, u, dt);
         double urms = snorm2(o, u) / sqrt((double)o->nunk);
         for (long q = 0; q < nv; ++q) rhsv[q] = -F[q] / scale_of(o, q);
-        JCtx ctx = {o, u, F, b, dt, urms};
+        JCtx ctx = {o, u, o->Ru, dt, urms};
         GmresInfo gi;
         gmres(nv, op_jv, op_pc, &ctx, rhsv, x, o->restart, o->max_cycles, o->eta, &gi);
         gits += gi.its;
@@ -1347,6 +1359,7 @@ static int newton(Or *o, double dt) {
             if (rc > max_corr) max_corr = rc;
         }
         cn_residual(o, u, b, dt, F);
+        memcpy(o->Ru, o->R1, sizeof(double) * nv);
         f = snorm2(o, F);
         its++;
         if (!isfinite(f) || !all_finite(nv, u)) { status = 3; break; }
@@ -1530,7 +1543,7 @@ static void or_free(Or *o) {
     if (!o) return;
     double **ptrs[] = {&o->u, &o->un, &o->sbal, &o->Vr, &o->Vt, &o->r2f, &o->hr2, &o->stf, &o->rfa, &o->rc,
                        &o->ith, &o->Vrc, &o->r2c, &o->hr2c, &o->Vtc, &o->stc, &o->rho, &o->eps, &o->p, &o->T, &o->chi, &o->q,
-                       &o->b, &o->F, &o->w1, &o->w2, &o->R1, &o->pc_W, &o->la, &o->lb, &o->lc,
+                       &o->b, &o->F, &o->w1, &o->w2, &o->R1, &o->Ru, &o->pc_W, &o->la, &o->lb, &o->lc,
                        &o->ld, &o->lx, &o->lt1, &o->lt2};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(*ptrs[i]);
     for (int d = 0; d < 3; ++d) {
@@ -1586,6 +1599,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->w1 = calloc(o->nvec, sizeof(double));
     o->w2 = calloc(o->nvec, sizeof(double));
     o->R1 = calloc(o->nvec, sizeof(double));
+    o->Ru = calloc(o->nvec, sizeof(double));
     o->sbal = calloc(o->N, sizeof(double));
     o->pc_W = calloc(o->N, sizeof(double));
     double **pp[] = {&o->rho, &o->eps, &o->p, &o->T, &o->chi, &o->q};
@@ -1644,11 +1658,12 @@ void or_set_scales(void *h, const double *s) { Or *o = h; for (int f = 0; f < 5;
 /* Jv with F(u) recomputed from (u, b, dt) */
 void or_jv(void *h, const double *u, const double *b, double dt, const double *v, double *w) {
     Or *o = h;
-    double *Fu = calloc(o->nvec, sizeof(double));
-    cn_residual(o, u, b, dt, Fu);
+    double *Ru = calloc(o->nvec, sizeof(double));
+    (void)b; /* the product does not depend on the old-time term */
+    rhs(o, u, Ru);
     double urms = snorm2(o, u) / sqrt((double)o->nunk);
-    jv(o, u, Fu, b, dt, urms, v, w);
-    free(Fu);
+    jv(o, u, Ru, dt, urms, v, w);
+    free(Ru);
 }
 
 /* z = P^{-1} v with coefficients frozen at u */
