@@ -56,7 +56,8 @@ struct OutSpec {
     double* out;         // R, b, F or w
     double* out2;        // F (OUT_CN_OLD)
     const double* b;     // Crank-Nicolson old-time term
-    const double* Fu;    // F(u) for OUT_JV
+    const double* Ru;    // R(u) for OUT_JV
+    double* rout;        // R written here as well (any mode), or null
     double scale[5];     // variable scales for the fused norm
     double* partial;     // per-block sum of (F/S)^2, or null
 };

@@ -6,7 +6,9 @@
 // the three consumers
 //   b = u + dt/2 R(u)                 (old-time half of Crank-Nicolson)
 //   F = (u - b) - dt/2 R(u)           (residual)
-//   w = (F(u + eps S v) - F(u)) / (eps S)   (Jacobian-free product)
+//   w = v - dt/2 (R(u + eps S v) - R(u)) / (eps S)   (Jacobian-free product:
+//       the difference quotient of F, whose part u - b is linear, with only
+//       R differenced)
 // Three sweeps: cell primitives, face fluxes, then cell and face outputs.
 #include "kernels.hpp"
 
@@ -322,6 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         auto emit = [&](int f, double Rf) {
             const long x = (long)f * G.N + c;
             const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
+            if (o.rout) o.rout[x] = Rf;
             if (o.mode == OUT_RHS) {
                 o.out[x] = Rf;
             } else if (o.mode == OUT_CN_OLD) {
@@ -340,10 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             } else {  // OUT_JV
                 double w = 0.0;
                 const double e = s.eps[0];
-                if (!wallface && e != 0.0) {
-                    const double F = (st(s, f, c) - o.b[x]) - o.h * Rf;
-                    w = (F - o.Fu[x]) / (e * s.scale[f]);
-                }
+                if (!wallface && e != 0.0) w = s.v[x] - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);
                 o.out[x] = w;
             }
         };
@@ -492,10 +492,11 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     double b_out = 8.0 * G.N *
                        (2 * G.ndim + G.ndim * G.ndim + 1 + (gravity ? 1 : 0) + (G.internal ? G.ndim : 0) +
                         (sbal ? 1 : 0)) +
-                   (s.v ? 2.0 : 1.0) * vec + vec;
-    if (o.mode == OUT_CN_OLD) b_out += vec;
-    if (o.mode == OUT_RESIDUAL) b_out += vec;
-    if (o.mode == OUT_JV) b_out += 2.0 * vec;
+                   vec;  // the output
+    if (o.mode == OUT_CN_OLD) b_out += 2.0 * vec;  // u read, F written
+    if (o.mode == OUT_RESIDUAL) b_out += 2.0 * vec;  // u and b read
+    if (o.mode == OUT_JV) b_out += 2.0 * vec + (gravity ? 2.0 * 8.0 * G.N * G.ndim : 0.0);  // v, R(u) [, m]
+    if (o.rout) b_out += vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
         JFNK_LAUNCH_ND(G.ndim, k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);

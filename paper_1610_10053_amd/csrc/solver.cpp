@@ -62,6 +62,7 @@ struct jfnk_problem {
     double *u = nullptr, *un = nullptr, *b = nullptr, *F = nullptr, *x = nullptr, *rhs = nullptr,
            *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
            *s2 = nullptr;
+    double* Ru = nullptr;  // R at the current Newton iterate (Jacobian-free products)
     void* V = nullptr;
     double* Zb = nullptr;  // preconditioned basis vectors M^-1 v_j of a GMRES cycle
     Prim P{};
@@ -359,15 +360,17 @@ StateView view(jfnk_problem* p, const double* u, const double* v) {
     return s;
 }
 
+// rout: R written there too (the Newton iterate's R for the products)
 OutSpec outspec(jfnk_problem* p, int mode, double dt, double* out, double* out2, const double* b,
-                const double* Fu, bool want_norm) {
+                const double* Ru, bool want_norm, double* rout = nullptr) {
     OutSpec o;
     o.mode = mode;
     o.h = 0.5 * dt;
     o.out = out;
     o.out2 = out2;
     o.b = b;
-    o.Fu = Fu;
+    o.Ru = Ru;
+    o.rout = rout;
     for (int f = 0; f < 5; ++f) o.scale[f] = p->scale[f];
     o.partial = want_norm ? p->part : nullptr;
     return o;
@@ -519,11 +522,10 @@ void pc_apply(jfnk_problem* p, const double* v, double* z) {
     launch_jv_eps(p->dsum + D_USQ, p->part, nb, (double)p->nunk, p->dsum + D_EPS, p->stream);
 }
 
-// Jacobian-free product along v (eps already on the device)
-void jv(jfnk_problem* p, const double* u, const double* Fu, const double* b, double dt, const double* v,
-        double* w) {
+// Jacobian-free product along v (eps already on the device), Ru = R(u)
+void jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const double* v, double* w) {
     launch_residual(p->G, view(p, u, v), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_JV, dt, w, nullptr, b, Fu, false), p->stream);
+                    outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false), p->stream);
 }
 
 // eps for a product along x from |x|
@@ -682,10 +684,10 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
     const long n = p->G.nvec;
     auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
     auto pc = [&](int, const double* v, double* z) { pc_apply(p, v, z); };
-    auto op = [&](const double* z, double* w) { jv(p, u, p->F, p->b, dt, z, w); };
+    auto op = [&](const double* z, double* w) { jv(p, u, p->Ru, dt, z, w); };
     auto opx = [&](const double* x, double* t) {
         eps_for(p, x);
-        jv(p, u, p->F, p->b, dt, x, t);
+        jv(p, u, p->Ru, dt, x, t);
     };
     return gmres_core<T>(p, n, (T*)p->V, p->Zb, p->rhs, p->x, p->r, p->w, p->t, p->vj, norm, pc, op, opx, info);
 }
@@ -698,7 +700,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
     launch_copy(p->un, p->u, n, p->stream);
     CK(time_step(p, p->u, nullptr));  // scales from u^n
     launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_CN_OLD, dt, p->b, p->F, nullptr, nullptr, true), p->stream);
+                    outspec(p, OUT_CN_OLD, dt, p->b, p->F, nullptr, nullptr, true, p->Ru), p->stream);
     HIPCHK(hipGetLastError());
     double f0;
     CK(residual_norm(p, &f0));
@@ -728,7 +730,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         launch_update_state(p->u, p->x, G, p->scale, p->part, p->nred, p->stream);
         launch_final_max(p->part, p->nred, 1, p->dsum + D_TMP + 1, p->stream);
         launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
-                        outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->b, nullptr, true), p->stream);
+                        outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->b, nullptr, true, p->Ru), p->stream);
         launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
         HIPCHK(hipGetLastError());
         double rb[2];
@@ -1002,7 +1004,7 @@ int freeze_sources(jfnk_problem* p) {
 // device bytes create_problem requests (buffer for buffer)
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 13 * nv * 8;                                                       // vectors
+    size_t b = 14 * nv * 8;                                                       // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
     b += (size_t)o.gmres_restart * nv * 8;                                        // preconditioned basis
     b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
@@ -1122,7 +1124,7 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         int r_ = dalloc(p, &(ptr), (cnt)); \
         if (r_) return cleanup(r_);      \
     } while (0)
-    AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->F, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n);
+    AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->F, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n); AL(p->Ru, n);
     AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->vj, n); AL(p->s1, n); AL(p->s2, n);
     if (opts->prec == JFNK_MIXED) {
         float* V = nullptr;
@@ -1512,10 +1514,10 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
     if ((rc = copy_in(p, p->s2, b, on_device))) return rc;
     if ((rc = copy_in(p, p->z, v, on_device))) return rc;
     launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->s2, nullptr, false), p->stream);
+                    outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->s2, nullptr, false, p->Ru), p->stream);
     set_usq(p, p->s1);
     eps_for(p, p->z);
-    jv(p, p->s1, p->F, p->s2, dt, p->z, p->w);
+    jv(p, p->s1, p->Ru, dt, p->z, p->w);
     HIPCHK(hipGetLastError());
     return copy_out(p, w, p->w, on_device);
 }
