@@ -58,6 +58,7 @@ struct OutSpec {
     const double* b;     // Crank-Nicolson old-time term
     const double* Ru;    // R(u) for OUT_JV
     double* rout;        // R written here as well (any mode), or null
+    int neg_scaled;      // the F output holds -F/S (the Newton right-hand side) instead of F
     double scale[5];     // variable scales for the fused norm
     double* partial;     // per-block sum of (F/S)^2, or null
 };
@@ -120,7 +121,6 @@ void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t s
 template <typename T>
 void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, bool acc, hipStream_t stream);
 void launch_add(double* x, const double* z, long n, hipStream_t stream);
-void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* scale5, hipStream_t stream);
 void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t stream);
 void launch_update_state(double* u, const double* x, const Grid& G, const double* scale5, double* part,
                          int nblk, hipStream_t stream);

@@ -271,21 +271,6 @@ void launch_add(double* x, const double* z, long n, hipStream_t stream) {
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_neg_scaled(const double* __restrict__ F, double* __restrict__ r,
-                                                       long N, long n, Scales5 s) {
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
-        r[e] = -F[e] / s.v[e / N];
-}
-void launch_neg_scaled(const double* F, double* r, const Grid& G, const double* scale5, hipStream_t stream) {
-    Scales5 s;
-    for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
-    {
-        JFNK_PROF(KC_OTHER, stream);
-        JFNK_KLAUNCH(k_neg_scaled, dim3(grid_blocks(G.nvec, kBlock * 4)), dim3(kBlock), 0, stream, F, r, G.N,
-                           G.nvec, s);
-    }
-}
-
 __global__ void __launch_bounds__(kBlock) k_sub(const double* __restrict__ a, const double* __restrict__ b,
                                                 double* __restrict__ r, long n) {
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)

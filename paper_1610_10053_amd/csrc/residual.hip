@@ -332,12 +332,12 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 const double b = u0 + o.h * Rf;
                 o.out[x] = b;
                 const double F = wallface ? 0.0 : (u0 - b) - o.h * Rf;
-                o.out2[x] = F;
+                o.out2[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
             } else if (o.mode == OUT_RESIDUAL) {
                 const double F = wallface ? 0.0 : (st(s, f, c) - o.b[x]) - o.h * Rf;
-                o.out[x] = F;
+                o.out[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
             } else {  // OUT_JV

@@ -59,7 +59,7 @@ struct jfnk_problem {
     char* slab = nullptr;
     size_t slab_size = 0, slab_off = 0;
     // vectors of nvec doubles
-    double *u = nullptr, *un = nullptr, *b = nullptr, *F = nullptr, *x = nullptr, *rhs = nullptr,
+    double *u = nullptr, *un = nullptr, *b = nullptr, *x = nullptr, *rhs = nullptr,
            *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
            *s2 = nullptr;
     double* Ru = nullptr;  // R at the current Newton iterate (Jacobian-free products)
@@ -371,8 +371,17 @@ OutSpec outspec(jfnk_problem* p, int mode, double dt, double* out, double* out2,
     o.b = b;
     o.Ru = Ru;
     o.rout = rout;
+    o.neg_scaled = 0;
     for (int f = 0; f < 5; ++f) o.scale[f] = p->scale[f];
     o.partial = want_norm ? p->part : nullptr;
+    return o;
+}
+
+// residual evaluation at a Newton iterate: the norm partials, R kept for the
+// products, and the Newton right-hand side -S^-1 F written in place of F
+OutSpec newton_spec(jfnk_problem* p, int mode, double dt, double* out, double* out2, const double* b) {
+    OutSpec o = outspec(p, mode, dt, out, out2, b, nullptr, true, p->Ru);
+    o.neg_scaled = 1;
     return o;
 }
 
@@ -700,7 +709,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
     launch_copy(p->un, p->u, n, p->stream);
     CK(time_step(p, p->u, nullptr));  // scales from u^n
     launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_CN_OLD, dt, p->b, p->F, nullptr, nullptr, true, p->Ru), p->stream);
+                    newton_spec(p, OUT_CN_OLD, dt, p->b, p->rhs, nullptr), p->stream);
     HIPCHK(hipGetLastError());
     double f0;
     CK(residual_norm(p, &f0));
@@ -718,7 +727,6 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         }
         CK(pc_build(p, p->u, dt));
         set_usq(p, p->u);
-        launch_neg_scaled(p->F, p->rhs, G, p->scale, p->stream);
         GmresInfo gi;
         int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi) : gmres<double>(p, p->u, dt, &gi);
         if (rc) return rc;
@@ -730,7 +738,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         launch_update_state(p->u, p->x, G, p->scale, p->part, p->nred, p->stream);
         launch_final_max(p->part, p->nred, 1, p->dsum + D_TMP + 1, p->stream);
         launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
-                        outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->b, nullptr, true, p->Ru), p->stream);
+                        newton_spec(p, OUT_RESIDUAL, dt, p->rhs, nullptr, p->b), p->stream);
         launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
         HIPCHK(hipGetLastError());
         double rb[2];
@@ -1004,7 +1012,7 @@ int freeze_sources(jfnk_problem* p) {
 // device bytes create_problem requests (buffer for buffer)
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 14 * nv * 8;                                                       // vectors
+    size_t b = 13 * nv * 8;                                                       // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
     b += (size_t)o.gmres_restart * nv * 8;                                        // preconditioned basis
     b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
@@ -1124,7 +1132,7 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         int r_ = dalloc(p, &(ptr), (cnt)); \
         if (r_) return cleanup(r_);      \
     } while (0)
-    AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->F, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n); AL(p->Ru, n);
+    AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n); AL(p->Ru, n);
     AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->vj, n); AL(p->s1, n); AL(p->s2, n);
     if (opts->prec == JFNK_MIXED) {
         float* V = nullptr;
@@ -1514,7 +1522,7 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
     if ((rc = copy_in(p, p->s2, b, on_device))) return rc;
     if ((rc = copy_in(p, p->z, v, on_device))) return rc;
     launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_RESIDUAL, dt, p->F, nullptr, p->s2, nullptr, false, p->Ru), p->stream);
+                    outspec(p, OUT_RESIDUAL, dt, p->w, nullptr, p->s2, nullptr, false, p->Ru), p->stream);
     set_usq(p, p->s1);
     eps_for(p, p->z);
     jv(p, p->s1, p->Ru, dt, p->z, p->w);
