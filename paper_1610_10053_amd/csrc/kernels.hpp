@@ -153,7 +153,18 @@ struct LevelT {
     // of colour (i+j+k)&1 together, x-pairs merged (H entries per colour,
     // hn0 per row), so that a half-sweep reads and writes them contiguously
     int split, hn0, H;
+    // finest level of a Cartesian operator: the couplings are formed on the
+    // fly from one cell field, a_d = (K0 ((qf_lo + qf_c) / 2)) i2_d on the
+    // lower face (bitwise the stored a), so a sweep reads one array instead
+    // of ndim; null on other levels
+    const double* qf;
+    double K0, i2[3];
 };
+// coupling on the face between cells lo and c of a level with qf set
+template <typename R>
+__device__ __forceinline__ R qf_coupling(const LevelT<R>& L, int d, int lo, int c) {
+    return (R)((L.K0 * (0.5 * (L.qf[lo] + L.qf[c]))) * L.i2[d]);
+}
 // index of cell (i, j, k) in a level's x, b and x2 arrays (levels hold fewer
 // than 2^30 cells)
 template <typename R>
@@ -168,7 +179,8 @@ struct LevelSet {
 };
 
 struct PcCoef {
-    double* hf[3];    // face enthalpy
+    double* H;        // cell enthalpy (E + p) / rho; the face value is the mean of the two cells'
+    double* chi;      // cell conductivity (with a conduction operator)
     double* kap[3];   // acoustic couplings tau^2 (gamma-1) h_f / dx^2
     double* beta[3];  // conduction couplings tau chi_f / dx^2
     double* W;        // (gamma-1)/rho

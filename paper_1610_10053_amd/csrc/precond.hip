@@ -35,11 +35,12 @@ __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __rest
         // couplings per unit volume, or, on spherical grids, of the
         // volume-weighted system: face area over centre distance
         const double i2 = G.sph ? sph_area(G, d, q.v[0], q.v[1]) * face_ids(G, d, q.v[0]) : G.idx[d] * G.idx[d];
-        C.hf[d][c] = hf;
         C.kap[d][c] = ((tau * tau) * G.gm1) * hf * i2;
         C.beta[d][c] = (tau * chif) * i2;
     }
     C.W[c] = G.gm1 / P.rho[c];
+    C.H[c] = (E[c] + P.p[c]) / P.rho[c];
+    if (G.has_chi) C.chi[c] = P.chi[c];
 }
 
 void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
@@ -206,11 +207,24 @@ __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R
     R num = b[xbq(L, q)];
     R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
+        // a neighbour beyond a wall stays at q: its loads are issued (in
+        // bounds) like every other and their values discarded
         LIjk qu = q, qd = q;
         const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
-        const R alo = L.a[d][c], ahi = hu ? L.a[d][lflat(L, qu.v[0], qu.v[1], qu.v[2])] : (R)0.0;
-        if (hd) num = num + alo * (first ? (R)0.0 : x[xbq(L, qd)]);
-        if (hu) num = num + ahi * (first ? (R)0.0 : x[xbq(L, qu)]);
+        const int lo = lflat(L, qd.v[0], qd.v[1], qd.v[2]), up = lflat(L, qu.v[0], qu.v[1], qu.v[2]);
+        R alo, ahi;
+        if (L.qf) {
+            alo = qf_coupling(L, d, lo, c);
+            ahi = qf_coupling(L, d, c, up);
+        } else {
+            alo = L.a[d][c];
+            ahi = L.a[d][up];
+        }
+        alo = hd ? alo : (R)0.0;
+        ahi = hu ? ahi : (R)0.0;
+        const R xlo = first ? (R)0.0 : x[xbq(L, qd)], xhi = first ? (R)0.0 : x[xbq(L, qu)];
+        num = hd ? num + alo * xlo : num;
+        num = hu ? num + ahi * xhi : num;
         den = den + alo;
         den = den + ahi;
     }
@@ -234,17 +248,21 @@ __device__ __forceinline__ bool odd_periodic(const Grid& G, const LevelT<R>& L) 
     return odd;
 }
 
-// residual of one fine cell
+// residual of one fine cell, from the stored couplings (forming them from the
+// cell field, as the sweeps do on the finest level, measured slower here)
 template <typename R, int ND>
 __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
                                         int c) {
     const R xc = x[xbq(L, q)];
     R acc = L.unit_sig ? xc : L.sig[c] * xc;
     for (int d = 0; d < ND; ++d) {
-        LIjk qu = q, qd = q;
+        LIjk qu = q, qd = q;  // beyond a wall a neighbour stays at q (loads issued, values discarded)
         const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
-        if (hd) acc = acc + L.a[d][c] * (xc - x[xbq(L, qd)]);
-        if (hu) acc = acc + L.a[d][lflat(L, qu.v[0], qu.v[1], qu.v[2])] * (xc - x[xbq(L, qu)]);
+        const int lo = lflat(L, qd.v[0], qd.v[1], qd.v[2]), up = lflat(L, qu.v[0], qu.v[1], qu.v[2]);
+        const R alo = L.a[d][c], ahi = L.a[d][up];
+        const R xlo = x[xbq(L, qd)], xhi = x[xbq(L, qu)];
+        acc = hd ? acc + alo * (xc - xlo) : acc;
+        acc = hu ? acc + ahi * (xc - xhi) : acc;
     }
     return b[xbq(L, q)] - acc;
 }
@@ -525,10 +543,12 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     if (light > 0 && L.N <= light) nu1 = nu2 = 1;
     const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
     // compulsory bytes of a half-sweep: the couplings of every face (ndim per
-    // cell), b (and D without unit sigma) and the other colour's x for half
-    // the cells, this colour's x written; the two-buffer sweep of an odd
-    // periodic coarsest level also writes the other colour's copy
-    const double bs = (double)L.N * sizeof(R) * (G.ndim + 1.5 + (L.unit_sig ? 0.0 : 0.5));
+    // cell, or the one cell field they are formed from), b (and D without
+    // unit sigma) and the other colour's x for half the cells, this colour's
+    // x written; the two-buffer sweep of an odd periodic coarsest level also
+    // writes the other colour's copy
+    const double bs = (double)L.N * sizeof(R) * ((L.qf ? 0 : G.ndim) + 1.5 + (L.unit_sig ? 0.0 : 0.5)) +
+                      (L.qf ? (double)L.N * sizeof(double) : 0.0);
     const double bs_pp = bs + 0.5 * (double)L.N * sizeof(R);
     if (l == nlev - 1) {
         // coarsest level too large for the single-workgroup solve: the same
@@ -619,6 +639,13 @@ __device__ __forceinline__ int xb_shifted(const LevelT<R>& L, const Ijk& q, int 
     v[d] = a;
     return xbi(L, v[0], v[1], v[2]);
 }
+// enthalpy on the lower face of cell c along d: the mean of the two cells'
+// values, 0 on a wall
+__device__ __forceinline__ double face_h(const Grid& G, const PcCoef& C, const Ijk& q, long c, int d) {
+    const bool wall = G.bc[d] == WALL && q.v[d] == 0;
+    const double h = 0.5 * (C.H[wall ? c : shifted(G, q, d, -1)] + C.H[c]);  // load issued on walls too
+    return wall ? 0.0 : h;
+}
 template <typename R, int ND>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
@@ -630,12 +657,11 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
     for (int d = 0; d < ND; ++d) {
         const double* vm = v + (long)(2 + d) * G.N;
         const double s = sc.v[2 + d];
-        const double flo = C.hf[d][c] * (s * vm[c]);
-        double fhi = 0.0;
-        if (!(G.bc[d] == WALL && q.v[d] == G.n[d] - 1)) {
-            const long up = shifted(G, q, d, 1);
-            fhi = C.hf[d][up] * (s * vm[up]);
-        }
+        const double flo = face_h(G, C, q, c, d) * (s * vm[c]);
+        const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
+        const long up = top ? c : shifted(G, q, d, 1);  // loads issued at a top wall too, value discarded
+        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * vm[up]);
+        const double fhi = top ? 0.0 : fu;
         if (G.sph) {
             const int i = q.v[0], j = q.v[1];
             const double Alo = sph_area(G, d, i, j), Ahi = sph_area(G, d, d == 0 ? i + 1 : i, d == 1 ? j + 1 : j);
@@ -716,8 +742,8 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
         const double drho = sc.v[0] * v[c] - C.tau * acc;
         acc = 0.0;
         for (int d = 0; d < ND; ++d) {
-            const double flo = C.hf[d][c] * dmlo[d];
-            const double fhi = top[d] ? 0.0 : C.hf[d][upi[d]] * dmhi[d];
+            const double flo = face_h(G, C, q, c, d) * dmlo[d];
+            const double fhi = top[d] ? 0.0 : (0.5 * (C.H[c] + C.H[upi[d]])) * dmhi[d];
             acc = acc + divterm(d, fhi, flo);
         }
         const double dE = re - C.tau * acc;
@@ -787,7 +813,7 @@ template <typename R>
 void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc,
                    const LevelT<R>& L0, hipStream_t stream) {
     {
-        JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (1 + 2 * G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (2 + G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
         JFNK_LAUNCH_RND(G.ndim, k_pc_rhs, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, L0);
     }
 }
@@ -804,7 +830,7 @@ void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const doubl
                     const LevelT<R>& L0, Scales5 sc, double* z, double* part, int nblk, hipStream_t stream) {
     (void)nblk;
     {
-        JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (1 + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
         JFNK_LAUNCH_RND(G.ndim, k_pc_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, L0, sc,
                         z, part);
     }

@@ -437,6 +437,17 @@ template <typename R>
 void build_hierarchy(jfnk_problem* p, int which) {
     const Grid& G = p->G;
     LevelSet<R>& S = levels<R>(p, which);
+    // the finest level of a Cartesian operator forms its couplings from one
+    // cell field (enthalpy, or conductivity) in the sweeps; the stored arrays
+    // serve the coarsening
+    LevelT<R>& L0 = S.L[0];
+    L0.qf = nullptr;
+    if (!G.sph && (which == 0 || G.has_chi)) {
+        const double tau = p->C.tau;
+        L0.qf = which == 0 ? p->C.H : p->C.chi;
+        L0.K0 = which == 0 ? (tau * tau) * G.gm1 : tau;
+        for (int d = 0; d < 3; ++d) L0.i2[d] = d < G.ndim ? G.idx[d] * G.idx[d] : 0.0;
+    }
     launch_level0<R>(G, p->C, which, S.L[0], p->stream);
     launch_level_diag<R>(G, S.L[0], p->stream);
     for (int l = 1; l < p->nlev; ++l) {
@@ -1020,7 +1031,7 @@ size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]
         if (G.bc[d] == WALL && G.has_chi) b += 2 * (size_t)G.n[(d + 1) % 3] * G.n[(d + 2) % 3] * 8;
     if (G.heat_balance) b += N * 8;                                               // heat-balance source
     if (G.sph) b += (size_t)sph_table_len(G) * 8;                                 // spherical metric
-    b += 10 * N * 8 + N * 8 + 4 * N * 8;                                          // pc coefficients, rE, lines
+    b += 9 * N * 8 + N * 8 + 4 * N * 8;                                           // pc coefficients, rE, lines
     const size_t rs = o.prec == JFNK_MIXED ? 4 : 8;
     for (int l = 0; l < nlev; ++l) b += 2 * level_bytes(nl[l], l == nlev - 1, rs);  // two operators
     b += 2 * kMaxLevels * (o.prec == JFNK_MIXED ? sizeof(LevelT<float>) : sizeof(LevelT<double>));
@@ -1195,13 +1206,14 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         sph_bind(p->G, met);
     }
     double* pcb = nullptr;
-    AL(pcb, (size_t)10 * N);
+    AL(pcb, (size_t)9 * N);
     for (int d = 0; d < 3; ++d) {
-        p->C.hf[d] = pcb + d * N;
-        p->C.kap[d] = pcb + (3 + d) * N;
-        p->C.beta[d] = pcb + (6 + d) * N;
+        p->C.kap[d] = pcb + d * N;
+        p->C.beta[d] = pcb + (3 + d) * N;
     }
-    p->C.W = pcb + 9 * N;
+    p->C.W = pcb + 6 * N;
+    p->C.H = pcb + 7 * N;
+    p->C.chi = pcb + 8 * N;
     AL(p->rEd, N);
     AL(p->lines, (size_t)4 * N);
     const bool split = opts->pc_solver == JFNK_PCS_MULTIGRID;
