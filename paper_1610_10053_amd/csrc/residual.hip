@@ -32,18 +32,14 @@ __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
     double qk = 0.0;
     for (int d = 0; d < ND; ++d) {
         const bool wall = G.bc[d] == WALL;
-        double a = 0.0, b = 0.0;
-        if (!(wall && q.v[d] == 0)) {
-            const double rl = st(s, 0, shifted(G, q, d, -1));
-            const double rf = 0.5 * (rl + rho);
-            a = st(s, 2 + d, c) / rf;
-        }
-        if (!(wall && q.v[d] == G.n[d] - 1)) {
-            const long cu = shifted(G, q, d, 1);
-            const double ru = st(s, 0, cu);
-            const double rf = 0.5 * (rho + ru);
-            b = st(s, 2 + d, cu) / rf;
-        }
+        // both neighbours are loaded on walls too (the periodic wrap keeps
+        // them in bounds) and the wall faces' values replaced by 0
+        const long cu = shifted(G, q, d, 1);
+        const double rl = st(s, 0, shifted(G, q, d, -1)), ru = st(s, 0, cu);
+        const double ml = st(s, 2 + d, c), mu = st(s, 2 + d, cu);
+        const double a0 = ml / (0.5 * (rl + rho)), b0 = mu / (0.5 * (rho + ru));
+        const double a = (wall && q.v[d] == 0) ? 0.0 : a0;
+        const double b = (wall && q.v[d] == G.n[d] - 1) ? 0.0 : b0;
         qk = qk + 0.5 * (a * a + b * b);
         P.uf[d][c] = a;
     }
@@ -136,22 +132,19 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
         const long L = shifted(G, q, d, -1);
         const double v = P.uf[d][c];
         const double rc = rho_at(0), rL = rho_at(-1), ec = eps_at(0), eL = eps_at(-1);
-        double rLL, eLL, rR, eR;
+        // second neighbours loaded everywhere (in bounds by the wrap; beyond
+        // a wall in the LDS tile the entry is unset and replaced) and
+        // replaced by the ghost values next to a wall
+        double rLL = rho_at(-2), eLL = eps_at(-2), rR = rho_at(1), eR = eps_at(1);
         if (wall && id == 1) {
             const Ghost gh = wall_ghost(G, P, L, c, d, false);
             rLL = gh.rho;
             eLL = gh.eps;
-        } else {
-            rLL = rho_at(-2);
-            eLL = eps_at(-2);
         }
         if (wall && id == G.n[d] - 1) {
             const Ghost gh = wall_ghost(G, P, c, L, d, true);
             rR = gh.rho;
             eR = gh.eps;
-        } else {
-            rR = rho_at(1);
-            eR = eps_at(1);
         }
         const double sl = van_leer(rc - rL, rL - rLL);
         const double sr = van_leer(rR - rc, rc - rL);
@@ -336,29 +329,28 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 const double t = F / o.scale[f];
                 part += t * t;
             } else if (o.mode == OUT_RESIDUAL) {
-                const double F = wallface ? 0.0 : (st(s, f, c) - o.b[x]) - o.h * Rf;
+                const double F0 = (st(s, f, c) - o.b[x]) - o.h * Rf;  // loaded on wall faces too
+                const double F = wallface ? 0.0 : F0;
                 o.out[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
             } else {  // OUT_JV
-                double w = 0.0;
                 const double e = s.eps[0];
-                if (!wallface && e != 0.0) w = s.v[x] - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);
-                o.out[x] = w;
+                const double w0 = s.v[x] - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
+                o.out[x] = (!wallface && e != 0.0) ? w0 : 0.0;
             }
         };
         // mass and energy in the cell
         double ar = 0.0, ae = 0.0;
         for (int d = 0; d < ND; ++d) {
             const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
-            double frh, feh;
+            // the upper neighbour's fluxes are loaded at a top wall too (the
+            // wrap keeps them in bounds) and replaced by the wall's
+            const long cu = shifted(G, q, d, 1);
+            double frh = Fx.fr[d][cu], feh = Fx.fe[d][cu];
             if (top) {
                 frh = 0.0;
                 feh = W.hi[d] ? W.hi[d][transverse(G, q, d)] : 0.0;
-            } else {
-                const long cu = shifted(G, q, d, 1);
-                frh = Fx.fr[d][cu];
-                feh = Fx.fe[d][cu];
             }
             if (G.sph) {
                 // (1/V) sum of area-weighted face fluxes
@@ -378,7 +370,8 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             for (int d = 0; d < ND; ++d) {
                 const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
                 const double ulo = P.uf[d][c];
-                const double uhi = top ? 0.0 : P.uf[d][shifted(G, q, d, 1)];
+                const double uu = P.uf[d][shifted(G, q, d, 1)];  // wrapped at a top wall, replaced by 0
+                const double uhi = top ? 0.0 : uu;
                 if (G.sph) {
                     const int i = q.v[0], j = q.v[1];
                     const double V = sph_vol(G, i, j);
@@ -393,7 +386,8 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 if (G.g[d] == 0.0) continue;
                 const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
                 const double mlo = st(s, 2 + d, c);
-                const double mhi = top ? 0.0 : st(s, 2 + d, shifted(G, q, d, 1));
+                const double mu = st(s, 2 + d, shifted(G, q, d, 1));  // wrapped at a top wall, replaced by 0
+                const double mhi = top ? 0.0 : mu;
                 ae = ae + G.g[d] * (0.5 * (mlo + mhi));
             }
         }
@@ -402,14 +396,13 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         emit(1, ae);
         // momentum on the lower faces
         for (int d = 0; d < ND; ++d) {
-            if (G.bc[d] == WALL && q.v[d] == 0) {
-                emit(2 + d, 0.0);
-                continue;
-            }
+            const bool wallface = G.bc[d] == WALL && q.v[d] == 0;
             if (G.sph) {
-                emit(2 + d, sph_momentum(G, P, Fx, q, c, d));
+                emit(2 + d, wallface ? 0.0 : sph_momentum(G, P, Fx, q, c, d));
                 continue;
             }
+            // formed on a wall face too (the wrapped lower neighbour is in
+            // bounds) and replaced by 0 there
             double a = 0.0;
             const long cl = shifted(G, q, d, -1);
 #pragma unroll
@@ -418,15 +411,14 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                     a = a - (Fx.phic[d][c] - Fx.phic[d][cl]) * G.idx[d];
                 } else {
                     // the edge above along e; on a wall of e it carries no flux
-                    const double up = (G.bc[e] == WALL && q.v[e] == G.n[e] - 1)
-                                          ? 0.0
-                                          : Fx.phie[d][e][shifted(G, q, e, 1)];
+                    const double pu = Fx.phie[d][e][shifted(G, q, e, 1)];
+                    const double up = (G.bc[e] == WALL && q.v[e] == G.n[e] - 1) ? 0.0 : pu;
                     a = a - (up - Fx.phie[d][e][c]) * G.idx[e];
                 }
             }
             a = a - (P.p[c] - P.p[cl]) * G.idx[d];
             if (G.g[d] != 0.0) a = a + (0.5 * (P.rho[cl] + P.rho[c])) * G.g[d];
-            emit(2 + d, a);
+            emit(2 + d, wallface ? 0.0 : a);
         }
     }
     if (o.partial) {
