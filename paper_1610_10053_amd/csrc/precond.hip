@@ -24,14 +24,14 @@ __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __rest
     if (!cell_from_launch(G, q, c)) return;
     const double* E = u + G.N;
     for (int d = 0; d < ND; ++d) {
-        double hf = 0.0, chif = 0.0;
-        if (!(G.bc[d] == WALL && q.v[d] == 0)) {
-            const long xl = shifted(G, q, d, -1);
-            const double hl = (E[xl] + P.p[xl]) / P.rho[xl];
-            const double hr = (E[c] + P.p[c]) / P.rho[c];
-            hf = 0.5 * (hl + hr);
-            if (G.has_chi) chif = 0.5 * (P.chi[xl] + P.chi[c]);
-        }
+        // the lower neighbour is loaded on a wall too (wrapped, in bounds)
+        // and the wall face's values replaced by 0
+        const bool wall = G.bc[d] == WALL && q.v[d] == 0;
+        const long xl = shifted(G, q, d, -1);
+        const double hl = (E[xl] + P.p[xl]) / P.rho[xl];
+        const double hr = (E[c] + P.p[c]) / P.rho[c];
+        const double hf = wall ? 0.0 : 0.5 * (hl + hr);
+        const double chif = (wall || !G.has_chi) ? 0.0 : 0.5 * (P.chi[xl] + P.chi[c]);
         // couplings per unit volume, or, on spherical grids, of the
         // volume-weighted system: face area over centre distance
         const double i2 = G.sph ? sph_area(G, d, q.v[0], q.v[1]) * face_ids(G, d, q.v[0]) : G.idx[d] * G.idx[d];
@@ -715,19 +715,15 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
         for (int d = 0; d < ND; ++d) {
             const double* vm = v + (long)(2 + d) * G.N;
             const double s = sc.v[2 + d];
-            if (G.bc[d] == WALL && q.v[d] == 0) {
-                dmlo[d] = 0.0;
-            } else {
-                dmlo[d] = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * face_ids(G, d, q.v[0]));
-            }
+            // both neighbours are loaded on walls too (the wrap keeps them in
+            // bounds) and the wall faces' values replaced by 0
+            const long up = shifted(G, q, d, 1);
+            const double lo = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * face_ids(G, d, q.v[0]));
+            const double hi = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * face_ids(G, d, q.v[0]));
             top[d] = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
-            dmhi[d] = 0.0;
-            upi[d] = c;
-            if (!top[d]) {
-                const long up = shifted(G, q, d, 1);
-                upi[d] = up;
-                dmhi[d] = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * face_ids(G, d, q.v[0]));
-            }
+            dmlo[d] = (G.bc[d] == WALL && q.v[d] == 0) ? 0.0 : lo;
+            dmhi[d] = top[d] ? 0.0 : hi;
+            upi[d] = up;
         }
         // divergence of face values: (hi - lo)/dx, or on spherical grids
         // (A_hi hi - A_lo lo)/V
