@@ -201,9 +201,10 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 
 // Gauss-Seidel value of one cell from its neighbours in x (first: neighbours
 // taken as 0)
-template <typename R, int ND>
-__device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c,
-                                      bool first) {
+// FIRST, QF (couplings from the level's cell field) and UNIT (sigma == 1)
+// are compile-time so that a sweep's loads form one straight-line block
+template <typename R, int ND, bool FIRST, bool QF, bool UNIT>
+__device__ __forceinline__ R gs_value_t(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
     R num = b[xbq(L, q)];
     R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
@@ -213,7 +214,7 @@ __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R
         const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
         const int lo = lflat(L, qd.v[0], qd.v[1], qd.v[2]), up = lflat(L, qu.v[0], qu.v[1], qu.v[2]);
         R alo, ahi;
-        if (L.qf) {
+        if (QF) {
             alo = qf_coupling(L, d, lo, c);
             ahi = qf_coupling(L, d, c, up);
         } else {
@@ -222,20 +223,27 @@ __device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R
         }
         alo = hd ? alo : (R)0.0;
         ahi = hu ? ahi : (R)0.0;
-        const R xlo = first ? (R)0.0 : x[xbq(L, qd)], xhi = first ? (R)0.0 : x[xbq(L, qu)];
+        const R xlo = FIRST ? (R)0.0 : x[xbq(L, qd)], xhi = FIRST ? (R)0.0 : x[xbq(L, qu)];
         num = hd ? num + alo * xlo : num;
         num = hu ? num + ahi * xhi : num;
         den = den + alo;
         den = den + ahi;
     }
-    return num / (L.unit_sig ? den : L.D[c]);
+    return num / (UNIT ? den : L.D[c]);
 }
-// in-place red-black update of one cell: valid while no two cells of one
-// colour are neighbours, i.e. every periodic axis of the level has even length
+template <typename R, int ND, bool FIRST>
+__device__ __forceinline__ R gs_value_f(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
+    if (L.qf) {
+        if (L.unit_sig) return gs_value_t<R, ND, FIRST, true, true>(G, L, b, x, q, c);
+        return gs_value_t<R, ND, FIRST, true, false>(G, L, b, x, q, c);
+    }
+    if (L.unit_sig) return gs_value_t<R, ND, FIRST, false, true>(G, L, b, x, q, c);
+    return gs_value_t<R, ND, FIRST, false, false>(G, L, b, x, q, c);
+}
 template <typename R, int ND>
-__device__ __forceinline__ void gs_cell(const Grid& G, const LevelT<R>& L, const R* b, R* x, LIjk q, int c,
-                                        bool first) {
-    x[xbq(L, q)] = gs_value<R, ND>(G, L, b, x, q, c, first);
+__device__ __forceinline__ R gs_value(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c,
+                                      bool first) {
+    return first ? gs_value_f<R, ND, true>(G, L, b, x, q, c) : gs_value_f<R, ND, false>(G, L, b, x, q, c);
 }
 // a periodic axis of odd length (possible on the coarsest level only): the
 // two cells facing each other across the wrap share a colour, so a colour's
@@ -250,11 +258,11 @@ __device__ __forceinline__ bool odd_periodic(const Grid& G, const LevelT<R>& L) 
 
 // residual of one fine cell, from the stored couplings (forming them from the
 // cell field, as the sweeps do on the finest level, measured slower here)
-template <typename R, int ND>
-__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
-                                        int c) {
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ R resid_cell_t(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
+                                          int c) {
     const R xc = x[xbq(L, q)];
-    R acc = L.unit_sig ? xc : L.sig[c] * xc;
+    R acc = UNIT ? xc : L.sig[c] * xc;
     for (int d = 0; d < ND; ++d) {
         LIjk qu = q, qd = q;  // beyond a wall a neighbour stays at q (loads issued, values discarded)
         const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
@@ -265,6 +273,11 @@ __device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const
         acc = hu ? acc + ahi * (xc - xhi) : acc;
     }
     return b[xbq(L, q)] - acc;
+}
+template <typename R, int ND>
+__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
+                                        int c) {
+    return L.unit_sig ? resid_cell_t<R, ND, true>(G, L, b, x, q, c) : resid_cell_t<R, ND, false>(G, L, b, x, q, c);
 }
 
 // coarse right-hand side: mean of the children's residuals
@@ -313,12 +326,34 @@ __device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, co
 }
 
 // ---------------------------------------------------------------- multigrid kernels (multi-block levels)
-template <typename R, int ND>
-__global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color, int first) {
+template <typename R, int ND, bool FIRST, bool QF, bool UNIT>
+__global__ void __launch_bounds__(kBlock) k_gs(Grid G, LevelT<R> L, int color) {
     LIjk q;
     int c;
     if (!lcell_color(L, color, q, c)) return;
-    gs_cell<R, ND>(G, L, L.b, L.x, q, c, first != 0);
+    L.x[xbq(L, q)] = gs_value_t<R, ND, FIRST, QF, UNIT>(G, L, L.b, L.x, q, c);
+}
+// one half-sweep of a multi-block level
+template <typename R, int ND, bool FIRST, bool QF>
+void launch_gs_u(const Grid& G, const LevelT<R>& L, int color, hipStream_t stream) {
+    const dim3 g = color_grid3(L.n), bl(kBx, kBy);
+    if (L.unit_sig) JFNK_KLAUNCH((k_gs<R, ND, FIRST, QF, true>), g, bl, 0, stream, G, L, color);
+    else JFNK_KLAUNCH((k_gs<R, ND, FIRST, QF, false>), g, bl, 0, stream, G, L, color);
+}
+template <typename R, int ND>
+void launch_gs_nd(const Grid& G, const LevelT<R>& L, int color, bool first, hipStream_t stream) {
+    if (L.qf) {
+        if (first) launch_gs_u<R, ND, true, true>(G, L, color, stream);
+        else launch_gs_u<R, ND, false, true>(G, L, color, stream);
+    } else {
+        if (first) launch_gs_u<R, ND, true, false>(G, L, color, stream);
+        else launch_gs_u<R, ND, false, false>(G, L, color, stream);
+    }
+}
+template <typename R>
+void launch_gs(const Grid& G, const LevelT<R>& L, int color, bool first, hipStream_t stream) {
+    if (G.ndim == 3) launch_gs_nd<R, 3>(G, L, color, first, stream);
+    else launch_gs_nd<R, 2>(G, L, color, first, stream);
 }
 // half-sweep of one colour from xin into xout (the other colour copied, or
 // zeroed on a first sweep): the update for levels with an odd periodic axis
@@ -347,7 +382,7 @@ inline dim3 restrict_grid(const int n[3]) {
     const dim3 b = restrict_block<ND>();
     return dim3((n[0] + b.x - 1) / b.x, (n[1] + b.y - 1) / b.y, ND > 2 ? (n[2] + 1) / 2 : n[2]);
 }
-template <typename R, int ND>
+template <typename R, int ND, bool UNIT>
 __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT<R> Cl) {
     constexpr int BX = ND > 2 ? kRx : 2 * kRx, BZ = ND > 2 ? 2 : 1;
     __shared__ R rs[BZ][kRy][BX];
@@ -358,7 +393,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict(Grid G, LevelT<R> F, LevelT
     f.v[2] = (int)(t.z * BZ + threadIdx.z);
     R r = (R)0.0;
     if (f.v[0] < F.n[0] && f.v[1] < F.n[1] && f.v[2] < F.n[2])
-        r = resid_cell<R, ND>(G, F, F.b, F.x, f, lflat(F, f.v[0], f.v[1], f.v[2]));
+        r = resid_cell_t<R, ND, UNIT>(G, F, F.b, F.x, f, lflat(F, f.v[0], f.v[1], f.v[2]));
     rs[threadIdx.z][threadIdx.y][threadIdx.x] = r;
     __syncthreads();
     // coarse cells of the tile: (BX/2) x (kRy/2) x 1
@@ -402,7 +437,7 @@ constexpr int kCoarseMaxLevelCells = 512;  // largest level the single-workgroup
 // own thread (levels of at most kCoarseMaxLevelCells <= kCoarseThreads
 // cells), whose coordinates, colour and neighbour indices are found once per
 // call; the update is gs_value's, operation for operation.
-template <typename R, int ND>
+template <typename R, int ND, bool UNIT>
 __device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
     const bool together = odd_periodic<R, ND>(G, L);
     const int c = (int)threadIdx.x;
@@ -422,9 +457,9 @@ __device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, in
             den = den + ahi[d];
         }
         bc = L.b[c];
-        if (!L.unit_sig) Dc = L.D[c];
+        if (!UNIT) Dc = L.D[c];
     }
-    const R dv = L.unit_sig ? den : Dc;
+    const R dv = UNIT ? den : Dc;
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             const bool f = first && s == 0 && color == 0;
@@ -461,7 +496,7 @@ __device__ __forceinline__ LevelT<R> lds_level(const LevelT<R>& g, R* sm, int ba
     L.b = sm + base + (3 + ND) * n;
     return L;
 }
-template <typename R, int ND>
+template <typename R, int ND, bool UNIT>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const LevelT<R>* __restrict__ Ld,
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
                                                                    int first_top, int light) {
@@ -495,10 +530,10 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         const bool first = l == from ? top_first : true;
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
-        lds_smooth<R, ND>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
+        lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
         // restriction: every fine residual once, then the children's sums in
         // the order of restrict_cell
-        for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell<R, ND>(G, L, L.b, L.x, lcoords(L, c), c);
+        for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell_t<R, ND, UNIT>(G, L, L.b, L.x, lcoords(L, c), c);
         __syncthreads();
         for (int c = threadIdx.x; c < C.N; c += blockDim.x) {
             const LIjk q = lcoords(C, c);
@@ -514,14 +549,14 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     }
     {
         const LevelT<R> L = lds_level<R, ND>(Ld[nlev - 1], sm, base[nlev - 1]);
-        lds_smooth<R, ND>(G, L, nuc, nlev - 1 == from ? top_first : true);
+        lds_smooth<R, ND, UNIT>(G, L, nuc, nlev - 1 == from ? top_first : true);
     }
     for (int l = nlev - 2; l >= from; --l) {
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
-        lds_smooth<R, ND>(G, L, (light > 0 && L.N <= light) ? 1 : nu2, false);
+        lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu2, false);
     }
     const LevelT<R> gT = Ld[from];
     const LevelT<R> T = lds_level<R, ND>(gT, sm, base[from]);
@@ -535,8 +570,19 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
                          int coarse_from, int nu1, int nu2, int nuc, int light, bool first, hipStream_t stream) {
     if (l >= coarse_from) {
         JFNK_PROF(KC_MG_COARSE, stream);
-        JFNK_LAUNCH_RND(G.ndim, k_coarse_vcycle, R, dim3(1), dim3(kCoarseThreads), 0, stream, G, Ld, l, nlev, nu1,
-                        nu2, nuc, first ? 1 : 0, light);
+        const int ft = first ? 1 : 0;
+        const dim3 g(1), bl(kCoarseThreads);
+        if (G.ndim == 3) {
+            if (S.L[l].unit_sig)
+                JFNK_KLAUNCH((k_coarse_vcycle<R, 3, true>), g, bl, 0, stream, G, Ld, l, nlev, nu1, nu2, nuc, ft, light);
+            else
+                JFNK_KLAUNCH((k_coarse_vcycle<R, 3, false>), g, bl, 0, stream, G, Ld, l, nlev, nu1, nu2, nuc, ft, light);
+        } else {
+            if (S.L[l].unit_sig)
+                JFNK_KLAUNCH((k_coarse_vcycle<R, 2, true>), g, bl, 0, stream, G, Ld, l, nlev, nu1, nu2, nuc, ft, light);
+            else
+                JFNK_KLAUNCH((k_coarse_vcycle<R, 2, false>), g, bl, 0, stream, G, Ld, l, nlev, nu1, nu2, nuc, ft, light);
+        }
         return;
     }
     const LevelT<R>& L = S.L[l];
@@ -573,11 +619,11 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         for (int s = 0; s < nuc; ++s) {
             {
                 JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-                JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+                launch_gs<R>(G, L, 0, (first && s == 0) ? 1 : 0, stream);
             }
             {
                 JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-                JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
+                launch_gs<R>(G, L, 1, 0, stream);
             }
         }
         return;
@@ -585,21 +631,28 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     for (int s = 0; s < nu1; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, (first && s == 0) ? 1 : 0);
+            launch_gs<R>(G, L, 0, (first && s == 0) ? 1 : 0, stream);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
+            launch_gs<R>(G, L, 1, 0, stream);
         }
     }
     {
         // fine x, b, couplings (and sigma) read once, coarse b written
         JFNK_PROFB(KC_MG_RESTRICT, stream,
                    (double)L.N * sizeof(R) * (2 + G.ndim + (L.unit_sig ? 0 : 1)) + (double)S.L[l + 1].N * sizeof(R));
-        if (G.ndim == 3)
-            JFNK_KLAUNCH((k_restrict<R, 3>), restrict_grid<3>(L.n), restrict_block<3>(), 0, stream, G, L, S.L[l + 1]);
-        else
-            JFNK_KLAUNCH((k_restrict<R, 2>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
+        if (G.ndim == 3) {
+            if (L.unit_sig)
+                JFNK_KLAUNCH((k_restrict<R, 3, true>), restrict_grid<3>(L.n), restrict_block<3>(), 0, stream, G, L, S.L[l + 1]);
+            else
+                JFNK_KLAUNCH((k_restrict<R, 3, false>), restrict_grid<3>(L.n), restrict_block<3>(), 0, stream, G, L, S.L[l + 1]);
+        } else {
+            if (L.unit_sig)
+                JFNK_KLAUNCH((k_restrict<R, 2, true>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
+            else
+                JFNK_KLAUNCH((k_restrict<R, 2, false>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
+        }
     }
     vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, light, true, stream);
     {
@@ -612,11 +665,11 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     for (int s = 0; s < nu2; ++s) {
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 0, 0);
+            launch_gs<R>(G, L, 0, 0, stream);
         }
         {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
-            JFNK_LAUNCH_RND(G.ndim, k_gs, R, cg, bl, 0, stream, G, L, 1, 0);
+            launch_gs<R>(G, L, 1, 0, stream);
         }
     }
 }
@@ -646,13 +699,15 @@ __device__ __forceinline__ double face_h(const Grid& G, const PcCoef& C, const I
     const double h = 0.5 * (C.H[wall ? c : shifted(G, q, d, -1)] + C.H[c]);  // load issued on walls too
     return wall ? 0.0 : h;
 }
-template <typename R, int ND>
+// RE: the energy right-hand side comes from the conduction solve (rE), else
+// from v (compile-time, so that the loads form one block)
+template <typename R, int ND, bool RE>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
+    const double re = RE ? rE[c] : sc.v[1] * v[G.N + c];
     double acc = 0.0;
     for (int d = 0; d < ND; ++d) {
         const double* vm = v + (long)(2 + d) * G.N;
@@ -698,7 +753,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
     rE[c] = G.sph ? sc.v[1] * v[G.N + c] + acc / sph_vol(G, q.v[0], q.v[1]) : acc;
 }
 
-template <typename R, int ND>
+template <typename R, int ND, bool RE>
 __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
                                                     const double* __restrict__ rE, const R* __restrict__ dp,
                                                     LevelT<R> L0, Scales5 sc, double* __restrict__ z,
@@ -707,7 +762,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
     long c = 0;
     double ss = 0.0;
     if (cell_from_launch(G, q, c)) {
-        const double re = rE ? rE[c] : sc.v[1] * v[G.N + c];
+        const double re = RE ? rE[c] : sc.v[1] * v[G.N + c];
         const double dpc = (double)dp[xbi(L0, q.v[0], q.v[1], q.v[2])];
         double dmlo[3], dmhi[3];
         bool top[3];
@@ -810,7 +865,14 @@ void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double
                    const LevelT<R>& L0, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (2 + G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        JFNK_LAUNCH_RND(G.ndim, k_pc_rhs, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, sc, L0);
+        const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+        if (G.ndim == 3) {
+            if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 3, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+            else JFNK_KLAUNCH((k_pc_rhs<R, 3, false>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+        } else {
+            if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 2, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+            else JFNK_KLAUNCH((k_pc_rhs<R, 2, false>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+        }
     }
 }
 template <typename R>
@@ -827,8 +889,14 @@ void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const doubl
     (void)nblk;
     {
         JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (1 + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
-        JFNK_LAUNCH_RND(G.ndim, k_pc_back, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, C, v, rE, dp, L0, sc,
-                        z, part);
+        const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+        if (G.ndim == 3) {
+            if (rE) JFNK_KLAUNCH((k_pc_back<R, 3, true>), g, bl, 0, stream, G, C, v, rE, dp, L0, sc, z, part);
+            else JFNK_KLAUNCH((k_pc_back<R, 3, false>), g, bl, 0, stream, G, C, v, rE, dp, L0, sc, z, part);
+        } else {
+            if (rE) JFNK_KLAUNCH((k_pc_back<R, 2, true>), g, bl, 0, stream, G, C, v, rE, dp, L0, sc, z, part);
+            else JFNK_KLAUNCH((k_pc_back<R, 2, false>), g, bl, 0, stream, G, C, v, rE, dp, L0, sc, z, part);
+        }
     }
 }
 template <typename R>
