@@ -14,29 +14,36 @@
 
 namespace jfnk {
 
-// value of state field f at cell c, optionally perturbed along v
-__device__ __forceinline__ double st(const StateView& s, int f, long c) {
+// value of state field f at cell c, perturbed along v when PERT
+template <bool PERT>
+__device__ __forceinline__ double st_t(const StateView& s, int f, long c) {
     const long x = (long)f * s.N + c;
     double a = s.u[x];
-    if (s.v) a = a + (s.eps[0] * s.scale[f]) * s.v[x];
+    if (PERT) a = a + (s.eps[0] * s.scale[f]) * s.v[x];
     return a;
+}
+__device__ __forceinline__ double st(const StateView& s, int f, long c) {
+    return s.v ? st_t<true>(s, f, c) : st_t<false>(s, f, c);
 }
 
 // ---------------------------------------------------------------- sweep 1: primitives per cell
-template <int ND>
+// PERT (state perturbed along v) is compile-time so that the state loads
+// form one straight-line block
+template <int ND, bool PERT>
 __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    const double rho = st(s, 0, c), E = st(s, 1, c);
+    const auto st = [&](int f, long cc) { return st_t<PERT>(s, f, cc); };
+    const double rho = st(0, c), E = st(1, c);
     double qk = 0.0;
     for (int d = 0; d < ND; ++d) {
         const bool wall = G.bc[d] == WALL;
         // both neighbours are loaded on walls too (the periodic wrap keeps
         // them in bounds) and the wall faces' values replaced by 0
         const long cu = shifted(G, q, d, 1);
-        const double rl = st(s, 0, shifted(G, q, d, -1)), ru = st(s, 0, cu);
-        const double ml = st(s, 2 + d, c), mu = st(s, 2 + d, cu);
+        const double rl = st(0, shifted(G, q, d, -1)), ru = st(0, cu);
+        const double ml = st(2 + d, c), mu = st(2 + d, cu);
         const double a0 = ml / (0.5 * (rl + rho)), b0 = mu / (0.5 * (rho + ru));
         const double a = (wall && q.v[d] == 0) ? 0.0 : a0;
         const double b = (wall && q.v[d] == G.n[d] - 1) ? 0.0 : b0;
@@ -305,7 +312,9 @@ __device__ __forceinline__ double sph_momentum(const Grid& G, const Prim& P, con
     return a;
 }
 
-template <int ND>
+// MODE and PERT (state perturbed along v) are compile-time so that each
+// instance's loads form straight-line blocks
+template <int ND, int MODE, bool PERT>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o) {
     Ijk q;
@@ -318,9 +327,9 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             const long x = (long)f * G.N + c;
             const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
             if (o.rout) o.rout[x] = Rf;
-            if (o.mode == OUT_RHS) {
+            if (MODE == OUT_RHS) {
                 o.out[x] = Rf;
-            } else if (o.mode == OUT_CN_OLD) {
+            } else if (MODE == OUT_CN_OLD) {
                 const double u0 = s.u[x];
                 const double b = u0 + o.h * Rf;
                 o.out[x] = b;
@@ -328,8 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 o.out2[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
-            } else if (o.mode == OUT_RESIDUAL) {
-                const double F0 = (st(s, f, c) - o.b[x]) - o.h * Rf;  // loaded on wall faces too
+            } else if (MODE == OUT_RESIDUAL) {
+                const double F0 = (st_t<PERT>(s, f, c) - o.b[x]) - o.h * Rf;  // loaded on wall faces too
                 const double F = wallface ? 0.0 : F0;
                 o.out[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
@@ -385,8 +394,8 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             for (int d = 0; d < ND; ++d) {
                 if (G.g[d] == 0.0) continue;
                 const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
-                const double mlo = st(s, 2 + d, c);
-                const double mu = st(s, 2 + d, shifted(G, q, d, 1));  // wrapped at a top wall, replaced by 0
+                const double mlo = st_t<PERT>(s, 2 + d, c);
+                const double mu = st_t<PERT>(s, 2 + d, shifted(G, q, d, 1));  // wrapped at a top wall, replaced by 0
                 const double mhi = top ? 0.0 : mu;
                 ae = ae + G.g[d] * (0.5 * (mlo + mhi));
             }
@@ -468,6 +477,35 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
 // ---------------------------------------------------------------- host launchers
 
 // compulsory bytes of the three sweeps (each array read or written once)
+template <int ND, int MODE>
+static void launch_out_m(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                         const double* sbal, const OutSpec& o, hipStream_t stream) {
+    const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+    if (s.v) JFNK_KLAUNCH((k_out<ND, MODE, true>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o);
+    else JFNK_KLAUNCH((k_out<ND, MODE, false>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o);
+}
+template <int ND>
+static void launch_out_nd(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                          const double* sbal, const OutSpec& o, hipStream_t stream) {
+    switch (o.mode) {
+        case OUT_RHS: launch_out_m<ND, OUT_RHS>(G, s, P, Fx, W, sbal, o, stream); break;
+        case OUT_CN_OLD: launch_out_m<ND, OUT_CN_OLD>(G, s, P, Fx, W, sbal, o, stream); break;
+        case OUT_RESIDUAL: launch_out_m<ND, OUT_RESIDUAL>(G, s, P, Fx, W, sbal, o, stream); break;
+        default: launch_out_m<ND, OUT_JV>(G, s, P, Fx, W, sbal, o, stream); break;
+    }
+}
+
+static void launch_prim_kernel(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
+    const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+    if (G.ndim == 3) {
+        if (s.v) JFNK_KLAUNCH((k_prim<3, true>), g, bl, 0, stream, G, s, P);
+        else JFNK_KLAUNCH((k_prim<3, false>), g, bl, 0, stream, G, s, P);
+    } else {
+        if (s.v) JFNK_KLAUNCH((k_prim<2, true>), g, bl, 0, stream, G, s, P);
+        else JFNK_KLAUNCH((k_prim<2, false>), g, bl, 0, stream, G, s, P);
+    }
+}
+
 static double prim_writes(const Grid& G) {
     return 8.0 * G.N * (3 + G.ndim + ((G.has_wall || G.has_chi) ? 1 : 0) + (G.has_chi ? 1 : 0) + (G.has_wall ? 1 : 0));
 }
@@ -491,7 +529,7 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     if (o.rout) b_out += vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
-        JFNK_LAUNCH_ND(G.ndim, k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
+        launch_prim_kernel(G, s, P, stream);
     }
     {
         JFNK_PROFB(KC_FLUX, stream, b_flux);
@@ -503,7 +541,8 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     }
     {
         JFNK_PROFB(KC_OUT, stream, b_out);
-        JFNK_LAUNCH_ND(G.ndim, k_out, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P, Fx, W, sbal, o);
+        if (G.ndim == 3) launch_out_nd<3>(G, s, P, Fx, W, sbal, o, stream);
+        else launch_out_nd<2>(G, s, P, Fx, W, sbal, o, stream);
     }
 }
 
@@ -519,7 +558,7 @@ void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Fl
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     {
         JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));
-        JFNK_LAUNCH_ND(G.ndim, k_prim, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, s, P);
+        launch_prim_kernel(G, s, P, stream);
     }
 }
 
