@@ -177,9 +177,12 @@ __global__ void __launch_bounds__(kBlock) k_flux(Grid G, Prim P, Flux Fx, WallFl
 // Velocity component d on the d-face with index a along d (row of the
 // other coordinates of q), across walls: the wall faces carry 0 and faces
 // beyond a wall are the negated mirror images (reflecting wall).
+// WALLS: the grid has a wall on some axis (compile-time; without walls every
+// axis wraps and the sweep has no wall branches)
+template <bool WALLS>
 __device__ __forceinline__ double uf_normal(const Grid& G, const Prim& P, const Ijk& q, int d, int a) {
     const int n = G.n[d];
-    if (G.bc[d] == WALL) {
+    if (WALLS && G.bc[d] == WALL) {
         double sgn = 1.0;
         if (a < 0) { a = -a; sgn = -1.0; }
         else if (a > n) { a = 2 * n - a; sgn = -1.0; }
@@ -193,10 +196,11 @@ __device__ __forceinline__ double uf_normal(const Grid& G, const Prim& P, const 
 
 // Velocity component c on its face at row a along another axis e, across
 // walls of e: stress-free mirror images.
+template <bool WALLS>
 __device__ __forceinline__ double uf_tangential(const Grid& G, const Prim& P, const Ijk& q, int c, int e,
                                                 int a) {
     const int n = G.n[e];
-    if (G.bc[e] == WALL) {
+    if (WALLS && G.bc[e] == WALL) {
         if (a < 0) a = -1 - a;
         else if (a >= n) a = 2 * n - 1 - a;
     } else {
@@ -208,15 +212,16 @@ __device__ __forceinline__ double uf_tangential(const Grid& G, const Prim& P, co
 
 // Cell-centred momentum flux of component d along d at the cell with
 // coordinates x (x on or inside the domain along d).
+template <bool WALLS>
 __device__ __forceinline__ double phi_cell(const Grid& G, const Prim& P, const Flux& Fx, const Ijk& x,
                                            int d) {
     const long c = flat(G, x.v[0], x.v[1], x.v[2]);
-    const bool top = G.bc[d] == WALL && x.v[d] == G.n[d] - 1;
+    const bool top = WALLS && G.bc[d] == WALL && x.v[d] == G.n[d] - 1;
     const double fhi = top ? 0.0 : Fx.fr[d][shifted(G, x, d, 1)];
     const double Fb = 0.5 * (Fx.fr[d][c] + fhi);
     const int a0 = x.v[d];
-    const double ua = uf_normal(G, P, x, d, a0 - 1), ub = uf_normal(G, P, x, d, a0);
-    const double uc = uf_normal(G, P, x, d, a0 + 1), ud = uf_normal(G, P, x, d, a0 + 2);
+    const double ua = uf_normal<WALLS>(G, P, x, d, a0 - 1), ub = uf_normal<WALLS>(G, P, x, d, a0);
+    const double uc = uf_normal<WALLS>(G, P, x, d, a0 + 1), ud = uf_normal<WALLS>(G, P, x, d, a0 + 2);
     const double sl = van_leer(uc - ub, ub - ua);
     const double sr = van_leer(ud - uc, uc - ub);
     return Fb * upstream(Fb, ub, sl, uc, sr);
@@ -224,12 +229,13 @@ __device__ __forceinline__ double phi_cell(const Grid& G, const Prim& P, const F
 
 // Edge momentum flux of component d along e != d at the lower e-side of the
 // d-face whose cell has coordinates x; x.v[e] may equal n_e (upper edge).
+template <bool WALLS>
 __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const Flux& Fx, Ijk x, int d,
                                            int e) {
     const int ne = G.n[e];
     double Gm;
     const int a0 = x.v[e];
-    if (G.bc[e] == WALL && (a0 == 0 || a0 == ne)) {
+    if (WALLS && G.bc[e] == WALL && (a0 == 0 || a0 == ne)) {
         Gm = 0.0;
     } else {
         Ijk xw = x;
@@ -238,8 +244,8 @@ __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const F
         const long cl = shifted(G, xw, d, -1);
         Gm = 0.5 * (Fx.fr[e][cl] + Fx.fr[e][cx]);
     }
-    const double ua = uf_tangential(G, P, x, d, e, a0 - 2), ub = uf_tangential(G, P, x, d, e, a0 - 1);
-    const double uc = uf_tangential(G, P, x, d, e, a0), ud = uf_tangential(G, P, x, d, e, a0 + 1);
+    const double ua = uf_tangential<WALLS>(G, P, x, d, e, a0 - 2), ub = uf_tangential<WALLS>(G, P, x, d, e, a0 - 1);
+    const double uc = uf_tangential<WALLS>(G, P, x, d, e, a0), ud = uf_tangential<WALLS>(G, P, x, d, e, a0 + 1);
     const double sl = van_leer(uc - ub, ub - ua);
     const double sr = van_leer(ud - uc, uc - ub);
     return Gm * upstream(Gm, ub, sl, uc, sr);
@@ -248,19 +254,21 @@ __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const F
 // Momentum transport fluxes of the staggered control volumes, one per
 // (component, direction) and cell: cell-centred for d == e, at the lower
 // e-edge of the d-face otherwise (wall faces, which are not unknowns, get 0).
-template <int ND>
+// Each flux is stored as soon as it is formed (forming all before storing
+// any measured slower: 114 VGPRs, occupancy 4).
+template <int ND, bool WALLS>
 __global__ void __launch_bounds__(kBlock) k_mflux(Grid G, Prim P, Flux Fx) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
-        Fx.phic[d][c] = phi_cell(G, P, Fx, q, d);
-        const bool wallface = G.bc[d] == WALL && q.v[d] == 0;
+        Fx.phic[d][c] = phi_cell<WALLS>(G, P, Fx, q, d);
+        const bool wallface = WALLS && G.bc[d] == WALL && q.v[d] == 0;
 #pragma unroll
         for (int e = 0; e < ND; ++e) {
             if (e == d) continue;
-            Fx.phie[d][e][c] = wallface ? 0.0 : phi_edge(G, P, Fx, q, d, e);
+            Fx.phie[d][e][c] = wallface ? 0.0 : phi_edge<WALLS>(G, P, Fx, q, d, e);
         }
     }
 }
@@ -537,7 +545,14 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     }
     {
         JFNK_PROFB(KC_MFLUX, stream, 8.0 * G.N * (2 * G.ndim + G.ndim * G.ndim));
-        JFNK_LAUNCH_ND(G.ndim, k_mflux, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, P, Fx);
+        const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+        if (G.ndim == 3) {
+            if (G.has_wall) JFNK_KLAUNCH((k_mflux<3, true>), g, bl, 0, stream, G, P, Fx);
+            else JFNK_KLAUNCH((k_mflux<3, false>), g, bl, 0, stream, G, P, Fx);
+        } else {
+            if (G.has_wall) JFNK_KLAUNCH((k_mflux<2, true>), g, bl, 0, stream, G, P, Fx);
+            else JFNK_KLAUNCH((k_mflux<2, false>), g, bl, 0, stream, G, P, Fx);
+        }
     }
     {
         JFNK_PROFB(KC_OUT, stream, b_out);
