@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
             L.sig[c] = gL.sig[c];
             for (int d = 0; d < ND; ++d) L.a[d][c] = gL.a[d][c];
-            L.D[c] = gL.D[c];
+            if (!UNIT) L.D[c] = gL.D[c];  // built only without unit sigma
             if (l == from) {
                 L.b[c] = gL.b[c];
                 if (!top_first) L.x[c] = gL.x[c];

@@ -448,20 +448,24 @@ void build_hierarchy(jfnk_problem* p, int which) {
         L0.K0 = which == 0 ? (tau * tau) * G.gm1 : tau;
         for (int d = 0; d < 3; ++d) L0.i2[d] = d < G.ndim ? G.idx[d] * G.idx[d] : 0.0;
     }
+    // D is built only without unit sigma: with sigma == 1 the sweeps form it
+    // from the couplings
+    const bool diag = !S.L[0].unit_sig;
     launch_level0<R>(G, p->C, which, S.L[0], p->stream);
-    launch_level_diag<R>(G, S.L[0], p->stream);
+    if (diag) launch_level_diag<R>(G, S.L[0], p->stream);
     for (int l = 1; l < p->nlev; ++l) {
         launch_coarsen<R>(G, S.L[l - 1], S.L[l], p->stream);
-        launch_level_diag<R>(G, S.L[l], p->stream);
+        if (diag) launch_level_diag<R>(G, S.L[l], p->stream);
     }
 }
 
-// frozen coefficients at state u
-int pc_build(jfnk_problem* p, const double* u, double dt) {
+// frozen coefficients at state u; prim_valid: the primitives in P are
+// already those of u (the Newton loop has just evaluated the residual there)
+int pc_build(jfnk_problem* p, const double* u, double dt, bool prim_valid) {
     const Grid& G = p->G;
     p->C.tau = 0.5 * dt;
     if (p->opts.pc == JFNK_PC_NONE) return 0;
-    launch_prim(G, view(p, u, nullptr), p->P, p->stream);
+    if (!prim_valid) launch_prim(G, view(p, u, nullptr), p->P, p->stream);
     launch_pc_coef(G, u, p->P, p->C, dt, p->stream);
     if (p->opts.pc_solver == JFNK_PCS_MULTIGRID) {
         const bool diff = p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION;
@@ -736,7 +740,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
             status = 1;
             break;
         }
-        CK(pc_build(p, p->u, dt));
+        CK(pc_build(p, p->u, dt, true));  // P holds the primitives of u from the residual just evaluated
         set_usq(p, p->u);
         GmresInfo gi;
         int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi) : gmres<double>(p, p->u, dt, &gi);
@@ -1549,7 +1553,7 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
     int rc;
     if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
     if ((rc = copy_in(p, p->s2, v, on_device))) return rc;
-    if ((rc = pc_build(p, p->s1, dt))) return rc;
+    if ((rc = pc_build(p, p->s1, dt, false))) return rc;
     HIPCHK(hipMemsetAsync(p->dsum + D_USQ, 0, sizeof(double), p->stream));
     pc_apply(p, p->s2, p->w);
     HIPCHK(hipGetLastError());
