@@ -274,29 +274,6 @@ __device__ __forceinline__ R resid_cell_t(const Grid& G, const LevelT<R>& L, con
     }
     return b[xbq(L, q)] - acc;
 }
-template <typename R, int ND>
-__device__ __forceinline__ R resid_cell(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q,
-                                        int c) {
-    return L.unit_sig ? resid_cell_t<R, ND, true>(G, L, b, x, q, c) : resid_cell_t<R, ND, false>(G, L, b, x, q, c);
-}
-
-// coarse right-hand side: mean of the children's residuals
-template <typename R, int ND>
-__device__ __forceinline__ R restrict_cell(const Grid& G, const LevelT<R>& F, const R* fb, const R* fx, LIjk q) {
-    const int kk = ND > 2 ? 2 : 1;
-    const R inv_ch = (R)(1.0 / (1 << ND));
-    R s = 0.0;
-    for (int dk = 0; dk < kk; ++dk)
-        for (int dj = 0; dj < 2; ++dj)
-            for (int di = 0; di < 2; ++di) {
-                LIjk f;
-                f.v[0] = 2 * q.v[0] + di;
-                f.v[1] = 2 * q.v[1] + dj;
-                f.v[2] = ND > 2 ? 2 * q.v[2] + dk : q.v[2];
-                s = s + resid_cell<R, ND>(G, F, fb, fx, f, lflat(F, f.v[0], f.v[1], f.v[2]));
-            }
-    return s * inv_ch;
-}
 
 // cell-centred (bi/tri)linear prolongation of the coarse correction, weights
 // 3/4 and 1/4 per axis; beyond a wall the parent value is reused
@@ -370,9 +347,11 @@ __global__ void __launch_bounds__(kBlock) k_gs_pp(Grid G, LevelT<R> L, int color
     }
     xout[e] = gs_value<R, ND>(G, L, L.b, xin, q, c, first != 0);
 }
-// Restriction of a multi-block level: one thread per fine cell computes its
+// Restriction of a multi-block level: the coarse right-hand side is the mean
+// of the children's residuals.  One thread per fine cell computes its
 // residual, and the 2^ND children of each coarse cell (all in one workgroup)
-// are summed in LDS in the order of restrict_cell.  Workgroups are
+// are summed in LDS in a fixed order (k, then j, then i of the child, each
+// from the lower one), then times 1/2^ND.  Workgroups are
 // kRx x kRy x kRz fine cells (kRz = 2 in 3D, 1 in 2D).
 constexpr int kRx = 32, kRy = 4;
 template <int ND>
@@ -532,7 +511,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
         lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
         // restriction: every fine residual once, then the children's sums in
-        // the order of restrict_cell
+        // the order of the multi-block restriction
         for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell_t<R, ND, UNIT>(G, L, L.b, L.x, lcoords(L, c), c);
         __syncthreads();
         for (int c = threadIdx.x; c < C.N; c += blockDim.x) {

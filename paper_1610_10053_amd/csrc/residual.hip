@@ -22,9 +22,6 @@ __device__ __forceinline__ double st_t(const StateView& s, int f, long c) {
     if (PERT) a = a + (s.eps[0] * s.scale[f]) * s.v[x];
     return a;
 }
-__device__ __forceinline__ double st(const StateView& s, int f, long c) {
-    return s.v ? st_t<true>(s, f, c) : st_t<false>(s, f, c);
-}
 
 // ---------------------------------------------------------------- sweep 1: primitives per cell
 // PERT (state perturbed along v) is compile-time so that the state loads
