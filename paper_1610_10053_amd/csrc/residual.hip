@@ -5,11 +5,13 @@
 // chi = chi0 T^3, upstream linear extrapolation with the van Leer limiter, and
 // the three consumers
 //   b = u + dt/2 R(u)                 (old-time half of Crank-Nicolson)
-//   F = (u - b) - dt/2 R(u)           (residual)
+//   F = (u - b) - dt/2 R(u)           (residual; at a Newton iterate it is
+//                                      written as -S^-1 F, the right-hand side)
 //   w = v - dt/2 (R(u + eps S v) - R(u)) / (eps S)   (Jacobian-free product:
 //       the difference quotient of F, whose part u - b is linear, with only
 //       R differenced)
-// Three sweeps: cell primitives, face fluxes, then cell and face outputs.
+// Four sweeps: cell primitives, face fluxes of mass and energy, momentum
+// transport fluxes, then the cell and face outputs.
 #include "kernels.hpp"
 
 namespace jfnk {
@@ -481,7 +483,7 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
 
 // ---------------------------------------------------------------- host launchers
 
-// compulsory bytes of the three sweeps (each array read or written once)
+// the output sweep's instance for the mode and the perturbation flag
 template <int ND, int MODE>
 static void launch_out_m(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                          const double* sbal, const OutSpec& o, hipStream_t stream) {
@@ -511,6 +513,7 @@ static void launch_prim_kernel(const Grid& G, const StateView& s, const Prim& P,
     }
 }
 
+// compulsory bytes of the sweeps (each array read or written once)
 static double prim_writes(const Grid& G) {
     return 8.0 * G.N * (3 + G.ndim + ((G.has_wall || G.has_chi) ? 1 : 0) + (G.has_chi ? 1 : 0) + (G.has_wall ? 1 : 0));
 }
