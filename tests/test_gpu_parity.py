@@ -87,6 +87,23 @@ def test_jv_parity(torch_cuda, name, n):
     assert rel_l2(g.apply_jv(u1, b, dt, v), o.jv(u1, b, dt, v)) < 1e-9
 
 
+@pytest.mark.parametrize("name,n", [("tg", 16), ("rad", 16)])
+def test_zero_direction_products(torch_cuda, name, n):
+    """Degenerate direction v = 0: the product's step eps is 0 and the
+    product is exactly 0 (no division by the zero step reaches the output);
+    the preconditioner maps 0 to 0; both as the oracle."""
+    desc, opts, u, g, o = _pair(name, n)
+    ts = o.time_step(u)
+    g.eval_time_step(u)
+    dt = ts["dt"]
+    b = o.cn_old(u, dt)
+    v = np.zeros_like(u)
+    w = g.apply_jv(u, b, dt, v)
+    assert not np.any(w) and np.array_equal(w, o.jv(u, b, dt, v))
+    z = g.apply_precond(u, dt, v)
+    assert not np.any(z) and np.array_equal(z, o.precond(u, dt, v))
+
+
 @pytest.mark.parametrize("solver", ["mg", "adi"])
 @pytest.mark.parametrize("name,n", CASES + FULL)
 def test_preconditioner_bitwise(torch_cuda, name, n, solver):
