@@ -179,8 +179,11 @@ int jfnk_eval_residual(jfnk_problem* p, const double* u, const double* b, double
 int jfnk_eval_time_step(jfnk_problem* p, const double* u, double* out9, int on_device);
 /* Override the variable scales S (5 values: rho, E, m_x, m_y, m_z). */
 int jfnk_set_scales(jfnk_problem* p, const double* s5);
-/* Jacobian-free product in scaled variables:
- * w = S^-1 (F(u + eps S v) - F(u)) / eps, eps = sqrt(2^-52)(1 + rms(S^-1 u))/rms(v). */
+/* Jacobian-free product in scaled variables (section 2, JFNK):
+ * w = S^-1 (F(u + eps S v) - F(u)) / eps, eps = sqrt(2^-52)(1 + rms(S^-1 u))/rms(v),
+ * evaluated as v - (dt/2) S^-1 (R(u + eps S v) - R(u)) / eps: the part u - b of
+ * F is linear, so only R is differenced.  Wall faces of w are 0; v = 0 gives
+ * eps = 0 and w = 0. */
 int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, const double* v,
                   double* w, int on_device);
 /* Preconditioner with coefficients frozen at u: z = S^-1 P^-1 (S v). */
