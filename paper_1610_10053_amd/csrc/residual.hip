@@ -321,9 +321,14 @@ __device__ __forceinline__ double sph_momentum(const Grid& G, const Prim& P, con
 
 // MODE and PERT (state perturbed along v) are compile-time so that each
 // instance's loads form straight-line blocks
+// The outputs come as their own __restrict__ parameters (they never alias
+// an input), so that the loads of a later field need not wait for the stores
+// of an earlier one.
 template <int ND, int MODE, bool PERT>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
-                                                const double* __restrict__ sbal, OutSpec o) {
+                                                const double* __restrict__ sbal, OutSpec o,
+                                                double* __restrict__ out, double* __restrict__ out2,
+                                                double* __restrict__ rout, double* __restrict__ partial) {
     Ijk q;
     long c = 0;
     double part = 0.0;
@@ -333,27 +338,27 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         auto emit = [&](int f, double Rf) {
             const long x = (long)f * G.N + c;
             const bool wallface = f >= 2 && G.bc[f - 2] == WALL && q.v[f - 2] == 0;
-            if (o.rout) o.rout[x] = Rf;
+            if (rout) rout[x] = Rf;
             if (MODE == OUT_RHS) {
-                o.out[x] = Rf;
+                out[x] = Rf;
             } else if (MODE == OUT_CN_OLD) {
                 const double u0 = s.u[x];
                 const double b = u0 + o.h * Rf;
-                o.out[x] = b;
+                out[x] = b;
                 const double F = wallface ? 0.0 : (u0 - b) - o.h * Rf;
-                o.out2[x] = o.neg_scaled ? -F / o.scale[f] : F;
+                out2[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
             } else if (MODE == OUT_RESIDUAL) {
                 const double F0 = (st_t<PERT>(s, f, c) - o.b[x]) - o.h * Rf;  // loaded on wall faces too
                 const double F = wallface ? 0.0 : F0;
-                o.out[x] = o.neg_scaled ? -F / o.scale[f] : F;
+                out[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
             } else {  // OUT_JV
                 const double e = s.eps[0];
                 const double w0 = s.v[x] - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
-                o.out[x] = (!wallface && e != 0.0) ? w0 : 0.0;
+                out[x] = (!wallface && e != 0.0) ? w0 : 0.0;
             }
         };
         // mass and energy in the cell
@@ -437,10 +442,10 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             emit(2 + d, wallface ? 0.0 : a);
         }
     }
-    if (o.partial) {
+    if (partial) {
         __shared__ double sh[kBlock / 64];
         const double t = block_sum(part, sh);
-        if (lin_thread() == 0) o.partial[lin_block()] = t;
+        if (lin_thread() == 0) partial[lin_block()] = t;
     }
 }
 
@@ -488,8 +493,12 @@ template <int ND, int MODE>
 static void launch_out_m(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                          const double* sbal, const OutSpec& o, hipStream_t stream) {
     const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
-    if (s.v) JFNK_KLAUNCH((k_out<ND, MODE, true>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o);
-    else JFNK_KLAUNCH((k_out<ND, MODE, false>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o);
+    if (s.v)
+        JFNK_KLAUNCH((k_out<ND, MODE, true>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
+                     o.partial);
+    else
+        JFNK_KLAUNCH((k_out<ND, MODE, false>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
+                     o.partial);
 }
 template <int ND>
 static void launch_out_nd(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
