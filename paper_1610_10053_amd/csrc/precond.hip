@@ -276,26 +276,34 @@ __device__ __forceinline__ R resid_cell_t(const Grid& G, const LevelT<R>& L, con
 }
 
 // cell-centred (bi/tri)linear prolongation of the coarse correction, weights
-// 3/4 and 1/4 per axis; beyond a wall the parent value is reused
+// 3/4 and 1/4 per axis; beyond a wall the parent value is reused.  The two
+// parent indices of each axis are found once, with selects, and the corners
+// are summed in the order m = 0..2^ND-1 (bit d of m: the neighbour along d).
 template <typename R, int ND>
 __device__ __forceinline__ R prolong_cell(const Grid& G, const LevelT<R>& Cl, const R* cx, LIjk f) {
-    const int P[3] = {f.v[0] / 2, f.v[1] / 2, ND > 2 ? f.v[2] / 2 : f.v[2]};
+    int p0[3], p1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int P = d < ND ? f.v[d] / 2 : f.v[d];
+        p0[d] = P;
+        p1[d] = P;
+        if (d < ND) {
+            const int n = Cl.n[d];
+            const int a = P + ((f.v[d] % 2 == 0) ? -1 : 1);
+            const int w = a < 0 ? a + n : (a >= n ? a - n : a);
+            p1[d] = (a < 0 || a >= n) ? (G.bc[d] == WALL ? P : w) : a;
+        }
+    }
     R e = 0.0;
+#pragma unroll
     for (int m = 0; m < (1 << ND); ++m) {
-        int qq[3] = {P[0], P[1], P[2]};
         R w = 1.0;
-        for (int d = 0; d < ND; ++d) {
-            if (m & (1 << d)) {
-                const int off = (f.v[d] % 2 == 0) ? -1 : 1;
-                w = w * (R)0.25;
-                qq[d] += off;
-                if (qq[d] < 0 || qq[d] >= Cl.n[d]) {
-                    if (G.bc[d] == WALL) qq[d] -= off;
-                    else qq[d] = qq[d] < 0 ? qq[d] + Cl.n[d] : qq[d] - Cl.n[d];
-                }
-            } else {
-                w = w * (R)0.75;
-            }
+        int qq[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bool nb = d < ND && (m & (1 << d));
+            if (d < ND) w = w * (nb ? (R)0.25 : (R)0.75);
+            qq[d] = nb ? p1[d] : p0[d];
         }
         e = e + w * cx[xbi(Cl, qq[0], qq[1], qq[2])];
     }
