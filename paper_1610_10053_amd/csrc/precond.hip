@@ -266,7 +266,7 @@ __device__ __forceinline__ R resid_cell_t(const Grid& G, const LevelT<R>& L, con
     for (int d = 0; d < ND; ++d) {
         LIjk qu = q, qd = q;  // beyond a wall a neighbour stays at q (loads issued, values discarded)
         const bool hu = lnbq(G, L, qu, d, 1), hd = lnbq(G, L, qd, d, -1);
-        const int lo = lflat(L, qd.v[0], qd.v[1], qd.v[2]), up = lflat(L, qu.v[0], qu.v[1], qu.v[2]);
+        const int up = lflat(L, qu.v[0], qu.v[1], qu.v[2]);
         const R alo = L.a[d][c], ahi = L.a[d][up];
         const R xlo = x[xbq(L, qd)], xhi = x[xbq(L, qu)];
         acc = hd ? acc + alo * (xc - xlo) : acc;
