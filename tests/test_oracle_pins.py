@@ -648,19 +648,6 @@ def test_rt_mirror_symmetry_bitwise_unpreconditioned():
         assert np.array_equal(mirror_x(s, desc), s)
 
 
-def test_rt_mirror_symmetry_preconditioned_to_newton_tolerance():
-    """Red-black smoothing is not mirror-symmetric, so with the preconditioner
-    on, symmetry holds to the accuracy of the solve: the Newton tolerance
-    (1e-8 of the residual) times the relative size of a step's change
-    (~1e-2) bounds the asymmetry by ~1e-10."""
-    desc, o, u = make_config("rt", n=16)
-    orc = Oracle(desc, o, u)
-    for _ in range(3):
-        assert orc.implicit_step()[0] == 0
-    s = orc.get_state()
-    assert rel_l2(mirror_x(s, desc), s) < 1e-10
-
-
 # ---------------------------------------------------------------- failure handling
 
 def test_newton_failure_restores_state_and_reports():
