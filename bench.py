@@ -171,6 +171,25 @@ def serving(jfnk, args):
             "saturated": sat, "poisson_0.8x": poi}
 
 
+def model_bytes_per_cell(newton, gmres, ndim, basis_bytes_ratio):
+    """Algorithmic HBM bytes per cell of one implicit step with the given
+    Newton and GMRES iteration counts (the step's method minimum, each vector
+    read or written once): with S_v the bytes of one FP64 state vector per
+    cell and S_b the basis bytes per cell (S_v, or S_v/2 for an FP32 basis),
+    3 S_v for the time step and the Crank-Nicolson old-time term; per Newton
+    iteration 3 S_v for F, k S_b + 6 S_v for the update (k = GMRES
+    iterations per Newton iteration); per GMRES iteration 12 S_v (preconditioner
+    about 4, Jacobian-free product 5, new basis vector 3) plus 3 j S_b for the
+    fused CGS2 passes against the j vectors already in the basis."""
+    sv = 8.0 * (2 + ndim)
+    sb = sv * basis_bytes_ratio
+    if newton <= 0:
+        return 3.0 * sv
+    k = gmres / newton
+    return (3.0 * sv + newton * (3.0 * sv + k * sb + 6.0 * sv) + gmres * 12.0 * sv
+            + newton * 1.5 * k * (k + 1.0) * sb)
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tg128_fp64_hbm_traffic.md")
 
 
@@ -270,25 +289,34 @@ def main():
         o = dict(opts, prec=PREC_MIXED if f == "mixed" else PREC_FP64)
         res[f] = run_form(jfnk, torch, desc, o, u0, args.steps, args.warmup, prof=not args.no_prof)
 
-    def summary(r):
+    def summary(r, basis_ratio=1.0):
         ms = r["step_ms"]
         st = r["stats"]
         value = cells * len(ms) / r["wall"]
+        model = sum(model_bytes_per_cell(s["newton_its"], s["gmres_its"], desc["ndim"], basis_ratio) for s in st)
+        whole_gbs = model * cells / r["wall"] / 1e9
         ms_d, cnt, by = r["dom"]
         achieved = (by / (ms_d * 1e-3)) / 1e9 if ms_d > 0 else None
         kern = {}
         for k, (t, c, b) in sorted(r["table"].items(), key=lambda kv: -kv[1][0]):
+            gbs = b / (t * 1e-3) / 1e9 if b > 0 and t > 0 else None
             kern[k] = dict(ms=round(t, 3), launches=c, avg_us=round(1e3 * t / c, 2),
-                           gbs=round(b / (t * 1e-3) / 1e9, 1) if b > 0 and t > 0 else None)
+                           gbs=round(gbs, 1) if gbs else None,
+                           frac=round(gbs / PEAK_HBM_GBS, 3) if gbs else None)
         return dict(value=value, ms_per_step=1e3 * r["wall"] / len(ms), p50_ms=float(np.percentile(ms, 50)),
                     p99_ms=float(np.percentile(ms, 99)), first_step_ms=float(ms[0]),
                     newton_its_per_step=float(np.mean([s["newton_its"] for s in st])),
                     gmres_its_per_step=float(np.mean([s["gmres_its"] for s in st])),
                     dominant=r["dominant"], dominant_gbs=achieved,
-                    dominant_avg_us=1e3 * ms_d / cnt if cnt else None, kernels=kern)
+                    dominant_avg_us=1e3 * ms_d / cnt if cnt else None, kernels=kern,
+                    max_rel_res=float(max(s["rel_res"] for s in st)),
+                    newton_exit_counts={"residual": sum(1 for s in st if s["newton_exit"] == 0),
+                                        "density_correction": sum(1 for s in st if s["newton_exit"] == 1)},
+                    whole_step={"model_bytes_per_cell_step": model / len(st), "achieved": whole_gbs,
+                                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": whole_gbs / PEAK_HBM_GBS})
 
     main_form = forms[0]
-    s0 = summary(res[main_form])
+    s0 = summary(res[main_form], 0.5 if main_form == "mixed" else 1.0)
     out = {
         "metric": METRIC, "value": s0["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": s0["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -300,15 +328,17 @@ def main():
                    "separate instance)" % args.steps},
         "p50_ms": s0["p50_ms"], "p99_ms": s0["p99_ms"], "first_step_ms": s0["first_step_ms"],
         "newton_its_per_step": s0["newton_its_per_step"], "gmres_its_per_step": s0["gmres_its_per_step"],
+        "max_rel_res": s0["max_rel_res"], "newton_exit_counts": s0["newton_exit_counts"],
         "roofline": {"bound": "hbm", "kernel": s0["dominant"], "achieved": s0["dominant_gbs"],
                      "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": (s0["dominant_gbs"] / PEAK_HBM_GBS) if s0["dominant_gbs"] else None,
                      "avg_launch_us": s0["dominant_avg_us"], "traffic": measured_traffic(s0["dominant"]),
-                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"},
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                     "whole_step": s0["whole_step"]},
         "kernels": s0["kernels"],
     }
     for f in forms[1:]:
-        sf = summary(res[f])
+        sf = summary(res[f], 0.5 if f == "mixed" else 1.0)
         a, b = res[f]["state"], res[main_form]["state"]
         if f == "internal" or main_form == "internal":
             # the energy fields hold different variables: compare rho and m

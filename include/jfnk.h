@@ -115,6 +115,10 @@ typedef struct {
     int newton_its, gmres_its, rejections, status;
     double wall_ms;       /* host wall time of the call */
     int scalar_newton_its, scalar_gmres_its;  /* passive-scalar solve of the accepted attempt */
+    int newton_exit;      /* how Newton stopped: 0 the residual test (|S^-1 F| within its
+                             tolerance, also when F0 already was), 1 the density-correction
+                             test (max |d rho / rho| <= corr_tol) with |S^-1 F| still above
+                             its tolerance, -1 failure */
 } jfnk_step_stats;
 
 typedef struct jfnk_problem jfnk_problem;
@@ -186,6 +190,15 @@ int jfnk_set_scales(jfnk_problem* p, const double* s5);
  * eps = 0 and w = 0. */
 int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, const double* v,
                   double* w, int on_device);
+/* The product of jfnk_apply_jv with a given difference step eps (> 0,
+ * finite; -1 otherwise) in place of the automatic one: the same formula,
+ * w = v - (dt/2) S^-1 (R(u + eps S v) - R(u)) / eps, wall faces 0.  Two
+ * implementations that take the same eps difference the residual at the
+ * same perturbed state, so their products can be compared element by
+ * element (the automatic eps comes from two norms whose summation order is
+ * implementation-defined).  Synchronises the problem's stream. */
+int jfnk_apply_jv_eps(jfnk_problem* p, const double* u, const double* b, double dt, const double* v, double eps,
+                      double* w, int on_device);
 /* Preconditioner with coefficients frozen at u: z = S^-1 P^-1 (S v). */
 int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double* v, double* z,
                        int on_device);

@@ -103,7 +103,7 @@ typedef struct {
     /* statistics of the last solve */
     double st_dt, st_cfl_h, st_cfl_a, st_cfl_r, st_rel_res, st_max_rel_corr, st_mass_drift,
         st_energy_drift, st_f0, st_f;
-    int st_newton, st_gmres, st_rejections, st_status, st_gmres_fail;
+    int st_newton, st_gmres, st_rejections, st_status, st_gmres_fail, st_exit;
     /* passive scalars (section 2.2): nscal partial densities s_k = c_k rho */
     int nscal, renorm;
     double *sc, *sc_n;
@@ -724,10 +724,17 @@ static double time_step(Or *o, const double *u, double *hyd_out, double *adv_out
  * (F(u + e S v) - F(u)) / (e S) equals v - h (R(u + e S v) - R(u)) / (e S):
  * only R is differenced, the identity part is applied exactly (reading R27).
  * Ru = R(u); wall faces, which are not unknowns, give 0. */
+static void jv_at(Or *o, const double *u, const double *Ru, double dt, double e, const double *v, double *w);
+
 static void jv(Or *o, const double *u, const double *Ru, double dt, double urms, const double *v, double *w) {
     double vn = norm2(o->nvec, v) / sqrt((double)o->nunk);
     if (vn == 0.0) { memset(w, 0, sizeof(double) * o->nvec); return; }
     double e = sqrt(2.220446049250313e-16) * (1.0 + urms) / vn;
+    jv_at(o, u, Ru, dt, e, v, w);
+}
+
+/* the product at a given difference step e > 0 */
+static void jv_at(Or *o, const double *u, const double *Ru, double dt, double e, const double *v, double *w) {
     for (long x = 0; x < o->nvec; ++x) o->w2[x] = u[x] + (e * scale_of(o, x)) * v[x];
     rhs(o, o->w2, o->R1);
     double h = 0.5 * dt;
@@ -1369,6 +1376,9 @@ static int newton(Or *o, double dt) {
     }
     o->st_newton = its;
     o->st_gmres = gits;
+    /* how Newton stopped: 0 residual test, 1 density-correction test with the
+     * residual still above its tolerance, -1 failure */
+    o->st_exit = status != 0 ? -1 : (f > tol ? 1 : 0);
     o->st_f0 = f0;
     o->st_f = f;
     o->st_rel_res = f0 > 0.0 ? f / f0 : 0.0;
@@ -1666,6 +1676,16 @@ void or_jv(void *h, const double *u, const double *b, double dt, const double *v
     free(Ru);
 }
 
+/* Jv at a given difference step eps > 0 (F(u) recomputed from u) */
+void or_jv_eps(void *h, const double *u, const double *b, double dt, const double *v, double eps, double *w) {
+    Or *o = h;
+    double *Ru = calloc(o->nvec, sizeof(double));
+    (void)b;
+    rhs(o, u, Ru);
+    jv_at(o, u, Ru, dt, eps, v, w);
+    free(Ru);
+}
+
 /* z = P^{-1} v with coefficients frozen at u */
 void or_precond(void *h, const double *u, double dt, const double *v, double *z) {
     Or *o = h;
@@ -1678,6 +1698,7 @@ static void fill_stats(Or *o, double *st) {
     st[5] = o->st_rel_res; st[6] = o->st_max_rel_corr; st[7] = o->st_mass_drift;
     st[8] = o->st_energy_drift; st[9] = o->st_newton; st[10] = o->st_gmres;
     st[11] = o->st_rejections; st[12] = o->st_status; st[13] = o->st_f0; st[14] = o->st_f;
+    st[15] = o->st_exit;
 }
 
 /* one Crank-Nicolson step at the given dt (no retry) */

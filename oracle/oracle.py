@@ -35,6 +35,7 @@ def _load():
         "or_time_step": (None, [vp, _dp, _dp]),
         "or_set_scales": (None, [vp, _dp]),
         "or_jv": (None, [vp, _dp, _dp, C.c_double, _dp, _dp]),
+        "or_jv_eps": (None, [vp, _dp, _dp, C.c_double, _dp, C.c_double, _dp]),
         "or_precond": (None, [vp, _dp, C.c_double, _dp, _dp]),
         "or_newton_solve": (C.c_int, [vp, C.c_double, _dp]),
         "or_implicit_step": (C.c_int, [vp, _dp]),
@@ -67,7 +68,7 @@ def _arr(a, n=None):
 
 STAT_KEYS = ("t", "dt", "cfl_hydro", "cfl_adv", "cfl_rad", "rel_res", "max_rel_corr",
              "mass_drift", "energy_drift", "newton_its", "gmres_its", "rejections",
-             "status", "f0", "f")
+             "status", "f0", "f", "newton_exit")
 
 
 class Oracle:
@@ -144,6 +145,13 @@ class Oracle:
         u, b, v = _arr(u, self.nvec), _arr(b, self.nvec), _arr(v, self.nvec)
         w = np.empty(self.nvec)
         _lib.or_jv(self._h, _d(u), _d(b), float(dt), _d(v), _d(w))
+        return w
+
+    def jv_eps(self, u, b, dt, v, eps):
+        """Jv at a given difference step eps > 0"""
+        u, b, v = _arr(u, self.nvec), _arr(b, self.nvec), _arr(v, self.nvec)
+        w = np.empty(self.nvec)
+        _lib.or_jv_eps(self._h, _d(u), _d(b), float(dt), _d(v), float(eps), _d(w))
         return w
 
     def precond(self, u, dt, v):

@@ -122,6 +122,10 @@ struct jfnk_server {
             }
             if (ok) {
                 run(r, arena + off, stream, pinned);
+                // every path out of run(), a failed creation included, may have
+                // left copies or kernels on the stream that write into the
+                // range: drain them before the range can go to another request
+                if (hipStreamSynchronize(stream) != hipSuccess && r->st.status == 0) r->st.status = -3;
             } else {
                 r->st.status = -3;
             }

@@ -776,6 +776,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         st->max_rel_corr = max_corr;
         st->dt = dt;
         st->status = status;
+        st->newton_exit = status != 0 ? -1 : (f > tol ? 1 : 0);
     }
     if (status != 0) launch_copy(p->u, p->un, n, p->stream);
     HIPCHK(hipGetLastError());
@@ -1541,6 +1542,26 @@ int jfnk_apply_jv(jfnk_problem* p, const double* u, const double* b, double dt, 
                     outspec(p, OUT_RESIDUAL, dt, p->w, nullptr, p->s2, nullptr, false, p->Ru), p->stream);
     set_usq(p, p->s1);
     eps_for(p, p->z);
+    jv(p, p->s1, p->Ru, dt, p->z, p->w);
+    HIPCHK(hipGetLastError());
+    return copy_out(p, w, p->w, on_device);
+}
+
+int jfnk_apply_jv_eps(jfnk_problem* p, const double* u, const double* b, double dt, const double* v, double eps,
+                      double* w, int on_device) {
+    if (!p || !u || !b || !v || !w) return fail(-1, "null argument");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(-1, "eps must be positive and finite");
+    ProfGuard guard(p);
+    int rc;
+    if ((rc = copy_in(p, p->s1, u, on_device))) return rc;
+    if ((rc = copy_in(p, p->s2, b, on_device))) return rc;
+    if ((rc = copy_in(p, p->z, v, on_device))) return rc;
+    launch_residual(p->G, view(p, p->s1, nullptr), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_RESIDUAL, dt, p->w, nullptr, p->s2, nullptr, false, p->Ru), p->stream);
+    // the pinned staging slot is free: every earlier read-back has completed
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->hpin[0] = eps;
+    HIPCHK(hipMemcpyAsync(p->dsum + D_EPS, p->hpin, sizeof(double), hipMemcpyHostToDevice, p->stream));
     jv(p, p->s1, p->Ru, dt, p->z, p->w);
     HIPCHK(hipGetLastError());
     return copy_out(p, w, p->w, on_device);

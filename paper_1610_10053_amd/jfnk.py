@@ -41,7 +41,7 @@ class StepStats(C.Structure):
                 ("mass_drift", C.c_double), ("energy_drift", C.c_double), ("f0", C.c_double),
                 ("f", C.c_double), ("newton_its", C.c_int), ("gmres_its", C.c_int),
                 ("rejections", C.c_int), ("status", C.c_int), ("wall_ms", C.c_double),
-                ("scalar_newton_its", C.c_int), ("scalar_gmres_its", C.c_int)]
+                ("scalar_newton_its", C.c_int), ("scalar_gmres_its", C.c_int), ("newton_exit", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -69,7 +69,7 @@ EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_set_scalars",
            "jfnk_get_scalars", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
-           "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_velocity_error", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_precond",
+           "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_velocity_error", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_jv_eps", "jfnk_apply_precond",
            "jfnk_profile_enable", "jfnk_profile_sample", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
            "jfnk_server_submit", "jfnk_server_poll", "jfnk_server_wait", "jfnk_server_destroy",
            "jfnk_last_error")
@@ -115,6 +115,7 @@ def load():
         "jfnk_velocity_error": (ip, [vp, vp, vp, ip, ip, ip, P(C.c_double)]),
         "jfnk_set_scales": (ip, [vp, dp]),
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
+        "jfnk_apply_jv_eps": (ip, [vp, vp, vp, C.c_double, vp, C.c_double, vp, ip]),
         "jfnk_apply_precond": (ip, [vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_profile_enable": (ip, [vp, C.c_uint]),
         "jfnk_profile_sample": (ip, [vp, ip, ip]),
@@ -357,6 +358,16 @@ class Problem:
         pv, _, k3 = _ptr(v)
         po, _, k4 = _ptr(out)
         _check(_lib.jfnk_apply_jv(self._h, pu, pb, float(dt), pv, po, d))
+        return out
+
+    def apply_jv_eps(self, u, b, dt, v, eps):
+        """the Jacobian-free product with a given difference step eps"""
+        out = self._out(u)
+        pu, d, k1 = _ptr(u)
+        pb, _, k2 = _ptr(b)
+        pv, _, k3 = _ptr(v)
+        po, _, k4 = _ptr(out)
+        _check(_lib.jfnk_apply_jv_eps(self._h, pu, pb, float(dt), pv, float(eps), po, d))
         return out
 
     def profile_enable(self, classes):

@@ -27,14 +27,30 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
 
 
-def test_struct_layouts_match_header_sizes():
+def test_struct_layouts_match_header_sizes(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    the C compiler gives the header's struct."""
     import ctypes as C
+    import subprocess
     from paper_1610_10053_amd import jfnk
-    assert C.sizeof(jfnk.ProblemDesc) == 136
-    assert C.sizeof(jfnk.SolverOpts) == 120
-    assert C.sizeof(jfnk.StepStats) == 120
-    assert C.sizeof(jfnk.RequestStats) == 72
-    assert C.sizeof(jfnk.Diagnostics) == 48
+    pairs = [("jfnk_problem_desc", jfnk.ProblemDesc), ("jfnk_solver_opts", jfnk.SolverOpts),
+             ("jfnk_step_stats", jfnk.StepStats), ("jfnk_request_stats", jfnk.RequestStats),
+             ("jfnk_diagnostics", jfnk.Diagnostics)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "jfnk.h"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append('printf("%%s %%zu\\n", "%s", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%%s.%%s %%zu\\n", "%s", "%s", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for cname, py in pairs:
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
 
 
 def test_default_opts_and_footprint_are_host_only():

@@ -53,3 +53,16 @@ def test_committed_counter_summary_is_well_formed():
     classes = [dict(t.split("=", 1) for t in ln.split()[1:] if "=" in t) for ln in lines[1:]]
     assert {"mg_smooth", "residual_out", "residual_mflux", "residual_prim", "residual_flux"} <= {c["class"] for c in classes}
     assert all(float(c["bytes_per_launch"]) > 0 for c in classes)
+
+
+def test_whole_step_byte_model_reproduces_the_planning_figures():
+    """The whole-step algorithmic byte model gives the planning figures of
+    the Taylor-Green 128^3 byte budget: 3 Newton x 10 GMRES iterations,
+    36.6 KB per cell-step in FP64 and 26.1 KB with an FP32 basis; and the
+    round-1 measured counts (11.1 Newton, 31.45 GMRES) 27.7 KB."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert abs(bench.model_bytes_per_cell(3, 30, 3, 1.0) - 36600.0) < 1e-9
+    assert abs(bench.model_bytes_per_cell(3, 30, 3, 0.5) - 26100.0) < 1e-9
+    assert abs(bench.model_bytes_per_cell(11.1, 31.45, 3, 1.0) - 27.7e3) < 50.0
+    assert bench.model_bytes_per_cell(0, 0, 3, 1.0) == 120.0
