@@ -243,6 +243,25 @@ int jfnk_eval_diagnostics(jfnk_problem* p, const double* u, int on_device, doubl
 int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_high, int on_device, int ratio,
                         int axis, double* out);
 
+/* Allocation-free form of jfnk_velocity_error, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same eq. (17) error with the same
+ * kernels and summation order (bit for bit the result of jfnk_velocity_error
+ * on the same inputs), but u_low (NULL: the problem's current state) and
+ * u_high are device pointers on the problem's device, which must be the
+ * current device (-1 otherwise), and the per-block partial sums live in a
+ * scratch array of 32768 doubles (256 KiB) that the library keeps in every
+ * GPU's memory for the life of the process; no call allocates.  The scratch
+ * holds 2 doubles per block of the low-resolution grid plus 2, i.e. grids of
+ * up to about 4.19 million cells (16383 blocks of 64 x 4 cells); larger
+ * grids are refused with -4 before anything is launched.  Every call on a
+ * GPU shares its scratch: the library serialises its own calls in a process
+ * (a lock held until the result is read back), so concurrent calls from
+ * several threads of one process are safe but wait for each other.  Other
+ * errors as jfnk_velocity_error. */
+int jfnk_velocity_error_noalloc(jfnk_problem* p, const double* u_low, const double* u_high, int ratio, int axis,
+                                double* out);
+
 /* ---- kernel-class timing ----
  * Time the launches of the kernel classes in class_mask (bit c = class c;
  * 0 disables) during later calls on p, with a HIP event pair attached to the

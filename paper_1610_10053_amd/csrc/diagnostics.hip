@@ -4,6 +4,8 @@
 // section 5.3), mass and total energy, the maximum Mach number (section 3.1),
 // the mixing-region width of eqs. (12)-(14) along a vertical axis, and the
 // relative velocity error of eq. (17) against a higher-resolution solution.
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace jfnk {
@@ -158,6 +160,42 @@ void launch_vel_error(const Grid& Gl, const Grid& Gh, const double* ul, const do
                        part);
     }
     launch_final_sum(part, nb, 2, out2, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free velocity error
+// Workspace of jfnk_velocity_error_noalloc: the per-block partial sums of
+// eq. (17) and the two final sums, in a file-scope device array of
+// kNoallocScratchDoubles doubles (256 KiB).  Each GPU the library runs on
+// holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel or a copy: it looks up the array's address on
+// each device once (hipGetSymbolAddress, with that device current) and uses
+// that pointer.
+static __device__ __align__(256) double scratch[kNoallocScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kNoallocMaxDevices] = {};
+}  // namespace
+
+std::mutex& noalloc_scratch_lock() { return g_scratch_mu; }
+
+int noalloc_scratch(int device, double** ptr) {
+    if (device < 0 || device >= kNoallocMaxDevices) return -1;
+    if (!g_scratch_dev[device]) {
+        void* a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return -3;
+        g_scratch_dev[device] = (double*)a;
+    }
+    *ptr = g_scratch_dev[device];
+    return 0;
+}
+
+long noalloc_vel_error_doubles(const Grid& Gl) { return 2L * cell_blocks(Gl.n) + 2; }
+
+void launch_vel_error_scratch(const Grid& Gl, const Grid& Gh, const double* ul, const double* uh, int r, int axis,
+                              double* scr, hipStream_t stream) {
+    const int nb = cell_blocks(Gl.n);
+    launch_vel_error(Gl, Gh, ul, uh, r, axis, scr, scr + 2L * nb, stream);
 }
 
 int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, double rho_l, double rho_h,

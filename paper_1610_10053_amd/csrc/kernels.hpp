@@ -2,6 +2,8 @@
 // implicit-step library.
 #pragma once
 
+#include <mutex>
+
 #include "jfnk_internal.hpp"
 
 namespace jfnk {
@@ -103,6 +105,15 @@ int launch_diagnostics(const Grid& G, const Prim& P, const double* u, int axis, 
 // axis; part needs 2 cell_blocks(Gl.n) doubles
 void launch_vel_error(const Grid& Gl, const Grid& Gh, const double* ul, const double* uh, int r, int axis,
                       double* part, double* out2, hipStream_t stream);
+// allocation-free form: partial sums and the two final sums (at
+// scr + 2 * blocks) in the caller-given scratch of noalloc_vel_error_doubles(Gl)
+constexpr long kNoallocScratchDoubles = 32768;
+constexpr int kNoallocMaxDevices = 64;
+int noalloc_scratch(int device, double** ptr);
+std::mutex& noalloc_scratch_lock();
+long noalloc_vel_error_doubles(const Grid& Gl);
+void launch_vel_error_scratch(const Grid& Gl, const Grid& Gh, const double* ul, const double* uh, int r, int axis,
+                              double* scr, hipStream_t stream);
 
 // krylov.hip: deterministic two-stage reductions and Krylov vector kernels
 // partial layout: part[col * nblk + block]

@@ -54,6 +54,7 @@ struct jfnk_problem {
     jfnk_problem_desc desc{};
     jfnk_solver_opts opts{};
     hipStream_t stream = nullptr;
+    int device = 0;  // the device current at creation, which holds every buffer
     Buffers buf;
     // optional caller-provided device range that every buffer is carved from
     char* slab = nullptr;
@@ -1121,6 +1122,10 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         delete p;
         return fail(-4, "grid too large for 32-bit cell indexing");
     }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return fail(-3, "hipGetDevice");
+    }
     int nl[kMaxLevels][3];
     p->nlev = count_levels(G, nl);
     // the coarse kernel takes the deepest levels whose cells fit in its LDS
@@ -1518,6 +1523,47 @@ int jfnk_velocity_error(jfnk_problem* p, const double* u_low, const double* u_hi
     if (tmp) (void)hipFree(tmp);
     if (rc) return rc;
     *out = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+    return 0;
+}
+
+int jfnk_velocity_error_noalloc(jfnk_problem* p, const double* u_low, const double* u_high, int ratio, int axis,
+                                double* out) {
+    if (!p || !u_high || !out) return fail(-1, "null argument");
+    const Grid& G = p->G;
+    if (G.sph) return fail(-4, "the eq. (17) error is for Cartesian grids");
+    if (ratio < 1 || ratio > 1024) return fail(-1, "ratio must lie in 1..1024");
+    if (axis < 0 || axis >= G.ndim) return fail(-1, "axis must be a grid axis");
+    Grid Gh = G;
+    Gh.N = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < G.ndim) Gh.n[d] = G.n[d] * ratio;
+        Gh.N *= Gh.n[d];
+    }
+    Gh.nvec = (long)(2 + G.ndim) * Gh.N;
+    if (Gh.nvec >= (1L << 31)) return fail(-4, "high-resolution grid too large for 32-bit cell indexing");
+    const long need = noalloc_vel_error_doubles(G);
+    if (need > kNoallocScratchDoubles)
+        return fail(-4, "grid too large for the allocation-free scratch (" + std::to_string(need) +
+                            " doubles needed, at most " + std::to_string(kNoallocScratchDoubles) + ")");
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != p->device)
+        return fail(-1, "the problem's device must be the current device");
+    ProfGuard guard(p);
+    // one call at a time per process: the scratch is shared by every call on
+    // a device, and the lock is held until the result has been read back
+    std::lock_guard<std::mutex> lk(noalloc_scratch_lock());
+    double* scr = nullptr;
+    int rc = noalloc_scratch(p->device, &scr);
+    if (rc) return fail(rc, "hipGetSymbolAddress (allocation-free scratch)");
+    const double* lo = u_low ? u_low : p->u;
+    launch_vel_error_scratch(G, Gh, lo, u_high, ratio, axis, scr, p->stream);
+    HIPCHK(hipGetLastError());
+    // the pinned read-back slot of the problem is free: its last use was synchronised
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipMemcpyAsync(p->hpin, scr + (need - 2), 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    const double e = p->hpin[0], a = p->hpin[1];
+    *out = a > 0.0 ? e / a : 0.0;
     return 0;
 }
 

@@ -69,7 +69,7 @@ EXPORTS = ("jfnk_default_opts", "jfnk_footprint_bytes", "jfnk_create_problem", "
            "jfnk_set_state", "jfnk_get_state", "jfnk_set_time", "jfnk_set_opts", "jfnk_set_scalars",
            "jfnk_get_scalars", "jfnk_implicit_step",
            "jfnk_newton_solve", "jfnk_eval_rhs", "jfnk_eval_cn_old", "jfnk_eval_residual",
-           "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_velocity_error", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_jv_eps", "jfnk_apply_precond",
+           "jfnk_eval_time_step", "jfnk_eval_diagnostics", "jfnk_velocity_error", "jfnk_velocity_error_noalloc", "jfnk_set_scales", "jfnk_apply_jv", "jfnk_apply_jv_eps", "jfnk_apply_precond",
            "jfnk_profile_enable", "jfnk_profile_sample", "jfnk_profile_read", "jfnk_profile_class_name", "jfnk_server_create",
            "jfnk_server_submit", "jfnk_server_poll", "jfnk_server_wait", "jfnk_server_destroy",
            "jfnk_last_error")
@@ -113,6 +113,7 @@ def load():
         "jfnk_eval_time_step": (ip, [vp, vp, dp, ip]),
         "jfnk_eval_diagnostics": (ip, [vp, vp, ip, C.c_double, C.c_double, ip, P(Diagnostics)]),
         "jfnk_velocity_error": (ip, [vp, vp, vp, ip, ip, ip, P(C.c_double)]),
+        "jfnk_velocity_error_noalloc": (ip, [vp, vp, vp, ip, ip, P(C.c_double)]),
         "jfnk_set_scales": (ip, [vp, dp]),
         "jfnk_apply_jv": (ip, [vp, vp, vp, C.c_double, vp, vp, ip]),
         "jfnk_apply_jv_eps": (ip, [vp, vp, vp, C.c_double, vp, C.c_double, vp, ip]),
@@ -345,6 +346,24 @@ class Problem:
             if d2 != d:
                 raise ValueError("u_low and u_high must both be host or both device arrays")
         _check(_lib.jfnk_velocity_error(self._h, pl, ph, d, int(ratio), int(axis), C.byref(out)))
+        return out.value
+
+    def velocity_error_noalloc(self, u_high, ratio, axis, u_low=None):
+        """the allocation-free form of velocity_error: u_high (and u_low, or
+        None for the current state) must be device tensors"""
+        out = C.c_double()
+        ph, d, k1 = _ptr(u_high)
+        if d != 1:
+            raise ValueError("velocity_error_noalloc takes device tensors")
+        if k1.numel() != self.nvec * int(ratio) ** self.desc["ndim"]:
+            raise ValueError("u_high has the wrong size for ratio %d" % ratio)
+        pl, k2 = None, None
+        if u_low is not None:
+            pl, d2, k2 = _ptr(u_low)
+            self._check_size(k2)
+            if d2 != 1:
+                raise ValueError("velocity_error_noalloc takes device tensors")
+        _check(_lib.jfnk_velocity_error_noalloc(self._h, pl, ph, int(ratio), int(axis), C.byref(out)))
         return out.value
 
     def set_scales(self, s):
