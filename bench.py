@@ -225,21 +225,42 @@ def measured_traffic(cls):
     return per.get(cls)
 
 
-def cpu_baseline(n, steps):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, steps, threaded):
+    """The oracle (plain C, FP64) on the host: TG n^3, the benchmark's set-up,
+    `steps` implicit steps from t = 0 on one core (the serial build), or
+    with threaded=True its -fopenmp build on all the host threads OpenMP
+    starts (same results bit for bit: parallel cell loops, serial
+    reductions)."""
+    import oracle
     from oracle import Oracle
     from workloads import make_config
     desc, opts, u0 = make_config("tg", n=n)
-    orc = Oracle(desc, opts, u0)
+    orc = Oracle(desc, opts, u0, threaded=threaded)
+    its = []
     t0 = time.perf_counter()
     for _ in range(steps):
         rc, st = orc.implicit_step()
         if rc != 0:
             raise RuntimeError("oracle step failed")
+        its.append((st["newton_its"], st["gmres_its"]))
     t = time.perf_counter() - t0
     cells = n ** 3
-    return dict(value=cells * steps / t, unit="cell-steps/s", cores=1, kind="oracle",
-                sample="Taylor-Green %d^3 (same set-up: CFL 20, Newton rtol 1e-8, GMRES(30), multigrid "
-                       "preconditioner), %d implicit steps from t=0 on one host core, %.1f s" % (n, steps, t))
+    nthr = oracle.threads(threaded)
+    return dict(value=cells * steps / t, unit="cell-steps/s", cores=nthr, kind="oracle",
+                sample="Taylor-Green %d^3 (the benchmark's set-up: CFL 20, Newton rtol 1e-8, GMRES(30), multigrid "
+                       "preconditioner), %d implicit step(s) from t=0 (Newton/GMRES iterations %s), %s, %.1f s"
+                       % (n, steps, its, "%d threads (-fopenmp build)" % nthr if threaded else "one core", t),
+                nproc=os.cpu_count(), cpu_model=_cpu_model())
 
 
 def main():
@@ -250,8 +271,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--forms", default="fp64,mixed,internal",
                     help="fp64, mixed (FP32 preconditioner and basis), internal (FP64, energy variable rho e)")
-    ap.add_argument("--cpu-n", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -369,8 +390,10 @@ def main():
     if not args.no_serve:
         out["serving"] = serving(jfnk, args)
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps)
+        log("cpu baseline (oracle, one core)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps, threaded=False)
+        log("cpu baseline (oracle, all cores)")
+        out["cpu_baseline_all_cores"] = cpu_baseline(args.cpu_n, args.cpu_steps, threaded=True)
     print(json.dumps(out), flush=True)
 
 

@@ -3,4 +3,4 @@
 Only the test-suite, the smoke check and the CPU-baseline leg of the benchmark
 may import this package.  It shares no code with the GPU library.
 """
-from .oracle import Oracle, build, tridiag, gmres_dense, lib_path  # noqa: F401
+from .oracle import Oracle, build, tridiag, gmres_dense, lib_path, threads  # noqa: F401

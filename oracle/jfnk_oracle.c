@@ -127,6 +127,20 @@ static long pstride(const Or *o, int d) {
 
 #define FOR_CELLS(o) \
     for (int k = 0; k < (o)->n[2]; ++k) for (int j = 0; j < (o)->n[1]; ++j) for (int i = 0; i < (o)->n[0]; ++i)
+/* Every loop marked PARC (cells) or PAR1 (flat vectors) computes each cell's
+ * or entry's outputs from inputs the loop does not write.  Built with
+ * -fopenmp (the all-cores CPU timing) these loops run on several threads
+ * with unchanged arithmetic; the reductions (norms, dot products, maxima)
+ * stay serial, so results are bit for bit those of the serial build. */
+#ifdef _OPENMP
+#include <omp.h>
+#define PARC _Pragma("omp parallel for collapse(2) schedule(static)")
+#define PAR1 _Pragma("omp parallel for schedule(static)")
+#else
+#define PARC
+#define PAR1
+#endif
+
 
 static int coord(int d, int i, int j, int k) { return d == 0 ? i : (d == 1 ? j : k); }
 
@@ -137,7 +151,7 @@ static void wrap(const Or *o, double *a) {
         int n = o->n[d], g = o->gh[d];
         int lo1 = -o->gh[(d + 1) % 3], hi1 = o->n[(d + 1) % 3] + o->gh[(d + 1) % 3];
         int lo2 = -o->gh[(d + 2) % 3], hi2 = o->n[(d + 2) % 3] + o->gh[(d + 2) % 3];
-        for (int b = lo2; b < hi2; ++b)
+        PAR1 for (int b = lo2; b < hi2; ++b)
             for (int a1 = lo1; a1 < hi1; ++a1)
                 for (int s = 1; s <= g; ++s) {
                     int c[3];
@@ -234,7 +248,7 @@ static double face_ids(const Or *o, int d, int i) {
 static void primitives(Or *o, const double *u) {
     const double *rho_c = field(o, u, 0), *E_c = field(o, u, 1);
     fill_nan(o, o->rho);
-    FOR_CELLS(o) o->rho[pidx(o, i, j, k)] = rho_c[cidx(o, i, j, k)];
+    PARC FOR_CELLS(o) o->rho[pidx(o, i, j, k)] = rho_c[cidx(o, i, j, k)];
     wrap(o, o->rho);
     for (int d = 0; d < o->ndim; ++d) {
         const double *m_c = field(o, u, 2 + d);
@@ -242,7 +256,7 @@ static void primitives(Or *o, const double *u) {
         long sd = pstride(o, d);
         fill_nan(o, uf);
         fill_nan(o, mm);
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long pc = pidx(o, i, j, k);
             double mv = m_c[cidx(o, i, j, k)];
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) {
@@ -293,7 +307,7 @@ static void primitives(Or *o, const double *u) {
     }
     /* cell thermodynamics */
     fill_nan(o, o->p); fill_nan(o, o->eps); fill_nan(o, o->T); fill_nan(o, o->chi); fill_nan(o, o->q);
-    FOR_CELLS(o) {
+    PARC FOR_CELLS(o) {
         long pc = pidx(o, i, j, k);
         double q = 0.0;
         for (int d = 0; d < o->ndim; ++d) {
@@ -359,7 +373,7 @@ static void fluxes(Or *o) {
         long s = pstride(o, d);
         fill_nan(o, fr);
         fill_nan(o, fe);
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long c = pidx(o, i, j, k);
             int id = coord(d, i, j, k);
             if (o->bc[d] == BC_WALL && id == 0) continue;
@@ -415,7 +429,7 @@ static void momentum_fluxes(Or *o) {
             long sc = pstride(o, c), sd = pstride(o, d);
             fill_nan(o, ph);
             if (c == d) {
-                FOR_CELLS(o) {
+                PARC FOR_CELLS(o) {
                     long x = pidx(o, i, j, k);
                     /* cell-centre flux for component c at cell x */
                     double Fb = 0.5 * (o->fr[c][x] + o->fr[c][x + sc]);
@@ -430,7 +444,7 @@ static void momentum_fluxes(Or *o) {
                 /* positions along d from 0 to n_d inclusive, other axes interior */
                 int ext[3] = {o->n[0], o->n[1], o->n[2]};
                 ext[d] = o->n[d] + 1;
-                for (int k = 0; k < ext[2]; ++k)
+                PARC for (int k = 0; k < ext[2]; ++k)
                     for (int j = 0; j < ext[1]; ++j)
                         for (int i = 0; i < ext[0]; ++i) {
                             int id = coord(d, i, j, k);
@@ -498,7 +512,7 @@ static void rhs(Or *o, const double *u, double *R) {
     fluxes(o);
     momentum_fluxes(o);
     double *Rr = R, *RE = R + o->N;
-    FOR_CELLS(o) {
+    PARC FOR_CELLS(o) {
         long x = pidx(o, i, j, k), c = cidx(o, i, j, k);
         double ar = 0.0, ae = 0.0;
         for (int d = 0; d < o->ndim; ++d) {
@@ -536,7 +550,7 @@ static void rhs(Or *o, const double *u, double *R) {
     for (int d = 0; d < o->ndim; ++d) {
         double *Rm = R + (long)(2 + d) * o->N;
         long sd = pstride(o, d);
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long x = pidx(o, i, j, k), c = cidx(o, i, j, k);
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) { Rm[c] = 0.0; continue; }
             if (o->sph) { Rm[c] = sph_momentum(o, d, i, j, x); continue; }
@@ -589,7 +603,7 @@ static void freeze_sources(Or *o, const double *u) {
             double *f = o->fe[d];
             long s = pstride(o, d);
             fill_nan(o, f);
-            FOR_CELLS(o) {
+            PARC FOR_CELLS(o) {
                 long c = pidx(o, i, j, k);
                 if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) continue;
                 f[c] = diff_flux(o, c - s, c, face_ids(o, d, i));
@@ -607,7 +621,7 @@ static void freeze_sources(Or *o, const double *u) {
             }
             wrap(o, f);
         }
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long x = pidx(o, i, j, k);
             double acc = 0.0;
             for (int d = 0; d < o->ndim; ++d) {
@@ -632,19 +646,19 @@ static void freeze_sources(Or *o, const double *u) {
 static void cn_old(Or *o, const double *un, double dt, double *b) {
     rhs(o, un, o->R1);
     double h = 0.5 * dt;
-    for (long x = 0; x < o->nvec; ++x) b[x] = un[x] + h * o->R1[x];
+    PAR1 for (long x = 0; x < o->nvec; ++x) b[x] = un[x] + h * o->R1[x];
 }
 
 /* F(u) = u - u^n - dt/2 (R(u) + R(u^n)) = (u - b) - dt/2 R(u) */
 static void cn_residual(Or *o, const double *u, const double *b, double dt, double *F) {
     rhs(o, u, o->R1);
     double h = 0.5 * dt;
-    for (long x = 0; x < o->nvec; ++x) F[x] = (u[x] - b[x]) - h * o->R1[x];
+    PAR1 for (long x = 0; x < o->nvec; ++x) F[x] = (u[x] - b[x]) - h * o->R1[x];
     /* stored wall faces are not unknowns */
     for (int d = 0; d < o->ndim; ++d) {
         if (o->bc[d] != BC_WALL) continue;
         double *Fm = F + (long)(2 + d) * o->N;
-        FOR_CELLS(o) if (coord(d, i, j, k) == 0) Fm[cidx(o, i, j, k)] = 0.0;
+        PARC FOR_CELLS(o) if (coord(d, i, j, k) == 0) Fm[cidx(o, i, j, k)] = 0.0;
     }
 }
 
@@ -735,14 +749,14 @@ static void jv(Or *o, const double *u, const double *Ru, double dt, double urms,
 
 /* the product at a given difference step e > 0 */
 static void jv_at(Or *o, const double *u, const double *Ru, double dt, double e, const double *v, double *w) {
-    for (long x = 0; x < o->nvec; ++x) o->w2[x] = u[x] + (e * scale_of(o, x)) * v[x];
+    PAR1 for (long x = 0; x < o->nvec; ++x) o->w2[x] = u[x] + (e * scale_of(o, x)) * v[x];
     rhs(o, o->w2, o->R1);
     double h = 0.5 * dt;
-    for (long x = 0; x < o->nvec; ++x) w[x] = v[x] - (h * (o->R1[x] - Ru[x])) / (e * scale_of(o, x));
+    PAR1 for (long x = 0; x < o->nvec; ++x) w[x] = v[x] - (h * (o->R1[x] - Ru[x])) / (e * scale_of(o, x));
     for (int d = 0; d < o->ndim; ++d) {
         if (o->bc[d] != BC_WALL) continue;
         double *wm = w + (long)(2 + d) * o->N;
-        FOR_CELLS(o) if (coord(d, i, j, k) == 0) wm[cidx(o, i, j, k)] = 0.0;
+        PARC FOR_CELLS(o) if (coord(d, i, j, k) == 0) wm[cidx(o, i, j, k)] = 0.0;
     }
 }
 
@@ -835,7 +849,7 @@ static int count_levels(const Or *o) {
 
 /* diagonal D = sigma + sum of the face couplings of each cell */
 static void level_diag(const Or *o, Level *L) {
-    FOR_LEVEL(L) {
+    PARC FOR_LEVEL(L) {
         long c = lidx(L, i, j, k);
         double den = L->sig[c];
         for (int d = 0; d < o->ndim; ++d) {
@@ -864,7 +878,7 @@ static void mg_build(Or *o, Level *lev, const double *sig, double *const *a) {
         int n[3];
         for (int d = 0; d < 3; ++d) n[d] = d < o->ndim ? F->n[d] / 2 : 1;
         level_alloc(C, n);
-        FOR_LEVEL(C) {
+        PARC FOR_LEVEL(C) {
             long c = lidx(C, i, j, k);
             int kk = o->ndim > 2 ? 2 : 1, jj = 2, ii = 2;
             double s = 0.0;
@@ -899,7 +913,7 @@ static void mg_build(Or *o, Level *lev, const double *sig, double *const *a) {
 static void mg_smooth(const Or *o, Level *L, int sweeps) {
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
-            FOR_LEVEL(L) {
+            PARC FOR_LEVEL(L) {
                 if (((i + j + k) & 1) != color) continue;
                 long c = lidx(L, i, j, k);
                 double num = L->b[c];
@@ -910,7 +924,7 @@ static void mg_smooth(const Or *o, Level *L, int sweeps) {
                 }
                 L->t[c] = num / L->D[c];
             }
-            FOR_LEVEL(L) {
+            PARC FOR_LEVEL(L) {
                 if (((i + j + k) & 1) != color) continue;
                 long c = lidx(L, i, j, k);
                 L->x[c] = L->t[c];
@@ -919,7 +933,7 @@ static void mg_smooth(const Or *o, Level *L, int sweeps) {
 }
 
 static void mg_residual(const Or *o, Level *L) {
-    FOR_LEVEL(L) {
+    PARC FOR_LEVEL(L) {
         long c = lidx(L, i, j, k);
         double xc = L->x[c];
         double acc = L->sig[c] * xc;
@@ -943,7 +957,7 @@ static void mg_vcycle(Or *o, Level *lev, int l) {
     double inv_ch = 1.0 / nch;
     int kk = o->ndim > 2 ? 2 : 1;
     /* restriction: mean of the children */
-    FOR_LEVEL(C) {
+    PARC FOR_LEVEL(C) {
         double s = 0.0;
         for (int dk = 0; dk < kk; ++dk)
             for (int dj = 0; dj < 2; ++dj)
@@ -955,7 +969,7 @@ static void mg_vcycle(Or *o, Level *lev, int l) {
     mg_vcycle(o, lev, l + 1);
     /* prolongation: cell-centred (bi/tri)linear interpolation, weights 3/4 and
      * 1/4 per axis; beyond a wall the parent value is used */
-    FOR_LEVEL(L) {
+    PARC FOR_LEVEL(L) {
         int f[3] = {i, j, k}, P[3] = {i / 2, j / 2, o->ndim > 2 ? k / 2 : k};
         double e = 0.0;
         for (int m = 0; m < (1 << o->ndim); ++m) {
@@ -1002,7 +1016,7 @@ static void pc_build(Or *o, const double *u, double dt) {
     const double *Ec = field(o, u, 1);
     for (int d = 0; d < o->ndim; ++d) {
         long s = pstride(o, d);
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long x = pidx(o, i, j, k), c = cidx(o, i, j, k);
             double hf, chif;
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) {
@@ -1032,13 +1046,13 @@ static void pc_build(Or *o, const double *u, double dt) {
             o->pc_beta[d][c] = (tau * chif) * w;
         }
     }
-    FOR_CELLS(o) o->pc_W[cidx(o, i, j, k)] = gm1 / o->rho[pidx(o, i, j, k)];
+    PARC FOR_CELLS(o) o->pc_W[cidx(o, i, j, k)] = gm1 / o->rho[pidx(o, i, j, k)];
     if (o->pc_solver == PCS_MULTIGRID && o->pc != PC_NONE) {
         double *sig = calloc(o->N, sizeof(double));
-        FOR_CELLS(o) sig[cidx(o, i, j, k)] = o->sph ? sph_vol(o, i, j) : 1.0;
+        PARC FOR_CELLS(o) sig[cidx(o, i, j, k)] = o->sph ? sph_vol(o, i, j) : 1.0;
         mg_build(o, o->mg_ac, sig, o->pc_kap);
         if (o->pc == PC_ACOUSTIC_DIFFUSION) {
-            FOR_CELLS(o) {
+            PARC FOR_CELLS(o) {
                 long c = cidx(o, i, j, k);
                 sig[c] = o->sph ? sph_vol(o, i, j) / o->pc_W[c] : 1.0 / o->pc_W[c];
             }
@@ -1107,7 +1121,7 @@ static void line_solve(Or *o, int d, int kind, double *v) {
 
 /* discrete divergence of face values (optionally weighted by h_f) into a cell vector */
 static void div_faces(Or *o, const double *const *mf, int weighted, double *out) {
-    FOR_CELLS(o) {
+    PARC FOR_CELLS(o) {
         long c = cidx(o, i, j, k);
         double acc = 0.0;
         for (int d = 0; d < o->ndim; ++d) {
@@ -1141,9 +1155,9 @@ static void pc_apply(Or *o, const double *v, double *z) {
     long N = o->N;
     double tau = o->tau, gm1 = o->gamma - 1.0;
     double *r = o->w1; /* scratch: unscaled rhs */
-    for (long x = 0; x < o->nvec; ++x) r[x] = scale_of(o, x) * v[x];
+    PAR1 for (long x = 0; x < o->nvec; ++x) r[x] = scale_of(o, x) * v[x];
     if (o->pc == PC_NONE) {
-        for (long x = 0; x < o->nvec; ++x) z[x] = v[x];
+        PAR1 for (long x = 0; x < o->nvec; ++x) z[x] = v[x];
         return;
     }
     double *rr = r, *rE = r + N;
@@ -1157,10 +1171,10 @@ static void pc_apply(Or *o, const double *v, double *z) {
              * dE = r_E + tau D(chi_f G s), which keeps sum(dE) = sum(r_E) */
             double *sv = o->w2;
             memcpy(sv, rE, sizeof(double) * N);
-            if (o->sph) FOR_CELLS(o) sv[cidx(o, i, j, k)] *= sph_vol(o, i, j);  /* volume-weighted system */
+            if (o->sph) {PARC FOR_CELLS(o) sv[cidx(o, i, j, k)] *= sph_vol(o, i, j); } /* volume-weighted system */
             mg_solve(o, o->mg_df, sv);
             double *y = o->w2 + N;
-            FOR_CELLS(o) {
+            PARC FOR_CELLS(o) {
                 long c = cidx(o, i, j, k);
                 double acc = o->sph ? 0.0 : rE[c];
                 for (int d = 0; d < o->ndim; ++d) {
@@ -1176,8 +1190,8 @@ static void pc_apply(Or *o, const double *v, double *z) {
     }
     double *dp = o->w2;
     div_faces(o, rm, 1, dp);
-    for (long c = 0; c < N; ++c) dp[c] = gm1 * (rE[c] - tau * dp[c]);
-    if (o->sph) FOR_CELLS(o) dp[cidx(o, i, j, k)] *= sph_vol(o, i, j);  /* volume-weighted system */
+    PAR1 for (long c = 0; c < N; ++c) dp[c] = gm1 * (rE[c] - tau * dp[c]);
+    if (o->sph) {PARC FOR_CELLS(o) dp[cidx(o, i, j, k)] *= sph_vol(o, i, j); } /* volume-weighted system */
     if (o->pc_solver == PCS_ADI) {
         for (int d = 0; d < o->ndim; ++d) line_solve(o, d, 0, dp);
     } else {
@@ -1185,7 +1199,7 @@ static void pc_apply(Or *o, const double *v, double *z) {
     }
     double *dm[3] = {z + 2 * N, o->ndim > 1 ? z + 3 * N : NULL, o->ndim > 2 ? z + 4 * N : NULL};
     for (int d = 0; d < o->ndim; ++d) {
-        FOR_CELLS(o) {
+        PARC FOR_CELLS(o) {
             long c = cidx(o, i, j, k);
             if (o->bc[d] == BC_WALL && coord(d, i, j, k) == 0) { dm[d][c] = 0.0; continue; }
             long lo = nb(o, i, j, k, d, -1);
@@ -1194,10 +1208,10 @@ static void pc_apply(Or *o, const double *v, double *z) {
     }
     double *tmp = dp; /* dp no longer needed */
     div_faces(o, (const double *const *)dm, 0, tmp);
-    for (long c = 0; c < N; ++c) z[c] = rr[c] - tau * tmp[c];
+    PAR1 for (long c = 0; c < N; ++c) z[c] = rr[c] - tau * tmp[c];
     div_faces(o, (const double *const *)dm, 1, tmp);
-    for (long c = 0; c < N; ++c) z[N + c] = rE[c] - tau * tmp[c];
-    for (long x = 0; x < o->nvec; ++x) z[x] = z[x] / scale_of(o, x);
+    PAR1 for (long c = 0; c < N; ++c) z[N + c] = rE[c] - tau * tmp[c];
+    PAR1 for (long x = 0; x < o->nvec; ++x) z[x] = z[x] / scale_of(o, x);
 }
 
 /* ------------------------------------------------------------------ GMRES (Saad & Schultz) */
@@ -1231,7 +1245,7 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
         info->res = beta;
         if (beta <= eta * beta0) { info->converged = 1; break; }
         info->cycles++;
-        for (long i = 0; i < n; ++i) V[i] = r[i] / beta;
+        PAR1 for (long i = 0; i < n; ++i) V[i] = r[i] / beta;
         for (int i = 0; i <= m; ++i) gv[i] = 0.0;
         gv[0] = beta;
         int kdim = 0, conv = 0;
@@ -1243,12 +1257,12 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
             for (int i = 0; i <= j; ++i) h1[i] = dot(n, V + (long)i * n, w);
             for (int i = 0; i <= j; ++i) {
                 const double *vi = V + (long)i * n;
-                for (long q = 0; q < n; ++q) w[q] -= h1[i] * vi[q];
+                PAR1 for (long q = 0; q < n; ++q) w[q] -= h1[i] * vi[q];
             }
             for (int i = 0; i <= j; ++i) h2[i] = dot(n, V + (long)i * n, w);
             for (int i = 0; i <= j; ++i) {
                 const double *vi = V + (long)i * n;
-                for (long q = 0; q < n; ++q) w[q] -= h2[i] * vi[q];
+                PAR1 for (long q = 0; q < n; ++q) w[q] -= h2[i] * vi[q];
             }
             double hn = norm2(n, w);
             for (int i = 0; i <= j; ++i) H[(long)i * m + j] = h1[i] + h2[i];
@@ -1270,7 +1284,7 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
             kdim = j + 1;
             info->res = fabs(gv[j + 1]);
             if (hn <= 1e-14 * w0) { conv = 1; break; } /* happy breakdown */
-            for (long q = 0; q < n; ++q) w[q] = w[q] / hn;
+            PAR1 for (long q = 0; q < n; ++q) w[q] = w[q] / hn;
             if (info->res <= eta * beta0) { conv = 1; break; }
         }
         /* back substitution R y = g */
@@ -1281,16 +1295,16 @@ static void gmres(long n, opfn A, opfn Minv, void *ctx, const double *rhs, doubl
         }
         /* x += M^-1 V y = sum_i y_i M^-1 v_i (M^-1 is a fixed linear map), from
          * the preconditioned vectors the Arnoldi process formed */
-        for (long q = 0; q < n; ++q) t[q] = 0.0;
+        PAR1 for (long q = 0; q < n; ++q) t[q] = 0.0;
         for (int i = 0; i < kdim; ++i) {
             const double *zi = Z + (long)i * n;
-            for (long q = 0; q < n; ++q) t[q] += y[i] * zi[q];
+            PAR1 for (long q = 0; q < n; ++q) t[q] += y[i] * zi[q];
         }
-        for (long q = 0; q < n; ++q) x[q] += t[q];
+        PAR1 for (long q = 0; q < n; ++q) x[q] += t[q];
         if (conv) { info->converged = 1; break; }
         /* true residual for the restart */
         A(ctx, x, t);
-        for (long q = 0; q < n; ++q) r[q] = rhs[q] - t[q];
+        PAR1 for (long q = 0; q < n; ++q) r[q] = rhs[q] - t[q];
         info->res = norm2(n, r);
     }
 done:
@@ -1353,14 +1367,14 @@ static int newton(Or *o, double dt) {
         if (its >= o->newton_max) { status = 1; break; }
         pc_build(o, u, dt);
         double urms = snorm2(o, u) / sqrt((double)o->nunk);
-        for (long q = 0; q < nv; ++q) rhsv[q] = -F[q] / scale_of(o, q);
+        PAR1 for (long q = 0; q < nv; ++q) rhsv[q] = -F[q] / scale_of(o, q);
         JCtx ctx = {o, u, o->Ru, dt, urms};
         GmresInfo gi;
         gmres(nv, op_jv, op_pc, &ctx, rhsv, x, o->restart, o->max_cycles, o->eta, &gi);
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) { status = 2; o->st_gmres_fail = 1; break; }
         max_corr = 0.0;
-        for (long q = 0; q < nv; ++q) u[q] = u[q] + scale_of(o, q) * x[q];
+        PAR1 for (long q = 0; q < nv; ++q) u[q] = u[q] + scale_of(o, q) * x[q];
         for (long c = 0; c < o->N; ++c) {
             double rc = fabs(scale_of(o, c) * x[c] / u[c]);
             if (rc > max_corr) max_corr = rc;
@@ -1674,6 +1688,15 @@ void or_jv(void *h, const double *u, const double *b, double dt, const double *v
     double urms = snorm2(o, u) / sqrt((double)o->nunk);
     jv(o, u, Ru, dt, urms, v, w);
     free(Ru);
+}
+
+/* threads the parallel loops run on (1 in the serial build) */
+int or_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Jv at a given difference step eps > 0 (F(u) recomputed from u) */

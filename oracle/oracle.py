@@ -4,25 +4,30 @@ import os
 
 import numpy as np
 
-from .build import OUT as lib_path, build as _build
+from .build import OUT as lib_path, OUT_OMP as lib_path_omp, build as _build
 
 _lib = None
+_lib_omp = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
 
 
 def build(force=True):
-    global _lib
+    global _lib, _lib_omp
     _lib = None
+    _lib_omp = None
     return _build(force=force)
 
 
-def _load():
-    global _lib
-    if _lib is not None:
+def _load(threaded=False):
+    """the serial oracle, or (threaded=True) its -fopenmp build"""
+    global _lib, _lib_omp
+    if threaded and _lib_omp is not None:
+        return _lib_omp
+    if not threaded and _lib is not None:
         return _lib
     _build(force=False)
-    lib = C.CDLL(lib_path)
+    lib = C.CDLL(lib_path_omp if threaded else lib_path)
     vp = C.c_void_p
     sig = {
         "or_create": (vp, [_ip, _dp, _dp]),
@@ -44,6 +49,7 @@ def _load():
         "or_get_scalars": (None, [vp, _dp]),
         "or_scalar_rhs": (None, [vp, _dp, _dp, _dp]),
         "or_scalar_its": (C.c_int, [vp, _ip]),
+        "or_threads": (C.c_int, []),
         "or_tridiag": (None, [C.c_int, _dp, _dp, _dp, _dp, _dp, C.c_int]),
         "or_gmres_dense": (None, [C.c_long, _dp, _dp, _dp, _dp, C.c_int, C.c_int, C.c_double, _dp]),
     }
@@ -51,7 +57,10 @@ def _load():
         f = getattr(lib, name)
         f.restype = res
         f.argtypes = args
-    _lib = lib
+    if threaded:
+        _lib_omp = lib
+    else:
+        _lib = lib
     return lib
 
 
@@ -74,8 +83,11 @@ STAT_KEYS = ("t", "dt", "cfl_hydro", "cfl_adv", "cfl_rad", "rel_res", "max_rel_c
 class Oracle:
     """One problem held by the oracle: desc/opts dicts as built by workloads."""
 
-    def __init__(self, desc, opts, u0):
-        lib = _load()
+    def __init__(self, desc, opts, u0, threaded=False):
+        """threaded=True: the -fopenmp build (same results bit for bit, used
+        to time the oracle on all host cores)"""
+        lib = _load(threaded)
+        self._lib = lib
         self.desc, self.opts = dict(desc), dict(opts)
         n = desc["n"]
         self.N = n[0] * n[1] * n[2]
@@ -97,107 +109,112 @@ class Oracle:
             raise RuntimeError("or_create failed")
 
     def __del__(self):
-        if getattr(self, "_h", None) and _lib is not None:
-            _lib.or_destroy(self._h)
+        if getattr(self, "_h", None) and getattr(self, "_lib", None) is not None:
+            self._lib.or_destroy(self._h)
             self._h = None
 
     # state
     def set_state(self, u):
         u = _arr(u, self.nvec)
-        _lib.or_set_state(self._h, _d(u))
+        self._lib.or_set_state(self._h, _d(u))
 
     def get_state(self):
         u = np.empty(self.nvec)
-        _lib.or_get_state(self._h, _d(u))
+        self._lib.or_get_state(self._h, _d(u))
         return u
 
     # kernels
     def rhs(self, u):
         u = _arr(u, self.nvec)
         R = np.empty(self.nvec)
-        _lib.or_rhs(self._h, _d(u), _d(R))
+        self._lib.or_rhs(self._h, _d(u), _d(R))
         return R
 
     def cn_old(self, un, dt):
         un = _arr(un, self.nvec)
         b = np.empty(self.nvec)
-        _lib.or_cn_old(self._h, _d(un), float(dt), _d(b))
+        self._lib.or_cn_old(self._h, _d(un), float(dt), _d(b))
         return b
 
     def residual(self, u, b, dt):
         u, b = _arr(u, self.nvec), _arr(b, self.nvec)
         F = np.empty(self.nvec)
-        _lib.or_residual(self._h, _d(u), _d(b), float(dt), _d(F))
+        self._lib.or_residual(self._h, _d(u), _d(b), float(dt), _d(F))
         return F
 
     def time_step(self, u):
         """dt, max (|u|+c)/dx, max |u|/dx, max D/dx^2, scales[5] (sets scales)."""
         u = _arr(u, self.nvec)
         out = np.empty(9)
-        _lib.or_time_step(self._h, _d(u), _d(out))
+        self._lib.or_time_step(self._h, _d(u), _d(out))
         return dict(dt=out[0], hyd=out[1], adv=out[2], rad=out[3], scales=out[4:9].copy())
 
     def set_scales(self, s):
         s = _arr(list(s) + [1.0] * (5 - len(s)), 5)
-        _lib.or_set_scales(self._h, _d(s))
+        self._lib.or_set_scales(self._h, _d(s))
 
     def jv(self, u, b, dt, v):
         u, b, v = _arr(u, self.nvec), _arr(b, self.nvec), _arr(v, self.nvec)
         w = np.empty(self.nvec)
-        _lib.or_jv(self._h, _d(u), _d(b), float(dt), _d(v), _d(w))
+        self._lib.or_jv(self._h, _d(u), _d(b), float(dt), _d(v), _d(w))
         return w
 
     def jv_eps(self, u, b, dt, v, eps):
         """Jv at a given difference step eps > 0"""
         u, b, v = _arr(u, self.nvec), _arr(b, self.nvec), _arr(v, self.nvec)
         w = np.empty(self.nvec)
-        _lib.or_jv_eps(self._h, _d(u), _d(b), float(dt), _d(v), float(eps), _d(w))
+        self._lib.or_jv_eps(self._h, _d(u), _d(b), float(dt), _d(v), float(eps), _d(w))
         return w
 
     def precond(self, u, dt, v):
         u, v = _arr(u, self.nvec), _arr(v, self.nvec)
         z = np.empty(self.nvec)
-        _lib.or_precond(self._h, _d(u), float(dt), _d(v), _d(z))
+        self._lib.or_precond(self._h, _d(u), float(dt), _d(v), _d(z))
         return z
 
     def sources(self):
         s = np.empty(self.N)
-        _lib.or_get_sources(self._h, _d(s))
+        self._lib.or_get_sources(self._h, _d(s))
         return s
 
     # passive scalars (partial densities s_k = c_k rho, nscal * N values)
     def set_scalars(self, s, nscal, renormalize=True):
         s = _arr(s, nscal * self.N)
         self.nscal = int(nscal)
-        _lib.or_set_scalars(self._h, self.nscal, 1 if renormalize else 0, _d(s))
+        self._lib.or_set_scalars(self._h, self.nscal, 1 if renormalize else 0, _d(s))
 
     def get_scalars(self):
         out = np.empty(self.nscal * self.N)
-        _lib.or_get_scalars(self._h, _d(out))
+        self._lib.or_get_scalars(self._h, _d(out))
         return out
 
     def scalar_rhs(self, u, s):
         u = _arr(u, self.nvec)
         s = _arr(s)
         out = np.empty(s.size)
-        _lib.or_scalar_rhs(self._h, _d(u), _d(s), _d(out))
+        self._lib.or_scalar_rhs(self._h, _d(u), _d(s), _d(out))
         return out
 
     def scalar_its(self):
         out = (C.c_int * 2)()
-        _lib.or_scalar_its(self._h, out)
+        self._lib.or_scalar_its(self._h, out)
         return int(out[0]), int(out[1])
 
     # solver
     def newton_solve(self, dt):
         st = np.empty(len(STAT_KEYS))
-        rc = _lib.or_newton_solve(self._h, float(dt), _d(st))
+        rc = self._lib.or_newton_solve(self._h, float(dt), _d(st))
         return rc, dict(zip(STAT_KEYS, st.tolist()))
 
     def implicit_step(self):
         st = np.empty(len(STAT_KEYS))
-        rc = _lib.or_implicit_step(self._h, _d(st))
+        rc = self._lib.or_implicit_step(self._h, _d(st))
         return rc, dict(zip(STAT_KEYS, st.tolist()))
+
+
+def threads(threaded=False):
+    """host threads the serial or the -fopenmp oracle runs on"""
+    return int(_load(threaded).or_threads())
 
 
 def tridiag(a, b, c, d, periodic=False):
