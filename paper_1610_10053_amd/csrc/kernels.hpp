@@ -16,7 +16,8 @@ struct Scales5 {
 // step eps read from device memory (v may be null).
 struct StateView {
     const double* u;
-    const double* v;
+    const double* v;    // FP64 direction, or
+    const float* vf;    // FP32 direction (the mixed form's preconditioned basis); at most one is set
     const double* eps;
     double scale[5];
     long N;
@@ -213,27 +214,31 @@ template <typename R>
 void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
                int nuc, int light, bool first, hipStream_t stream);
 
+// The preconditioner's input v and output z are vectors of the
+// preconditioner's precision R (FP64; the mixed form's FP32 Krylov basis and
+// preconditioned basis); its arithmetic outside the elliptic solves is FP64.
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>
-void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc,
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE, Scales5 sc,
                    const LevelT<R>& L0, hipStream_t stream);
 // conduction block: rE = S_E v_E + tau D(chi_f G s)
 template <typename R>
-void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const LevelT<R>& L0, Scales5 sc,
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const R* v, const LevelT<R>& L0, Scales5 sc,
                          double* rE, hipStream_t stream);
 // dm = r_m - tau G dp, drho = r_rho - tau D dm, dE = r_E - tau D(h_f dm),
-// z = S^-1 delta and per-block |z|^2
+// z = S^-1 delta (stored in precision R) and per-block |z|^2 of the stored values
 template <typename R>
-void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp,
-                    const LevelT<R>& L0, Scales5 sc, double* z, double* part, int nblk, hipStream_t stream);
+void launch_pc_back(const Grid& G, const PcCoef& C, const R* v, const double* rE, const R* dp,
+                    const LevelT<R>& L0, Scales5 sc, R* z, double* part, int nblk, hipStream_t stream);
 // out = s * v[off : off + N] in precision R
 template <typename R>
 void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream);
 // L0.b = s * v (a cell field) in precision R, in the level's x/b order
 template <typename R>
-void launch_field_to_level(const Grid& G, const double* v, double s, const LevelT<R>& L0, hipStream_t stream);
+void launch_field_to_level(const Grid& G, const R* v, double s, const LevelT<R>& L0, hipStream_t stream);
 // z = v and per-block |z|^2 (no preconditioner)
-void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream);
+template <typename T>
+void launch_copy_sumsq(const T* v, T* z, long n, double* part, int nblk, hipStream_t stream);
 // eps of the Jacobian-free product from sum (S^-1 u)^2 and sum v^2
 void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
                    hipStream_t stream);

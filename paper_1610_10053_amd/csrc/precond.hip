@@ -689,20 +689,20 @@ __device__ __forceinline__ double face_h(const Grid& G, const PcCoef& C, const I
 // RE: the energy right-hand side comes from the conduction solve (rE), else
 // from v (compile-time, so that the loads form one block)
 template <typename R, int ND, bool RE>
-__global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const double* __restrict__ v,
+__global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    const double re = RE ? rE[c] : sc.v[1] * v[G.N + c];
+    const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
     double acc = 0.0;
     for (int d = 0; d < ND; ++d) {
-        const double* vm = v + (long)(2 + d) * G.N;
+        const R* vm = v + (long)(2 + d) * G.N;
         const double s = sc.v[2 + d];
-        const double flo = face_h(G, C, q, c, d) * (s * vm[c]);
+        const double flo = face_h(G, C, q, c, d) * (s * (double)vm[c]);
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
         const long up = top ? c : shifted(G, q, d, 1);  // loads issued at a top wall too, value discarded
-        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * vm[up]);
+        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * (double)vm[up]);
         const double fhi = top ? 0.0 : fu;
         if (G.sph) {
             const int i = q.v[0], j = q.v[1];
@@ -718,13 +718,13 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const doubl
 }
 
 template <typename R, int ND>
-__global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const double* __restrict__ v,
+__global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const R* __restrict__ v,
                                                          LevelT<R> L0, Scales5 sc, double* __restrict__ rE) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
     const R* __restrict__ s = L0.x;
-    double acc = G.sph ? 0.0 : sc.v[1] * v[G.N + c];
+    double acc = G.sph ? 0.0 : sc.v[1] * (double)v[G.N + c];
     const double sc0 = (double)s[xbi(L0, q.v[0], q.v[1], q.v[2])];
     for (int d = 0; d < ND; ++d) {
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
@@ -737,31 +737,31 @@ __global__ void __launch_bounds__(kBlock) k_pc_diff_back(Grid G, PcCoef C, const
         if (!bot) tlo = C.beta[d][c] * (sc0 - (double)s[xb_shifted(L0, q, d, -1)]);
         acc = acc + (thi - tlo);
     }
-    rE[c] = G.sph ? sc.v[1] * v[G.N + c] + acc / sph_vol(G, q.v[0], q.v[1]) : acc;
+    rE[c] = G.sph ? sc.v[1] * (double)v[G.N + c] + acc / sph_vol(G, q.v[0], q.v[1]) : acc;
 }
 
 template <typename R, int ND, bool RE>
-__global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const double* __restrict__ v,
+__global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const R* __restrict__ v,
                                                     const double* __restrict__ rE, const R* __restrict__ dp,
-                                                    LevelT<R> L0, Scales5 sc, double* __restrict__ z,
+                                                    LevelT<R> L0, Scales5 sc, R* __restrict__ z,
                                                     double* __restrict__ part) {
     Ijk q;
     long c = 0;
     double ss = 0.0;
     if (cell_from_launch(G, q, c)) {
-        const double re = RE ? rE[c] : sc.v[1] * v[G.N + c];
+        const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
         const double dpc = (double)dp[xbi(L0, q.v[0], q.v[1], q.v[2])];
         double dmlo[3], dmhi[3];
         bool top[3];
         long upi[3];
         for (int d = 0; d < ND; ++d) {
-            const double* vm = v + (long)(2 + d) * G.N;
+            const R* vm = v + (long)(2 + d) * G.N;
             const double s = sc.v[2 + d];
             // both neighbours are loaded on walls too (the wrap keeps them in
             // bounds) and the wall faces' values replaced by 0
             const long up = shifted(G, q, d, 1);
-            const double lo = s * vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * face_ids(G, d, q.v[0]));
-            const double hi = s * vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * face_ids(G, d, q.v[0]));
+            const double lo = s * (double)vm[c] - C.tau * ((dpc - (double)dp[xb_shifted(L0, q, d, -1)]) * face_ids(G, d, q.v[0]));
+            const double hi = s * (double)vm[up] - C.tau * (((double)dp[xb_shifted(L0, q, d, 1)] - dpc) * face_ids(G, d, q.v[0]));
             top[d] = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
             dmlo[d] = (G.bc[d] == WALL && q.v[d] == 0) ? 0.0 : lo;
             dmhi[d] = top[d] ? 0.0 : hi;
@@ -777,7 +777,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
         };
         double acc = 0.0;
         for (int d = 0; d < ND; ++d) acc = acc + divterm(d, dmhi[d], dmlo[d]);
-        const double drho = sc.v[0] * v[c] - C.tau * acc;
+        const double drho = sc.v[0] * (double)v[c] - C.tau * acc;
         acc = 0.0;
         for (int d = 0; d < ND; ++d) {
             const double flo = face_h(G, C, q, c, d) * dmlo[d];
@@ -785,15 +785,16 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const doub
             acc = acc + divterm(d, fhi, flo);
         }
         const double dE = re - C.tau * acc;
-        double t = drho / sc.v[0];
-        z[c] = t;
+        // the norm is that of the stored values (the product's direction)
+        double t = (double)(R)(drho / sc.v[0]);
+        z[c] = (R)t;
         ss += t * t;
-        t = dE / sc.v[1];
-        z[G.N + c] = t;
+        t = (double)(R)(dE / sc.v[1]);
+        z[G.N + c] = (R)t;
         ss += t * t;
         for (int d = 0; d < ND; ++d) {
-            t = dmlo[d] / sc.v[2 + d];
-            z[(long)(2 + d) * G.N + c] = t;
+            t = (double)(R)(dmlo[d] / sc.v[2 + d]);
+            z[(long)(2 + d) * G.N + c] = (R)t;
             ss += t * t;
         }
     }
@@ -810,23 +811,24 @@ __global__ void __launch_bounds__(kBlock) k_field_scaled(const double* __restric
 }
 
 template <typename R, int ND>
-__global__ void __launch_bounds__(kBlock) k_field_to_level(Grid G, const double* __restrict__ v, double s,
+__global__ void __launch_bounds__(kBlock) k_field_to_level(Grid G, const R* __restrict__ v, double s,
                                                            LevelT<R> L0) {
     Ijk q;
     long c;
     if (!cell_from_launch(G, q, c)) return;
-    double b = s * v[c];
+    double b = s * (double)v[c];
     if (G.sph) b = b * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
     L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)b;
 }
 
-__global__ void __launch_bounds__(kBlock) k_copy_sumsq(const double* __restrict__ v, double* __restrict__ z,
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_copy_sumsq(const T* __restrict__ v, T* __restrict__ z,
                                                        long n, double* __restrict__ part) {
     double ss = 0.0;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const double t = v[e];
+        const T t = v[e];
         z[e] = t;
-        ss += t * t;
+        ss += (double)t * (double)t;
     }
     __shared__ double sh[kBlock / 64];
     const double t = block_sum(ss, sh);
@@ -848,10 +850,13 @@ __global__ void __launch_bounds__(kFinalThreads) k_jv_eps(const double* __restri
 }
 
 template <typename R>
-void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double* rE, Scales5 sc,
+void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE, Scales5 sc,
                    const LevelT<R>& L0, hipStream_t stream) {
     {
-        JFNK_PROFB(KC_PC_RHS, stream, 8.0 * G.N * (2 + G.ndim + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        // v (sizeof(R)), enthalpy, rE; the level's right-hand side
+        JFNK_PROFB(KC_PC_RHS, stream,
+                   (double)sizeof(R) * G.N * (G.ndim + (rE ? 0 : 1)) + 8.0 * G.N * (1 + (rE ? 1 : 0)) +
+                       (double)sizeof(R) * G.N);
         const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
         if (G.ndim == 3) {
             if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 3, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
@@ -863,7 +868,7 @@ void launch_pc_rhs(const Grid& G, const PcCoef& C, const double* v, const double
     }
 }
 template <typename R>
-void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const LevelT<R>& L0, Scales5 sc,
+void launch_pc_diff_back(const Grid& G, const PcCoef& C, const R* v, const LevelT<R>& L0, Scales5 sc,
                          double* rE, hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
@@ -871,11 +876,13 @@ void launch_pc_diff_back(const Grid& G, const PcCoef& C, const double* v, const 
     }
 }
 template <typename R>
-void launch_pc_back(const Grid& G, const PcCoef& C, const double* v, const double* rE, const R* dp,
-                    const LevelT<R>& L0, Scales5 sc, double* z, double* part, int nblk, hipStream_t stream) {
+void launch_pc_back(const Grid& G, const PcCoef& C, const R* v, const double* rE, const R* dp,
+                    const LevelT<R>& L0, Scales5 sc, R* z, double* part, int nblk, hipStream_t stream) {
     (void)nblk;
     {
-        JFNK_PROFB(KC_PC_BACK, stream, 8.0 * G.nvec * 2 + 8.0 * G.N * (1 + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
+        // v read and z written (sizeof(R)), enthalpy, rE, dp
+        JFNK_PROFB(KC_PC_BACK, stream,
+                   (double)sizeof(R) * G.nvec * 2 + 8.0 * G.N * (1 + (rE ? 1 : 0)) + (double)sizeof(R) * G.N);
         const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
         if (G.ndim == 3) {
             if (rE) JFNK_KLAUNCH((k_pc_back<R, 3, true>), g, bl, 0, stream, G, C, v, rE, dp, L0, sc, z, part);
@@ -894,18 +901,21 @@ void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t 
     }
 }
 template <typename R>
-void launch_field_to_level(const Grid& G, const double* v, double s, const LevelT<R>& L0, hipStream_t stream) {
+void launch_field_to_level(const Grid& G, const R* v, double s, const LevelT<R>& L0, hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
         JFNK_LAUNCH_RND(G.ndim, k_field_to_level, R, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, v, s, L0);
     }
 }
-void launch_copy_sumsq(const double* v, double* z, long n, double* part, int nblk, hipStream_t stream) {
+template <typename T>
+void launch_copy_sumsq(const T* v, T* z, long n, double* part, int nblk, hipStream_t stream) {
     {
         JFNK_PROF(KC_OTHER, stream);
-        JFNK_KLAUNCH(k_copy_sumsq, dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
+        JFNK_KLAUNCH((k_copy_sumsq<T>), dim3(nblk), dim3(kBlock), 0, stream, v, z, n, part);
     }
 }
+template void launch_copy_sumsq<double>(const double*, double*, long, double*, int, hipStream_t);
+template void launch_copy_sumsq<float>(const float*, float*, long, double*, int, hipStream_t);
 void launch_jv_eps(const double* usumsq, const double* part_v, int nblk, double nunk, double* eps,
                    hipStream_t stream) {
     {
@@ -1027,14 +1037,14 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
     template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, const LevelT<R>*, int, int, int, int, int,     \
                                int, bool, hipStream_t);                                                      \
-    template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const double*, const double*, Scales5,        \
+    template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const R*, const double*, Scales5,        \
                                    const LevelT<R>&, hipStream_t);                                           \
-    template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const double*, const LevelT<R>&,        \
+    template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const R*, const LevelT<R>&,        \
                                          Scales5, double*, hipStream_t);                                     \
-    template void launch_pc_back<R>(const Grid&, const PcCoef&, const double*, const double*, const R*,      \
-                                    const LevelT<R>&, Scales5, double*, double*, int, hipStream_t);          \
+    template void launch_pc_back<R>(const Grid&, const PcCoef&, const R*, const double*, const R*,      \
+                                    const LevelT<R>&, Scales5, R*, double*, int, hipStream_t);               \
     template void launch_field_scaled<R>(const double*, double, R*, long, hipStream_t);                      \
-    template void launch_field_to_level<R>(const Grid&, const double*, double, const LevelT<R>&, hipStream_t); \
+    template void launch_field_to_level<R>(const Grid&, const R*, double, const LevelT<R>&, hipStream_t);     \
     template void launch_line_solve<R>(const Grid&, const PcCoef&, int, int, R*, double*, hipStream_t);
 INST(double)
 INST(float)

@@ -16,19 +16,25 @@
 
 namespace jfnk {
 
-// value of state field f at cell c, perturbed along v when PERT
-template <bool PERT>
+// PERT: 0 the state itself; 1 perturbed along the FP64 direction v; 2 along
+// the FP32 direction vf (the mixed form's preconditioned basis vectors)
+template <int PERT>
+__device__ __forceinline__ double dir_t(const StateView& s, long x) {
+    return PERT == 2 ? (double)s.vf[x] : s.v[x];
+}
+// value of state field f at cell c, perturbed along the direction when PERT
+template <int PERT>
 __device__ __forceinline__ double st_t(const StateView& s, int f, long c) {
     const long x = (long)f * s.N + c;
     double a = s.u[x];
-    if (PERT) a = a + (s.eps[0] * s.scale[f]) * s.v[x];
+    if (PERT) a = a + (s.eps[0] * s.scale[f]) * dir_t<PERT>(s, x);
     return a;
 }
 
 // ---------------------------------------------------------------- sweep 1: primitives per cell
-// PERT (state perturbed along v) is compile-time so that the state loads
-// form one straight-line block
-template <int ND, bool PERT>
+// PERT (state perturbed along a direction) is compile-time so that the
+// state loads form one straight-line block
+template <int ND, int PERT>
 __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
     Ijk q;
     long c;
@@ -324,7 +330,7 @@ __device__ __forceinline__ double sph_momentum(const Grid& G, const Prim& P, con
 // The outputs come as their own __restrict__ parameters (they never alias
 // an input), so that the loads of a later field need not wait for the stores
 // of an earlier one.
-template <int ND, int MODE, bool PERT>
+template <int ND, int MODE, int PERT>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o,
                                                 double* __restrict__ out, double* __restrict__ out2,
@@ -357,7 +363,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 part += t * t;
             } else {  // OUT_JV
                 const double e = s.eps[0];
-                const double w0 = s.v[x] - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
+                const double w0 = dir_t<PERT>(s, x) - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
                 out[x] = (!wallface && e != 0.0) ? w0 : 0.0;
             }
         };
@@ -494,10 +500,13 @@ static void launch_out_m(const Grid& G, const StateView& s, const Prim& P, const
                          const double* sbal, const OutSpec& o, hipStream_t stream) {
     const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
     if (s.v)
-        JFNK_KLAUNCH((k_out<ND, MODE, true>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
+        JFNK_KLAUNCH((k_out<ND, MODE, 1>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
                      o.partial);
+    else if (MODE == OUT_JV && s.vf)
+        JFNK_KLAUNCH((k_out<ND, MODE == OUT_JV ? MODE : OUT_JV, 2>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o,
+                     o.out, o.out2, o.rout, o.partial);
     else
-        JFNK_KLAUNCH((k_out<ND, MODE, false>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
+        JFNK_KLAUNCH((k_out<ND, MODE, 0>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
                      o.partial);
 }
 template <int ND>
@@ -514,11 +523,13 @@ static void launch_out_nd(const Grid& G, const StateView& s, const Prim& P, cons
 static void launch_prim_kernel(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
     if (G.ndim == 3) {
-        if (s.v) JFNK_KLAUNCH((k_prim<3, true>), g, bl, 0, stream, G, s, P);
-        else JFNK_KLAUNCH((k_prim<3, false>), g, bl, 0, stream, G, s, P);
+        if (s.v) JFNK_KLAUNCH((k_prim<3, 1>), g, bl, 0, stream, G, s, P);
+        else if (s.vf) JFNK_KLAUNCH((k_prim<3, 2>), g, bl, 0, stream, G, s, P);
+        else JFNK_KLAUNCH((k_prim<3, 0>), g, bl, 0, stream, G, s, P);
     } else {
-        if (s.v) JFNK_KLAUNCH((k_prim<2, true>), g, bl, 0, stream, G, s, P);
-        else JFNK_KLAUNCH((k_prim<2, false>), g, bl, 0, stream, G, s, P);
+        if (s.v) JFNK_KLAUNCH((k_prim<2, 1>), g, bl, 0, stream, G, s, P);
+        else if (s.vf) JFNK_KLAUNCH((k_prim<2, 2>), g, bl, 0, stream, G, s, P);
+        else JFNK_KLAUNCH((k_prim<2, 0>), g, bl, 0, stream, G, s, P);
     }
 }
 
@@ -530,7 +541,8 @@ static double prim_writes(const Grid& G) {
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                      const double* sbal, const OutSpec& o, hipStream_t stream) {
     const double vec = 8.0 * G.nvec;
-    const double b_prim = (s.v ? 2.0 : 1.0) * vec + prim_writes(G);
+    const double dirb = s.v ? vec : (s.vf ? 0.5 * vec : 0.0);  // the direction's bytes
+    const double b_prim = vec + dirb + prim_writes(G);
     const double b_flux = prim_writes(G) + 8.0 * G.N * 2 * G.ndim;
     // fluxes, momentum fluxes, p, rho (with gravity), the face velocities
     // (internal-energy form), the heat-balance source, the state, the output
@@ -542,7 +554,7 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
                    vec;  // the output
     if (o.mode == OUT_CN_OLD) b_out += 2.0 * vec;  // u read, F written
     if (o.mode == OUT_RESIDUAL) b_out += 2.0 * vec;  // u and b read
-    if (o.mode == OUT_JV) b_out += 2.0 * vec + (gravity ? 2.0 * 8.0 * G.N * G.ndim : 0.0);  // v, R(u) [, m]
+    if (o.mode == OUT_JV) b_out += dirb + vec + (gravity ? 2.0 * 8.0 * G.N * G.ndim : 0.0);  // v, R(u) [, m]
     if (o.rout) b_out += vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
@@ -581,7 +593,7 @@ void launch_prim_flux(const Grid& G, const StateView& s, const Prim& P, const Fl
 
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     {
-        JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : 1.0) * 8.0 * G.nvec + prim_writes(G));
+        JFNK_PROFB(KC_PRIM, stream, (s.v ? 2.0 : (s.vf ? 1.5 : 1.0)) * 8.0 * G.nvec + prim_writes(G));
         launch_prim_kernel(G, s, P, stream);
     }
 }

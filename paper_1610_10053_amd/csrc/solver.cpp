@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/jfnk.h"
@@ -61,11 +62,11 @@ struct jfnk_problem {
     size_t slab_size = 0, slab_off = 0;
     // vectors of nvec doubles
     double *u = nullptr, *un = nullptr, *b = nullptr, *x = nullptr, *rhs = nullptr,
-           *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *vj = nullptr, *s1 = nullptr,
+           *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *s1 = nullptr,
            *s2 = nullptr;
     double* Ru = nullptr;  // R at the current Newton iterate (Jacobian-free products)
     void* V = nullptr;
-    double* Zb = nullptr;  // preconditioned basis vectors M^-1 v_j of a GMRES cycle
+    void* Zb = nullptr;  // preconditioned basis vectors M^-1 v_j of a GMRES cycle (FP64, or FP32 in the mixed form)
     Prim P{};
     Flux Fx{};
     WallFlux W{};
@@ -351,10 +352,11 @@ struct ProfGuard {
     }
 };
 
-StateView view(jfnk_problem* p, const double* u, const double* v) {
+StateView view(jfnk_problem* p, const double* u, const double* v, const float* vf = nullptr) {
     StateView s;
     s.u = u;
     s.v = v;
+    s.vf = vf;
     s.eps = p->dsum + D_EPS;
     for (int f = 0; f < 5; ++f) s.scale[f] = p->scale[f];
     s.N = p->G.N;
@@ -501,9 +503,10 @@ void mg_solve(jfnk_problem* p, int which) {
                      p->opts.mg_nuc, p->opts.mg_light_cells, c == 0, p->stream);
 }
 
-// z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z
+// z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z;
+// v and z are vectors of the preconditioner's precision R
 template <typename R>
-void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
+void pc_apply_t(jfnk_problem* p, const R* v, R* z) {
     const Grid& G = p->G;
     Scales5 sc;
     for (int f = 0; f < 5; ++f) sc.v[f] = p->scale[f];
@@ -515,7 +518,7 @@ void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
             launch_field_to_level<R>(G, v + G.N, sc.v[1], S.L[0], p->stream);
             mg_solve<R>(p, 1);
             launch_pc_diff_back<R>(G, p->C, v, S.L[0], sc, p->rEd, p->stream);
-        } else {
+        } else if constexpr (std::is_same<R, double>::value) {  // ADI: FP64 only
             launch_field_scaled<double>(v + G.N, sc.v[1], p->rEd, G.N, p->stream);
             for (int d = 0; d < G.ndim; ++d) launch_line_solve<double>(G, p->C, d, 1, p->rEd, p->lines, p->stream);
         }
@@ -534,15 +537,17 @@ void pc_apply_t(jfnk_problem* p, const double* v, double* z) {
     launch_pc_back<R>(G, p->C, v, rE, dp, A.L[0], sc, z, p->part, p->ncell_blk, p->stream);
 }
 
-void pc_apply(jfnk_problem* p, const double* v, double* z) {
+// T: double (FP64 form) or float (mixed form, whose Krylov basis and
+// preconditioned basis are FP32)
+template <typename T>
+void pc_apply(jfnk_problem* p, const T* v, T* z) {
     int nb;
     if (p->opts.pc == JFNK_PC_NONE) {
         nb = p->nred;
-        launch_copy_sumsq(v, z, p->G.nvec, p->part, nb, p->stream);
+        launch_copy_sumsq<T>(v, z, p->G.nvec, p->part, nb, p->stream);
     } else {
         nb = p->ncell_blk;
-        if (p->opts.prec == JFNK_MIXED) pc_apply_t<float>(p, v, z);
-        else pc_apply_t<double>(p, v, z);
+        pc_apply_t<T>(p, v, z);
     }
     launch_jv_eps(p->dsum + D_USQ, p->part, nb, (double)p->nunk, p->dsum + D_EPS, p->stream);
 }
@@ -550,6 +555,10 @@ void pc_apply(jfnk_problem* p, const double* v, double* z) {
 // Jacobian-free product along v (eps already on the device), Ru = R(u)
 void jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const double* v, double* w) {
     launch_residual(p->G, view(p, u, v), p->P, p->Fx, p->W, p->sbal,
+                    outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false), p->stream);
+}
+void jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const float* v, double* w) {
+    launch_residual(p->G, view(p, u, nullptr, v), p->P, p->Fx, p->W, p->sbal,
                     outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false), p->stream);
 }
 
@@ -589,12 +598,13 @@ struct GmresInfo {
 //   norm(v, &out): the 2-norm of v (synchronises);
 //   pc(j, v, z):   z_j = M^-1 v_j into Zb column j (not called when Zb is null:
 //                  no preconditioner, the basis vectors themselves are used);
-//   op(z, w):      w = A z for a preconditioned basis vector;
+//                  v and z in the basis precision T;
+//   op(z, w):      w = A z for a preconditioned basis vector (precision T);
 //   opx(x, t):     t = A x for the restart residual.
 // x += M^-1 V y is formed from the kept preconditioned vectors.
 template <typename T, class Norm, class Pc, class Op, class OpX>
-int gmres_core(jfnk_problem* p, long n, T* V, double* Zb, const double* rhs, double* x, double* r, double* w,
-               double* t, double* vtmp, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info) {
+int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* x, double* r, double* w,
+               double* t, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info) {
     const int m = p->opts.gmres_restart;
     const double eta = p->opts.gmres_eta;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
@@ -629,16 +639,9 @@ int gmres_core(jfnk_problem* p, long n, T* V, double* Zb, const double* rhs, dou
         bool conv = false;
         for (int j = 0; j < m; ++j) {
             const T* vj = V + (long)j * n;
-            const double* vin;
-            if (sizeof(T) == sizeof(double)) {
-                vin = (const double*)vj;
-            } else {
-                launch_widen<T>(vj, vtmp, n, p->stream);
-                vin = vtmp;
-            }
-            const double* zj = vin;
+            const T* zj = vj;
             if (Zb) {
-                pc(j, vin, Zb + (long)j * n);
+                pc(j, vj, Zb + (long)j * n);
                 zj = Zb + (long)j * n;
             }
             op(zj, w);
@@ -688,7 +691,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, double* Zb, const double* rhs, dou
         std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
         HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
         // x += M^-1 V y, formed from the preconditioned vectors already at hand
-        if (Zb) launch_combine<double>(Zb, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
+        if (Zb) launch_combine<T>(Zb, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
         else launch_combine<T>(V, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
         if (conv) {
             info->converged = 1;
@@ -708,13 +711,13 @@ template <typename T>
 int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
     const long n = p->G.nvec;
     auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
-    auto pc = [&](int, const double* v, double* z) { pc_apply(p, v, z); };
-    auto op = [&](const double* z, double* w) { jv(p, u, p->Ru, dt, z, w); };
+    auto pc = [&](int, const T* v, T* z) { pc_apply<T>(p, v, z); };
+    auto op = [&](const T* z, double* w) { jv(p, u, p->Ru, dt, z, w); };
     auto opx = [&](const double* x, double* t) {
         eps_for(p, x);
         jv(p, u, p->Ru, dt, x, t);
     };
-    return gmres_core<T>(p, n, (T*)p->V, p->Zb, p->rhs, p->x, p->r, p->w, p->t, p->vj, norm, pc, op, opx, info);
+    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, info);
 }
 
 // Newton-Raphson from u^n at dt; on failure the state is restored
@@ -869,8 +872,7 @@ int scalar_step(jfnk_problem* p, double dt) {
         launch_final_sum(p->part, nb, 1, p->dsum + D_SUSQ, p->stream);
         launch_negate(p->sG, p->srhs, n, p->stream);
         GmresInfo gi;
-        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, nullptr, norm, pc, op, op,
-                              &gi));
+        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op, op, &gi));
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
             status = 2;
@@ -1029,9 +1031,9 @@ int freeze_sources(jfnk_problem* p) {
 // device bytes create_problem requests (buffer for buffer)
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 13 * nv * 8;                                                       // vectors
+    size_t b = 12 * nv * 8;                                                       // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
-    b += (size_t)o.gmres_restart * nv * 8;                                        // preconditioned basis
+    b += (size_t)o.gmres_restart * nv * (o.prec == JFNK_MIXED ? 4 : 8);          // preconditioned basis
     b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
     for (int d = 0; d < G.ndim; ++d)                                              // frozen wall fluxes
         if (G.bc[d] == WALL && G.has_chi) b += 2 * (size_t)G.n[(d + 1) % 3] * G.n[(d + 2) % 3] * 8;
@@ -1154,7 +1156,7 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         if (r_) return cleanup(r_);      \
     } while (0)
     AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n); AL(p->Ru, n);
-    AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->vj, n); AL(p->s1, n); AL(p->s2, n);
+    AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->s1, n); AL(p->s2, n);
     if (opts->prec == JFNK_MIXED) {
         float* V = nullptr;
         AL(V, (size_t)(opts->gmres_restart + 1) * n);
@@ -1164,7 +1166,15 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         AL(V, (size_t)(opts->gmres_restart + 1) * n);
         p->V = V;
     }
-    AL(p->Zb, (size_t)opts->gmres_restart * n);
+    if (opts->prec == JFNK_MIXED) {
+        float* Z = nullptr;
+        AL(Z, (size_t)opts->gmres_restart * n);
+        p->Zb = Z;
+    } else {
+        double* Z = nullptr;
+        AL(Z, (size_t)opts->gmres_restart * n);
+        p->Zb = Z;
+    }
     double* prim = nullptr;
     AL(prim, (size_t)9 * N);
     p->P.rho = prim;
@@ -1622,7 +1632,17 @@ int jfnk_apply_precond(jfnk_problem* p, const double* u, double dt, const double
     if ((rc = copy_in(p, p->s2, v, on_device))) return rc;
     if ((rc = pc_build(p, p->s1, dt, false))) return rc;
     HIPCHK(hipMemsetAsync(p->dsum + D_USQ, 0, sizeof(double), p->stream));
-    pc_apply(p, p->s2, p->w);
+    if (p->opts.prec == JFNK_MIXED) {
+        // the mixed form's preconditioner maps FP32 vectors: v rounded into
+        // basis column 0, z from column 1 (the basis is idle between solves)
+        float* V = (float*)p->V;
+        const long n = p->G.nvec;
+        launch_store_scaled<float>(p->s2, V, 1.0, n, p->stream);
+        pc_apply<float>(p, V, V + n);
+        launch_widen<float>(V + n, p->w, n, p->stream);
+    } else {
+        pc_apply<double>(p, p->s2, p->w);
+    }
     HIPCHK(hipGetLastError());
     return copy_out(p, z, p->w, on_device);
 }
