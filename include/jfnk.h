@@ -103,6 +103,16 @@ typedef struct {
     int max_halvings;       /* step retries at dt/2 after a failed Newton solve */
     int mg_light_cells;     /* multigrid levels of at most this many cells (not the coarsest) take one
                                pre- and one post-smoothing sweep; 0: every level takes mg_nu1/mg_nu2 */
+    int newton_target;      /* time-step controller (on when dt_grow > 1): Newton iterations a step
+                               should take; 0: grow by dt_grow after every accepted step */
+    double dt_grow;         /* section 2.1: dt is adjusted for efficiency within the CFL limits above.
+                               > 1 turns the controller on: a step's dt is the CFL dt of its state, but
+                               at most dt_ctrl, which after an accepted step at dt with k Newton
+                               iterations becomes dt * f, f = newton_target / k clamped to
+                               [0.5, dt_grow] (f = dt_grow when newton_target is 0), and after a
+                               failed step the last (halved) dt tried.  dt_ctrl starts unset at
+                               creation and after jfnk_set_opts; it survives jfnk_set_state.
+                               <= 1: off, every step at its CFL dt */
 } jfnk_solver_opts;
 
 /* Statistics of the last step. */

@@ -68,6 +68,10 @@ typedef struct {
     int pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles;
     int mg_light; /* levels of at most this many cells: one pre- and one post-sweep (0: off) */
     double corr_tol;
+    /* time-step controller (section 2.1: dt adjusted for efficiency within
+     * the user's limits): on when dt_grow > 1 */
+    double dt_grow, dt_ctrl;
+    int newton_target;
     /* spherical metric, per radial index i and colatitude index j:
      *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
      *   (cell volume Vr Vt per radian of azimuth); r2f[i] = r_{i-1/2}^2 and
@@ -1598,6 +1602,9 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->sph = ip[19];
     o->mg_light = ip[20];
     o->corr_tol = dp[18];
+    o->dt_grow = dp[19];
+    o->newton_target = ip[21];
+    o->dt_ctrl = 0.0;
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];
     o->cfl_hydro = dp[14]; o->cfl_adv_max = dp[15]; o->cfl_rad_max = dp[16]; o->dt_max = dp[17];
@@ -1742,12 +1749,28 @@ int or_implicit_step(void *h, double *stats) {
     Or *o = h;
     double hy, ad, ra;
     double dt = time_step(o, o->u, &hy, &ad, &ra);
+    /* the controller bounds dt by the previous accepted dt times a factor
+     * set by that step's Newton count; the CFL limits still apply */
+    int ctrl = o->dt_grow > 1.0;
+    if (ctrl && o->dt_ctrl > 0.0 && o->dt_ctrl < dt) dt = o->dt_ctrl;
     int rej = 0, s = 0;
     for (;;) {
         s = step_at(o, dt);
         if (s == 0 || rej >= o->max_halvings) break;
         rej++;
         dt = 0.5 * dt;
+    }
+    if (ctrl) {
+        if (s == 0) {
+            double f = o->dt_grow;
+            if (o->newton_target > 0 && o->st_newton > 0) {
+                double r = (double)o->newton_target / (double)o->st_newton;
+                f = r < 0.5 ? 0.5 : (r > o->dt_grow ? o->dt_grow : r);
+            }
+            o->dt_ctrl = dt * f;
+        } else {
+            o->dt_ctrl = dt;
+        }
     }
     if (s == 0) o->t += dt;
     o->st_rejections = rej;

@@ -97,11 +97,12 @@ class Oracle:
                        opts["gmres_restart"], opts["gmres_max_cycles"], opts["pc"],
                        opts["max_halvings"], opts["pc_solver"], opts["mg_nu1"], opts["mg_nu2"],
                        opts["mg_nuc"], opts["mg_cycles"], desc.get("energy_form", 0),
-                       desc.get("geometry", 0), opts.get("mg_light_cells", 0)], dtype=np.int32)
+                       desc.get("geometry", 0), opts.get("mg_light_cells", 0),
+                       opts.get("newton_target", 0)], dtype=np.int32)
         dp = np.array(list(desc["lo"]) + list(desc["hi"]) + [desc["gamma"]] + list(desc["g"]) +
                       [desc["chi0"], opts["newton_rtol"], opts["newton_atol"], opts["gmres_eta"],
                        opts["cfl_hydro"], opts["cfl_adv_max"], opts["cfl_rad_max"], opts["dt_max"],
-                       opts["newton_corr_tol"]],
+                       opts["newton_corr_tol"], opts.get("dt_grow", 0.0)],
                       dtype=np.float64)
         u0 = _arr(u0, self.nvec)
         self._h = lib.or_create(ip.ctypes.data_as(_ip), _d(dp), _d(u0))

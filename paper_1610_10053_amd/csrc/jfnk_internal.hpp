@@ -294,9 +294,15 @@ struct ProfScope {
 #define JFNK_PROF(cls, stream) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls))
 #define JFNK_PROFB(cls, stream, b) ::jfnk::ProfScope JFNK_CAT(prof_scope_, __LINE__)((cls), (double)(b))
 // kernel launch carrying the armed event pair, if any (then disarmed)
-#define JFNK_KLAUNCH(kern, grid, block, shm, stream, ...)                                          \
-    do {                                                                                          \
-        hipEvent_t jfnk_es_ = ::jfnk::g_ev_start, jfnk_ee_ = ::jfnk::g_ev_stop;                   \
-        ::jfnk::g_ev_start = ::jfnk::g_ev_stop = nullptr;                                         \
-        hipExtLaunchKernelGGL(kern, grid, block, shm, stream, jfnk_es_, jfnk_ee_, 0u, __VA_ARGS__); \
+// A launch that carries timing events goes through hipExtLaunchKernelGGL
+// (events on the dispatch itself); every other launch is a plain one, which
+// stream capture records into a graph.
+#define JFNK_KLAUNCH(kern, grid, block, shm, stream, ...)                                              \
+    do {                                                                                              \
+        hipEvent_t jfnk_es_ = ::jfnk::g_ev_start, jfnk_ee_ = ::jfnk::g_ev_stop;                       \
+        ::jfnk::g_ev_start = ::jfnk::g_ev_stop = nullptr;                                             \
+        if (jfnk_es_ || jfnk_ee_)                                                                     \
+            hipExtLaunchKernelGGL(kern, grid, block, shm, stream, jfnk_es_, jfnk_ee_, 0u, __VA_ARGS__); \
+        else                                                                                          \
+            hipLaunchKernelGGL(kern, grid, block, shm, stream, __VA_ARGS__);                         \
     } while (0)

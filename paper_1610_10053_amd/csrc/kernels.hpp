@@ -118,6 +118,8 @@ void launch_vel_error_scratch(const Grid& Gl, const Grid& Gh, const double* ul, 
 
 // krylov.hip: deterministic two-stage reductions and Krylov vector kernels
 // partial layout: part[col * nblk + block]
+// dst[0] = v, ordered on the stream
+void launch_put_scalar(double* dst, double v, hipStream_t stream);
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
 void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale5, double* part, int nblk,
@@ -168,14 +170,16 @@ struct LevelT {
     // finest level of a Cartesian operator: the couplings are formed on the
     // fly from one cell field, a_d = (K0 ((qf_lo + qf_c) / 2)) i2_d on the
     // lower face (bitwise the stored a), so a sweep reads one array instead
-    // of ndim; null on other levels
+    // of ndim; null on other levels.  K0 (which changes with dt) is read from
+    // device memory, so that a captured launch sequence stays valid
     const double* qf;
-    double K0, i2[3];
+    const double* K0;
+    double i2[3];
 };
 // coupling on the face between cells lo and c of a level with qf set
 template <typename R>
 __device__ __forceinline__ R qf_coupling(const LevelT<R>& L, int d, int lo, int c) {
-    return (R)((L.K0 * (0.5 * (L.qf[lo] + L.qf[c]))) * L.i2[d]);
+    return (R)((L.K0[0] * (0.5 * (L.qf[lo] + L.qf[c]))) * L.i2[d]);
 }
 // index of cell (i, j, k) in a level's x, b and x2 arrays (levels hold fewer
 // than 2^30 cells)

@@ -30,6 +30,14 @@ __global__ void __launch_bounds__(kFinalThreads) k_final_max(const double* __res
     if (threadIdx.x == 0) out[col] = t;
 }
 
+__global__ void k_put_scalar(double* __restrict__ dst, double v) {
+    if (threadIdx.x == 0) dst[0] = v;
+}
+void launch_put_scalar(double* dst, double v, hipStream_t stream) {
+    JFNK_PROF(KC_OTHER, stream);
+    JFNK_KLAUNCH(k_put_scalar, dim3(1), dim3(64), 0, stream, dst, v);
+}
+
 void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);
     JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kFinalThreads), 0, stream, part, nblk, out);

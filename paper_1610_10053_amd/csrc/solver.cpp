@@ -38,7 +38,7 @@ int fail(int code, const std::string& msg) {
 constexpr int kDsum = 512;  // device scalar area
 // offsets in the device scalar area
 constexpr int D_H1 = 0, D_H2 = 80, D_HN = 160, D_Y = 170, D_USQ = 250, D_EPS = 251, D_TMP = 260, D_SUSQ = 300,
-              D_SEPS = 301;
+              D_SEPS = 301, D_K0 = 302;  // D_K0, D_K0 + 1: finest-level coupling factor per operator
 
 struct Buffers {
     std::vector<void*> ptrs;
@@ -89,6 +89,7 @@ struct jfnk_problem {
     bool own_hpin = false;
     double scale[5] = {1, 1, 1, 1, 1};
     double t_now = 0.0;
+    double dt_ctrl = 0.0;  // the controller's bound on the next dt (0: unset)
     long nunk = 0;
     int nred = 1, ncell_blk = 1;
     // last dt limits
@@ -103,7 +104,13 @@ struct jfnk_problem {
            *sr = nullptr, *sw = nullptr, *stmp = nullptr, *sV = nullptr;
     double *srho0 = nullptr, *srho1 = nullptr, *sfr0 = nullptr, *sfr1 = nullptr;
     int sc_newton = 0, sc_gmres = 0;
+    // the multigrid solve of each operator (acoustic, conduction) replayed as
+    // a HIP graph on the problem's stream (captured at its first use)
+    hipGraphExec_t mg_exec[2] = {nullptr, nullptr};
+    bool use_graphs = true;
     ~jfnk_problem() {
+        for (auto& g : mg_exec)
+            if (g) (void)hipGraphExecDestroy(g);
         if (hpin && own_hpin) (void)hipHostFree(hpin);
     }
 };
@@ -177,6 +184,8 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
         return fail(-4, "the mixed-precision form supports the multigrid preconditioner only");
     if (!(o->cfl_hydro > 0.0)) return fail(-1, "cfl_hydro must be positive");
     if (o->max_halvings < 0) return fail(-1, "max_halvings must be >= 0");
+    if (o->newton_target < 0) return fail(-1, "newton_target must be >= 0");
+    if (!(o->dt_grow == o->dt_grow)) return fail(-1, "dt_grow must be a number");
     return 0;
 }
 
@@ -448,7 +457,8 @@ void build_hierarchy(jfnk_problem* p, int which) {
     if (!G.sph && (which == 0 || G.has_chi)) {
         const double tau = p->C.tau;
         L0.qf = which == 0 ? p->C.H : p->C.chi;
-        L0.K0 = which == 0 ? (tau * tau) * G.gm1 : tau;
+        launch_put_scalar(p->dsum + D_K0 + which, which == 0 ? (tau * tau) * G.gm1 : tau, p->stream);
+        L0.K0 = p->dsum + D_K0 + which;
         for (int d = 0; d < 3; ++d) L0.i2[d] = d < G.ndim ? G.idx[d] * G.idx[d] : 0.0;
     }
     // D is built only without unit sigma: with sigma == 1 the sweeps form it
@@ -496,11 +506,51 @@ const LevelT<float>* dlevels<float>(jfnk_problem* p, int which) {
 }
 
 template <typename R>
-void mg_solve(jfnk_problem* p, int which) {
+void mg_launches(jfnk_problem* p, int which) {
     const LevelSet<R>& S = levels<R>(p, which);
     for (int c = 0; c < p->opts.mg_cycles; ++c)
         mg_vcycle<R>(p->G, S, dlevels<R>(p, which), p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2,
                      p->opts.mg_nuc, p->opts.mg_light_cells, c == 0, p->stream);
+}
+
+// The V-cycles' launches depend only on the problem (level arrays, sweep
+// counts), never on values, so on a stream of its own the sequence is
+// captured once into a graph and replayed; with kernel timing on, or on the
+// legacy default stream (which cannot be captured), the launches are issued
+// one by one.
+template <typename R>
+void mg_solve(jfnk_problem* p, int which) {
+    const bool timed = g_prof && g_prof->mask;
+    if (!p->stream || timed || !p->use_graphs) {
+        mg_launches<R>(p, which);
+        return;
+    }
+    hipGraphExec_t& ge = p->mg_exec[which];
+    if (!ge) {
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            mg_launches<R>(p, which);
+            return;
+        }
+        mg_launches<R>(p, which);
+        if (hipStreamEndCapture(p->stream, &g) != hipSuccess || !g) {
+            (void)hipGetLastError();
+            p->use_graphs = false;
+            mg_launches<R>(p, which);
+            return;
+        }
+        const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            ge = nullptr;
+            p->use_graphs = false;
+            mg_launches<R>(p, which);
+            return;
+        }
+    }
+    (void)hipGraphLaunch(ge, p->stream);
 }
 
 // z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z;
@@ -1060,6 +1110,8 @@ void jfnk_default_opts(jfnk_solver_opts* o) {
     o->newton_atol = 1e-14;
     o->newton_corr_tol = 1e-12;
     o->newton_max = 20;
+    o->newton_target = 0;
+    o->dt_grow = 0.0;
     o->gmres_restart = 30;
     o->gmres_max_cycles = 10;
     o->gmres_eta = 1e-2;
@@ -1346,6 +1398,13 @@ int jfnk_set_opts(jfnk_problem* p, const jfnk_solver_opts* opts) {
     if (opts->prec != p->opts.prec || opts->gmres_restart > p->opts.gmres_restart)
         return fail(-1, "precision and a larger restart need a new problem");
     p->opts = *opts;
+    p->dt_ctrl = 0.0;
+    // the captured multigrid sequence depends on the sweep options
+    (void)hipStreamSynchronize(p->stream);
+    for (auto& g : p->mg_exec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
     return 0;
 }
 
@@ -1389,6 +1448,10 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
     int rc = time_step(p, p->u, &dt);
     if (rc) return rc;
     const double hyd = p->hyd, adv = p->adv, rad = p->rad;
+    const bool ctrl = p->opts.dt_grow > 1.0;
+    // the controller's bound on dt (section 2.1: dt adjusted for efficiency
+    // within the user's CFL limits, the most restrictive applying)
+    if (ctrl && p->dt_ctrl > 0.0 && p->dt_ctrl < dt) dt = p->dt_ctrl;
     int rej = 0;
     for (;;) {
         rc = step_at(p, dt, &st);
@@ -1396,6 +1459,18 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
         if (rc == 0 || rej >= p->opts.max_halvings) break;
         rej++;
         dt = 0.5 * dt;
+    }
+    if (ctrl) {
+        if (rc == 0) {
+            double f = p->opts.dt_grow;
+            if (p->opts.newton_target > 0 && st.newton_its > 0) {
+                const double r = (double)p->opts.newton_target / (double)st.newton_its;
+                f = r < 0.5 ? 0.5 : (r > p->opts.dt_grow ? p->opts.dt_grow : r);
+            }
+            p->dt_ctrl = dt * f;
+        } else {
+            p->dt_ctrl = dt;
+        }
     }
     if (rc == 0) p->t_now += dt;
     st.rejections = rej;

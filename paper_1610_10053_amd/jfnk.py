@@ -32,7 +32,8 @@ class SolverOpts(C.Structure):
                 ("gmres_eta", C.c_double), ("pc", C.c_int), ("pc_solver", C.c_int), ("mg_nu1", C.c_int),
                 ("mg_nu2", C.c_int), ("mg_nuc", C.c_int), ("mg_cycles", C.c_int), ("prec", C.c_int),
                 ("cfl_hydro", C.c_double), ("cfl_adv_max", C.c_double), ("cfl_rad_max", C.c_double),
-                ("dt_max", C.c_double), ("max_halvings", C.c_int), ("mg_light_cells", C.c_int)]
+                ("dt_max", C.c_double), ("max_halvings", C.c_int), ("mg_light_cells", C.c_int),
+                ("newton_target", C.c_int), ("dt_grow", C.c_double)]
 
 
 class StepStats(C.Structure):

@@ -517,3 +517,35 @@ def test_tg128_step_converges_by_oracle_residual(torch_cuda, prec, form):
     for k in (("rho", "E") if form == 0 else ("rho",)):
         a0, a1 = split_state(un, desc)[k], split_state(unew, desc)[k]
         assert abs(exact_sum(a1) - exact_sum(a0)) <= 1e-13 * np.abs(a0).sum()
+
+
+# ---------------------------------------------------------------- multigrid replayed as a HIP graph
+
+@pytest.mark.parametrize("name,n,prec", [("rt", None, 0), ("kh", 64, 0), ("rad", 32, 0), ("tg", 16, 0),
+                                         ("tg", 16, PREC_MIXED), ("srad", 16, 0)])
+def test_graph_replayed_multigrid_is_bitwise_the_launches(torch_cuda, name, n, prec):
+    """On a stream of its own the problem captures each multigrid solve once
+    and replays it as a HIP graph (on the legacy default stream it launches
+    the kernels one by one).  Every replay, with the solver's own work and
+    synchronisations between replays, gives bit for bit the eager result:
+    the preconditioner applied repeatedly, and whole implicit steps."""
+    torch = torch_cuda
+    jfnk = _lib()
+    desc, opts, u = make_config(name, n=n, prec=prec)
+    print("case", name, n, prec, flush=True)
+    side = torch.cuda.Stream()
+    eager = jfnk.Problem(desc, opts, u)  # created on the default stream
+    with torch.cuda.stream(side):
+        graph = jfnk.Problem(desc, opts, u)
+        dt = eager.eval_time_step(u)["dt"]
+        graph.eval_time_step(u)
+        for k in range(3):
+            v = _direction(desc, 20 + k)
+            assert np.array_equal(graph.apply_precond(u, dt, v), eager.apply_precond(u, dt, v))
+        for k in range(3):
+            rg, sg = graph.implicit_step()
+            re, se = eager.implicit_step()
+            assert rg == re == 0 and sg["gmres_its"] == se["gmres_its"]
+            assert np.array_equal(graph.get_state(), eager.get_state()), k
+        graph.close()
+    eager.close()
