@@ -161,14 +161,16 @@ def serving(jfnk, args):
     hbm = int(args.serve_hbm_gb * (1 << 30))
     log("serving: %d requests, saturated pass" % len(mix))
     sat = run_serving(jfnk, mix, hbm, args.serve_active, 0.0, args.serve_seed)
-    rate = 0.8 * sat["requests_per_s"]
-    log("serving: Poisson arrivals at %.2f requests/s" % rate)
-    poi = run_serving(jfnk, mix, hbm, args.serve_active, rate, args.serve_seed)
-    poi["arrival_rate_per_s"] = rate
-    return {"workload": "serving mix: %d requests (rt/kh/tg/rad, 2D 32..512, 3D 32..128 cubed, %d..%d steps, "
-                        "FP64 or mixed), seed %d" % (len(mix), lo, hi, args.serve_seed),
-            "max_active": args.serve_active, "arena_gb": args.serve_hbm_gb,
-            "saturated": sat, "poisson_0.8x": poi}
+    out = {"workload": "serving mix: %d requests (rt/kh/tg/rad, 2D 32..512, 3D 32..128 cubed, %d..%d steps, "
+                       "FP64 or mixed), seed %d" % (len(mix), lo, hi, args.serve_seed),
+           "max_active": args.serve_active, "arena_gb": args.serve_hbm_gb, "saturated": sat}
+    if args.serve_poisson:
+        rate = 0.8 * sat["requests_per_s"]
+        log("serving: Poisson arrivals at %.2f requests/s" % rate)
+        poi = run_serving(jfnk, mix, hbm, args.serve_active, rate, args.serve_seed)
+        poi["arrival_rate_per_s"] = rate
+        out["poisson_0.8x"] = poi
+    return out
 
 
 def model_bytes_per_cell(newton, gmres, ndim, basis_bytes_ratio):
@@ -271,16 +273,20 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--forms", default="fp64,mixed,internal",
                     help="fp64, mixed (FP32 preconditioner and basis), internal (FP64, energy variable rho e)")
-    ap.add_argument("--cpu-n", type=int, default=128)
-    ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--cpu-n", type=int, default=128, help="grid of the one-core oracle leg")
+    ap.add_argument("--cpu-steps", type=int, default=1, help="implicit steps of the one-core oracle leg")
+    ap.add_argument("--cpu-n-all", type=int, default=128, help="grid of the all-cores oracle leg")
+    ap.add_argument("--cpu-steps-all", type=int, default=3, help="implicit steps of the all-cores oracle leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prof", action="store_true", help="no HIP-event timing (for external profilers)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-geometries", action="store_true",
                     help="skip the radiative layer in Cartesian and spherical geometry")
     ap.add_argument("--geo-steps", type=int, default=20)
-    ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-steps", default="10,60", help="lo,hi implicit steps per request")
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-steps", default="20,200", help="lo,hi implicit steps per request")
+    ap.add_argument("--serve-poisson", action="store_true",
+                    help="also run the mix with Poisson arrivals at 0.8x the saturated request rate")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
@@ -393,7 +399,7 @@ def main():
         log("cpu baseline (oracle, one core)")
         out["cpu_baseline"] = cpu_baseline(args.cpu_n, args.cpu_steps, threaded=False)
         log("cpu baseline (oracle, all cores)")
-        out["cpu_baseline_all_cores"] = cpu_baseline(args.cpu_n, args.cpu_steps, threaded=True)
+        out["cpu_baseline_all_cores"] = cpu_baseline(args.cpu_n_all, args.cpu_steps_all, threaded=True)
     print(json.dumps(out), flush=True)
 
 
