@@ -93,7 +93,11 @@ typedef struct {
     int gmres_max_cycles;
     double gmres_eta;       /* relative linear tolerance */
     int pc;                 /* JFNK_PC_* */
-    int pc_solver;          /* JFNK_PCS_*: elliptic solves by multigrid or ADI lines */
+    int pc_solver;          /* JFNK_PCS_*: elliptic solves by multigrid or by ADI tridiagonal
+                               (cyclic on periodic lines) line solves, each line solved by the
+                               Thomas algorithm in one thread, consecutive threads on lines
+                               adjacent in x where the lines run along y or z; in the mixed
+                               form the acoustic lines hold FP32 values (FP64 arithmetic) */
     int mg_nu1, mg_nu2, mg_nuc, mg_cycles;
     int prec;               /* JFNK_FP64, or JFNK_MIXED: FP32 preconditioner and Krylov basis */
     double cfl_hydro;       /* eq. (5) target */

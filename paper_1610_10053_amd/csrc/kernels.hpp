@@ -234,9 +234,9 @@ void launch_pc_diff_back(const Grid& G, const PcCoef& C, const R* v, const Level
 template <typename R>
 void launch_pc_back(const Grid& G, const PcCoef& C, const R* v, const double* rE, const R* dp,
                     const LevelT<R>& L0, Scales5 sc, R* z, double* part, int nblk, hipStream_t stream);
-// out = s * v[off : off + N] in precision R
+// out = s * v for a cell field v of the preconditioner's vector precision R
 template <typename R>
-void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream);
+void launch_field_scaled(const R* v, double s, double* out, long N, hipStream_t stream);
 // L0.b = s * v (a cell field) in precision R, in the level's x/b order
 template <typename R>
 void launch_field_to_level(const Grid& G, const R* v, double s, const LevelT<R>& L0, hipStream_t stream);

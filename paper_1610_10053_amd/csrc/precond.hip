@@ -804,10 +804,10 @@ __global__ void __launch_bounds__(kBlock) k_pc_back(Grid G, PcCoef C, const R* _
 }
 
 template <typename R>
-__global__ void __launch_bounds__(kBlock) k_field_scaled(const double* __restrict__ v, double s,
-                                                         R* __restrict__ out, long N) {
+__global__ void __launch_bounds__(kBlock) k_field_scaled(const R* __restrict__ v, double s,
+                                                         double* __restrict__ out, long N) {
     const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < N) out[c] = (R)(s * v[c]);
+    if (c < N) out[c] = s * (double)v[c];
 }
 
 template <typename R, int ND>
@@ -894,7 +894,7 @@ void launch_pc_back(const Grid& G, const PcCoef& C, const R* v, const double* rE
     }
 }
 template <typename R>
-void launch_field_scaled(const double* v, double s, R* out, long N, hipStream_t stream) {
+void launch_field_scaled(const R* v, double s, double* out, long N, hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_RHS, stream);
         JFNK_KLAUNCH((k_field_scaled<R>), dim3(grid_blocks(N)), dim3(kBlock), 0, stream, v, s, out, N);
@@ -957,7 +957,10 @@ template <typename R>
 __global__ void __launch_bounds__(kBlock) k_line(Grid G, PcCoef C, int d, int kind, R* __restrict__ x,
                                                  double* __restrict__ cp, double* __restrict__ dpv,
                                                  double* __restrict__ x1, double* __restrict__ zz) {
-    const int r1 = (d + 1) % 3, r2 = (d + 2) % 3;
+    // consecutive threads take lines adjacent along the lowest other axis:
+    // for y- and z-lines that is x, so a wave's loads and stores at one
+    // position along the line are contiguous
+    const int r1 = d == 0 ? 1 : 0, r2 = d == 2 ? 1 : 2;
     const long nl = (long)G.n[r1] * G.n[r2];
     const long line = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (line >= nl) return;
@@ -1043,7 +1046,7 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
                                          Scales5, double*, hipStream_t);                                     \
     template void launch_pc_back<R>(const Grid&, const PcCoef&, const R*, const double*, const R*,      \
                                     const LevelT<R>&, Scales5, R*, double*, int, hipStream_t);               \
-    template void launch_field_scaled<R>(const double*, double, R*, long, hipStream_t);                      \
+    template void launch_field_scaled<R>(const R*, double, double*, long, hipStream_t);                      \
     template void launch_field_to_level<R>(const Grid&, const R*, double, const LevelT<R>&, hipStream_t);     \
     template void launch_line_solve<R>(const Grid&, const PcCoef&, int, int, R*, double*, hipStream_t);
 INST(double)

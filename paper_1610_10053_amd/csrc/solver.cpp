@@ -180,8 +180,6 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (o->mg_nu1 < 1 || o->mg_nu2 < 0 || o->mg_nuc < 1 || o->mg_cycles < 1 || o->mg_light_cells < 0)
         return fail(-1, "multigrid sweeps: nu1 >= 1, nu2 >= 0, nuc >= 1, cycles >= 1, light cells >= 0");
     if (o->prec != JFNK_FP64 && o->prec != JFNK_MIXED) return fail(-1, "unknown precision");
-    if (o->prec == JFNK_MIXED && o->pc_solver == JFNK_PCS_ADI)
-        return fail(-4, "the mixed-precision form supports the multigrid preconditioner only");
     if (!(o->cfl_hydro > 0.0)) return fail(-1, "cfl_hydro must be positive");
     if (o->max_halvings < 0) return fail(-1, "max_halvings must be >= 0");
     if (o->newton_target < 0) return fail(-1, "newton_target must be >= 0");
@@ -568,8 +566,9 @@ void pc_apply_t(jfnk_problem* p, const R* v, R* z) {
             launch_field_to_level<R>(G, v + G.N, sc.v[1], S.L[0], p->stream);
             mg_solve<R>(p, 1);
             launch_pc_diff_back<R>(G, p->C, v, S.L[0], sc, p->rEd, p->stream);
-        } else if constexpr (std::is_same<R, double>::value) {  // ADI: FP64 only
-            launch_field_scaled<double>(v + G.N, sc.v[1], p->rEd, G.N, p->stream);
+        } else {
+            // the conduction lines run in FP64 on an FP64 copy of r_E in both forms
+            launch_field_scaled<R>(v + G.N, sc.v[1], p->rEd, G.N, p->stream);
             for (int d = 0; d < G.ndim; ++d) launch_line_solve<double>(G, p->C, d, 1, p->rEd, p->lines, p->stream);
         }
         rE = p->rEd;

@@ -81,8 +81,10 @@ def test_invalid_arguments_are_rejected_on_host():
     with pytest.raises(jfnk.JfnkError):
         jfnk.footprint_bytes(desc, dict(opts, gmres_restart=0))
     with pytest.raises(jfnk.JfnkError) as e:
-        jfnk.footprint_bytes(desc, dict(opts, prec=jfnk.MIXED, pc_solver=jfnk.PCS_ADI))
-    assert e.value.code == -4
+        jfnk.footprint_bytes(desc, dict(opts, newton_target=-1))
+    assert e.value.code == -1
+    # the mixed form takes the line solves too
+    assert jfnk.footprint_bytes(desc, dict(opts, prec=jfnk.MIXED, pc_solver=jfnk.PCS_ADI)) > 0
 
 
 def test_server_arguments_are_rejected_on_host():

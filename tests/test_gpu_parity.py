@@ -228,6 +228,26 @@ def test_adi_and_unpreconditioned_paths(torch_cuda, name, n):
             assert rel_l2(g.get_state(), o.get_state()) <= 1e-10
 
 
+@pytest.mark.parametrize("name,n", [("tg", 16), ("rad", 16), ("kh", 32)])
+def test_adi_mixed_precision_converges_to_fp64(torch_cuda, name, n):
+    """ADI line solves in the mixed form (FP32 lines of the acoustic block,
+    FP64 conduction lines): the same Newton tolerance reached, the state
+    within 1e-8 of the FP64 ADI run after two steps"""
+    jfnk = _lib()
+    out = []
+    for prec in (0, PREC_MIXED):
+        desc, opts, u = make_config(name, n=n, pc_solver=PCS_ADI, gmres_max_cycles=40, prec=prec)
+        print("case", name, n, prec, flush=True)
+        p = jfnk.Problem(desc, opts, u)
+        for _ in range(2):
+            rc, st = p.implicit_step()
+            assert rc == 0, st
+            assert st["newton_exit"] == 0 or st["max_rel_corr"] <= 1e-12
+        out.append(p.get_state())
+        p.close()
+    assert rel_l2(out[1], out[0]) <= 1e-8
+
+
 # ---------------------------------------------------------------- internal-energy form (eq. 2 as written)
 
 @pytest.mark.parametrize("name,n", CASES + [("rad", None), ("kh", 54), ("rt", 20)])
