@@ -143,9 +143,15 @@ void jfnk_default_opts(jfnk_solver_opts* opts);
 /* Device bytes a problem would allocate (admission control). */
 int jfnk_footprint_bytes(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts, size_t* out);
 
-/* Create a problem with initial state u0 (layout above).  The frozen wall
- * conductive fluxes and the heat-balance source are computed from u0.
- * hip_stream: a hipStream_t (NULL for the default stream). */
+/* Create a problem with initial state u0 (layout above): eqs. (1)-(3) of
+ * section 2 on the staggered grid of section 2 (rho, E at cell centres,
+ * momenta on faces), with the ghost-cell boundaries of section 3.1 (walls)
+ * and section 6 (constant-luminosity walls).  The frozen wall conductive
+ * fluxes and the heat-balance source are computed from u0.  Allocates the
+ * state, the Krylov workspaces and the preconditioner hierarchy on the
+ * current device (-2 if device memory runs out; nothing is left allocated).
+ * hip_stream: a hipStream_t (NULL for the default stream); on a stream of
+ * its own the multigrid solves are replayed as HIP graphs. */
 int jfnk_create_problem(const jfnk_problem_desc* desc, const jfnk_solver_opts* opts,
                         const double* u0, int on_device, void* hip_stream, jfnk_problem** out);
 int jfnk_destroy_problem(jfnk_problem* p);
@@ -156,14 +162,21 @@ int jfnk_get_state(jfnk_problem* p, double* u, int on_device);
 int jfnk_set_time(jfnk_problem* p, double t);
 int jfnk_set_opts(jfnk_problem* p, const jfnk_solver_opts* opts);
 
-/* One adaptive implicit step: dt from the CFL limits of the current state,
- * Newton solve, and on failure state restored and dt halved up to
- * max_halvings times.  On a final failure the state is u^n and the status
- * code is returned. */
+/* One adaptive implicit step (section 2.1 for dt, section 2 for the step):
+ * dt from the CFL limits of eqs. (5)-(7) of the current state, the most
+ * restrictive applying (and the efficiency controller's bound when
+ * dt_grow > 1); a Crank-Nicolson step F(u) = u - u^n - dt/2 (R(u) + R(u^n))
+ * = 0 solved by Newton-Raphson with right-preconditioned restarted GMRES
+ * and Jacobian-free products; on failure the state is restored and dt
+ * halved up to max_halvings times.  On a final failure the state is u^n
+ * and the status code is returned.  Synchronises the problem's stream. */
 int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out);
 
-/* One Crank-Nicolson step at the given dt with no retry.  On failure the
- * state is restored to u^n. */
+/* One Crank-Nicolson step (section 2) at the given dt > 0 with no retry
+ * and no time-step controller: Newton-Raphson on F(u) = 0 from u^n, the
+ * linear systems by GMRES with the physics-based preconditioner (section
+ * 2, last paragraph).  On failure (status > 0) the state is restored to
+ * u^n.  Synchronises the problem's stream. */
 int jfnk_newton_solve(jfnk_problem* p, double dt, jfnk_step_stats* out);
 
 /* ---- passive scalars (section 2.2) ----
