@@ -117,6 +117,12 @@ typedef struct {
                                failed step the last (halved) dt tried.  dt_ctrl starts unset at
                                creation and after jfnk_set_opts; it survives jfnk_set_state.
                                <= 1: off, every step at its CFL dt */
+    int scalar_converge;    /* passive scalars (section 2.2): 1 (default) their Newton iterations run
+                               until their own residual meets the flow's tolerances (the option of
+                               section 3.3 that "requires the scalars' corrections to converge");
+                               0 they take as many Newton iterations as the flow's solve of the
+                               step did (at least one), relying on the convergence of the flow
+                               alone, with no test of their own (the paper's default) */
 } jfnk_solver_opts;
 
 /* Statistics of the last step. */

@@ -72,6 +72,9 @@ typedef struct {
      * the user's limits): on when dt_grow > 1 */
     double dt_grow, dt_ctrl;
     int newton_target;
+    /* passive scalars (section 2.2): 1 their Newton iterations converge on
+     * their own residual; 0 they take the flow's Newton count of the step */
+    int scalar_converge;
     /* spherical metric, per radial index i and colatitude index j:
      *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
      *   (cell volume Vr Vt per radian of azimuth); r2f[i] = r_{i-1/2}^2 and
@@ -1525,7 +1528,8 @@ static int scalar_step(Or *o, double dt) {
     if (floor_ > tol) tol = floor_;
     int status = 0, its = 0, gits = 0;
     if (!isfinite(g0)) status = 3;
-    while (status == 0 && g > tol) {
+    int nfix = o->st_newton > 1 ? o->st_newton : 1; /* the flow's Newton count of this step */
+    while (status == 0 && (o->scalar_converge ? g > tol : (its < nfix && g > floor_))) {
         if (its >= o->newton_max) { status = 1; break; }
         ctx.srms = norm2(n, s) / sqrt((double)n);
         for (long q = 0; q < n; ++q) rhs[q] = -G[q];
@@ -1604,6 +1608,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->corr_tol = dp[18];
     o->dt_grow = dp[19];
     o->newton_target = ip[21];
+    o->scalar_converge = ip[22];
     o->dt_ctrl = 0.0;
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];

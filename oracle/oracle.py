@@ -98,7 +98,7 @@ class Oracle:
                        opts["max_halvings"], opts["pc_solver"], opts["mg_nu1"], opts["mg_nu2"],
                        opts["mg_nuc"], opts["mg_cycles"], desc.get("energy_form", 0),
                        desc.get("geometry", 0), opts.get("mg_light_cells", 0),
-                       opts.get("newton_target", 0)], dtype=np.int32)
+                       opts.get("newton_target", 0), opts.get("scalar_converge", 1)], dtype=np.int32)
         dp = np.array(list(desc["lo"]) + list(desc["hi"]) + [desc["gamma"]] + list(desc["g"]) +
                       [desc["chi0"], opts["newton_rtol"], opts["newton_atol"], opts["gmres_eta"],
                        opts["cfl_hydro"], opts["cfl_adv_max"], opts["cfl_rad_max"], opts["dt_max"],

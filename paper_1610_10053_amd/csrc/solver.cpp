@@ -183,6 +183,7 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (!(o->cfl_hydro > 0.0)) return fail(-1, "cfl_hydro must be positive");
     if (o->max_halvings < 0) return fail(-1, "max_halvings must be >= 0");
     if (o->newton_target < 0) return fail(-1, "newton_target must be >= 0");
+    if (o->scalar_converge != 0 && o->scalar_converge != 1) return fail(-1, "scalar_converge must be 0 or 1");
     if (!(o->dt_grow == o->dt_grow)) return fail(-1, "dt_grow must be a number");
     return 0;
 }
@@ -869,7 +870,9 @@ int vec_norm(jfnk_problem* p, const double* v, long n, double* out) {
     return 0;
 }
 
-int scalar_step(jfnk_problem* p, double dt) {
+// flow_its: the Newton iterations of the flow's solve of this step (the
+// scalars' count when they do not converge on their own)
+int scalar_step(jfnk_problem* p, double dt, int flow_its) {
     const Grid& G = p->G;
     const long N = G.N, n = (long)p->nscal * N;
     const jfnk_solver_opts& o = p->opts;
@@ -912,7 +915,8 @@ int scalar_step(jfnk_problem* p, double dt) {
         A.v = v;
         launch_scalar_out(G, A, p->stream);
     };
-    while (status == 0 && g > tol) {
+    const int nfix = flow_its > 1 ? flow_its : 1;
+    while (status == 0 && (o.scalar_converge ? g > tol : (its < nfix && g > floor_))) {
         if (its >= o.newton_max) {
             status = 1;
             break;
@@ -948,7 +952,7 @@ int step_at(jfnk_problem* p, double dt, jfnk_step_stats* st) {
     int rc = newton(p, dt, st);
     p->sc_newton = p->sc_gmres = 0;
     if (rc == 0 && p->nscal > 0) {
-        rc = scalar_step(p, dt);
+        rc = scalar_step(p, dt, st ? st->newton_its : 1);
         if (rc != 0) launch_copy(p->u, p->un, p->G.nvec, p->stream);
         if (rc > 0 && st) st->status = rc;
     }
@@ -1111,6 +1115,7 @@ void jfnk_default_opts(jfnk_solver_opts* o) {
     o->newton_max = 20;
     o->newton_target = 0;
     o->dt_grow = 0.0;
+    o->scalar_converge = 1;
     o->gmres_restart = 30;
     o->gmres_max_cycles = 10;
     o->gmres_eta = 1e-2;

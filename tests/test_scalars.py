@@ -96,17 +96,42 @@ def test_scalar_failure_restores_flow_and_scalars():
     assert np.array_equal(o2.get_state(), u) and np.array_equal(o2.get_scalars(), s0)
 
 
+def test_scalars_relying_on_the_flow_take_its_newton_count():
+    """scalar_converge = 0 (section 2.2's default: the non-linear iterations
+    stop on the fluid's convergence alone): each step's scalar solve takes
+    exactly as many Newton iterations as the flow's solve of that step, and
+    the result stays within the flow's tolerance level of the converged
+    scalars; the flow is untouched either way"""
+    desc, opts, u = make_config("kh", n=32)
+    s0 = _two_scalars(desc, u)
+    runs = {}
+    for conv in (1, 0):
+        o = Oracle(desc, dict(opts, scalar_converge=conv), u)
+        o.set_scalars(s0, 2, renormalize=False)
+        its = []
+        for _ in range(3):
+            rc, st = o.implicit_step()
+            assert rc == 0
+            its.append((int(st["newton_its"]), o.scalar_its()[0]))
+        runs[conv] = (o.get_state(), o.get_scalars(), its)
+    assert all(sc == max(fl, 1) for fl, sc in runs[0][2]), runs[0][2]
+    assert np.array_equal(runs[0][0], runs[1][0])
+    e = np.linalg.norm(runs[0][1] - runs[1][1]) / np.linalg.norm(runs[1][1])
+    assert e <= 1e-6, e
+
+
 # ---------------------------------------------------------------- GPU against the oracle
 @pytest.mark.gpu
-@pytest.mark.parametrize("name,n,steps,renorm", [("kh", 32, 3, True), ("rt", None, 4, True), ("tg", 16, 2, False),
-                                                 ("rad", 16, 2, True)])
-def test_gpu_scalars_match_oracle(name, n, steps, renorm):
+@pytest.mark.parametrize("name,n,steps,renorm,conv", [("kh", 32, 3, True, 1), ("rt", None, 4, True, 1),
+                                                      ("tg", 16, 2, False, 1), ("rad", 16, 2, True, 1),
+                                                      ("kh", 32, 3, True, 0), ("rt", None, 4, False, 0)])
+def test_gpu_scalars_match_oracle(name, n, steps, renorm, conv):
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1610_10053_amd import jfnk
     jfnk.load()
-    desc, opts, u = make_config(name, n=n)
+    desc, opts, u = make_config(name, n=n, scalar_converge=conv)
     s0 = _two_scalars(desc, u)
     g = jfnk.Problem(desc, opts, u)
     g.set_scalars(s0, 2, renorm)
