@@ -287,7 +287,9 @@ def main():
     ap.add_argument("--serve-steps", default="20,200", help="lo,hi implicit steps per request")
     ap.add_argument("--serve-poisson", action="store_true",
                     help="also run the mix with Poisson arrivals at 0.8x the saturated request rate")
-    ap.add_argument("--serve-active", type=int, default=8)
+    # as many workers as the process's hardware queues (GPU_MAX_HW_QUEUES, 4 by
+    # default): more concurrent requests only lengthen each step
+    ap.add_argument("--serve-active", type=int, default=4)
     ap.add_argument("--serve-hbm-gb", type=float, default=64.0)
     ap.add_argument("--serve-seed", type=int, default=4)
     args = ap.parse_args()
