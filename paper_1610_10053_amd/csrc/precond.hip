@@ -490,26 +490,67 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
     __shared__ R rbuf[kCoarseMaxLevelCells];  // residuals of the level being restricted
     __shared__ int base[kMaxLevels];
-    if (threadIdx.x == 0) {
-        int off = 0;
-        for (int l = from; l < nlev; ++l) {
-            base[l] = off;
-            off += (4 + ND) * (int)Ld[l].N;
+    // the load into LDS: the arrays each level needs (sigma and D only
+    // without unit sigma, x and b of the first level only), every element of
+    // them one entry of a single index space, so that a thread's loads do
+    // not wait for one another level by level
+    __shared__ int lN[kMaxLevels], nload[kMaxLevels], first_el[kMaxLevels + 1];
+    __shared__ const R* lsrc[kMaxLevels][4 + ND];
+    __shared__ int lslot[kMaxLevels][4 + ND];
+    const bool top_first = first_top != 0;
+    if ((int)threadIdx.x < nlev - from) {
+        const int l = from + (int)threadIdx.x;
+        const LevelT<R> gL = Ld[l];
+        int k = 0;
+        auto add = [&](const R* p, int slot) {
+            lsrc[l][k] = p;
+            lslot[l][k] = slot;
+            ++k;
+        };
+        if (!UNIT) add(gL.sig, 0);
+        for (int d = 0; d < ND; ++d) add(gL.a[d], 1 + d);
+        if (!UNIT) add(gL.D, 1 + ND);  // built only without unit sigma
+        if (l == from) {
+            if (!top_first) add(gL.x, 2 + ND);
+            add(gL.b, 3 + ND);
         }
+        nload[l] = k;
+        lN[l] = (int)gL.N;
     }
     __syncthreads();
-    const bool top_first = first_top != 0;
-    for (int l = from; l < nlev; ++l) {
-        const LevelT<R> gL = Ld[l];
-        const LevelT<R> L = lds_level<R, ND>(gL, sm, base[l]);
-        for (int c = threadIdx.x; c < L.N; c += blockDim.x) {
-            L.sig[c] = gL.sig[c];
-            for (int d = 0; d < ND; ++d) L.a[d][c] = gL.a[d][c];
-            if (!UNIT) L.D[c] = gL.D[c];  // built only without unit sigma
-            if (l == from) {
-                L.b[c] = gL.b[c];
-                if (!top_first) L.x[c] = gL.x[c];
+    if (threadIdx.x == 0) {
+        int off = 0, el = 0;
+        for (int l = from; l < nlev; ++l) {
+            base[l] = off;
+            off += (4 + ND) * lN[l];
+            first_el[l] = el;
+            el += nload[l] * lN[l];
+        }
+        first_el[nlev] = el;
+    }
+    __syncthreads();
+    {
+        constexpr int U = 4;  // loads in flight per thread
+        const int total = first_el[nlev];
+        for (int e0 = (int)threadIdx.x; e0 < total; e0 += U * kCoarseThreads) {
+            R v[U];
+            int dst[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kCoarseThreads;
+                dst[u] = -1;
+                v[u] = (R)0.0;
+                if (e < total) {
+                    int l = from;
+                    while (e >= first_el[l + 1]) ++l;
+                    const int n = lN[l], r = e - first_el[l], k = r / n, c = r - k * n;
+                    v[u] = lsrc[l][k][c];
+                    dst[u] = base[l] + lslot[l][k] * n + c;
+                }
             }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (dst[u] >= 0) sm[dst[u]] = v[u];
         }
     }
     __syncthreads();
