@@ -152,6 +152,9 @@ constexpr int kMaxLevels = 16;
 // x and b of the levels solved by the single-workgroup coarse kernel live in
 // LDS: at most this many cells over those levels
 constexpr int kCoarseLdsCells = 704;
+// above those levels the coarse kernel may take one more level of at most
+// this many cells (its x in LDS, its coefficients in registers)
+constexpr int kCoarseBigCells = 4096;
 template <typename R>
 struct LevelT {
     int n[3];

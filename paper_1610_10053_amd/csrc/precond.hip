@@ -414,59 +414,187 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
     F.x[e] = F.x[e] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
 }
 
-// The rest of the V-cycle, levels from..nlev-1 (at most kCoarseLdsCells cells
-// in all), in one workgroup with every array of those levels in LDS.  Level
-// descriptors come from device memory (Ld) so that the level loop may index
-// them at run time.
+// The rest of the V-cycle, levels from..nlev-1, in one workgroup.  Every
+// level of at most kCoarseMaxLevelCells cells (at most kCoarseLdsCells cells
+// over those levels) keeps its arrays in LDS.  The first level may instead be
+// a larger one of at most kCoarseBigCells cells (never the coarsest): its x
+// and residuals live in LDS, and each thread holds its cells' couplings,
+// right-hand side and divisor in registers.  Level descriptors come from
+// device memory (Ld) so that the level loop may index them at run time.
 constexpr int kCoarseThreads = 1024;
-constexpr int kCoarseMaxLevelCells = 512;  // largest level the single-workgroup solve takes
-// Sweeps of a level held in LDS by the single workgroup: every cell has its
-// own thread (levels of at most kCoarseMaxLevelCells <= kCoarseThreads
-// cells), whose coordinates, colour and neighbour indices are found once per
-// call; the update is gs_value's, operation for operation.
+constexpr int kCoarseMaxLevelCells = 512;  // largest level whose arrays the workgroup keeps in LDS
+constexpr int kCoarseBigPer = kCoarseBigCells / kCoarseThreads;  // cells per thread on the larger first level
+
+// A cell of a level in the single-workgroup solve: its colour, neighbour
+// indices (-1 beyond a wall), couplings, right-hand side, sigma and divisor,
+// found once per call.  The update and the residual are gs_value's and
+// resid_cell_t's, operation for operation.
+template <typename R, int ND>
+struct CoarseCell {
+    int up[ND], dn[ND], colour;
+    R alo[ND], ahi[ND], bc, sig, dv;
+};
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const LevelT<R>& L, const R* b, int c) {
+    CoarseCell<R, ND> k;
+    const LIjk q = lcoords(L, c);
+    k.colour = (q.v[0] + q.v[1] + q.v[2]) & 1;
+    R den = (R)1.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        k.up[d] = lnb(G, L, q, d, 1);
+        k.dn[d] = lnb(G, L, q, d, -1);
+        k.alo[d] = L.a[d][c];
+        k.ahi[d] = k.up[d] >= 0 ? L.a[d][k.up[d]] : (R)0.0;
+        den = den + k.alo[d];
+        den = den + k.ahi[d];
+    }
+    k.bc = b[c];
+    k.sig = UNIT ? (R)1.0 : L.sig[c];
+    k.dv = UNIT ? den : L.D[c];
+    return k;
+}
+// Gauss-Seidel value of the cell from x (f: first sweep, x taken as 0)
+template <typename R, int ND>
+__device__ __forceinline__ R coarse_update(const CoarseCell<R, ND>& k, const R* x, bool f) {
+    R num = k.bc;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        if (k.dn[d] >= 0) num = num + k.alo[d] * (f ? (R)0.0 : x[k.dn[d]]);
+        if (k.up[d] >= 0) num = num + k.ahi[d] * (f ? (R)0.0 : x[k.up[d]]);
+    }
+    return num / k.dv;
+}
+// Sweeps of a level held in LDS: every cell has its own thread (levels of at
+// most kCoarseMaxLevelCells <= kCoarseThreads cells)
 template <typename R, int ND, bool UNIT>
 __device__ __forceinline__ void lds_smooth(const Grid& G, const LevelT<R>& L, int sweeps, bool first) {
     const bool together = odd_periodic<R, ND>(G, L);
     const int c = (int)threadIdx.x;
     const bool mine = c < L.N;
-    int up[ND], dn[ND], colour = -1;
-    R alo[ND], ahi[ND], den = (R)1.0, bc = (R)0.0, Dc = (R)1.0;
-    if (mine) {
-        const LIjk q = lcoords(L, c);
-        colour = (q.v[0] + q.v[1] + q.v[2]) & 1;
-#pragma unroll
-        for (int d = 0; d < ND; ++d) {
-            up[d] = lnb(G, L, q, d, 1);
-            dn[d] = lnb(G, L, q, d, -1);
-            alo[d] = L.a[d][c];
-            ahi[d] = up[d] >= 0 ? L.a[d][up[d]] : (R)0.0;
-            den = den + alo[d];
-            den = den + ahi[d];
-        }
-        bc = L.b[c];
-        if (!UNIT) Dc = L.D[c];
-    }
-    const R dv = UNIT ? den : Dc;
+    CoarseCell<R, ND> k;
+    k.colour = -1;
+    if (mine) k = coarse_cell<R, ND, UNIT>(G, L, L.b, c);
     for (int s = 0; s < sweeps; ++s)
         for (int color = 0; color < 2; ++color) {
             const bool f = first && s == 0 && color == 0;
             R val = (R)0.0;
-            if (colour == color) {
-                R num = bc;
-#pragma unroll
-                for (int d = 0; d < ND; ++d) {
-                    if (dn[d] >= 0) num = num + alo[d] * (f ? (R)0.0 : L.x[dn[d]]);
-                    if (up[d] >= 0) num = num + ahi[d] * (f ? (R)0.0 : L.x[up[d]]);
-                }
-                val = num / dv;
-            }
+            if (k.colour == color) val = coarse_update<R, ND>(k, L.x, f);
             if (!together) {
-                if (colour == color) L.x[c] = val;
+                if (k.colour == color) L.x[c] = val;
             } else {
                 __syncthreads();
-                if (colour == color) L.x[c] = val;
+                if (k.colour == color) L.x[c] = val;
                 else if (f && mine) L.x[c] = (R)0.0;
             }
+            __syncthreads();
+        }
+}
+// A cell of the larger first level, in registers: couplings, right-hand
+// side and (without unit sigma) divisor, its index (-1: no cell) and its
+// coordinates packed as i | j << 10 | k << 20 (every axis of that level is
+// shorter than 1024).  To keep the registers few, the neighbours are found
+// again from the coordinates at each use, the unit-sigma divisor is summed
+// again from the couplings in coarse_cell's order, and sigma is read again
+// where the residual needs it.  Thread t holds, for each colour, that
+// colour's cells t, t + 1024, ... in row order, so that every lane has work
+// in every half-sweep.
+template <typename R, int ND>
+struct BigCell {
+    R alo[ND], ahi[ND], bc, dv;
+    int c, pq;
+};
+__device__ __forceinline__ LIjk unpack_ijk(int pq) {
+    LIjk q;
+    q.v[0] = pq & 1023;
+    q.v[1] = (pq >> 10) & 1023;
+    q.v[2] = pq >> 20;
+    return q;
+}
+// the e-th cell of colour col on a level with even axes: its coordinates
+__device__ __forceinline__ LIjk colour_cell(const int n[3], int col, int e) {
+    const int hn0 = n[0] / 2;
+    const int row = e / hn0;
+    LIjk q;
+    q.v[1] = row % n[1];
+    q.v[2] = row / n[1];
+    q.v[0] = 2 * (e - row * hn0) + ((q.v[1] + q.v[2] + col) & 1);
+    return q;
+}
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ BigCell<R, ND> big_cell(const Grid& G, const LevelT<R>& L, const LIjk& q) {
+    const int c = lflat(L, q.v[0], q.v[1], q.v[2]);
+    const CoarseCell<R, ND> k = coarse_cell<R, ND, UNIT>(G, L, L.b, c);
+    BigCell<R, ND> b;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        b.alo[d] = k.alo[d];
+        b.ahi[d] = k.ahi[d];
+    }
+    b.bc = k.bc;
+    b.dv = k.dv;
+    b.c = c;
+    b.pq = q.v[0] | (q.v[1] << 10) | (q.v[2] << 20);
+    return b;
+}
+// index of the neighbour along d (s = -1 or 1) of the cell, -1 beyond a wall:
+// lnb's result, from the cell's index and coordinates
+template <typename R>
+__device__ __forceinline__ int big_nb(const Grid& G, const LevelT<R>& L, int c, int pq, int d, int s) {
+    const int a = (pq >> (10 * d)) & 1023, n = L.n[d];
+    const int stride = d == 0 ? 1 : (d == 1 ? L.n[0] : L.n[0] * L.n[1]);
+    const bool edge = s < 0 ? a == 0 : a == n - 1;
+    if (!edge) return c + s * stride;
+    if (G.bc[d] == WALL) return -1;
+    return c - s * (n - 1) * stride;
+}
+// coarse_update and the residual of resid_cell_t, operation for operation
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ R big_update(const Grid& G, const LevelT<R>& L, const BigCell<R, ND>& k, const R* x,
+                                        bool f) {
+    R den = (R)1.0;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        den = den + k.alo[d];
+        den = den + k.ahi[d];
+    }
+    R num = k.bc;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int dn = big_nb(G, L, k.c, k.pq, d, -1), up = big_nb(G, L, k.c, k.pq, d, 1);
+        if (dn >= 0) num = num + k.alo[d] * (f ? (R)0.0 : x[dn]);
+        if (up >= 0) num = num + k.ahi[d] * (f ? (R)0.0 : x[up]);
+    }
+    return num / (UNIT ? den : k.dv);
+}
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ R big_resid(const Grid& G, const LevelT<R>& L, const BigCell<R, ND>& k, const R* x) {
+    const R xc = x[k.c];
+    R acc = UNIT ? xc : L.sig[k.c] * xc;
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        const int dn = big_nb(G, L, k.c, k.pq, d, -1), up = big_nb(G, L, k.c, k.pq, d, 1);
+        acc = dn >= 0 ? acc + k.alo[d] * (xc - x[dn]) : acc;
+        acc = up >= 0 ? acc + k.ahi[d] * (xc - x[up]) : acc;
+    }
+    return k.bc - acc;
+}
+// Sweeps of the larger first level (no odd periodic axis: the level is not
+// the coarsest); k[col][m] is the thread's m-th cell of colour col
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ void big_smooth(const Grid& G, const LevelT<R>& L, R* x,
+                                           const BigCell<R, ND> (*k)[kCoarseBigPer / 2], int sweeps, bool first) {
+    for (int s = 0; s < sweeps; ++s)
+#pragma unroll
+        for (int color = 0; color < 2; ++color) {
+            const bool f = first && s == 0 && color == 0;
+            R val[kCoarseBigPer / 2];
+#pragma unroll
+            for (int m = 0; m < kCoarseBigPer / 2; ++m)
+                val[m] = k[color][m].c >= 0 ? big_update<R, ND, UNIT>(G, L, k[color][m], x, f) : (R)0.0;
+#pragma unroll
+            for (int m = 0; m < kCoarseBigPer / 2; ++m)
+                if (k[color][m].c >= 0) x[k[color][m].c] = val[m];
             __syncthreads();
         }
 }
@@ -483,23 +611,49 @@ __device__ __forceinline__ LevelT<R> lds_level(const LevelT<R>& g, R* sm, int ba
     L.b = sm + base + (3 + ND) * n;
     return L;
 }
+// residuals of level L's cells t, t + step, ... into rb
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ void lds_resid(const Grid& G, const LevelT<R>& L, R* rb, int t, int step) {
+    for (int c = t; c < L.N; c += step) rb[c] = resid_cell_t<R, ND, UNIT>(G, L, L.b, L.x, lcoords(L, c), c);
+}
+// coarse right-hand sides from the fine residuals rb (natural order of the
+// fine level F): the children's sums in the order of the multi-block
+// restriction
+template <typename R, int ND>
+__device__ __forceinline__ void lds_restrict_sum(const LevelT<R>& F, const LevelT<R>& C, const R* rb) {
+    for (int c = (int)threadIdx.x; c < C.N; c += kCoarseThreads) {
+        const LIjk q = lcoords(C, c);
+        const int kk = ND > 2 ? 2 : 1;
+        R sum = 0.0;
+        for (int dk = 0; dk < kk; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di)
+                    sum = sum + rb[lflat(F, 2 * q.v[0] + di, 2 * q.v[1] + dj, ND > 2 ? 2 * q.v[2] + dk : q.v[2])];
+        C.b[c] = sum * (R)(1.0 / (1 << ND));
+    }
+}
 template <typename R, int ND, bool UNIT>
 __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const LevelT<R>* __restrict__ Ld,
                                                                    int from, int nlev, int nu1, int nu2, int nuc,
                                                                    int first_top, int light) {
     __shared__ R sm[(4 + ND) * kCoarseLdsCells];
-    __shared__ R rbuf[kCoarseMaxLevelCells];  // residuals of the level being restricted
+    __shared__ R bigx[kCoarseBigCells];  // x of the larger first level
+    __shared__ R rbuf[kCoarseBigCells];  // residuals of the level being restricted
     __shared__ int base[kMaxLevels];
-    // the load into LDS: the arrays each level needs (sigma and D only
+    // the load into LDS: the arrays each LDS level needs (sigma and D only
     // without unit sigma, x and b of the first level only), every element of
     // them one entry of a single index space, so that a thread's loads do
     // not wait for one another level by level
     __shared__ int lN[kMaxLevels], nload[kMaxLevels], first_el[kMaxLevels + 1];
     __shared__ const R* lsrc[kMaxLevels][4 + ND];
     __shared__ int lslot[kMaxLevels][4 + ND];
+    const int tid = (int)threadIdx.x;
     const bool top_first = first_top != 0;
-    if ((int)threadIdx.x < nlev - from) {
-        const int l = from + (int)threadIdx.x;
+    const LevelT<R> gB = Ld[from];
+    const bool big = gB.N > kCoarseMaxLevelCells;
+    const int lf = big ? from + 1 : from;  // first level held in LDS
+    if (tid < nlev - lf) {
+        const int l = lf + tid;
         const LevelT<R> gL = Ld[l];
         int k = 0;
         auto add = [&](const R* p, int slot) {
@@ -517,10 +671,26 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         nload[l] = k;
         lN[l] = (int)gL.N;
     }
+    // the larger first level: couplings, b and divisor of each thread's cells
+    BigCell<R, ND> bk[2][kCoarseBigPer / 2];
+    if (big) {
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+            for (int m = 0; m < kCoarseBigPer / 2; ++m) {
+                const int e = tid + kCoarseThreads * m;
+                bk[col][m].c = -1;
+                if (e < gB.N / 2) {
+                    bk[col][m] = big_cell<R, ND, UNIT>(G, gB, colour_cell(gB.n, col, e));
+                    const int c = bk[col][m].c;
+                    bigx[c] = top_first ? (R)0.0 : gB.x[c];
+                }
+            }
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         int off = 0, el = 0;
-        for (int l = from; l < nlev; ++l) {
+        for (int l = lf; l < nlev; ++l) {
             base[l] = off;
             off += (4 + ND) * lN[l];
             first_el[l] = el;
@@ -532,7 +702,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     {
         constexpr int U = 4;  // loads in flight per thread
         const int total = first_el[nlev];
-        for (int e0 = (int)threadIdx.x; e0 < total; e0 += U * kCoarseThreads) {
+        for (int e0 = tid; e0 < total; e0 += U * kCoarseThreads) {
             R v[U];
             int dst[U];
 #pragma unroll
@@ -541,7 +711,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
                 dst[u] = -1;
                 v[u] = (R)0.0;
                 if (e < total) {
-                    int l = from;
+                    int l = lf;
                     while (e >= first_el[l + 1]) ++l;
                     const int n = lN[l], r = e - first_el[l], k = r / n, c = r - k * n;
                     v[u] = lsrc[l][k][c];
@@ -554,41 +724,57 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         }
     }
     __syncthreads();
-    for (int l = from; l < nlev - 1; ++l) {
-        const bool first = l == from ? top_first : true;
+    if (big) {
+        // pre-smoothing, residual and restriction onto the first LDS level
+        big_smooth<R, ND, UNIT>(G, gB, bigx, bk, (light > 0 && gB.N <= light) ? 1 : nu1, top_first);
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+            for (int m = 0; m < kCoarseBigPer / 2; ++m)
+                if (bk[col][m].c >= 0) rbuf[bk[col][m].c] = big_resid<R, ND, UNIT>(G, gB, bk[col][m], bigx);
+        __syncthreads();
+        lds_restrict_sum<R, ND>(gB, lds_level<R, ND>(Ld[lf], sm, base[lf]), rbuf);
+        __syncthreads();
+    }
+    // the LDS levels: x of the first one starts at 0 below a larger level
+    const bool lds_first = big ? true : top_first;
+    for (int l = lf; l < nlev - 1; ++l) {
+        const bool first = l == lf ? lds_first : true;
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
         lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
-        // restriction: every fine residual once, then the children's sums in
-        // the order of the multi-block restriction
-        for (int c = threadIdx.x; c < L.N; c += blockDim.x) rbuf[c] = resid_cell_t<R, ND, UNIT>(G, L, L.b, L.x, lcoords(L, c), c);
+        lds_resid<R, ND, UNIT>(G, L, rbuf, tid, kCoarseThreads);
         __syncthreads();
-        for (int c = threadIdx.x; c < C.N; c += blockDim.x) {
-            const LIjk q = lcoords(C, c);
-            const int kk = ND > 2 ? 2 : 1;
-            R sum = 0.0;
-            for (int dk = 0; dk < kk; ++dk)
-                for (int dj = 0; dj < 2; ++dj)
-                    for (int di = 0; di < 2; ++di)
-                        sum = sum + rbuf[lflat(L, 2 * q.v[0] + di, 2 * q.v[1] + dj, ND > 2 ? 2 * q.v[2] + dk : q.v[2])];
-            C.b[c] = sum * (R)(1.0 / (1 << ND));
-        }
+        lds_restrict_sum<R, ND>(L, C, rbuf);
         __syncthreads();
     }
     {
         const LevelT<R> L = lds_level<R, ND>(Ld[nlev - 1], sm, base[nlev - 1]);
-        lds_smooth<R, ND, UNIT>(G, L, nuc, nlev - 1 == from ? top_first : true);
+        lds_smooth<R, ND, UNIT>(G, L, nuc, nlev - 1 == lf ? lds_first : true);
     }
-    for (int l = nlev - 2; l >= from; --l) {
+    for (int l = nlev - 2; l >= lf; --l) {
         const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
         const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
-        for (int c = threadIdx.x; c < L.N; c += blockDim.x) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
+        for (int c = tid; c < L.N; c += kCoarseThreads) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
         lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu2, false);
     }
-    const LevelT<R> gT = Ld[from];
-    const LevelT<R> T = lds_level<R, ND>(gT, sm, base[from]);
-    for (int c = threadIdx.x; c < T.N; c += blockDim.x) gT.x[c] = T.x[c];
+    if (big) {
+        const LevelT<R> C = lds_level<R, ND>(Ld[lf], sm, base[lf]);
+#pragma unroll
+        for (int col = 0; col < 2; ++col)
+#pragma unroll
+            for (int m = 0; m < kCoarseBigPer / 2; ++m) {
+                const int c = bk[col][m].c;
+                if (c >= 0) bigx[c] = bigx[c] + prolong_cell<R, ND>(G, C, C.x, unpack_ijk(bk[col][m].pq));
+            }
+        __syncthreads();
+        big_smooth<R, ND, UNIT>(G, gB, bigx, bk, (light > 0 && gB.N <= light) ? 1 : nu2, false);
+        for (int c = tid; c < gB.N; c += kCoarseThreads) gB.x[c] = bigx[c];
+    } else {
+        const LevelT<R> T = lds_level<R, ND>(gB, sm, base[from]);
+        for (int c = tid; c < T.N; c += kCoarseThreads) gB.x[c] = T.x[c];
+    }
 }
 
 // light: levels (not the coarsest) of at most this many cells take one pre-

@@ -1188,7 +1188,10 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     p->nlev = count_levels(G, nl);
     // the coarse kernel takes the deepest levels whose cells fit in its LDS
     // (none if the coarsest level alone does not: that level is then smoothed
-    // by multi-block sweeps)
+    // by multi-block sweeps), and above them one level of more than
+    // kCoarseCells and at most kCoarseBigCells cells, every axis shorter than
+    // 1024 (not the coarsest, so every axis it has is even); the kernel tells
+    // that level from the LDS levels by its size
     p->coarse_from = p->nlev;
     {
         long tail = 0;
@@ -1197,6 +1200,11 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
             if (tail > kCoarseLdsCells || (long)nl[l][0] * nl[l][1] * nl[l][2] > kCoarseCells) break;
             p->coarse_from = l;
         }
+        const int l = p->coarse_from - 1;
+        const long nc = l >= 0 ? (long)nl[l][0] * nl[l][1] * nl[l][2] : 0;
+        if (p->coarse_from < p->nlev && l >= 0 && nc > kCoarseCells && nc <= kCoarseBigCells && nl[l][0] < 1024 &&
+            nl[l][1] < 1024 && nl[l][2] < 1024)
+            p->coarse_from = l;
     }
     p->ncell_blk = cell_blocks(G.n);
     p->nred = std::min(kRedBlocks, grid_blocks(G.nvec));
