@@ -150,8 +150,10 @@ void launch_widen(const T* v, double* out, long n, hipStream_t stream);
 // in precision R (FP64, or FP32 in the mixed form).
 constexpr int kMaxLevels = 16;
 // x and b of the levels solved by the single-workgroup coarse kernel live in
-// LDS: at most this many cells over those levels
-constexpr int kCoarseLdsCells = 704;
+// LDS: at most this many cells over those levels, and at most
+// kCoarseMaxLevelCells (one per thread) in each
+constexpr int kCoarseLdsCells = 1408;
+constexpr int kCoarseMaxLevelCells = 1024;
 // above those levels the coarse kernel may take one more level of at most
 // this many cells (its x in LDS, its coefficients in registers)
 constexpr int kCoarseBigCells = 4096;

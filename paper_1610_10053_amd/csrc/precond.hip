@@ -422,7 +422,6 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
 // right-hand side and divisor in registers.  Level descriptors come from
 // device memory (Ld) so that the level loop may index them at run time.
 constexpr int kCoarseThreads = 1024;
-constexpr int kCoarseMaxLevelCells = 512;  // largest level whose arrays the workgroup keeps in LDS
 constexpr int kCoarseBigPer = kCoarseBigCells / kCoarseThreads;  // cells per thread on the larger first level
 
 // A cell of a level in the single-workgroup solve: its colour, neighbour

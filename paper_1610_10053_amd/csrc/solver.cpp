@@ -294,8 +294,6 @@ int count_levels(const Grid& G, int n_out[][3]) {
     return L;
 }
 
-constexpr long kCoarseCells = 512;  // levels at or below this size run in one workgroup from LDS
-                                     // (kCoarseMaxLevelCells of the coarse kernel)
 
 // entries of a level's x, b and x2 arrays: room for the colour-split order
 // (x-pairs merged, one slot per colour), which holds every natural index too
@@ -1189,21 +1187,21 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     // the coarse kernel takes the deepest levels whose cells fit in its LDS
     // (none if the coarsest level alone does not: that level is then smoothed
     // by multi-block sweeps), and above them one level of more than
-    // kCoarseCells and at most kCoarseBigCells cells, every axis shorter than
-    // 1024 (not the coarsest, so every axis it has is even); the kernel tells
-    // that level from the LDS levels by its size
+    // kCoarseMaxLevelCells and at most kCoarseBigCells cells, every axis
+    // shorter than 1024 (not the coarsest, so every axis it has is even); the
+    // kernel tells that level from the LDS levels by its size
     p->coarse_from = p->nlev;
     {
         long tail = 0;
         for (int l = p->nlev - 1; l >= 0; --l) {
             tail += (long)nl[l][0] * nl[l][1] * nl[l][2];
-            if (tail > kCoarseLdsCells || (long)nl[l][0] * nl[l][1] * nl[l][2] > kCoarseCells) break;
+            if (tail > kCoarseLdsCells || (long)nl[l][0] * nl[l][1] * nl[l][2] > kCoarseMaxLevelCells) break;
             p->coarse_from = l;
         }
         const int l = p->coarse_from - 1;
         const long nc = l >= 0 ? (long)nl[l][0] * nl[l][1] * nl[l][2] : 0;
-        if (p->coarse_from < p->nlev && l >= 0 && nc > kCoarseCells && nc <= kCoarseBigCells && nl[l][0] < 1024 &&
-            nl[l][1] < 1024 && nl[l][2] < 1024)
+        if (p->coarse_from < p->nlev && l >= 0 && nc > kCoarseMaxLevelCells && nc <= kCoarseBigCells &&
+            nl[l][0] < 1024 && nl[l][1] < 1024 && nl[l][2] < 1024)
             p->coarse_from = l;
     }
     p->ncell_blk = cell_blocks(G.n);
