@@ -425,13 +425,12 @@ constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseBigPer = kCoarseBigCells / kCoarseThreads;  // cells per thread on the larger first level
 
 // A cell of a level in the single-workgroup solve: its colour, neighbour
-// indices (-1 beyond a wall), couplings, right-hand side, sigma and divisor,
-// found once per call.  The update and the residual are gs_value's and
-// resid_cell_t's, operation for operation.
+// indices (-1 beyond a wall), couplings, right-hand side and divisor, found
+// once per call.  The update is gs_value's, operation for operation.
 template <typename R, int ND>
 struct CoarseCell {
     int up[ND], dn[ND], colour;
-    R alo[ND], ahi[ND], bc, sig, dv;
+    R alo[ND], ahi[ND], bc, dv;
 };
 template <typename R, int ND, bool UNIT>
 __device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const LevelT<R>& L, const R* b, int c) {
@@ -449,7 +448,6 @@ __device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const Le
         den = den + k.ahi[d];
     }
     k.bc = b[c];
-    k.sig = UNIT ? (R)1.0 : L.sig[c];
     k.dv = UNIT ? den : L.D[c];
     return k;
 }
