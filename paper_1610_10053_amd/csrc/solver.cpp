@@ -547,7 +547,14 @@ void mg_solve(jfnk_problem* p, int which) {
             return;
         }
     }
-    (void)hipGraphLaunch(ge, p->stream);
+    if (hipGraphLaunch(ge, p->stream) != hipSuccess) {
+        // nothing was queued: the launches go one by one from now on
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+        p->use_graphs = false;
+        mg_launches<R>(p, which);
+    }
 }
 
 // z = S^-1 P^-1 S v, and the Jacobian-free step for the next product along z;
