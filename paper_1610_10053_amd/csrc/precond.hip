@@ -55,13 +55,29 @@ void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef&
 struct LIjk {
     int v[3];
 };
+// a / b (and the remainder) for 0 <= a < 2^20 and b >= 1: a float estimate
+// (off by at most one at these sizes) corrected once, in a few instructions
+// instead of an integer division's few dozen
+__device__ __forceinline__ int small_div(int a, int b, int& rem) {
+    int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+    int r = a - q * b;
+    if (r < 0) {
+        --q;
+        r += b;
+    } else if (r >= b) {
+        ++q;
+        r -= b;
+    }
+    rem = r;
+    return q;
+}
+// coordinates of cell c of a level (the single-workgroup solve's levels, far
+// below 2^20 cells)
 template <typename R>
 __device__ __forceinline__ LIjk lcoords(const LevelT<R>& L, int c) {
     LIjk r;
-    r.v[0] = c % L.n[0];
-    const int t = c / L.n[0];
-    r.v[1] = t % L.n[1];
-    r.v[2] = t / L.n[1];
+    const int t = small_div(c, L.n[0], r.v[0]);
+    r.v[2] = small_div(t, L.n[1], r.v[1]);
     return r;
 }
 template <typename R>
@@ -433,9 +449,9 @@ struct CoarseCell {
     R alo[ND], ahi[ND], bc, dv;
 };
 template <typename R, int ND, bool UNIT>
-__device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const LevelT<R>& L, const R* b, int c) {
+__device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const LevelT<R>& L, const R* b, int c,
+                                                        const LIjk& q) {
     CoarseCell<R, ND> k;
-    const LIjk q = lcoords(L, c);
     k.colour = (q.v[0] + q.v[1] + q.v[2]) & 1;
     R den = (R)1.0;
 #pragma unroll
@@ -450,6 +466,10 @@ __device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const Le
     k.bc = b[c];
     k.dv = UNIT ? den : L.D[c];
     return k;
+}
+template <typename R, int ND, bool UNIT>
+__device__ __forceinline__ CoarseCell<R, ND> coarse_cell(const Grid& G, const LevelT<R>& L, const R* b, int c) {
+    return coarse_cell<R, ND, UNIT>(G, L, b, c, lcoords(L, c));
 }
 // Gauss-Seidel value of the cell from x (f: first sweep, x taken as 0)
 template <typename R, int ND>
@@ -510,18 +530,17 @@ __device__ __forceinline__ LIjk unpack_ijk(int pq) {
 }
 // the e-th cell of colour col on a level with even axes: its coordinates
 __device__ __forceinline__ LIjk colour_cell(const int n[3], int col, int e) {
-    const int hn0 = n[0] / 2;
-    const int row = e / hn0;
+    int h;
+    const int row = small_div(e, n[0] / 2, h);
     LIjk q;
-    q.v[1] = row % n[1];
-    q.v[2] = row / n[1];
-    q.v[0] = 2 * (e - row * hn0) + ((q.v[1] + q.v[2] + col) & 1);
+    q.v[2] = small_div(row, n[1], q.v[1]);
+    q.v[0] = 2 * h + ((q.v[1] + q.v[2] + col) & 1);
     return q;
 }
 template <typename R, int ND, bool UNIT>
 __device__ __forceinline__ BigCell<R, ND> big_cell(const Grid& G, const LevelT<R>& L, const LIjk& q) {
     const int c = lflat(L, q.v[0], q.v[1], q.v[2]);
-    const CoarseCell<R, ND> k = coarse_cell<R, ND, UNIT>(G, L, L.b, c);
+    const CoarseCell<R, ND> k = coarse_cell<R, ND, UNIT>(G, L, L.b, c, q);
     BigCell<R, ND> b;
 #pragma unroll
     for (int d = 0; d < ND; ++d) {
