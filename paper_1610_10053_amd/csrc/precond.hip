@@ -615,11 +615,18 @@ __device__ __forceinline__ void big_smooth(const Grid& G, const LevelT<R>& L, R*
         }
 }
 // LDS view of level l: its arrays at sm + base (sig, a[0..ND-1], D, x, b),
-// built in registers so that every access is a direct LDS access
+// built in registers so that every access is a direct LDS access, from the
+// dimensions kept in LDS (ldim: n[0..2], N of each level) read as
+// wavefront-uniform values, so that after the kernel's first load no level
+// loop waits on a descriptor in device memory.  Only the fields the
+// single-workgroup solve uses are set (its levels are in natural order).
 template <typename R, int ND>
-__device__ __forceinline__ LevelT<R> lds_level(const LevelT<R>& g, R* sm, int base) {
-    LevelT<R> L = g;
-    const int n = (int)g.N;
+__device__ __forceinline__ LevelT<R> lds_view(const int (*ldim)[4], int l, R* sm, int base) {
+    LevelT<R> L{};
+    for (int a = 0; a < 3; ++a) L.n[a] = __builtin_amdgcn_readfirstlane(ldim[l][a]);
+    const int n = __builtin_amdgcn_readfirstlane(ldim[l][3]);
+    L.N = n;
+    base = __builtin_amdgcn_readfirstlane(base);
     L.sig = sm + base;
     for (int d = 0; d < 3; ++d) L.a[d] = d < ND ? sm + base + (1 + d) * n : nullptr;
     L.D = sm + base + (1 + ND) * n;
@@ -663,6 +670,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
     __shared__ int lN[kMaxLevels], nload[kMaxLevels], first_el[kMaxLevels + 1];
     __shared__ const R* lsrc[kMaxLevels][4 + ND];
     __shared__ int lslot[kMaxLevels][4 + ND];
+    __shared__ int ldim[kMaxLevels][4];
     const int tid = (int)threadIdx.x;
     const bool top_first = first_top != 0;
     const LevelT<R> gB = Ld[from];
@@ -686,6 +694,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         }
         nload[l] = k;
         lN[l] = (int)gL.N;
+        for (int a = 0; a < 3; ++a) ldim[l][a] = gL.n[a];
+        ldim[l][3] = (int)gL.N;
     }
     // the larger first level: couplings, b and divisor of each thread's cells
     BigCell<R, ND> bk[2][kCoarseBigPer / 2];
@@ -749,15 +759,15 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
             for (int m = 0; m < kCoarseBigPer / 2; ++m)
                 if (bk[col][m].c >= 0) rbuf[bk[col][m].c] = big_resid<R, ND, UNIT>(G, gB, bk[col][m], bigx);
         __syncthreads();
-        lds_restrict_sum<R, ND>(gB, lds_level<R, ND>(Ld[lf], sm, base[lf]), rbuf);
+        lds_restrict_sum<R, ND>(gB, lds_view<R, ND>(ldim, lf, sm, base[lf]), rbuf);
         __syncthreads();
     }
     // the LDS levels: x of the first one starts at 0 below a larger level
     const bool lds_first = big ? true : top_first;
     for (int l = lf; l < nlev - 1; ++l) {
         const bool first = l == lf ? lds_first : true;
-        const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
-        const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
+        const LevelT<R> L = lds_view<R, ND>(ldim, l, sm, base[l]);
+        const LevelT<R> C = lds_view<R, ND>(ldim, l + 1, sm, base[l + 1]);
         lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu1, first);
         lds_resid<R, ND, UNIT>(G, L, rbuf, tid, kCoarseThreads);
         __syncthreads();
@@ -765,18 +775,18 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         __syncthreads();
     }
     {
-        const LevelT<R> L = lds_level<R, ND>(Ld[nlev - 1], sm, base[nlev - 1]);
+        const LevelT<R> L = lds_view<R, ND>(ldim, nlev - 1, sm, base[nlev - 1]);
         lds_smooth<R, ND, UNIT>(G, L, nuc, nlev - 1 == lf ? lds_first : true);
     }
     for (int l = nlev - 2; l >= lf; --l) {
-        const LevelT<R> L = lds_level<R, ND>(Ld[l], sm, base[l]);
-        const LevelT<R> C = lds_level<R, ND>(Ld[l + 1], sm, base[l + 1]);
+        const LevelT<R> L = lds_view<R, ND>(ldim, l, sm, base[l]);
+        const LevelT<R> C = lds_view<R, ND>(ldim, l + 1, sm, base[l + 1]);
         for (int c = tid; c < L.N; c += kCoarseThreads) L.x[c] = L.x[c] + prolong_cell<R, ND>(G, C, C.x, lcoords(L, c));
         __syncthreads();
         lds_smooth<R, ND, UNIT>(G, L, (light > 0 && L.N <= light) ? 1 : nu2, false);
     }
     if (big) {
-        const LevelT<R> C = lds_level<R, ND>(Ld[lf], sm, base[lf]);
+        const LevelT<R> C = lds_view<R, ND>(ldim, lf, sm, base[lf]);
 #pragma unroll
         for (int col = 0; col < 2; ++col)
 #pragma unroll
@@ -788,7 +798,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
         big_smooth<R, ND, UNIT>(G, gB, bigx, bk, (light > 0 && gB.N <= light) ? 1 : nu2, false);
         for (int c = tid; c < gB.N; c += kCoarseThreads) gB.x[c] = bigx[c];
     } else {
-        const LevelT<R> T = lds_level<R, ND>(gB, sm, base[from]);
+        const LevelT<R> T = lds_view<R, ND>(ldim, from, sm, base[from]);
         for (int c = tid; c < T.N; c += kCoarseThreads) gB.x[c] = T.x[c];
     }
 }
