@@ -152,13 +152,14 @@ def test_preconditioner_bitwise(torch_cuda, name, n, solver):
 
 
 @pytest.mark.parametrize("name,n", [("kh", 66), ("rad", 68), ("kh", 54), ("kh", 108), ("rad", 60), ("kh", 40),
-                                    ("tg", 24), ("rt", 20)])
+                                    ("tg", 24), ("rt", 20), ("kh", 48), ("rt", 24)])
 def test_odd_and_large_coarsest_level_parity(torch_cuda, name, n):
     """Coarsest multigrid levels with an odd periodic axis, too large for the
     single-workgroup solve (33x33, 17x68: multi-block sweeps between two
     buffers) or inside it (27x27, 15x60, 5x5, 3x3x3, 5x10: two-phase sweeps in
-    LDS, below a larger first level of the workgroup's for 54x54, 30x120 and
-    12^3); preconditioner bitwise, Newton step to 1e-10."""
+    LDS, below a larger first level of the workgroup's for 54x54, 30x120,
+    12^3, 48x48 and 24x48, the last two with 3x3 and 3x6 coarsest levels);
+    preconditioner bitwise, Newton step to 1e-10."""
     desc, opts, u, g, o = _pair(name, n)
     dt = o.time_step(u)["dt"]
     g.eval_time_step(u)
