@@ -173,7 +173,7 @@ def test_odd_and_large_coarsest_level_parity(torch_cuda, name, n):
 
 # ---------------------------------------------------------------- Newton steps
 
-@pytest.mark.parametrize("name,n", CASES + [("rad_perturbed", 16), ("rad_perturbed", 32)])
+@pytest.mark.parametrize("name,n", CASES + FULL + [("rad_perturbed", 16), ("rad_perturbed", 32)])
 def test_newton_solve_parity(torch_cuda, name, n):
     if name == "rad_perturbed":
         from oracle import Oracle
