@@ -505,6 +505,33 @@ def test_tg128_components_against_oracle(torch_cuda):
     assert np.array_equal(g.apply_jv_eps(u, b, dt, v, 1.3e-8), o.jv_eps(u, b, dt, v, 1.3e-8))
 
 
+def test_tg128_newton_step_parity(torch_cuda):
+    """The benchmark's workload itself: one Newton solve of Taylor-Green
+    128^3 at the CFL time step from t = 0, on the GPU and in the oracle (its
+    OpenMP build, bit for bit the serial one), with identical Newton and
+    GMRES counts and the states within 1e-10 overall and per field."""
+    from oracle import Oracle
+    jfnk = _lib()
+    desc, opts, u = make_config("tg")
+    print("case tg 128^3 newton step", flush=True)
+    g, o = jfnk.Problem(desc, opts, u), Oracle(desc, opts, u, threaded=True)
+    ts = o.time_step(u)
+    dt = ts["dt"]
+    rg, sg = g.newton_solve(dt)
+    ro, so = o.newton_solve(dt)
+    print("gpu", sg["newton_its"], sg["gmres_its"], "oracle", so["newton_its"], so["gmres_its"], flush=True)
+    assert rg == 0 and ro == 0
+    assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+    assert sg["newton_exit"] == so["newton_exit"]
+    ug, uo = g.get_state(), o.get_state()
+    assert rel_l2(ug, uo) <= 1e-10
+    fr = _fields_rel(ug, uo, desc, ts["scales"])
+    print("per-field", {k: "%.2e" % e for k, e in fr.items()}, flush=True)
+    for k, e in fr.items():
+        assert e <= 1e-10, (k, e)
+    g.close()
+
+
 @pytest.mark.parametrize("prec,form", [(0, 0), (1, 0), (0, 1)])
 def test_tg128_step_converges_by_oracle_residual(torch_cuda, prec, form):
     """One full-size step (FP64 and mixed, total-energy form; FP64 in the
