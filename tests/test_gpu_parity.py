@@ -592,6 +592,39 @@ def test_tg128_step_converges_by_oracle_residual(torch_cuda, prec, form):
         assert abs(exact_sum(a1) - exact_sum(a0)) <= 1e-13 * np.abs(a0).sum()
 
 
+def test_tg256_step_converges_by_oracle_residual(torch_cuda):
+    """Eight times the benchmark's cells (256^3, 84 million unknowns, 56 GB of
+    device memory): one FP64 step, the oracle confirms the Newton tolerance
+    on the GPU's new state by its own residual, and mass and total energy
+    are unchanged."""
+    from oracle import Oracle
+    jfnk = _lib()
+    desc, opts, u = make_config("tg", n=256)
+    print("case tg 256^3 step", flush=True)
+    g = jfnk.Problem(desc, opts, u)
+    rc, st = g.implicit_step()
+    print("newton", st["newton_its"], "gmres", st["gmres_its"], "rel_res", st["rel_res"], flush=True)
+    assert rc == 0 and st["newton_exit"] == 0
+    unew = g.get_state()
+    g.close()
+    o = Oracle(desc, opts, u)
+    S = o.time_step(u)["scales"]
+    b = o.cn_old(u, st["dt"])
+    F0 = o.residual(u, b, st["dt"])
+    F1 = o.residual(unew, b, st["dt"])
+    N = 256 ** 3
+
+    def snorm(F):
+        return np.sqrt(sum(np.sum((F[f * N:(f + 1) * N] / S[f]) ** 2) for f in range(5)))
+    f0, f1 = snorm(F0), snorm(F1)
+    print("oracle f1/f0", f1 / f0, flush=True)
+    assert abs(st["rel_res"] - f1 / f0) <= 1e-6 * (f1 / f0) + 1e-15
+    assert f1 <= 1.05e-8 * f0
+    for k in ("rho", "E"):
+        a0, a1 = split_state(u, desc)[k], split_state(unew, desc)[k]
+        assert abs(exact_sum(a1) - exact_sum(a0)) <= 1e-13 * np.abs(a0).sum()
+
+
 # ---------------------------------------------------------------- multigrid replayed as a HIP graph
 
 @pytest.mark.parametrize("name,n,prec", [("rt", None, 0), ("kh", 64, 0), ("rad", 32, 0), ("tg", 16, 0),
