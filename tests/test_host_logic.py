@@ -1,6 +1,9 @@
 """Host logic of the serving runtime, built with g++ and run on the CPU: the
 first-fit range allocator over the device arena (against a brute-force model
-of the free ranges) and the admission choice with its starvation bound."""
+of the free ranges) and the admission choice with its starvation bound.  The
+driver is built with AddressSanitizer and UndefinedBehaviorSanitizer where
+the compiler provides them, so that an out-of-range access or undefined
+arithmetic in the allocator fails the run."""
 import os
 import random
 import shutil
@@ -17,8 +20,11 @@ def driver(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("adm") / "admission_driver")
-    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-I", CSRC,
-                    os.path.join(HERE, "cpp", "admission_driver.cpp"), "-o", exe], check=True)
+    base = ["g++", "-std=c++17", "-O1", "-g", "-Wall", "-Werror", "-I", CSRC,
+            os.path.join(HERE, "cpp", "admission_driver.cpp"), "-o", exe]
+    san = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer"]
+    if subprocess.run(base + san, capture_output=True).returncode != 0:
+        subprocess.run(base, check=True)  # no sanitizer runtime: a plain build
     return exe
 
 
