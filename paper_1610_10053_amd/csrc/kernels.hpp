@@ -132,6 +132,9 @@ int launch_update_mdot(const T* V, long ld, int k, const double* h, double* w, l
                        bool want_dots, hipStream_t stream);
 template <typename T>
 void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t stream);
+// v = w / sqrt(hnsq[0]), hnsq in device memory
+template <typename T>
+void launch_store_scaled_dev(const double* w, T* v, const double* hnsq, long n, hipStream_t stream);
 template <typename T>
 void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, bool acc, hipStream_t stream);
 void launch_add(double* x, const double* z, long n, hipStream_t stream);

@@ -251,6 +251,22 @@ void launch_store_scaled(const double* w, T* v, double hn, long n, hipStream_t s
     JFNK_KLAUNCH((k_store_scaled<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hn, n);
 }
 
+// the same store with hn = sqrt(|w|^2) formed on the device from the sum
+// the last CGS2 pass left there (the value the host forms from it)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_store_scaled_dev(const double* __restrict__ w, T* __restrict__ v,
+                                                             const double* __restrict__ hnsq, long n) {
+    const double hn = sqrt(hnsq[0]);
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        v[e] = (T)(w[e] / hn);
+}
+template <typename T>
+void launch_store_scaled_dev(const double* w, T* v, const double* hnsq, long n, hipStream_t stream) {
+    JFNK_PROFB(KC_STORE, stream, (double)n * (8 + sizeof(T)));
+    JFNK_KLAUNCH((k_store_scaled_dev<T>), dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, w, v, hnsq,
+                 n);
+}
+
 template <typename T>
 void launch_combine(const T* V, long ld, int k, const double* y, double* t, long n, bool acc, hipStream_t stream) {
     const int nb = grid_blocks(n, kBlock * 4);
@@ -383,6 +399,8 @@ template int launch_update_mdot<float>(const float*, long, int, const double*, d
                                        hipStream_t);
 template void launch_store_scaled<double>(const double*, double*, double, long, hipStream_t);
 template void launch_store_scaled<float>(const double*, float*, double, long, hipStream_t);
+template void launch_store_scaled_dev<double>(const double*, double*, const double*, long, hipStream_t);
+template void launch_store_scaled_dev<float>(const double*, float*, const double*, long, hipStream_t);
 template void launch_combine<double>(const double*, long, int, const double*, double*, long, bool, hipStream_t);
 template void launch_combine<float>(const float*, long, int, const double*, double*, long, bool, hipStream_t);
 

@@ -108,9 +108,13 @@ struct jfnk_problem {
     // a HIP graph on the problem's stream (captured at its first use)
     hipGraphExec_t mg_exec[2] = {nullptr, nullptr};
     bool use_graphs = true;
+    // marks the end of a GMRES step's scalar read-back, so that the host can
+    // wait for it while later work already runs on the stream
+    hipEvent_t rb_event = nullptr;
     ~jfnk_problem() {
         for (auto& g : mg_exec)
             if (g) (void)hipGraphExecDestroy(g);
+        if (rb_event) (void)hipEventDestroy(rb_event);
         if (hpin && own_hpin) (void)hipHostFree(hpin);
     }
 };
@@ -342,6 +346,22 @@ int read_scalars(jfnk_problem* p, int off, int count, double* out) {
     HIPCHK(hipStreamSynchronize(p->stream));
     std::memcpy(out, p->hpin, sizeof(double) * count);
     if (g_prof) g_prof->drain();
+    return 0;
+}
+
+// read-back of scalars with more work queued behind it: the copy, an event,
+// then `after` (launches), and a wait for the event only, so that the device
+// runs the queued work while the host takes the scalars
+// vectors at least this long store the next basis vector during the read-back
+constexpr long kOverlapStoreMin = 65536;
+template <class After>
+int read_scalars_then(jfnk_problem* p, int off, int count, double* out, After after) {
+    HIPCHK(hipMemcpyAsync(p->hpin, p->dsum + off, sizeof(double) * count, hipMemcpyDeviceToHost, p->stream));
+    HIPCHK(hipEventRecord(p->rb_event, p->stream));
+    after();
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(p->rb_event));
+    std::memcpy(out, p->hpin, sizeof(double) * count);
     return 0;
 }
 
@@ -649,7 +669,8 @@ struct GmresInfo {
 // ---------------------------------------------------------------- GMRES(m), right preconditioned, CGS2
 // Restarted GMRES on vectors of n doubles: basis V (T), classical
 // Gram-Schmidt applied twice on the device, Givens rotations and the
-// triangular solve on the host (one read-back per iteration).
+// triangular solve on the host (one read-back per iteration, during which
+// the device already stores the next basis vector).
 //   norm(v, &out): the 2-norm of v (synchronises);
 //   pc(j, v, z):   z_j = M^-1 v_j into Zb column j (not called when Zb is null:
 //                  no preconditioner, the basis vectors themselves are used);
@@ -707,7 +728,18 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
             nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, w, n, p->part, false, p->stream);
             launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream);
             HIPCHK(hipGetLastError());
-            CK(read_scalars(p, 0, D_HN + 1, hb.data()));
+            // on long vectors the next basis vector is stored (from |w|^2 on
+            // the device, the same bits as the host's division) while the
+            // host takes the scalars; a step that ends the cycle never reads
+            // it.  On short ones the store is too brief to hide the wait and
+            // follows the read-back.
+            T* vnext = V + (long)(j + 1) * n;
+            const bool overlap = n >= kOverlapStoreMin;
+            if (overlap)
+                CK(read_scalars_then(p, 0, D_HN + 1, hb.data(),
+                                     [&] { launch_store_scaled_dev<T>(w, vnext, p->dsum + D_HN, n, p->stream); }));
+            else
+                CK(read_scalars(p, 0, D_HN + 1, hb.data()));
             const double w0 = std::sqrt(hb[D_H1 + j + 1]);
             const double hn = std::sqrt(hb[D_HN]);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[D_H1 + i] + hb[D_H2 + i];
@@ -732,7 +764,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
                 conv = true;
                 break;
             }
-            launch_store_scaled<T>(w, V + (long)(j + 1) * n, hn, n, p->stream);
+            if (!overlap) launch_store_scaled<T>(w, vnext, hn, n, p->stream);
             if (info->res <= eta * beta0) {
                 conv = true;
                 break;
@@ -1324,6 +1356,8 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         if (e != hipSuccess) return cleanup(fail(-2, "hipHostMalloc failed"));
         p->own_hpin = true;
     }
+    if (hipEventCreateWithFlags(&p->rb_event, hipEventDisableTiming) != hipSuccess)
+        return cleanup(fail(-3, "hipEventCreateWithFlags"));
     if (hipMemsetAsync(p->dsum, 0, sizeof(double) * kDsum, p->stream) != hipSuccess) return cleanup(fail(-3, "memset"));
     if ((rc = copy_in(p, p->u, u0, on_device))) return cleanup(rc);
     launch_zero_walls(p->u, G, p->stream);
