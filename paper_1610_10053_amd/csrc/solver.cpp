@@ -780,9 +780,11 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
         // x += M^-1 V y, formed from the preconditioned vectors already at hand
         if (Zb) launch_combine<T>(Zb, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
         else launch_combine<T>(V, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
+        // no wait here: the Newton update queues behind the correction, and
+        // the pinned slot that holds y is written again only after a later
+        // read-back has drained the stream
         if (conv) {
             info->converged = 1;
-            HIPCHK(hipStreamSynchronize(p->stream));
             break;
         }
         opx(x, t);
