@@ -678,16 +678,18 @@ struct GmresInfo {
 //   op(z, w):      w = A z for a preconditioned basis vector (precision T);
 //   opx(x, t):     t = A x for the restart residual.
 // x += M^-1 V y is formed from the kept preconditioned vectors.
+// rhs_norm >= 0: |rhs| as the caller already has it (no reduction and no
+// read-back before the first basis vector); < 0: formed here.
 template <typename T, class Norm, class Pc, class Op, class OpX>
 int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* x, double* r, double* w,
-               double* t, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info) {
+               double* t, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info, double rhs_norm = -1.0) {
     const int m = p->opts.gmres_restart;
     const double eta = p->opts.gmres_eta;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
     // x starts at 0: the first cycle's correction is written, later ones added;
     // the residual of the first cycle is the right-hand side itself
-    double beta0;
-    CK(norm(rhs, &beta0));
+    double beta0 = rhs_norm;
+    if (!(beta0 >= 0.0)) CK(norm(rhs, &beta0));
     info->its = 0;
     info->cycles = 0;
     info->converged = 0;
@@ -797,7 +799,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
 
 // the flow's linear system in scaled variables, with the physics-based preconditioner
 template <typename T>
-int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
+int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double rhs_norm) {
     const long n = p->G.nvec;
     auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
     auto pc = [&](int, const T* v, T* z) { pc_apply<T>(p, v, z); };
@@ -806,7 +808,8 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info) {
         eps_for(p, x);
         jv(p, u, p->Ru, dt, x, t);
     };
-    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, info);
+    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, info,
+                         rhs_norm);
 }
 
 // Newton-Raphson from u^n at dt; on failure the state is restored
@@ -836,7 +839,9 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         CK(pc_build(p, p->u, dt, true));  // P holds the primitives of u from the residual just evaluated
         set_usq(p, p->u);
         GmresInfo gi;
-        int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi) : gmres<double>(p, p->u, dt, &gi);
+        // the right-hand side -S^-1 F is the residual just measured: its norm
+        // is f (the same squares, summed by the residual sweep's blocks)
+        int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi, f) : gmres<double>(p, p->u, dt, &gi, f);
         if (rc) return rc;
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
