@@ -219,8 +219,10 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 // taken as 0)
 // FIRST, QF (couplings from the level's cell field) and UNIT (sigma == 1)
 // are compile-time so that a sweep's loads form one straight-line block
-template <typename R, int ND, bool FIRST, bool QF, bool UNIT>
-__device__ __forceinline__ R gs_value_t(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
+// XNB(n, d, side): the value of x at neighbour n, the lower (side 0) or
+// upper (side 1) one along d
+template <typename R, int ND, bool FIRST, bool QF, bool UNIT, class XNB>
+__device__ __forceinline__ R gs_value_nb(const Grid& G, const LevelT<R>& L, const R* b, XNB xnb, LIjk q, int c) {
     R num = b[xbq(L, q)];
     R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
@@ -239,13 +241,18 @@ __device__ __forceinline__ R gs_value_t(const Grid& G, const LevelT<R>& L, const
         }
         alo = hd ? alo : (R)0.0;
         ahi = hu ? ahi : (R)0.0;
-        const R xlo = FIRST ? (R)0.0 : x[xbq(L, qd)], xhi = FIRST ? (R)0.0 : x[xbq(L, qu)];
+        const R xlo = FIRST ? (R)0.0 : xnb(qd, d, 0), xhi = FIRST ? (R)0.0 : xnb(qu, d, 1);
         num = hd ? num + alo * xlo : num;
         num = hu ? num + ahi * xhi : num;
         den = den + alo;
         den = den + ahi;
     }
     return num / (UNIT ? den : L.D[c]);
+}
+template <typename R, int ND, bool FIRST, bool QF, bool UNIT>
+__device__ __forceinline__ R gs_value_t(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
+    return gs_value_nb<R, ND, FIRST, QF, UNIT>(G, L, b, [&](const LIjk& n, int, int) { return x[xbq(L, n)]; }, q,
+                                               c);
 }
 template <typename R, int ND, bool FIRST>
 __device__ __forceinline__ R gs_value_f(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
@@ -428,6 +435,110 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
     if (color < 0 ? !lcell(F, q, c) : !lcell_color(F, color, q, c)) return;
     const int e = xbq(F, q);
     F.x[e] = F.x[e] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
+}
+constexpr long kGsProlongMaxCells = 1L << 18;
+// Prolongation and the first post-smoothing half-sweep (colour 0) in one
+// launch: each colour-0 cell takes its neighbours' corrected values
+// x + prolong_cell (the sums k_prolong would store) as it goes.  The
+// half-sweep overwrites colour 0 without reading it, and nothing else reads
+// the corrected colour-1 values (the colour-1 half-sweep that follows
+// overwrites them without reading them), so no corrected value is stored and
+// the result is that of correcting every cell and sweeping.
+//
+// The six neighbours' prolongations share their coarse values.  Along each
+// axis the parents of the cell and of its two neighbours lie among three
+// coarse rows, h - 1, h and h + 1 (h = the cell's coordinate / 2; wrapped on
+// a periodic axis, and on a wall the parent h where prolong_cell reuses the
+// parent): the cell's own pair is (h, o) with o = h - 1 for an even
+// coordinate and h + 1 for an odd one, and t is the third row.  Of the two
+// neighbours along an axis one has the pair (o, h) and the other (h, t).  So
+// the values of the cell's own 2^ND parents (cube) and, per axis, of the
+// 2^(ND-1) cells one row further (row t, the other axes as in the cube) are
+// loaded once, and each neighbour's correction is summed from them with
+// prolong_cell's weights in its corner order.
+template <typename R, int ND, bool QF, bool UNIT>
+__global__ void __launch_bounds__(kBlock) k_gs_prolong(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    LIjk q;
+    int c;
+    if (!lcell_color(F, 0, q, c)) return;
+    int P[3], o[3], t[3];
+    bool even[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        even[d] = true;
+        P[d] = o[d] = t[d] = q.v[d];
+        if (d < ND) {
+            const int h = q.v[d] >> 1, n = Cl.n[d];
+            const bool wall = G.bc[d] == WALL;
+            int lo = h - 1, hi = h + 1;
+            lo = lo < 0 ? (wall ? h : lo + n) : lo;
+            hi = hi >= n ? (wall ? h : hi - n) : hi;
+            even[d] = (q.v[d] & 1) == 0;
+            P[d] = h;
+            o[d] = even[d] ? lo : hi;
+            t[d] = even[d] ? hi : lo;
+        }
+    }
+    constexpr int NC = 1 << ND, NE = 1 << (ND - 1);
+    R cube[NC], ext[ND][NE], w[NC];
+#pragma unroll
+    for (int m = 0; m < NC; ++m) {
+        int qq[3];
+        R wm = 1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const bool nb = d < ND && (m & (1 << d));
+            if (d < ND) wm = wm * (nb ? (R)0.25 : (R)0.75);
+            qq[d] = nb ? o[d] : P[d];
+        }
+        w[m] = wm;
+        cube[m] = Cl.x[xbi(Cl, qq[0], qq[1], qq[2])];
+    }
+#pragma unroll
+    for (int d = 0; d < ND; ++d)
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            int qq[3] = {P[0], P[1], P[2]};
+            int j = 0;
+#pragma unroll
+            for (int e = 0; e < ND; ++e) {
+                if (e == d) continue;
+                qq[e] = (k & (1 << j)) ? o[e] : P[e];
+                ++j;
+            }
+            qq[d] = t[d];
+            ext[d][k] = Cl.x[xbi(Cl, qq[0], qq[1], qq[2])];
+        }
+    // corrections of the neighbours along d: pair (o, h) reads the cube with
+    // bit d flipped, pair (h, t) reads row t where bit d is set
+    const auto xnb = [&](const LIjk& n, int d, int side) {
+        R ea = 0.0, eb = 0.0;
+#pragma unroll
+        for (int m = 0; m < NC; ++m) {
+            const int sq = ((m >> (d + 1)) << d) | (m & ((1 << d) - 1));
+            ea = ea + w[m] * cube[m ^ (1 << d)];
+            eb = eb + w[m] * ((m & (1 << d)) ? ext[d][sq] : cube[m]);
+        }
+        const bool pair_oh = even[d] == (side == 0);
+        return F.x[xbq(F, n)] + (pair_oh ? ea : eb);
+    };
+    F.x[xbq(F, q)] = gs_value_nb<R, ND, false, QF, UNIT>(G, F, F.b, xnb, q, c);
+}
+template <typename R, int ND, bool QF>
+void launch_gs_prolong_u(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, hipStream_t stream) {
+    const dim3 g = color_grid3(F.n), bl(kBx, kBy);
+    if (F.unit_sig) JFNK_KLAUNCH((k_gs_prolong<R, ND, QF, true>), g, bl, 0, stream, G, F, Cl);
+    else JFNK_KLAUNCH((k_gs_prolong<R, ND, QF, false>), g, bl, 0, stream, G, F, Cl);
+}
+template <typename R>
+void launch_gs_prolong(const Grid& G, const LevelT<R>& F, const LevelT<R>& Cl, hipStream_t stream) {
+    if (G.ndim == 3) {
+        if (F.qf) launch_gs_prolong_u<R, 3, true>(G, F, Cl, stream);
+        else launch_gs_prolong_u<R, 3, false>(G, F, Cl, stream);
+    } else {
+        if (F.qf) launch_gs_prolong_u<R, 2, true>(G, F, Cl, stream);
+        else launch_gs_prolong_u<R, 2, false>(G, F, Cl, stream);
+    }
 }
 
 // The rest of the V-cycle, levels from..nlev-1, in one workgroup.  Every
@@ -827,7 +938,7 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
     }
     const LevelT<R>& L = S.L[l];
     if (light > 0 && L.N <= light) nu1 = nu2 = 1;
-    const dim3 cg = color_grid3(L.n), bl(kBx, kBy);
+    const dim3 bl(kBx, kBy);
     // compulsory bytes of a half-sweep: the couplings of every face (ndim per
     // cell, or the one cell field they are formed from), b (and D without
     // unit sigma) and the other colour's x for half the cells, this colour's
@@ -895,15 +1006,24 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         }
     }
     vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, light, true, stream);
-    {
-        const bool half = nu2 > 0;
-        JFNK_PROFB(KC_MG_PROLONG, stream,
-                   (double)L.N * sizeof(R) * (half ? 1 : 2) + (double)S.L[l + 1].N * sizeof(R));
-        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, half ? cg : cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1],
-                        half ? 1 : -1);
+    // the prolongation goes into the first post-smoothing half-sweep on
+    // levels of at most kGsProlongMaxCells cells; on larger ones the fused
+    // sweep (about 80 VGPRs in FP64, 5 waves per SIMD) measured slower than
+    // the prolongation and the half-sweep as two launches
+    const bool fuse = nu2 > 0 && L.N <= kGsProlongMaxCells;
+    if (nu2 == 0) {
+        JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) * 2 + (double)S.L[l + 1].N * sizeof(R));
+        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1], -1);
+    } else if (!fuse) {
+        JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) + (double)S.L[l + 1].N * sizeof(R));
+        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, color_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1], 1);
     }
     for (int s = 0; s < nu2; ++s) {
-        {
+        if (s == 0 && fuse) {
+            // the correction read with the half-sweep: the coarse x once more
+            JFNK_PROFB(KC_MG_SMOOTH, stream, bs + (double)S.L[l + 1].N * sizeof(R));
+            launch_gs_prolong<R>(G, L, S.L[l + 1], stream);
+        } else {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
             launch_gs<R>(G, L, 0, 0, stream);
         }
