@@ -163,6 +163,39 @@ __global__ void __launch_bounds__(kBlock) k_combine(const T* __restrict__ V, lon
     }
 }
 
+// The final correction of a converged GMRES solve and the Newton update in
+// one pass: x = sum_i y_i V_i (plus the x of earlier cycles when acc),
+// u += S x and the block maxima of |S x / u| over the density entries,
+// each value formed as k_combine and k_update_state form it; x itself is
+// not stored (nothing reads it after the update).
+template <typename T, int K>
+__global__ void __launch_bounds__(kBlock) k_combine_update(const T* __restrict__ V, long ld,
+                                                           const double* __restrict__ y,
+                                                           const double* __restrict__ x, int acc,
+                                                           double* __restrict__ u, long N, long n, Scales5 sc,
+                                                           double* __restrict__ part) {
+    double yy[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) yy[i] = y[i];
+    double m = 0.0;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        double vv[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) vv[i] = (double)V[(long)i * ld + e];
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) s += yy[i] * vv[i];
+        const double xe = acc ? x[e] + s : s;
+        const double f = sc.v[e / N];
+        const double un = u[e] + f * xe;
+        u[e] = un;
+        if (e < N) m = fmax(m, fabs(f * xe / un));
+    }
+    __shared__ double sh[kBlock / 64];
+    const double t = block_max(m, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // blocks that fill the device once for a kernel (grid-stride loops take the
 // rest), capped by the partial-sum capacity
 template <typename Kern>
@@ -275,6 +308,26 @@ void launch_combine(const T* V, long ld, int k, const double* y, double* t, long
 #define C(K)                                                                                        \
     case K:                                                                                         \
         JFNK_KLAUNCH((k_combine<T, K>), dim3(nb), dim3(kBlock), 0, stream, V, ld, y, t, n, acc ? 1 : 0); \
+        break;
+        JFNK_K_CASES(C)
+#undef C
+        default:
+            break;
+    }
+}
+
+template <typename T>
+void launch_combine_update(const T* V, long ld, int k, const double* y, const double* x, bool acc, double* u,
+                           const Grid& G, const double* scale5, double* part, int nblk, hipStream_t stream) {
+    Scales5 s;
+    for (int f = 0; f < 5; ++f) s.v[f] = scale5[f];
+    const long n = G.nvec;
+    JFNK_PROFB(KC_COMBINE, stream, (double)n * (k * sizeof(T) + (acc ? 24 : 16)));
+    switch (k) {
+#define C(K)                                                                                                    \
+    case K:                                                                                                     \
+        JFNK_KLAUNCH((k_combine_update<T, K>), dim3(nblk), dim3(kBlock), 0, stream, V, ld, y, x, acc ? 1 : 0, u, \
+                     G.N, n, s, part);                                                                          \
         break;
         JFNK_K_CASES(C)
 #undef C
@@ -403,5 +456,9 @@ template void launch_store_scaled_dev<double>(const double*, double*, const doub
 template void launch_store_scaled_dev<float>(const double*, float*, const double*, long, hipStream_t);
 template void launch_combine<double>(const double*, long, int, const double*, double*, long, bool, hipStream_t);
 template void launch_combine<float>(const float*, long, int, const double*, double*, long, bool, hipStream_t);
+template void launch_combine_update<double>(const double*, long, int, const double*, const double*, bool, double*,
+                                            const Grid&, const double*, double*, int, hipStream_t);
+template void launch_combine_update<float>(const float*, long, int, const double*, const double*, bool, double*,
+                                           const Grid&, const double*, double*, int, hipStream_t);
 
 }  // namespace jfnk

@@ -663,6 +663,7 @@ int plain_norm(jfnk_problem* p, const double* v, double* out) {
 
 struct GmresInfo {
     int its = 0, cycles = 0, converged = 0;
+    int finished = 0;  // the converged correction went to fin instead of x
     double res = 0.0, beta0 = 0.0;
 };
 
@@ -680,9 +681,12 @@ struct GmresInfo {
 // x += M^-1 V y is formed from the kept preconditioned vectors.
 // rhs_norm >= 0: |rhs| as the caller already has it (no reduction and no
 // read-back before the first basis vector); < 0: formed here.
-template <typename T, class Norm, class Pc, class Op, class OpX>
+//   fin(Z, k, acc): given the correction of a converged solve (Z, y on the
+//                  device, acc: add to x), either consumes it in place of x
+//                  and returns true (info->finished) or returns false.
+template <typename T, class Norm, class Pc, class Op, class OpX, class Fin>
 int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* x, double* r, double* w,
-               double* t, Norm norm, Pc pc, Op op, OpX opx, GmresInfo* info, double rhs_norm = -1.0) {
+               double* t, Norm norm, Pc pc, Op op, OpX opx, Fin fin, GmresInfo* info, double rhs_norm = -1.0) {
     const int m = p->opts.gmres_restart;
     const double eta = p->opts.gmres_eta;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
@@ -693,6 +697,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
     info->its = 0;
     info->cycles = 0;
     info->converged = 0;
+    info->finished = 0;
     info->res = beta0;
     info->beta0 = beta0;
     if (beta0 == 0.0) {
@@ -780,8 +785,13 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
         std::memcpy(p->hpin, y.data(), sizeof(double) * kdim);
         HIPCHK(hipMemcpyAsync(p->dsum + D_Y, p->hpin, sizeof(double) * kdim, hipMemcpyHostToDevice, p->stream));
         // x += M^-1 V y, formed from the preconditioned vectors already at hand
-        if (Zb) launch_combine<T>(Zb, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
-        else launch_combine<T>(V, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
+        const T* Zs = Zb ? Zb : V;
+        if (conv && fin(Zs, kdim, cyc > 0)) {
+            info->finished = 1;
+            info->converged = 1;
+            break;
+        }
+        launch_combine<T>(Zs, n, kdim, p->dsum + D_Y, x, n, cyc > 0, p->stream);
         // no wait here: the Newton update queues behind the correction, and
         // the pinned slot that holds y is written again only after a later
         // read-back has drained the stream
@@ -808,7 +818,14 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
         eps_for(p, x);
         jv(p, u, p->Ru, dt, x, t);
     };
-    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, info,
+    // a converged solve's correction goes straight into the Newton update
+    // u += S x (and its max |S x / u| partials) without storing x
+    auto fin = [&](const T* Z, int k, bool acc) {
+        launch_combine_update<T>(Z, n, k, p->dsum + D_Y, p->x, acc, p->u, p->G, p->scale, p->part, p->nred,
+                                 p->stream);
+        return true;
+    };
+    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, fin, info,
                          rhs_norm);
 }
 
@@ -848,7 +865,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
             status = 2;
             break;
         }
-        launch_update_state(p->u, p->x, G, p->scale, p->part, p->nred, p->stream);
+        if (!gi.finished) launch_update_state(p->u, p->x, G, p->scale, p->part, p->nred, p->stream);
         launch_final_max(p->part, p->nred, 1, p->dsum + D_TMP + 1, p->stream);
         launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
                         newton_spec(p, OUT_RESIDUAL, dt, p->rhs, nullptr, p->b), p->stream);
@@ -969,7 +986,9 @@ int scalar_step(jfnk_problem* p, double dt, int flow_its) {
         launch_final_sum(p->part, nb, 1, p->dsum + D_SUSQ, p->stream);
         launch_negate(p->sG, p->srhs, n, p->stream);
         GmresInfo gi;
-        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op, op, &gi));
+        auto keep_x = [](const double*, int, bool) { return false; };
+        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op, op, keep_x,
+                              &gi));
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
             status = 2;
