@@ -234,6 +234,9 @@ void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nle
 // preconditioned basis); its arithmetic outside the elliptic solves is FP64.
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>
+void launch_store_pc_rhs(const Grid& G, const PcCoef& C, const double* w, R* v, double hn, const double* hnsq,
+                         Scales5 sc, const LevelT<R>& L0, hipStream_t stream);
+template <typename R>
 void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE, Scales5 sc,
                    const LevelT<R>& L0, hipStream_t stream);
 // conduction block: rE = S_E v_E + tau D(chi_f G s)

@@ -1061,21 +1061,19 @@ __device__ __forceinline__ double face_h(const Grid& G, const PcCoef& C, const I
 }
 // RE: the energy right-hand side comes from the conduction solve (rE), else
 // from v (compile-time, so that the loads form one block)
-template <typename R, int ND, bool RE>
-__global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __restrict__ v,
-                                                   const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
-    Ijk q;
-    long c;
-    if (!cell_from_launch(G, q, c)) return;
-    const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
+// Right-hand side of the Schur complement at cell q from the energy
+// right-hand side re and the momentum entries of v, read through VM(d, x):
+// the value of v's component d at cell x
+template <int ND, class VM>
+__device__ __forceinline__ double pc_rhs_value(const Grid& G, const PcCoef& C, const Ijk& q, long c, double re,
+                                               Scales5 sc, VM vm) {
     double acc = 0.0;
     for (int d = 0; d < ND; ++d) {
-        const R* vm = v + (long)(2 + d) * G.N;
         const double s = sc.v[2 + d];
-        const double flo = face_h(G, C, q, c, d) * (s * (double)vm[c]);
+        const double flo = face_h(G, C, q, c, d) * (s * vm(d, c));
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
         const long up = top ? c : shifted(G, q, d, 1);  // loads issued at a top wall too, value discarded
-        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * (double)vm[up]);
+        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * vm(d, up));
         const double fhi = top ? 0.0 : fu;
         if (G.sph) {
             const int i = q.v[0], j = q.v[1];
@@ -1087,7 +1085,37 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __
     }
     double rp = G.gm1 * (re - C.tau * acc);
     if (G.sph) rp = rp * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
-    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)rp;
+    return rp;
+}
+template <typename R, int ND, bool RE>
+__global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __restrict__ v,
+                                                   const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+    const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
+    const auto vm = [&](int d, long x) { return (double)v[(long)(2 + d) * G.N + x]; };
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)pc_rhs_value<ND>(G, C, q, c, re, sc, vm);
+}
+// A Krylov basis vector v = w / hn stored (the cell's 2 + ND entries) together
+// with the acoustic right-hand side k_pc_rhs forms from it: the neighbours'
+// entries of v are formed again from w (the same bits as the stored ones),
+// so the next preconditioner application need not read v for it.  hn is
+// given, or (DEV) formed on the device as sqrt of the sum in hnsq.
+template <typename R, int ND, bool DEV>
+__global__ void __launch_bounds__(kBlock) k_store_pc_rhs(Grid G, PcCoef C, const double* __restrict__ w,
+                                                         R* __restrict__ v, double hn_given,
+                                                         const double* __restrict__ hnsq, Scales5 sc,
+                                                         LevelT<R> L0) {
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+    const double hn = DEV ? sqrt(hnsq[0]) : hn_given;
+#pragma unroll
+    for (int f = 0; f < 2 + ND; ++f) v[(long)f * G.N + c] = (R)(w[(long)f * G.N + c] / hn);
+    const double re = sc.v[1] * (double)(R)(w[G.N + c] / hn);
+    const auto vm = [&](int d, long x) { return (double)(R)(w[(long)(2 + d) * G.N + x] / hn); };
+    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)pc_rhs_value<ND>(G, C, q, c, re, sc, vm);
 }
 
 template <typename R, int ND>
@@ -1238,6 +1266,20 @@ void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE,
             if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 2, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
             else JFNK_KLAUNCH((k_pc_rhs<R, 2, false>), g, bl, 0, stream, G, C, v, rE, sc, L0);
         }
+    }
+}
+template <typename R>
+void launch_store_pc_rhs(const Grid& G, const PcCoef& C, const double* w, R* v, double hn, const double* hnsq,
+                         Scales5 sc, const LevelT<R>& L0, hipStream_t stream) {
+    // w read, v and the level's right-hand side written, the enthalpy read
+    JFNK_PROFB(KC_STORE, stream, (double)G.nvec * (8 + sizeof(R)) + (double)G.N * (8 + sizeof(R)));
+    const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+    if (G.ndim == 3) {
+        if (hnsq) JFNK_KLAUNCH((k_store_pc_rhs<R, 3, true>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
+        else JFNK_KLAUNCH((k_store_pc_rhs<R, 3, false>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
+    } else {
+        if (hnsq) JFNK_KLAUNCH((k_store_pc_rhs<R, 2, true>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
+        else JFNK_KLAUNCH((k_store_pc_rhs<R, 2, false>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
     }
 }
 template <typename R>
@@ -1415,6 +1457,8 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
                                int, bool, hipStream_t);                                                      \
     template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const R*, const double*, Scales5,        \
                                    const LevelT<R>&, hipStream_t);                                           \
+    template void launch_store_pc_rhs<R>(const Grid&, const PcCoef&, const double*, R*, double,          \
+                                         const double*, Scales5, const LevelT<R>&, hipStream_t);              \
     template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const R*, const LevelT<R>&,        \
                                          Scales5, double*, hipStream_t);                                     \
     template void launch_pc_back<R>(const Grid&, const PcCoef&, const R*, const double*, const R*,      \

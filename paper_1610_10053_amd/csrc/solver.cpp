@@ -111,6 +111,9 @@ struct jfnk_problem {
     // marks the end of a GMRES step's scalar read-back, so that the host can
     // wait for it while later work already runs on the stream
     hipEvent_t rb_event = nullptr;
+    // the acoustic right-hand side of the next basis vector to be
+    // preconditioned was formed when that vector was stored
+    bool pc_rhs_formed = false;
     ~jfnk_problem() {
         for (auto& g : mg_exec)
             if (g) (void)hipGraphExecDestroy(g);
@@ -354,6 +357,7 @@ int read_scalars(jfnk_problem* p, int off, int count, double* out) {
 // runs the queued work while the host takes the scalars
 // vectors at least this long store the next basis vector during the read-back
 constexpr long kOverlapStoreMin = 65536;
+constexpr long kStoreRhsMaxCells = 1L << 18;
 template <class After>
 int read_scalars_then(jfnk_problem* p, int off, int count, double* out, After after) {
     HIPCHK(hipMemcpyAsync(p->hpin, p->dsum + off, sizeof(double) * count, hipMemcpyDeviceToHost, p->stream));
@@ -494,6 +498,7 @@ void build_hierarchy(jfnk_problem* p, int which) {
 int pc_build(jfnk_problem* p, const double* u, double dt, bool prim_valid) {
     const Grid& G = p->G;
     p->C.tau = 0.5 * dt;
+    p->pc_rhs_formed = false;
     if (p->opts.pc == JFNK_PC_NONE) return 0;
     if (!prim_valid) launch_prim(G, view(p, u, nullptr), p->P, p->stream);
     launch_pc_coef(G, u, p->P, p->C, dt, p->stream);
@@ -600,7 +605,8 @@ void pc_apply_t(jfnk_problem* p, const R* v, R* z) {
         rE = p->rEd;
     }
     LevelSet<R>& A = levels<R>(p, 0);
-    launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0], p->stream);
+    if (!p->pc_rhs_formed) launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0], p->stream);
+    p->pc_rhs_formed = false;
     const R* dp;
     if (mg) {
         mg_solve<R>(p, 0);
@@ -683,10 +689,13 @@ struct GmresInfo {
 // read-back before the first basis vector); < 0: formed here.
 //   fin(Z, k, acc): given the correction of a converged solve (Z, y on the
 //                  device, acc: add to x), either consumes it in place of x
-//                  and returns true (info->finished) or returns false.
-template <typename T, class Norm, class Pc, class Op, class OpX, class Fin>
+//                  and returns true (info->finished) or returns false;
+//   store(w, v, hn, hnsq): the basis vector v = w / hn (hn given, or, with
+//                  hnsq, sqrt of the sum there on the device).
+template <typename T, class Norm, class Pc, class Op, class OpX, class Fin, class Store>
 int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* x, double* r, double* w,
-               double* t, Norm norm, Pc pc, Op op, OpX opx, Fin fin, GmresInfo* info, double rhs_norm = -1.0) {
+               double* t, Norm norm, Pc pc, Op op, OpX opx, Fin fin, Store store, GmresInfo* info,
+               double rhs_norm = -1.0) {
     const int m = p->opts.gmres_restart;
     const double eta = p->opts.gmres_eta;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
@@ -715,7 +724,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
             break;
         }
         info->cycles++;
-        launch_store_scaled<T>(cyc == 0 ? rhs : r, V, beta, n, p->stream);
+        store(cyc == 0 ? rhs : r, V, beta, nullptr);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int kdim = 0;
@@ -743,8 +752,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
             T* vnext = V + (long)(j + 1) * n;
             const bool overlap = n >= kOverlapStoreMin;
             if (overlap)
-                CK(read_scalars_then(p, 0, D_HN + 1, hb.data(),
-                                     [&] { launch_store_scaled_dev<T>(w, vnext, p->dsum + D_HN, n, p->stream); }));
+                CK(read_scalars_then(p, 0, D_HN + 1, hb.data(), [&] { store(w, vnext, 0.0, p->dsum + D_HN); }));
             else
                 CK(read_scalars(p, 0, D_HN + 1, hb.data()));
             const double w0 = std::sqrt(hb[D_H1 + j + 1]);
@@ -771,7 +779,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
                 conv = true;
                 break;
             }
-            if (!overlap) launch_store_scaled<T>(w, vnext, hn, n, p->stream);
+            if (!overlap) store(w, vnext, hn, nullptr);
             if (info->res <= eta * beta0) {
                 conv = true;
                 break;
@@ -825,8 +833,31 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
                                  p->stream);
         return true;
     };
-    return gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, fin, info,
-                         rhs_norm);
+    // with the acoustic preconditioner alone each stored basis vector's
+    // right-hand side for it is formed in the same pass, in the mixed form
+    // and on FP64 grids of up to kStoreRhsMaxCells cells (on larger FP64
+    // grids the fused pass, which divides each neighbour's entries by |w|
+    // again, measured slower than the two launches)
+    const bool rhs_with_store =
+        p->opts.pc == JFNK_PC_ACOUSTIC && (sizeof(T) == sizeof(float) || p->G.N <= kStoreRhsMaxCells);
+    auto store = [&](const double* src, T* dst, double hn, const double* hnsq) {
+        if (rhs_with_store) {
+            Scales5 sc;
+            for (int f = 0; f < 5; ++f) sc.v[f] = p->scale[f];
+            launch_store_pc_rhs<T>(p->G, p->C, src, dst, hn, hnsq, sc, levels<T>(p, 0).L[0], p->stream);
+            p->pc_rhs_formed = true;
+        } else if (hnsq) {
+            launch_store_scaled_dev<T>(src, dst, hnsq, n, p->stream);
+        } else {
+            launch_store_scaled<T>(src, dst, hn, n, p->stream);
+        }
+    };
+    const int rc = gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, fin,
+                                 store, info, rhs_norm);
+    // a vector stored by a step that ended the solve is never preconditioned:
+    // later applications form their own right-hand side
+    p->pc_rhs_formed = false;
+    return rc;
 }
 
 // Newton-Raphson from u^n at dt; on failure the state is restored
@@ -987,8 +1018,12 @@ int scalar_step(jfnk_problem* p, double dt, int flow_its) {
         launch_negate(p->sG, p->srhs, n, p->stream);
         GmresInfo gi;
         auto keep_x = [](const double*, int, bool) { return false; };
+        auto store = [&](const double* src, double* dst, double hn, const double* hnsq) {
+            if (hnsq) launch_store_scaled_dev<double>(src, dst, hnsq, n, p->stream);
+            else launch_store_scaled<double>(src, dst, hn, n, p->stream);
+        };
         CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op, op, keep_x,
-                              &gi));
+                              store, &gi));
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
             status = 2;
