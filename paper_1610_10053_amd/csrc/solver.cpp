@@ -114,6 +114,10 @@ struct jfnk_problem {
     // the acoustic right-hand side of the next basis vector to be
     // preconditioned was formed when that vector was stored
     bool pc_rhs_formed = false;
+    // FP64 Cartesian problems: the acoustic couplings are formed directly in
+    // the finest level's coupling arrays (its sigma of 1 set once), so the
+    // hierarchy build needs no copy of them
+    bool kap_in_level0 = false;
     ~jfnk_problem() {
         for (auto& g : mg_exec)
             if (g) (void)hipGraphExecDestroy(g);
@@ -485,7 +489,7 @@ void build_hierarchy(jfnk_problem* p, int which) {
     // D is built only without unit sigma: with sigma == 1 the sweeps form it
     // from the couplings
     const bool diag = !S.L[0].unit_sig;
-    launch_level0<R>(G, p->C, which, S.L[0], p->stream);
+    if (!(which == 0 && p->kap_in_level0)) launch_level0<R>(G, p->C, which, S.L[0], p->stream);
     if (diag) launch_level_diag<R>(G, S.L[0], p->stream);
     for (int l = 1; l < p->nlev; ++l) {
         launch_coarsen<R>(G, S.L[l - 1], S.L[l], p->stream);
@@ -1405,6 +1409,17 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     } else {
         if ((rc = alloc_levels<double>(p, p->ac64, &p->dac64, nl, !G.sph, split))) return cleanup(rc);
         if ((rc = alloc_levels<double>(p, p->df64, &p->ddf64, nl, false, split))) return cleanup(rc);
+        if (!G.sph) {
+            // the finest acoustic level's couplings are C.kap itself; its
+            // sigma (1) is written once here, from zeroed couplings
+            LevelT<double>& L0 = p->ac64.L[0];
+            for (int d = 0; d < G.ndim; ++d) p->C.kap[d] = L0.a[d];
+            p->kap_in_level0 = true;
+            for (int d = 0; d < G.ndim; ++d)
+                if (hipMemsetAsync(L0.a[d], 0, sizeof(double) * N, p->stream) != hipSuccess)
+                    return cleanup(fail(-3, "memset"));
+            launch_level0<double>(G, p->C, 0, L0, p->stream);
+        }
     }
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
