@@ -64,6 +64,8 @@ struct OutSpec {
     int neg_scaled;      // the F output holds -F/S (the Newton right-hand side) instead of F
     double scale[5];     // variable scales for the fused norm
     double* partial;     // per-block sum of (F/S)^2, or null
+    double inv_scale[5]; // 1/S for the state's own norm
+    double* partial_u;   // per-block sum of (u/S)^2 (OUT_CN_OLD, OUT_RESIDUAL), or null
 };
 
 // residual.hip

@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                                                 double* __restrict__ rout, double* __restrict__ partial) {
     Ijk q;
     long c = 0;
-    double part = 0.0;
+    double part = 0.0, part_u = 0.0;
     if (cell_from_launch(G, q, c)) {
         // consumer of field f's right-hand side Rf, called field by field in
         // order (each value is written as soon as it is formed)
@@ -355,12 +355,17 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
                 out2[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
+                const double tu = u0 * o.inv_scale[f];
+                part_u += tu * tu;
             } else if (MODE == OUT_RESIDUAL) {
-                const double F0 = (st_t<PERT>(s, f, c) - o.b[x]) - o.h * Rf;  // loaded on wall faces too
+                const double uf = st_t<PERT>(s, f, c);
+                const double F0 = (uf - o.b[x]) - o.h * Rf;  // loaded on wall faces too
                 const double F = wallface ? 0.0 : F0;
                 out[x] = o.neg_scaled ? -F / o.scale[f] : F;
                 const double t = F / o.scale[f];
                 part += t * t;
+                const double tu = uf * o.inv_scale[f];
+                part_u += tu * tu;
             } else {  // OUT_JV
                 const double e = s.eps[0];
                 const double w0 = dir_t<PERT>(s, x) - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
@@ -452,6 +457,11 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         __shared__ double sh[kBlock / 64];
         const double t = block_sum(part, sh);
         if (lin_thread() == 0) partial[lin_block()] = t;
+    }
+    if (MODE != OUT_JV && o.partial_u) {
+        __shared__ double shu[kBlock / 64];
+        const double t = block_sum(part_u, shu);
+        if (lin_thread() == 0) o.partial_u[lin_block()] = t;
     }
 }
 

@@ -411,15 +411,23 @@ OutSpec outspec(jfnk_problem* p, int mode, double dt, double* out, double* out2,
     o.neg_scaled = 0;
     for (int f = 0; f < 5; ++f) o.scale[f] = p->scale[f];
     o.partial = want_norm ? p->part : nullptr;
+    for (int f = 0; f < 5; ++f) o.inv_scale[f] = 1.0 / p->scale[f];
+    o.partial_u = nullptr;
     return o;
 }
 
 // residual evaluation at a Newton iterate: the norm partials, R kept for the
-// products, and the Newton right-hand side -S^-1 F written in place of F
+// products, the Newton right-hand side -S^-1 F written in place of F, and the
+// partials of |S^-1 u|^2 for the products' difference step (summed into the
+// device scalar by usq_from_residual)
 OutSpec newton_spec(jfnk_problem* p, int mode, double dt, double* out, double* out2, const double* b) {
     OutSpec o = outspec(p, mode, dt, out, out2, b, nullptr, true, p->Ru);
     o.neg_scaled = 1;
+    o.partial_u = p->part + p->ncell_blk;
     return o;
+}
+void usq_from_residual(jfnk_problem* p) {
+    launch_final_sum(p->part + p->ncell_blk, p->ncell_blk, 1, p->dsum + D_USQ, p->stream);
 }
 
 // dt and limits of eqs. (5)-(7) for state u; sets the variable scales
@@ -873,6 +881,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
     CK(time_step(p, p->u, nullptr));  // scales from u^n
     launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
                     newton_spec(p, OUT_CN_OLD, dt, p->b, p->rhs, nullptr), p->stream);
+    usq_from_residual(p);
     HIPCHK(hipGetLastError());
     double f0;
     CK(residual_norm(p, &f0));
@@ -888,8 +897,9 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
             status = 1;
             break;
         }
-        CK(pc_build(p, p->u, dt, true));  // P holds the primitives of u from the residual just evaluated
-        set_usq(p, p->u);
+        // P holds the primitives of u from the residual just evaluated, and
+        // the device scalar |S^-1 u|^2 was summed from the same sweep
+        CK(pc_build(p, p->u, dt, true));
         GmresInfo gi;
         // the right-hand side -S^-1 F is the residual just measured: its norm
         // is f (the same squares, summed by the residual sweep's blocks)
@@ -905,6 +915,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
         launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
                         newton_spec(p, OUT_RESIDUAL, dt, p->rhs, nullptr, p->b), p->stream);
         launch_final_sum(p->part, p->ncell_blk, 1, p->dsum + D_TMP, p->stream);
+        usq_from_residual(p);
         HIPCHK(hipGetLastError());
         double rb[2];
         CK(read_scalars(p, D_TMP, 2, rb));
