@@ -122,7 +122,10 @@ void launch_vel_error_scratch(const Grid& Gl, const Grid& Gh, const double* ul, 
 // partial layout: part[col * nblk + block]
 // dst[0] = v, ordered on the stream
 void launch_put_scalar(double* dst, double v, hipStream_t stream);
-void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
+// host (or null): pinned host memory that receives a copy of the ncol
+// results; xsrc[0, xn) (earlier device results) is copied to xhost as well
+void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream,
+                      double* host = nullptr, const double* xsrc = nullptr, double* xhost = nullptr, int xn = 0);
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream);
 void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale5, double* part, int nblk,
                          hipStream_t stream);

@@ -10,14 +10,25 @@
 namespace jfnk {
 
 // ---------------------------------------------------------------- final reductions (one block per column, fixed order)
+// host (or null): pinned host memory that receives a copy of each result, so
+// that the host can read it once the kernel is done, with no copy launch;
+// block 0 also copies xn earlier device results xsrc to xhost, so that one
+// kernel's host stores carry a whole read-back
 __global__ void __launch_bounds__(kFinalThreads) k_final_sum(const double* __restrict__ part, int nblk,
-                                                             double* __restrict__ out) {
+                                                             double* __restrict__ out, double* __restrict__ host,
+                                                             const double* __restrict__ xsrc,
+                                                             double* __restrict__ xhost, int xn) {
     __shared__ double sh[kFinalThreads / 64];
     const int col = blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[(long)col * nblk + i];
     const double t = block_sum(s, sh);
-    if (threadIdx.x == 0) out[col] = t;
+    if (threadIdx.x == 0) {
+        out[col] = t;
+        if (host) host[col] = t;
+    }
+    if (col == 0)
+        for (int i = threadIdx.x; i < xn; i += blockDim.x) xhost[i] = xsrc[i];
 }
 
 __global__ void __launch_bounds__(kFinalThreads) k_final_max(const double* __restrict__ part, int nblk,
@@ -38,9 +49,11 @@ void launch_put_scalar(double* dst, double v, hipStream_t stream) {
     JFNK_KLAUNCH(k_put_scalar, dim3(1), dim3(64), 0, stream, dst, v);
 }
 
-void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
+void launch_final_sum(const double* part, int nblk, int ncol, double* out, hipStream_t stream, double* host,
+                      const double* xsrc, double* xhost, int xn) {
     JFNK_PROF(KC_REDUCE, stream);
-    JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kFinalThreads), 0, stream, part, nblk, out);
+    JFNK_KLAUNCH(k_final_sum, dim3(ncol), dim3(kFinalThreads), 0, stream, part, nblk, out, host, xsrc, xhost,
+                 xhost ? xn : 0);
 }
 void launch_final_max(const double* part, int nblk, int ncol, double* out, hipStream_t stream) {
     JFNK_PROF(KC_REDUCE, stream);

@@ -356,6 +356,22 @@ int read_scalars(jfnk_problem* p, int off, int count, double* out) {
     return 0;
 }
 
+// On short vectors the last reduction of a GMRES step also writes the
+// step's scalars into the pinned area's second half (the mirror, at the same
+// offsets as in dsum; its own result and the earlier ones copied from dsum),
+// so that the read-back, whose latency is then most of the step, needs no
+// copy launch: an event after the reduction, a wait for it, and the values
+// are in host memory.  (The residual and time-step read-backs measured no
+// better that way and keep the copy.)
+double* mirror(jfnk_problem* p, int off) { return p->hpin + kDsum + off; }
+int read_mirror(jfnk_problem* p, int off, int count, double* out) {
+    HIPCHK(hipEventRecord(p->rb_event, p->stream));
+    HIPCHK(hipEventSynchronize(p->rb_event));
+    std::memcpy(out, mirror(p, off), sizeof(double) * count);
+    if (g_prof) g_prof->drain();
+    return 0;
+}
+
 // read-back of scalars with more work queued behind it: the copy, an event,
 // then `after` (launches), and a wait for the event only, so that the device
 // runs the queued work while the host takes the scalars
@@ -754,19 +770,26 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
             nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, w, n, p->part, true, p->stream);
             launch_final_sum(p->part, nb, j + 1, p->dsum + D_H2, p->stream);
             nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H2, w, n, p->part, false, p->stream);
-            launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream);
+            T* vnext = V + (long)(j + 1) * n;
+            const bool overlap = n >= kOverlapStoreMin;
+            // short vectors: the scalars come back through the mirror (the
+            // read-back's latency is the iteration's); long ones: copied
+            // behind the reductions while the next basis vector is stored
+            if (overlap)
+                launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream);
+            else
+                launch_final_sum(p->part, nb, 1, p->dsum + D_HN, p->stream, mirror(p, D_HN), p->dsum + D_H1,
+                                 mirror(p, D_H1), D_HN - D_H1);
             HIPCHK(hipGetLastError());
             // on long vectors the next basis vector is stored (from |w|^2 on
             // the device, the same bits as the host's division) while the
             // host takes the scalars; a step that ends the cycle never reads
             // it.  On short ones the store is too brief to hide the wait and
             // follows the read-back.
-            T* vnext = V + (long)(j + 1) * n;
-            const bool overlap = n >= kOverlapStoreMin;
             if (overlap)
                 CK(read_scalars_then(p, 0, D_HN + 1, hb.data(), [&] { store(w, vnext, 0.0, p->dsum + D_HN); }));
             else
-                CK(read_scalars(p, 0, D_HN + 1, hb.data()));
+                CK(read_mirror(p, 0, D_HN + 1, hb.data()));
             const double w0 = std::sqrt(hb[D_H1 + j + 1]);
             const double hn = std::sqrt(hb[D_HN]);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[D_H1 + i] + hb[D_H2 + i];
@@ -1435,11 +1458,11 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
     AL(p->part, (size_t)p->npart);
     AL(p->dsum, (size_t)kDsum);
 #undef AL
-    static_assert(kPinnedBytes == sizeof(double) * kDsum, "read-back area size");
+    static_assert(kPinnedBytes == 2 * sizeof(double) * kDsum, "read-back area size: staging and mirror");
     if (pinned_host) {
         p->hpin = (double*)pinned_host;
     } else {
-        hipError_t e = hipHostMalloc((void**)&p->hpin, sizeof(double) * kDsum, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void**)&p->hpin, kPinnedBytes, hipHostMallocDefault);
         if (e != hipSuccess) return cleanup(fail(-2, "hipHostMalloc failed"));
         p->own_hpin = true;
     }
