@@ -231,8 +231,10 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream);
 // V-cycles on b of level 0; levels >= coarse_from run in one single-block
 // kernel; levels (not the coarsest) of at most `light` cells take V(1,1)
 template <typename R>
+// x0: the finest level's first colour-0 half-sweep values are already in x
+// (formed with the right-hand side); the first cycle skips that half-sweep
 void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
-               int nuc, int light, bool first, hipStream_t stream);
+               int nuc, int light, bool first, bool x0, hipStream_t stream);
 
 // The preconditioner's input v and output z are vectors of the
 // preconditioner's precision R (FP64; the mixed form's FP32 Krylov basis and
@@ -240,10 +242,12 @@ void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nle
 // r_p = (gamma-1)(r_E - tau D(h_f r_m)) with r = S v; r_E from rE if given
 template <typename R>
 void launch_store_pc_rhs(const Grid& G, const PcCoef& C, const double* w, R* v, double hn, const double* hnsq,
-                         Scales5 sc, const LevelT<R>& L0, hipStream_t stream);
+                         Scales5 sc, const LevelT<R>& L0, bool x0, hipStream_t stream);
+// x0: also the first multigrid half-sweep's colour-0 values from x = 0 (the
+// finest level's couplings formed from its cell field, unit sigma)
 template <typename R>
 void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE, Scales5 sc,
-                   const LevelT<R>& L0, hipStream_t stream);
+                   const LevelT<R>& L0, bool x0, hipStream_t stream);
 // conduction block: rE = S_E v_E + tau D(chi_f G s)
 template <typename R>
 void launch_pc_diff_back(const Grid& G, const PcCoef& C, const R* v, const LevelT<R>& L0, Scales5 sc,

@@ -222,8 +222,8 @@ void launch_level_diag(const Grid& G, const LevelT<R>& L, hipStream_t stream) {
 // XNB(n, d, side): the value of x at neighbour n, the lower (side 0) or
 // upper (side 1) one along d
 template <typename R, int ND, bool FIRST, bool QF, bool UNIT, class XNB>
-__device__ __forceinline__ R gs_value_nb(const Grid& G, const LevelT<R>& L, const R* b, XNB xnb, LIjk q, int c) {
-    R num = b[xbq(L, q)];
+__device__ __forceinline__ R gs_value_bv(const Grid& G, const LevelT<R>& L, R bq, XNB xnb, LIjk q, int c) {
+    R num = bq;
     R den = (R)1.0;  // sig + the couplings in the order of k_level_diag (when sig == 1)
     for (int d = 0; d < ND; ++d) {
         // a neighbour beyond a wall stays at q: its loads are issued (in
@@ -248,6 +248,10 @@ __device__ __forceinline__ R gs_value_nb(const Grid& G, const LevelT<R>& L, cons
         den = den + ahi;
     }
     return num / (UNIT ? den : L.D[c]);
+}
+template <typename R, int ND, bool FIRST, bool QF, bool UNIT, class XNB>
+__device__ __forceinline__ R gs_value_nb(const Grid& G, const LevelT<R>& L, const R* b, XNB xnb, LIjk q, int c) {
+    return gs_value_bv<R, ND, FIRST, QF, UNIT>(G, L, b[xbq(L, q)], xnb, q, c);
 }
 template <typename R, int ND, bool FIRST, bool QF, bool UNIT>
 __device__ __forceinline__ R gs_value_t(const Grid& G, const LevelT<R>& L, const R* b, const R* x, LIjk q, int c) {
@@ -915,10 +919,13 @@ __global__ void __launch_bounds__(kCoarseThreads) k_coarse_vcycle(Grid G, const 
 }
 
 // light: levels (not the coarsest) of at most this many cells take one pre-
-// and one post-smoothing sweep (0: none)
+// and one post-smoothing sweep (0: none); x0: the first half-sweep's colour-0
+// values of this (multi-block, not the coarsest) level are already in x
+// (formed with its right-hand side), so that half-sweep is skipped
 template <typename R>
 static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int l, int nlev,
-                         int coarse_from, int nu1, int nu2, int nuc, int light, bool first, hipStream_t stream) {
+                         int coarse_from, int nu1, int nu2, int nuc, int light, bool first, bool x0,
+                         hipStream_t stream) {
     if (l >= coarse_from) {
         JFNK_PROF(KC_MG_COARSE, stream);
         const int ft = first ? 1 : 0;
@@ -980,7 +987,7 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         return;
     }
     for (int s = 0; s < nu1; ++s) {
-        {
+        if (!(first && x0 && s == 0)) {
             JFNK_PROFB(KC_MG_SMOOTH, stream, bs);
             launch_gs<R>(G, L, 0, (first && s == 0) ? 1 : 0, stream);
         }
@@ -1005,7 +1012,7 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
                 JFNK_KLAUNCH((k_restrict<R, 2, false>), restrict_grid<2>(L.n), restrict_block<2>(), 0, stream, G, L, S.L[l + 1]);
         }
     }
-    vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, light, true, stream);
+    vcycle_level(G, S, Ld, l + 1, nlev, coarse_from, nu1, nu2, nuc, light, true, false, stream);
     // the prolongation goes into the first post-smoothing half-sweep on
     // levels of at most kGsProlongMaxCells cells; on larger ones the fused
     // sweep (about 80 VGPRs in FP64, 5 waves per SIMD) measured slower than
@@ -1036,8 +1043,8 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
 
 template <typename R>
 void mg_vcycle(const Grid& G, const LevelSet<R>& S, const LevelT<R>* Ld, int nlev, int coarse_from, int nu1, int nu2,
-               int nuc, int light, bool first, hipStream_t stream) {
-    vcycle_level(G, S, Ld, 0, nlev, coarse_from, nu1, nu2, nuc, light, first, stream);
+               int nuc, int light, bool first, bool x0, hipStream_t stream) {
+    vcycle_level(G, S, Ld, 0, nlev, coarse_from, nu1, nu2, nuc, light, first, x0, stream);
 }
 
 // ---------------------------------------------------------------- right-hand sides and back-substitution
@@ -1087,7 +1094,26 @@ __device__ __forceinline__ double pc_rhs_value(const Grid& G, const PcCoef& C, c
     if (G.sph) rp = rp * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
     return rp;
 }
-template <typename R, int ND, bool RE>
+// The level's right-hand side at cell q stored and, with X0 (the finest
+// level's couplings formed from its cell field, unit sigma), the first
+// multigrid half-sweep's colour-0 value from x = 0 as well: gs_value's
+// first-sweep update, operation for operation, so the V-cycle skips that
+// half-sweep.
+template <typename R, int ND, bool X0>
+__device__ __forceinline__ void put_level_rhs(const Grid& G, const LevelT<R>& L0, const Ijk& q, int c, double rp) {
+    LIjk lq;
+    lq.v[0] = q.v[0];
+    lq.v[1] = q.v[1];
+    lq.v[2] = q.v[2];
+    const int e = xbq(L0, lq);
+    const R bq = (R)rp;
+    L0.b[e] = bq;
+    if (X0 && ((q.v[0] + q.v[1] + q.v[2]) & 1) == 0) {
+        const auto zero = [](const LIjk&, int, int) { return (R)0.0; };
+        L0.x[e] = gs_value_bv<R, ND, true, true, true>(G, L0, bq, zero, lq, c);
+    }
+}
+template <typename R, int ND, bool RE, bool X0>
 __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __restrict__ v,
                                                    const double* __restrict__ rE, Scales5 sc, LevelT<R> L0) {
     Ijk q;
@@ -1095,14 +1121,14 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __
     if (!cell_from_launch(G, q, c)) return;
     const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
     const auto vm = [&](int d, long x) { return (double)v[(long)(2 + d) * G.N + x]; };
-    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)pc_rhs_value<ND>(G, C, q, c, re, sc, vm);
+    put_level_rhs<R, ND, X0>(G, L0, q, (int)c, pc_rhs_value<ND>(G, C, q, c, re, sc, vm));
 }
 // A Krylov basis vector v = w / hn stored (the cell's 2 + ND entries) together
 // with the acoustic right-hand side k_pc_rhs forms from it: the neighbours'
 // entries of v are formed again from w (the same bits as the stored ones),
 // so the next preconditioner application need not read v for it.  hn is
 // given, or (DEV) formed on the device as sqrt of the sum in hnsq.
-template <typename R, int ND, bool DEV>
+template <typename R, int ND, bool DEV, bool X0>
 __global__ void __launch_bounds__(kBlock) k_store_pc_rhs(Grid G, PcCoef C, const double* __restrict__ w,
                                                          R* __restrict__ v, double hn_given,
                                                          const double* __restrict__ hnsq, Scales5 sc,
@@ -1115,7 +1141,7 @@ __global__ void __launch_bounds__(kBlock) k_store_pc_rhs(Grid G, PcCoef C, const
     for (int f = 0; f < 2 + ND; ++f) v[(long)f * G.N + c] = (R)(w[(long)f * G.N + c] / hn);
     const double re = sc.v[1] * (double)(R)(w[G.N + c] / hn);
     const auto vm = [&](int d, long x) { return (double)(R)(w[(long)(2 + d) * G.N + x] / hn); };
-    L0.b[xbi(L0, q.v[0], q.v[1], q.v[2])] = (R)pc_rhs_value<ND>(G, C, q, c, re, sc, vm);
+    put_level_rhs<R, ND, X0>(G, L0, q, (int)c, pc_rhs_value<ND>(G, C, q, c, re, sc, vm));
 }
 
 template <typename R, int ND>
@@ -1252,35 +1278,40 @@ __global__ void __launch_bounds__(kFinalThreads) k_jv_eps(const double* __restri
 
 template <typename R>
 void launch_pc_rhs(const Grid& G, const PcCoef& C, const R* v, const double* rE, Scales5 sc,
-                   const LevelT<R>& L0, hipStream_t stream) {
+                   const LevelT<R>& L0, bool x0, hipStream_t stream) {
     {
         // v (sizeof(R)), enthalpy, rE; the level's right-hand side
         JFNK_PROFB(KC_PC_RHS, stream,
                    (double)sizeof(R) * G.N * (G.ndim + (rE ? 0 : 1)) + 8.0 * G.N * (1 + (rE ? 1 : 0)) +
                        (double)sizeof(R) * G.N);
         const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+#define RHS(ND, RE, X0) JFNK_KLAUNCH((k_pc_rhs<R, ND, RE, X0>), g, bl, 0, stream, G, C, v, rE, sc, L0)
         if (G.ndim == 3) {
-            if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 3, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
-            else JFNK_KLAUNCH((k_pc_rhs<R, 3, false>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+            if (rE) { if (x0) RHS(3, true, true); else RHS(3, true, false); }
+            else { if (x0) RHS(3, false, true); else RHS(3, false, false); }
         } else {
-            if (rE) JFNK_KLAUNCH((k_pc_rhs<R, 2, true>), g, bl, 0, stream, G, C, v, rE, sc, L0);
-            else JFNK_KLAUNCH((k_pc_rhs<R, 2, false>), g, bl, 0, stream, G, C, v, rE, sc, L0);
+            if (rE) { if (x0) RHS(2, true, true); else RHS(2, true, false); }
+            else { if (x0) RHS(2, false, true); else RHS(2, false, false); }
         }
+#undef RHS
     }
 }
 template <typename R>
 void launch_store_pc_rhs(const Grid& G, const PcCoef& C, const double* w, R* v, double hn, const double* hnsq,
-                         Scales5 sc, const LevelT<R>& L0, hipStream_t stream) {
+                         Scales5 sc, const LevelT<R>& L0, bool x0, hipStream_t stream) {
     // w read, v and the level's right-hand side written, the enthalpy read
     JFNK_PROFB(KC_STORE, stream, (double)G.nvec * (8 + sizeof(R)) + (double)G.N * (8 + sizeof(R)));
     const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+#define ST(ND, DEV, X0) \
+    JFNK_KLAUNCH((k_store_pc_rhs<R, ND, DEV, X0>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0)
     if (G.ndim == 3) {
-        if (hnsq) JFNK_KLAUNCH((k_store_pc_rhs<R, 3, true>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
-        else JFNK_KLAUNCH((k_store_pc_rhs<R, 3, false>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
+        if (hnsq) { if (x0) ST(3, true, true); else ST(3, true, false); }
+        else { if (x0) ST(3, false, true); else ST(3, false, false); }
     } else {
-        if (hnsq) JFNK_KLAUNCH((k_store_pc_rhs<R, 2, true>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
-        else JFNK_KLAUNCH((k_store_pc_rhs<R, 2, false>), g, bl, 0, stream, G, C, w, v, hn, hnsq, sc, L0);
+        if (hnsq) { if (x0) ST(2, true, true); else ST(2, true, false); }
+        else { if (x0) ST(2, false, true); else ST(2, false, false); }
     }
+#undef ST
 }
 template <typename R>
 void launch_pc_diff_back(const Grid& G, const PcCoef& C, const R* v, const LevelT<R>& L0, Scales5 sc,
@@ -1454,11 +1485,11 @@ void launch_line_solve(const Grid& G, const PcCoef& C, int d, int kind, R* x, do
     template void launch_coarsen<R>(const Grid&, const LevelT<R>&, const LevelT<R>&, hipStream_t);           \
     template void launch_level_diag<R>(const Grid&, const LevelT<R>&, hipStream_t);                          \
     template void mg_vcycle<R>(const Grid&, const LevelSet<R>&, const LevelT<R>*, int, int, int, int, int,     \
-                               int, bool, hipStream_t);                                                      \
+                               int, bool, bool, hipStream_t);                                                \
     template void launch_pc_rhs<R>(const Grid&, const PcCoef&, const R*, const double*, Scales5,        \
-                                   const LevelT<R>&, hipStream_t);                                           \
+                                   const LevelT<R>&, bool, hipStream_t);                                     \
     template void launch_store_pc_rhs<R>(const Grid&, const PcCoef&, const double*, R*, double,          \
-                                         const double*, Scales5, const LevelT<R>&, hipStream_t);              \
+                                         const double*, Scales5, const LevelT<R>&, bool, hipStream_t);        \
     template void launch_pc_diff_back<R>(const Grid&, const PcCoef&, const R*, const LevelT<R>&,        \
                                          Scales5, double*, hipStream_t);                                     \
     template void launch_pc_back<R>(const Grid&, const PcCoef&, const R*, const double*, const R*,      \

@@ -555,12 +555,21 @@ const LevelT<float>* dlevels<float>(jfnk_problem* p, int which) {
     return which == 0 ? p->dac32 : p->ddf32;
 }
 
+// the acoustic right-hand side kernels also form the first colour-0
+// half-sweep of the finest level (multigrid on a Cartesian grid, whose
+// finest level forms its couplings from the enthalpy, is a multi-block level
+// and not the coarsest), and the first V-cycle skips that half-sweep
+bool x0_with_rhs(const jfnk_problem* p) {
+    return p->opts.pc_solver == JFNK_PCS_MULTIGRID && !p->G.sph && p->coarse_from > 0 && p->nlev > 1;
+}
+
 template <typename R>
 void mg_launches(jfnk_problem* p, int which) {
     const LevelSet<R>& S = levels<R>(p, which);
     for (int c = 0; c < p->opts.mg_cycles; ++c)
         mg_vcycle<R>(p->G, S, dlevels<R>(p, which), p->nlev, p->coarse_from, p->opts.mg_nu1, p->opts.mg_nu2,
-                     p->opts.mg_nuc, p->opts.mg_light_cells, c == 0, p->stream);
+                     p->opts.mg_nuc, p->opts.mg_light_cells, c == 0, c == 0 && which == 0 && x0_with_rhs(p),
+                     p->stream);
 }
 
 // The V-cycles' launches depend only on the problem (level arrays, sweep
@@ -633,7 +642,7 @@ void pc_apply_t(jfnk_problem* p, const R* v, R* z) {
         rE = p->rEd;
     }
     LevelSet<R>& A = levels<R>(p, 0);
-    if (!p->pc_rhs_formed) launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0], p->stream);
+    if (!p->pc_rhs_formed) launch_pc_rhs<R>(G, p->C, v, rE, sc, A.L[0], x0_with_rhs(p), p->stream);
     p->pc_rhs_formed = false;
     const R* dp;
     if (mg) {
@@ -879,7 +888,8 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
         if (rhs_with_store) {
             Scales5 sc;
             for (int f = 0; f < 5; ++f) sc.v[f] = p->scale[f];
-            launch_store_pc_rhs<T>(p->G, p->C, src, dst, hn, hnsq, sc, levels<T>(p, 0).L[0], p->stream);
+            launch_store_pc_rhs<T>(p->G, p->C, src, dst, hn, hnsq, sc, levels<T>(p, 0).L[0], x0_with_rhs(p),
+                                   p->stream);
             p->pc_rhs_formed = true;
         } else if (hnsq) {
             launch_store_scaled_dev<T>(src, dst, hnsq, n, p->stream);
