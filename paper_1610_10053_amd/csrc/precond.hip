@@ -1070,17 +1070,21 @@ __device__ __forceinline__ double face_h(const Grid& G, const PcCoef& C, const I
 // from v (compile-time, so that the loads form one block)
 // Right-hand side of the Schur complement at cell q from the energy
 // right-hand side re and the momentum entries of v, read through VM(d, x):
-// the value of v's component d at cell x
-template <int ND, class VM>
+// the value of v's component d at cell x.  FACES(d, lower_open, h_lower,
+// upper_open, h_upper) receives the face enthalpies along d as formed here.
+template <int ND, class VM, class FACES>
 __device__ __forceinline__ double pc_rhs_value(const Grid& G, const PcCoef& C, const Ijk& q, long c, double re,
-                                               Scales5 sc, VM vm) {
+                                               Scales5 sc, VM vm, FACES faces) {
     double acc = 0.0;
     for (int d = 0; d < ND; ++d) {
         const double s = sc.v[2 + d];
-        const double flo = face_h(G, C, q, c, d) * (s * vm(d, c));
+        const double hlo = face_h(G, C, q, c, d);
+        const double flo = hlo * (s * vm(d, c));
         const bool top = G.bc[d] == WALL && q.v[d] == G.n[d] - 1;
         const long up = top ? c : shifted(G, q, d, 1);  // loads issued at a top wall too, value discarded
-        const double fu = (0.5 * (C.H[c] + C.H[up])) * (s * vm(d, up));
+        const double hhi = 0.5 * (C.H[c] + C.H[up]);
+        const double fu = hhi * (s * vm(d, up));
+        faces(d, !(G.bc[d] == WALL && q.v[d] == 0), hlo, !top, hhi);
         const double fhi = top ? 0.0 : fu;
         if (G.sph) {
             const int i = q.v[0], j = q.v[1];
@@ -1094,23 +1098,45 @@ __device__ __forceinline__ double pc_rhs_value(const Grid& G, const PcCoef& C, c
     if (G.sph) rp = rp * sph_vol(G, q.v[0], q.v[1]);  // volume-weighted system
     return rp;
 }
-// The level's right-hand side at cell q stored and, with X0 (the finest
-// level's couplings formed from its cell field, unit sigma), the first
-// multigrid half-sweep's colour-0 value from x = 0 as well: gs_value's
-// first-sweep update, operation for operation, so the V-cycle skips that
-// half-sweep.
-template <typename R, int ND, bool X0>
-__device__ __forceinline__ void put_level_rhs(const Grid& G, const LevelT<R>& L0, const Ijk& q, int c, double rp) {
-    LIjk lq;
-    lq.v[0] = q.v[0];
-    lq.v[1] = q.v[1];
-    lq.v[2] = q.v[2];
-    const int e = xbq(L0, lq);
+// The level's right-hand side at cell q and, with X0 (the finest level's
+// couplings formed from the enthalpy, unit sigma), the first multigrid
+// half-sweep's colour-0 value from x = 0 as well, so the V-cycle skips that
+// half-sweep.  The couplings come from the face enthalpies the right-hand
+// side has just formed (the sums qf_coupling forms from the same cells), and
+// the value is formed as gs_value forms a first-sweep value, operation for
+// operation.
+template <typename R, int ND>
+struct FirstSweep {
+    R alo[ND], ahi[ND];
+    bool hd[ND], hu[ND];
+};
+template <typename R, int ND, bool X0, class VM>
+__device__ __forceinline__ void put_level_rhs(const Grid& G, const PcCoef& C, const LevelT<R>& L0, const Ijk& q,
+                                              long c, double re, Scales5 sc, VM vm) {
+    FirstSweep<R, ND> f;
+    const bool red = ((q.v[0] + q.v[1] + q.v[2]) & 1) == 0;
+    const auto faces = [&](int d, bool lo_open, double hlo, bool hi_open, double hhi) {
+        if (!X0) return;
+        const double k0 = L0.K0[0];
+        f.hd[d] = lo_open;
+        f.hu[d] = hi_open;
+        f.alo[d] = lo_open ? (R)((k0 * hlo) * L0.i2[d]) : (R)0.0;
+        f.ahi[d] = hi_open ? (R)((k0 * hhi) * L0.i2[d]) : (R)0.0;
+    };
+    const double rp = pc_rhs_value<ND>(G, C, q, c, re, sc, vm, faces);
+    const int e = xbi(L0, q.v[0], q.v[1], q.v[2]);
     const R bq = (R)rp;
     L0.b[e] = bq;
-    if (X0 && ((q.v[0] + q.v[1] + q.v[2]) & 1) == 0) {
-        const auto zero = [](const LIjk&, int, int) { return (R)0.0; };
-        L0.x[e] = gs_value_bv<R, ND, true, true, true>(G, L0, bq, zero, lq, c);
+    if (X0 && red) {
+        R num = bq, den = (R)1.0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) {
+            num = f.hd[d] ? num + f.alo[d] * (R)0.0 : num;
+            num = f.hu[d] ? num + f.ahi[d] * (R)0.0 : num;
+            den = den + f.alo[d];
+            den = den + f.ahi[d];
+        }
+        L0.x[e] = num / den;
     }
 }
 template <typename R, int ND, bool RE, bool X0>
@@ -1121,7 +1147,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_rhs(Grid G, PcCoef C, const R* __
     if (!cell_from_launch(G, q, c)) return;
     const double re = RE ? rE[c] : sc.v[1] * (double)v[G.N + c];
     const auto vm = [&](int d, long x) { return (double)v[(long)(2 + d) * G.N + x]; };
-    put_level_rhs<R, ND, X0>(G, L0, q, (int)c, pc_rhs_value<ND>(G, C, q, c, re, sc, vm));
+    put_level_rhs<R, ND, X0>(G, C, L0, q, c, re, sc, vm);
 }
 // A Krylov basis vector v = w / hn stored (the cell's 2 + ND entries) together
 // with the acoustic right-hand side k_pc_rhs forms from it: the neighbours'
@@ -1141,7 +1167,7 @@ __global__ void __launch_bounds__(kBlock) k_store_pc_rhs(Grid G, PcCoef C, const
     for (int f = 0; f < 2 + ND; ++f) v[(long)f * G.N + c] = (R)(w[(long)f * G.N + c] / hn);
     const double re = sc.v[1] * (double)(R)(w[G.N + c] / hn);
     const auto vm = [&](int d, long x) { return (double)(R)(w[(long)(2 + d) * G.N + x] / hn); };
-    put_level_rhs<R, ND, X0>(G, L0, q, (int)c, pc_rhs_value<ND>(G, C, q, c, re, sc, vm));
+    put_level_rhs<R, ND, X0>(G, C, L0, q, c, re, sc, vm);
 }
 
 template <typename R, int ND>
