@@ -124,6 +124,29 @@ __device__ __forceinline__ bool cell_from_launch(const Grid& G, Ijk& q, long& c)
     c = flat(G, q.v[0], q.v[1], q.v[2]);
     return true;
 }
+// per-block sums of K columns with one barrier: wave shuffles, then one
+// thread per column adds the waves' values in a fixed order; t is the
+// thread's linear index in its block (waves are 64 consecutive t), and the
+// sums go to part[col * nblk + blk]
+template <int K>
+__device__ __forceinline__ void block_sum_cols(double (&acc)[K], double* __restrict__ part, int t, long blk,
+                                               long nblk) {
+    __shared__ double sh[(kBlock / 64) * K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_down(acc[i], o, 64);
+    const int lane = t & 63, wv = t >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < K; ++i) sh[wv * K + i] = acc[i];
+    }
+    __syncthreads();
+    if (t < K) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += sh[w * K + t];
+        part[(long)t * nblk + blk] = s;
+    }
+}
 // index of a workgroup's partial result (its logical tile)
 __device__ __forceinline__ int lin_block() { return (int)xcd_tile().id; }
 __device__ __forceinline__ int lin_thread() { return (int)(threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z)); }

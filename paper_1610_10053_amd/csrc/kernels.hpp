@@ -66,7 +66,16 @@ struct OutSpec {
     double* partial;     // per-block sum of (F/S)^2, or null
     double inv_scale[5]; // 1/S for the state's own norm
     double* partial_u;   // per-block sum of (u/S)^2 (OUT_CN_OLD, OUT_RESIDUAL), or null
+    // OUT_JV: the first pass of the orthogonalisation against the dotk
+    // (<= kJvDotsMax) basis vectors at dotv (FP64) or dotvf (FP32), leading
+    // dimension the vector length: per-block sums of V_i . w (columns i) and
+    // w . w (column dotk) into dot_part, column-major over the blocks
+    int dotk;
+    const double* dotv;
+    const float* dotvf;
+    double* dot_part;
 };
+constexpr int kJvDotsMax = 4;
 
 // residual.hip
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,

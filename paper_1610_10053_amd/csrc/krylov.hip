@@ -88,27 +88,6 @@ void launch_scaled_sumsq(const double* x, const Grid& G, const double* inv_scale
 // Every kernel is instantiated for the exact number K of basis vectors, so
 // the K loads of an element are issued together and all loops unroll.
 
-// per-block sums of K columns with one barrier: wave shuffles, then one
-// thread per column adds the waves' values in a fixed order
-template <int K>
-__device__ __forceinline__ void block_sum_cols(double (&acc)[K], double* __restrict__ part) {
-    __shared__ double sh[(kBlock / 64) * K];
-#pragma unroll
-    for (int i = 0; i < K; ++i)
-        for (int o = 32; o > 0; o >>= 1) acc[i] += __shfl_down(acc[i], o, 64);
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < K; ++i) sh[wv * K + i] = acc[i];
-    }
-    __syncthreads();
-    if (t < K) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += sh[w * K + t];
-        part[(long)t * gridDim.x + blockIdx.x] = s;
-    }
-}
-
 // pass 1: h_i = V_i . w (i < K) and w . w in column K
 template <typename T, int K>
 __global__ void __launch_bounds__(kBlock) k_mdot(const T* __restrict__ V, long ld, const double* __restrict__ w,
@@ -125,7 +104,7 @@ __global__ void __launch_bounds__(kBlock) k_mdot(const T* __restrict__ V, long l
         for (int i = 0; i < K; ++i) acc[i] += vv[i] * we;
         acc[K] += we * we;
     }
-    block_sum_cols<K + 1>(acc, part);
+    block_sum_cols<K + 1>(acc, part, (int)threadIdx.x, (long)blockIdx.x, (long)gridDim.x);
 }
 
 // passes 2 and 3: w -= sum_i h_i V_i (in order of i), then the new dots
@@ -155,7 +134,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const T* __restrict__ V, long
             acc[0] += we * we;
         }
     }
-    block_sum_cols<NC>(acc, part);
+    block_sum_cols<NC>(acc, part, (int)threadIdx.x, (long)blockIdx.x, (long)gridDim.x);
 }
 
 // t = sum_i y_i V_i, accumulated in order of i (then added to t when acc)

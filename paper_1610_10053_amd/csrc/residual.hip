@@ -330,7 +330,9 @@ __device__ __forceinline__ double sph_momentum(const Grid& G, const Prim& P, con
 // The outputs come as their own __restrict__ parameters (they never alias
 // an input), so that the loads of a later field need not wait for the stores
 // of an earlier one.
-template <int ND, int MODE, int PERT>
+// KD (OUT_JV only): the number of basis vectors whose dots with the product
+// are formed as its entries are (0: none)
+template <int ND, int MODE, int PERT, int KD>
 __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flux Fx, WallFlux W,
                                                 const double* __restrict__ sbal, OutSpec o,
                                                 double* __restrict__ out, double* __restrict__ out2,
@@ -338,6 +340,9 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
     Ijk q;
     long c = 0;
     double part = 0.0, part_u = 0.0;
+    double dacc[KD + 1];
+#pragma unroll
+    for (int i = 0; i <= KD; ++i) dacc[i] = 0.0;
     if (cell_from_launch(G, q, c)) {
         // consumer of field f's right-hand side Rf, called field by field in
         // order (each value is written as soon as it is formed)
@@ -369,7 +374,17 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
             } else {  // OUT_JV
                 const double e = s.eps[0];
                 const double w0 = dir_t<PERT>(s, x) - (o.h * (Rf - o.Ru[x])) / (e * s.scale[f]);  // loaded everywhere
-                out[x] = (!wallface && e != 0.0) ? w0 : 0.0;
+                const double wv = (!wallface && e != 0.0) ? w0 : 0.0;
+                out[x] = wv;
+                if (KD > 0) {
+                    const long ld = (long)(2 + ND) * G.N;
+#pragma unroll
+                    for (int i = 0; i < KD; ++i) {
+                        const double vi = PERT == 2 ? (double)o.dotvf[(long)i * ld + x] : o.dotv[(long)i * ld + x];
+                        dacc[i] += vi * wv;
+                    }
+                    dacc[KD] += wv * wv;
+                }
             }
         };
         // mass and energy in the cell
@@ -458,6 +473,9 @@ __global__ void __launch_bounds__(kBlock) k_out(Grid G, StateView s, Prim P, Flu
         const double t = block_sum(part, sh);
         if (lin_thread() == 0) partial[lin_block()] = t;
     }
+    if (KD > 0)
+        block_sum_cols<KD + 1>(dacc, o.dot_part, lin_thread(), (long)lin_block(),
+                               (long)gridDim.x * gridDim.y * gridDim.z);
     if (MODE != OUT_JV && o.partial_u) {
         __shared__ double shu[kBlock / 64];
         const double t = block_sum(part_u, shu);
@@ -504,20 +522,33 @@ __global__ void __launch_bounds__(kBlock) k_dt_partial(Grid G, Prim P, const dou
 
 // ---------------------------------------------------------------- host launchers
 
-// the output sweep's instance for the mode and the perturbation flag
+// the output sweep's instance for the mode, the perturbation flag and (for
+// products) the number of basis vectors dotted
+template <int ND, int MODE, int PERT>
+static void launch_out_k(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
+                         const double* sbal, const OutSpec& o, hipStream_t stream) {
+    const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+#define OUTK(KD) \
+    JFNK_KLAUNCH((k_out<ND, MODE, PERT, KD>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout, o.partial)
+    if (MODE == OUT_JV && PERT != 0) {
+        static_assert(kJvDotsMax == 4, "instances below");
+        switch (o.dotk) {
+            case 1: OUTK(1); return;
+            case 2: OUTK(2); return;
+            case 3: OUTK(3); return;
+            case 4: OUTK(4); return;
+            default: break;
+        }
+    }
+    OUTK(0);
+#undef OUTK
+}
 template <int ND, int MODE>
 static void launch_out_m(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
                          const double* sbal, const OutSpec& o, hipStream_t stream) {
-    const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
-    if (s.v)
-        JFNK_KLAUNCH((k_out<ND, MODE, 1>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
-                     o.partial);
-    else if (MODE == OUT_JV && s.vf)
-        JFNK_KLAUNCH((k_out<ND, MODE == OUT_JV ? MODE : OUT_JV, 2>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o,
-                     o.out, o.out2, o.rout, o.partial);
-    else
-        JFNK_KLAUNCH((k_out<ND, MODE, 0>), g, bl, 0, stream, G, s, P, Fx, W, sbal, o, o.out, o.out2, o.rout,
-                     o.partial);
+    if (s.v) launch_out_k<ND, MODE, 1>(G, s, P, Fx, W, sbal, o, stream);
+    else if (MODE == OUT_JV && s.vf) launch_out_k<ND, MODE == OUT_JV ? MODE : OUT_JV, 2>(G, s, P, Fx, W, sbal, o, stream);
+    else launch_out_k<ND, MODE, 0>(G, s, P, Fx, W, sbal, o, stream);
 }
 template <int ND>
 static void launch_out_nd(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
@@ -565,6 +596,7 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     if (o.mode == OUT_CN_OLD) b_out += 2.0 * vec;  // u read, F written
     if (o.mode == OUT_RESIDUAL) b_out += 2.0 * vec;  // u and b read
     if (o.mode == OUT_JV) b_out += dirb + vec + (gravity ? 2.0 * 8.0 * G.N * G.ndim : 0.0);  // v, R(u) [, m]
+    if (o.mode == OUT_JV && o.dotk > 0) b_out += o.dotk * (o.dotvf ? 0.5 : 1.0) * vec;      // the basis dotted
     if (o.rout) b_out += vec;
     {
         JFNK_PROFB(KC_PRIM, stream, b_prim);

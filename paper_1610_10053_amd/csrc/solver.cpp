@@ -429,6 +429,10 @@ OutSpec outspec(jfnk_problem* p, int mode, double dt, double* out, double* out2,
     o.partial = want_norm ? p->part : nullptr;
     for (int f = 0; f < 5; ++f) o.inv_scale[f] = 1.0 / p->scale[f];
     o.partial_u = nullptr;
+    o.dotk = 0;
+    o.dotv = nullptr;
+    o.dotvf = nullptr;
+    o.dot_part = nullptr;
     return o;
 }
 
@@ -671,13 +675,30 @@ void pc_apply(jfnk_problem* p, const T* v, T* z) {
 }
 
 // Jacobian-free product along v (eps already on the device), Ru = R(u)
-void jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const double* v, double* w) {
-    launch_residual(p->G, view(p, u, v), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false), p->stream);
+// With Vb (k <= kJvDotsMax basis vectors of the product's precision) the
+// output sweep also forms the first orthogonalisation pass's per-block sums
+// (V_i . w, then w . w) into p->part; returns their block count, else 0.
+int jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const double* v, double* w,
+       const double* Vb = nullptr, int k = 0) {
+    OutSpec o = outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false);
+    if (Vb && k >= 1 && k <= kJvDotsMax) {
+        o.dotk = k;
+        o.dotv = Vb;
+        o.dot_part = p->part;
+    }
+    launch_residual(p->G, view(p, u, v), p->P, p->Fx, p->W, p->sbal, o, p->stream);
+    return o.dotk ? p->ncell_blk : 0;
 }
-void jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const float* v, double* w) {
-    launch_residual(p->G, view(p, u, nullptr, v), p->P, p->Fx, p->W, p->sbal,
-                    outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false), p->stream);
+int jv(jfnk_problem* p, const double* u, const double* Ru, double dt, const float* v, double* w,
+       const float* Vb = nullptr, int k = 0) {
+    OutSpec o = outspec(p, OUT_JV, dt, w, nullptr, nullptr, Ru, false);
+    if (Vb && k >= 1 && k <= kJvDotsMax) {
+        o.dotk = k;
+        o.dotvf = Vb;
+        o.dot_part = p->part;
+    }
+    launch_residual(p->G, view(p, u, nullptr, v), p->P, p->Fx, p->W, p->sbal, o, p->stream);
+    return o.dotk ? p->ncell_blk : 0;
 }
 
 // eps for a product along x from |x|
@@ -719,7 +740,9 @@ struct GmresInfo {
 //   pc(j, v, z):   z_j = M^-1 v_j into Zb column j (not called when Zb is null:
 //                  no preconditioner, the basis vectors themselves are used);
 //                  v and z in the basis precision T;
-//   op(z, w):      w = A z for a preconditioned basis vector (precision T);
+//   op(z, w, V, k): w = A z for a preconditioned basis vector (precision T);
+//                  may also form the first CGS2 pass against V_0..V_{k-1}
+//                  (returns its partial-block count, or 0 when it did not);
 //   opx(x, t):     t = A x for the restart residual.
 // x += M^-1 V y is formed from the kept preconditioned vectors.
 // rhs_norm >= 0: |rhs| as the caller already has it (no reduction and no
@@ -773,8 +796,8 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
                 pc(j, vj, Zb + (long)j * n);
                 zj = Zb + (long)j * n;
             }
-            op(zj, w);
-            int nb = launch_mdot<T>(V, n, j + 1, w, n, p->part, p->stream);
+            int nb = op(zj, w, V, j + 1);
+            if (nb == 0) nb = launch_mdot<T>(V, n, j + 1, w, n, p->part, p->stream);
             launch_final_sum(p->part, nb, j + 2, p->dsum + D_H1, p->stream);
             nb = launch_update_mdot<T>(V, n, j + 1, p->dsum + D_H1, w, n, p->part, true, p->stream);
             launch_final_sum(p->part, nb, j + 1, p->dsum + D_H2, p->stream);
@@ -865,7 +888,7 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
     const long n = p->G.nvec;
     auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
     auto pc = [&](int, const T* v, T* z) { pc_apply<T>(p, v, z); };
-    auto op = [&](const T* z, double* w) { jv(p, u, p->Ru, dt, z, w); };
+    auto op = [&](const T* z, double* w, const T* Vb, int k) { return jv(p, u, p->Ru, dt, z, w, Vb, k); };
     auto opx = [&](const double* x, double* t) {
         eps_for(p, x);
         jv(p, u, p->Ru, dt, x, t);
@@ -1070,8 +1093,12 @@ int scalar_step(jfnk_problem* p, double dt, int flow_its) {
             if (hnsq) launch_store_scaled_dev<double>(src, dst, hnsq, n, p->stream);
             else launch_store_scaled<double>(src, dst, hn, n, p->stream);
         };
-        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op, op, keep_x,
-                              store, &gi));
+        auto op_dots = [&](const double* v, double* w, const double*, int) {
+            op(v, w);
+            return 0;
+        };
+        CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op_dots, op,
+                              keep_x, store, &gi));
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
             status = 2;
