@@ -440,6 +440,56 @@ __global__ void __launch_bounds__(kBlock) k_prolong(Grid G, LevelT<R> F, LevelT<
     const int e = xbq(F, q);
     F.x[e] = F.x[e] + prolong_cell<R, ND>(G, Cl, Cl.x, q);
 }
+// The same correction of the colour-1 cells, one thread per coarse cell
+// for its 2^(ND-1) colour-1 children (the children of a coarse cell at
+// offsets o with an odd offset sum): the parent rows one below and one above
+// along each axis are found once for all of them, each child then sums its
+// corners as prolong_cell does, in its corner order (bit d of the corner
+// picks the row on the child's side of the parent along d).
+template <typename R, int ND>
+__global__ void __launch_bounds__(kBlock) k_prolong_c1(Grid G, LevelT<R> F, LevelT<R> Cl) {
+    LIjk Q;
+    int cc;
+    if (!lcell(Cl, Q, cc)) return;
+    int P[3], side[3][2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        P[d] = Q.v[d];
+        side[d][0] = side[d][1] = P[d];
+        if (d < ND) {
+            const int n = Cl.n[d];
+            const bool wall = G.bc[d] == WALL;
+            const int lo = P[d] - 1, hi = P[d] + 1;
+            side[d][0] = lo < 0 ? (wall ? P[d] : lo + n) : lo;   // even child coordinate
+            side[d][1] = hi >= n ? (wall ? P[d] : hi - n) : hi;  // odd child coordinate
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < (1 << ND); ++o) {
+        int par = 0;
+#pragma unroll
+        for (int d = 0; d < ND; ++d) par += (o >> d) & 1;
+        if ((par & 1) == 0) continue;
+        R e = 0.0;
+#pragma unroll
+        for (int m = 0; m < (1 << ND); ++m) {
+            R w = 1.0;
+            int qq[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const bool nb = d < ND && (m & (1 << d));
+                if (d < ND) w = w * (nb ? (R)0.25 : (R)0.75);
+                qq[d] = nb ? side[d][(o >> d) & 1] : P[d];
+            }
+            e = e + w * Cl.x[xbi(Cl, qq[0], qq[1], qq[2])];
+        }
+        const int f0 = 2 * P[0] + (o & 1), f1 = 2 * P[1] + ((o >> 1) & 1),
+                  f2 = ND > 2 ? 2 * P[2] + ((o >> 2) & 1) : P[2];
+        const int fe = xbi(F, f0, f1, f2);
+        F.x[fe] = F.x[fe] + e;
+    }
+}
+
 constexpr long kGsProlongMaxCells = 1L << 18;
 // Prolongation and the first post-smoothing half-sweep (colour 0) in one
 // launch: each colour-0 cell takes its neighbours' corrected values
@@ -1023,7 +1073,7 @@ static void vcycle_level(const Grid& G, const LevelSet<R>& S, const LevelT<R>* L
         JFNK_LAUNCH_RND(G.ndim, k_prolong, R, cell_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1], -1);
     } else if (!fuse) {
         JFNK_PROFB(KC_MG_PROLONG, stream, (double)L.N * sizeof(R) + (double)S.L[l + 1].N * sizeof(R));
-        JFNK_LAUNCH_RND(G.ndim, k_prolong, R, color_grid3(L.n), bl, 0, stream, G, L, S.L[l + 1], 1);
+        JFNK_LAUNCH_RND(G.ndim, k_prolong_c1, R, cell_grid3(S.L[l + 1].n), bl, 0, stream, G, L, S.L[l + 1]);
     }
     for (int s = 0; s < nu2; ++s) {
         if (s == 0 && fuse) {

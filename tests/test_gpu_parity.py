@@ -151,6 +151,19 @@ def test_preconditioner_bitwise(torch_cuda, name, n, solver):
     assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
 
 
+@pytest.mark.parametrize("name,n", [("kh", 1024), ("rt", 512)])
+def test_large_2d_preconditioner_bitwise(torch_cuda, name, n):
+    """2D hierarchies whose finest level exceeds 2^18 cells (KH 1024^2
+    periodic, RT 512x1024 with walls along y), where the prolongation onto
+    the finest level runs one thread per coarse cell, are bit for bit the
+    oracle's multigrid preconditioner."""
+    desc, opts, u, g, o = _pair(name, n)
+    dt = o.time_step(u)["dt"]
+    g.eval_time_step(u)
+    v = _direction(desc, 6)
+    assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
+
+
 @pytest.mark.parametrize("name,n", [("kh", 32), ("tg", 16)])
 def test_preconditioner_after_steps_bitwise(torch_cuda, name, n):
     """The preconditioner applied after implicit steps, whose GMRES solves
