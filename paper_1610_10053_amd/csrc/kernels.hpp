@@ -228,7 +228,8 @@ struct PcCoef {
     double tau;
 };
 
-void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
+// diff: the conduction block's beta and W are formed too
+void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt, bool diff,
                     hipStream_t stream);
 // which = 0: acoustic operator (sig = 1, a = kap); 1: conduction (sig = 1/W, a = beta)
 template <typename R>

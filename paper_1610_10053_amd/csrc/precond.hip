@@ -16,7 +16,9 @@
 namespace jfnk {
 
 // ---------------------------------------------------------------- coefficients
-template <int ND>
+// DIFF: the conduction block is on (its couplings beta and the cells' W are
+// formed only then)
+template <int ND, bool DIFF>
 __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __restrict__ u, Prim P, PcCoef C,
                                                     double tau) {
     Ijk q;
@@ -36,18 +38,25 @@ __global__ void __launch_bounds__(kBlock) k_pc_coef(Grid G, const double* __rest
         // volume-weighted system: face area over centre distance
         const double i2 = G.sph ? sph_area(G, d, q.v[0], q.v[1]) * face_ids(G, d, q.v[0]) : G.idx[d] * G.idx[d];
         C.kap[d][c] = ((tau * tau) * G.gm1) * hf * i2;
-        C.beta[d][c] = (tau * chif) * i2;
+        if (DIFF) C.beta[d][c] = (tau * chif) * i2;
     }
-    C.W[c] = G.gm1 / P.rho[c];
+    if (DIFF) C.W[c] = G.gm1 / P.rho[c];
     C.H[c] = (E[c] + P.p[c]) / P.rho[c];
     if (G.has_chi) C.chi[c] = P.chi[c];
 }
 
-void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt,
+void launch_pc_coef(const Grid& G, const double* u, const Prim& P, const PcCoef& C, double dt, bool diff,
                     hipStream_t stream) {
     {
         JFNK_PROF(KC_PC_BUILD, stream);
-        JFNK_LAUNCH_ND(G.ndim, k_pc_coef, cell_grid3(G.n), dim3(kBx, kBy), 0, stream, G, u, P, C, 0.5 * dt);
+        const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
+        if (G.ndim == 3) {
+            if (diff) JFNK_KLAUNCH((k_pc_coef<3, true>), g, bl, 0, stream, G, u, P, C, 0.5 * dt);
+            else JFNK_KLAUNCH((k_pc_coef<3, false>), g, bl, 0, stream, G, u, P, C, 0.5 * dt);
+        } else {
+            if (diff) JFNK_KLAUNCH((k_pc_coef<2, true>), g, bl, 0, stream, G, u, P, C, 0.5 * dt);
+            else JFNK_KLAUNCH((k_pc_coef<2, false>), g, bl, 0, stream, G, u, P, C, 0.5 * dt);
+        }
     }
 }
 

@@ -533,7 +533,7 @@ int pc_build(jfnk_problem* p, const double* u, double dt, bool prim_valid) {
     p->pc_rhs_formed = false;
     if (p->opts.pc == JFNK_PC_NONE) return 0;
     if (!prim_valid) launch_prim(G, view(p, u, nullptr), p->P, p->stream);
-    launch_pc_coef(G, u, p->P, p->C, dt, p->stream);
+    launch_pc_coef(G, u, p->P, p->C, dt, p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION, p->stream);
     if (p->opts.pc_solver == JFNK_PCS_MULTIGRID) {
         const bool diff = p->opts.pc == JFNK_PC_ACOUSTIC_DIFFUSION;
         if (p->opts.prec == JFNK_MIXED) {
