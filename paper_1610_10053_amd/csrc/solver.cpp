@@ -789,6 +789,8 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
         g[0] = beta;
         int kdim = 0;
         bool conv = false;
+        // |g_j| and |g_{j-1}| of the least-squares residual before step j
+        double res_j = beta, res_jm1 = 0.0;
         for (int j = 0; j < m; ++j) {
             const T* vj = V + (long)j * n;
             const T* zj = vj;
@@ -815,13 +817,24 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
             HIPCHK(hipGetLastError());
             // on long vectors the next basis vector is stored (from |w|^2 on
             // the device, the same bits as the host's division) while the
-            // host takes the scalars; a step that ends the cycle never reads
-            // it.  On short ones the store is too brief to hide the wait and
-            // follows the read-back.
-            if (overlap)
-                CK(read_scalars_then(p, 0, D_HN + 1, hb.data(), [&] { store(w, vnext, 0.0, p->dsum + D_HN); }));
-            else
+            // host takes the scalars, unless this step ends the cycle or is
+            // expected to end the solve (the residual's last reduction
+            // ratio, applied once more, reaches the tolerance): a vector
+            // stored by a step that ends either is never read.  Otherwise,
+            // and on short vectors (where the store is too brief to hide the
+            // wait), the store follows the read-back when it is needed.
+            const bool last = j == m - 1;
+            bool spec = false;
+            if (overlap) {
+                const bool expect_end = res_jm1 > 0.0 && res_j * (res_j / res_jm1) <= eta * beta0;
+                spec = !last && !expect_end;
+                if (spec)
+                    CK(read_scalars_then(p, 0, D_HN + 1, hb.data(), [&] { store(w, vnext, 0.0, p->dsum + D_HN); }));
+                else
+                    CK(read_scalars(p, 0, D_HN + 1, hb.data()));
+            } else {
                 CK(read_mirror(p, 0, D_HN + 1, hb.data()));
+            }
             const double w0 = std::sqrt(hb[D_H1 + j + 1]);
             const double hn = std::sqrt(hb[D_HN]);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[D_H1 + i] + hb[D_H2 + i];
@@ -846,11 +859,13 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
                 conv = true;
                 break;
             }
-            if (!overlap) store(w, vnext, hn, nullptr);
             if (info->res <= eta * beta0) {
                 conv = true;
                 break;
             }
+            if (!spec && !last) store(w, vnext, hn, nullptr);
+            res_jm1 = res_j;
+            res_j = info->res;
         }
         for (int i = kdim - 1; i >= 0; --i) {
             double s = g[i];
