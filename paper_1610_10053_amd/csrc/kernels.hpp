@@ -78,8 +78,9 @@ struct OutSpec {
 constexpr int kJvDotsMax = 4;
 
 // residual.hip
+// prim_valid: P already holds the primitives of the (unperturbed) state
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
-                     const double* sbal, const OutSpec& o, hipStream_t stream);
+                     const double* sbal, const OutSpec& o, hipStream_t stream, bool prim_valid = false);
 void launch_prim(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream);
 void launch_dt_partial(const Grid& G, const Prim& P, const double* u, double* part, hipStream_t stream);
 // passive scalars: residual consumers of s_k = c_k rho under the mass fluxes

@@ -580,7 +580,7 @@ static double prim_writes(const Grid& G) {
 }
 
 void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flux& Fx, const WallFlux& W,
-                     const double* sbal, const OutSpec& o, hipStream_t stream) {
+                     const double* sbal, const OutSpec& o, hipStream_t stream, bool prim_valid) {
     const double vec = 8.0 * G.nvec;
     const double dirb = s.v ? vec : (s.vf ? 0.5 * vec : 0.0);  // the direction's bytes
     const double b_prim = vec + dirb + prim_writes(G);
@@ -598,7 +598,7 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
     if (o.mode == OUT_JV) b_out += dirb + vec + (gravity ? 2.0 * 8.0 * G.N * G.ndim : 0.0);  // v, R(u) [, m]
     if (o.mode == OUT_JV && o.dotk > 0) b_out += o.dotk * (o.dotvf ? 0.5 : 1.0) * vec;      // the basis dotted
     if (o.rout) b_out += vec;
-    {
+    if (!prim_valid) {
         JFNK_PROFB(KC_PRIM, stream, b_prim);
         launch_prim_kernel(G, s, P, stream);
     }

@@ -943,15 +943,17 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
     return rc;
 }
 
-// Newton-Raphson from u^n at dt; on failure the state is restored
-int newton(jfnk_problem* p, double dt, jfnk_step_stats* st) {
+// Newton-Raphson from u^n at dt; on failure the state is restored.
+// fresh: the caller has just evaluated the time step at u^n (the scales and
+// the primitives in P are those of u^n)
+int newton(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh) {
     const Grid& G = p->G;
     const long n = G.nvec;
     const jfnk_solver_opts& o = p->opts;
     launch_copy(p->un, p->u, n, p->stream);
-    CK(time_step(p, p->u, nullptr));  // scales from u^n
+    if (!fresh) CK(time_step(p, p->u, nullptr));  // scales (and the primitives in P) from u^n
     launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
-                    newton_spec(p, OUT_CN_OLD, dt, p->b, p->rhs, nullptr), p->stream);
+                    newton_spec(p, OUT_CN_OLD, dt, p->b, p->rhs, nullptr), p->stream, true);
     usq_from_residual(p);
     HIPCHK(hipGetLastError());
     double f0;
@@ -1136,8 +1138,8 @@ int scalar_step(jfnk_problem* p, double dt, int flow_its) {
 }
 
 // a step of the flow and then of the scalars at dt; on failure both are at u^n
-int step_at(jfnk_problem* p, double dt, jfnk_step_stats* st) {
-    int rc = newton(p, dt, st);
+int step_at(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh = false) {
+    int rc = newton(p, dt, st, fresh);
     p->sc_newton = p->sc_gmres = 0;
     if (rc == 0 && p->nscal > 0) {
         rc = scalar_step(p, dt, st ? st->newton_its : 1);
@@ -1667,7 +1669,9 @@ int jfnk_implicit_step(jfnk_problem* p, jfnk_step_stats* out) {
     if (ctrl && p->dt_ctrl > 0.0 && p->dt_ctrl < dt) dt = p->dt_ctrl;
     int rej = 0;
     for (;;) {
-        rc = step_at(p, dt, &st);
+        // the first attempt starts from the time step just evaluated at u^n;
+        // a retry re-evaluates it (the failed attempt overwrote P)
+        rc = step_at(p, dt, &st, rej == 0);
         if (rc < 0) return rc;
         if (rc == 0 || rej >= p->opts.max_halvings) break;
         rej++;
