@@ -123,7 +123,19 @@ typedef struct {
                                0 they take as many Newton iterations as the flow's solve of the
                                step did (at least one), relying on the convergence of the flow
                                alone, with no test of their own (the paper's default) */
+    int gmres_forcing;      /* JFNK_FORCING_*: the linear tolerance of each Newton iteration's GMRES
+                               solve.  FIXED (default): gmres_eta throughout.  EW: Eisenstat and
+                               Walker's choice 2 (SIAM J. Sci. Comput. 17, 1996) with gamma = 0.9,
+                               alpha = 2 and the safeguards of Kelley's inexact Newton (Iterative
+                               Methods for Linear and Nonlinear Equations, SIAM 1995, section 6.3):
+                               eta_0 = gmres_eta; then eta_k = 0.9 (f_k / f_{k-1})^2, raised to
+                               0.9 eta_{k-1}^2 when that exceeds 0.1, capped at gmres_eta, raised
+                               to 0.5 tol / f_k (tol the Newton tolerance, f_k = |S^-1 F(u_k)|)
+                               and capped at gmres_eta again (the flow's solve; the passive
+                               scalars' solve keeps gmres_eta). */
 } jfnk_solver_opts;
+#define JFNK_FORCING_FIXED 0
+#define JFNK_FORCING_EW 1
 
 /* Statistics of the last step. */
 typedef struct {

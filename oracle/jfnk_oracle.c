@@ -75,6 +75,14 @@ typedef struct {
     /* passive scalars (section 2.2): 1 their Newton iterations converge on
      * their own residual; 0 they take the flow's Newton count of the step */
     int scalar_converge;
+    /* linear tolerance of the flow's Newton iterations: 0 eta throughout,
+     * 1 Eisenstat-Walker choice 2 (or_ew_forcing) */
+    int forcing;
+    /* the last Newton solve: |S^-1 F(u_k)| for k = 0..hist_n-1 and the
+     * linear tolerance and the GMRES solve's final relative residual of
+     * iteration k (k < hist_n - 1) */
+    double hist_f[64], hist_eta[64], hist_lin[64];
+    int hist_n;
     /* spherical metric, per radial index i and colatitude index j:
      *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
      *   (cell volume Vr Vt per radian of azimuth); r2f[i] = r_{i-1/2}^2 and
@@ -1350,6 +1358,28 @@ static double field_sum(const Or *o, const double *u, int f) {
     return s;
 }
 
+/* Forcing term of inexact Newton iteration k >= 1 (the section 2 solver
+ * leaves the linear tolerance open; this is an option, not the default):
+ * Eisenstat and Walker's choice 2 (SIAM J. Sci. Comput. 17, 1996) with
+ * gamma = 0.9 and exponent 2, safeguarded as in Kelley, Iterative Methods
+ * for Linear and Nonlinear Equations (SIAM 1995), section 6.3: the ratio of
+ * the last two nonlinear residual norms squared times gamma; kept at least
+ * gamma eta_prev^2 when that exceeds 0.1 (no sudden drop of the tolerance);
+ * at most eta_max; at least half the nonlinear tolerance over the current
+ * residual (no oversolving of the last iteration); at most eta_max. */
+double or_ew_forcing(double f, double f_prev, double eta_prev, double eta_max, double tol) {
+    const double gamma = 0.9;
+    const double ratio = f / f_prev;
+    double eta = gamma * (ratio * ratio);
+    const double keep = gamma * (eta_prev * eta_prev);
+    if (keep > 0.1 && keep > eta) eta = keep;
+    if (eta > eta_max) eta = eta_max;
+    const double end = 0.5 * tol / f;
+    if (end > eta) eta = end;
+    if (eta > eta_max) eta = eta_max;
+    return eta;
+}
+
 /* Newton-Raphson on F(u) = 0 from u = u^n at a given dt; state updated in
  * place on success, restored on failure.  Returns 0 or a failure code. */
 static int newton(Or *o, double dt) {
@@ -1368,16 +1398,22 @@ static int newton(Or *o, double dt) {
     if (floor_ > tol) tol = floor_;
     int status = 0, its = 0, gits = 0;
     double max_corr = 0.0;
+    double eta = o->eta, f_prev = f0;
+    o->hist_f[0] = f0;
+    o->hist_n = 1;
     o->st_gmres_fail = 0;
     if (!isfinite(f0)) status = 3;
     while (status == 0 && f > tol) {
         if (its >= o->newton_max) { status = 1; break; }
+        if (o->forcing == 1 && its > 0) eta = or_ew_forcing(f, f_prev, eta, o->eta, tol);
+        if (its < 64) o->hist_eta[its] = eta;
         pc_build(o, u, dt);
         double urms = snorm2(o, u) / sqrt((double)o->nunk);
         PAR1 for (long q = 0; q < nv; ++q) rhsv[q] = -F[q] / scale_of(o, q);
         JCtx ctx = {o, u, o->Ru, dt, urms};
         GmresInfo gi;
-        gmres(nv, op_jv, op_pc, &ctx, rhsv, x, o->restart, o->max_cycles, o->eta, &gi);
+        gmres(nv, op_jv, op_pc, &ctx, rhsv, x, o->restart, o->max_cycles, eta, &gi);
+        if (its < 64) o->hist_lin[its] = gi.beta0 > 0.0 ? gi.res / gi.beta0 : 0.0;
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) { status = 2; o->st_gmres_fail = 1; break; }
         max_corr = 0.0;
@@ -1388,8 +1424,10 @@ static int newton(Or *o, double dt) {
         }
         cn_residual(o, u, b, dt, F);
         memcpy(o->Ru, o->R1, sizeof(double) * nv);
+        f_prev = f;
         f = snorm2(o, F);
         its++;
+        if (its < 64) { o->hist_f[its] = f; o->hist_n = its + 1; }
         if (!isfinite(f) || !all_finite(nv, u)) { status = 3; break; }
         /* density corrections converged to roundoff: the iteration has
          * reached its floor (the paper's stopping test is on density) */
@@ -1592,9 +1630,10 @@ static void or_free(Or *o) {
 /* ip: ndim, n0, n1, n2, bc0, bc1, bc2, heat_balance, newton_max, restart,
  *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles,
  *     energy form (0 total, 1 internal), geometry (0 Cartesian, 1 2D spherical),
- *     mg_light (levels of at most this many cells take V(1,1), 0 = off)
+ *     mg_light (levels of at most this many cells take V(1,1), 0 = off),
+ *     newton_target, scalar_converge, forcing (0 eta, 1 Eisenstat-Walker)
  * dp: lo0..2, hi0..2, gamma, g0..2, chi0, rtol, atol, eta, cfl_hydro,
- *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol */
+ *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol, dt_grow */
 void *or_create(const int *ip, const double *dp, const double *u0) {
     Or *o = calloc(1, sizeof(Or));
     o->ndim = ip[0];
@@ -1609,6 +1648,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->dt_grow = dp[19];
     o->newton_target = ip[21];
     o->scalar_converge = ip[22];
+    o->forcing = ip[23];
     o->dt_ctrl = 0.0;
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];
@@ -1734,6 +1774,18 @@ static void fill_stats(Or *o, double *st) {
     st[8] = o->st_energy_drift; st[9] = o->st_newton; st[10] = o->st_gmres;
     st[11] = o->st_rejections; st[12] = o->st_status; st[13] = o->st_f0; st[14] = o->st_f;
     st[15] = o->st_exit;
+}
+
+/* the last Newton solve's history (see Or.hist_*): returns the number of
+ * residual norms written to f; eta and lin receive one fewer entries */
+int or_newton_history(void *h, double *f, double *eta, double *lin, int max) {
+    Or *o = h;
+    int n = o->hist_n < max ? o->hist_n : max;
+    for (int k = 0; k < n; ++k) {
+        f[k] = o->hist_f[k];
+        if (k + 1 < n) { eta[k] = o->hist_eta[k]; lin[k] = o->hist_lin[k]; }
+    }
+    return n;
 }
 
 /* one Crank-Nicolson step at the given dt (no retry) */

@@ -43,6 +43,8 @@ def _load(threaded=False):
         "or_jv_eps": (None, [vp, _dp, _dp, C.c_double, _dp, C.c_double, _dp]),
         "or_precond": (None, [vp, _dp, C.c_double, _dp, _dp]),
         "or_newton_solve": (C.c_int, [vp, C.c_double, _dp]),
+        "or_newton_history": (C.c_int, [vp, _dp, _dp, _dp, C.c_int]),
+        "or_ew_forcing": (C.c_double, [C.c_double] * 5),
         "or_implicit_step": (C.c_int, [vp, _dp]),
         "or_get_sources": (None, [vp, _dp]),
         "or_set_scalars": (None, [vp, C.c_int, C.c_int, _dp]),
@@ -98,7 +100,8 @@ class Oracle:
                        opts["max_halvings"], opts["pc_solver"], opts["mg_nu1"], opts["mg_nu2"],
                        opts["mg_nuc"], opts["mg_cycles"], desc.get("energy_form", 0),
                        desc.get("geometry", 0), opts.get("mg_light_cells", 0),
-                       opts.get("newton_target", 0), opts.get("scalar_converge", 1)], dtype=np.int32)
+                       opts.get("newton_target", 0), opts.get("scalar_converge", 1),
+                       opts.get("gmres_forcing", 0)], dtype=np.int32)
         dp = np.array(list(desc["lo"]) + list(desc["hi"]) + [desc["gamma"]] + list(desc["g"]) +
                       [desc["chi0"], opts["newton_rtol"], opts["newton_atol"], opts["gmres_eta"],
                        opts["cfl_hydro"], opts["cfl_adv_max"], opts["cfl_rad_max"], opts["dt_max"],
@@ -211,6 +214,19 @@ class Oracle:
         st = np.empty(len(STAT_KEYS))
         rc = self._lib.or_implicit_step(self._h, _d(st))
         return rc, dict(zip(STAT_KEYS, st.tolist()))
+
+    def newton_history(self):
+        """the last Newton solve: residual norms |S^-1 F(u_k)|, and per
+        iteration the linear tolerance and the GMRES solve's final relative
+        residual"""
+        f, eta, lin = np.empty(64), np.empty(64), np.empty(64)
+        n = self._lib.or_newton_history(self._h, _d(f), _d(eta), _d(lin), 64)
+        return f[:n].copy(), eta[:n - 1].copy(), lin[:n - 1].copy()
+
+
+def ew_forcing(f, f_prev, eta_prev, eta_max, tol):
+    """the oracle's Eisenstat-Walker forcing term of a Newton iteration"""
+    return float(_load().or_ew_forcing(float(f), float(f_prev), float(eta_prev), float(eta_max), float(tol)))
 
 
 def threads(threaded=False):

@@ -195,6 +195,8 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (o->max_halvings < 0) return fail(-1, "max_halvings must be >= 0");
     if (o->newton_target < 0) return fail(-1, "newton_target must be >= 0");
     if (o->scalar_converge != 0 && o->scalar_converge != 1) return fail(-1, "scalar_converge must be 0 or 1");
+    if (o->gmres_forcing != JFNK_FORCING_FIXED && o->gmres_forcing != JFNK_FORCING_EW)
+        return fail(-1, "unknown gmres_forcing");
     if (!(o->dt_grow == o->dt_grow)) return fail(-1, "dt_grow must be a number");
     return 0;
 }
@@ -752,12 +754,12 @@ struct GmresInfo {
 //                  and returns true (info->finished) or returns false;
 //   store(w, v, hn, hnsq): the basis vector v = w / hn (hn given, or, with
 //                  hnsq, sqrt of the sum there on the device).
+// eta: the relative tolerance of this solve.
 template <typename T, class Norm, class Pc, class Op, class OpX, class Fin, class Store>
 int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* x, double* r, double* w,
-               double* t, Norm norm, Pc pc, Op op, OpX opx, Fin fin, Store store, GmresInfo* info,
+               double* t, Norm norm, Pc pc, Op op, OpX opx, Fin fin, Store store, GmresInfo* info, double eta,
                double rhs_norm = -1.0) {
     const int m = p->opts.gmres_restart;
-    const double eta = p->opts.gmres_eta;
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0), y(m, 0.0);
     // x starts at 0: the first cycle's correction is written, later ones added;
     // the residual of the first cycle is the right-hand side itself
@@ -899,7 +901,7 @@ int gmres_core(jfnk_problem* p, long n, T* V, T* Zb, const double* rhs, double* 
 
 // the flow's linear system in scaled variables, with the physics-based preconditioner
 template <typename T>
-int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double rhs_norm) {
+int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double eta, double rhs_norm) {
     const long n = p->G.nvec;
     auto norm = [&](const double* v, double* out) { return plain_norm(p, v, out); };
     auto pc = [&](int, const T* v, T* z) { pc_apply<T>(p, v, z); };
@@ -936,11 +938,29 @@ int gmres(jfnk_problem* p, const double* u, double dt, GmresInfo* info, double r
         }
     };
     const int rc = gmres_core<T>(p, n, (T*)p->V, (T*)p->Zb, p->rhs, p->x, p->r, p->w, p->t, norm, pc, op, opx, fin,
-                                 store, info, rhs_norm);
+                                 store, info, eta, rhs_norm);
     // a vector stored by a step that ended the solve is never preconditioned:
     // later applications form their own right-hand side
     p->pc_rhs_formed = false;
     return rc;
+}
+
+// Linear tolerance of Newton iteration k >= 1 under JFNK_FORCING_EW:
+// Eisenstat and Walker's choice 2 (gamma 0.9, exponent 2) with Kelley's
+// safeguards, from the residual norms f = |S^-1 F(u_k)| and f_prev of the
+// last two iterates, the previous tolerance, the cap eta_max (gmres_eta)
+// and the Newton tolerance tol.
+double ew_forcing(double f, double f_prev, double eta_prev, double eta_max, double tol) {
+    const double gamma = 0.9;
+    const double ratio = f / f_prev;
+    double eta = gamma * (ratio * ratio);
+    const double keep = gamma * (eta_prev * eta_prev);  // no sudden drop of the tolerance
+    if (keep > 0.1 && keep > eta) eta = keep;
+    if (eta > eta_max) eta = eta_max;
+    const double end = 0.5 * tol / f;  // no oversolving near the end
+    if (end > eta) eta = end;
+    if (eta > eta_max) eta = eta_max;
+    return eta;
 }
 
 // Newton-Raphson from u^n at dt; on failure the state is restored.
@@ -964,19 +984,21 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh) {
     if (floor_ > tol) tol = floor_;
     int status = 0, its = 0, gits = 0;
     double max_corr = 0.0;
+    double eta = o.gmres_eta, f_prev = f0;
     if (!std::isfinite(f0)) status = 3;
     while (status == 0 && f > tol) {
         if (its >= o.newton_max) {
             status = 1;
             break;
         }
+        if (o.gmres_forcing == JFNK_FORCING_EW && its > 0) eta = ew_forcing(f, f_prev, eta, o.gmres_eta, tol);
         // P holds the primitives of u from the residual just evaluated, and
         // the device scalar |S^-1 u|^2 was summed from the same sweep
         CK(pc_build(p, p->u, dt, true));
         GmresInfo gi;
         // the right-hand side -S^-1 F is the residual just measured: its norm
         // is f (the same squares, summed by the residual sweep's blocks)
-        int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi, f) : gmres<double>(p, p->u, dt, &gi, f);
+        int rc = o.prec == JFNK_MIXED ? gmres<float>(p, p->u, dt, &gi, eta, f) : gmres<double>(p, p->u, dt, &gi, eta, f);
         if (rc) return rc;
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
@@ -992,6 +1014,7 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh) {
         HIPCHK(hipGetLastError());
         double rb[2];
         CK(read_scalars(p, D_TMP, 2, rb));
+        f_prev = f;
         f = std::sqrt(rb[0]);
         max_corr = rb[1];
         its++;
@@ -1115,7 +1138,7 @@ int scalar_step(jfnk_problem* p, double dt, int flow_its) {
             return 0;
         };
         CK(gmres_core<double>(p, n, p->sV, nullptr, p->srhs, p->sx, p->sr, p->sw, p->stmp, norm, pc, op_dots, op,
-                              keep_x, store, &gi));
+                              keep_x, store, &gi, p->opts.gmres_eta));
         gits += gi.its;
         if (!gi.converged && gi.res >= 0.999 * gi.beta0) {
             status = 2;

@@ -33,7 +33,8 @@ class SolverOpts(C.Structure):
                 ("mg_nu2", C.c_int), ("mg_nuc", C.c_int), ("mg_cycles", C.c_int), ("prec", C.c_int),
                 ("cfl_hydro", C.c_double), ("cfl_adv_max", C.c_double), ("cfl_rad_max", C.c_double),
                 ("dt_max", C.c_double), ("max_halvings", C.c_int), ("mg_light_cells", C.c_int),
-                ("newton_target", C.c_int), ("dt_grow", C.c_double), ("scalar_converge", C.c_int)]
+                ("newton_target", C.c_int), ("dt_grow", C.c_double), ("scalar_converge", C.c_int),
+                ("gmres_forcing", C.c_int)]
 
 
 class StepStats(C.Structure):

@@ -151,6 +151,26 @@ def test_preconditioner_bitwise(torch_cuda, name, n, solver):
     assert np.array_equal(g.apply_precond(u, dt, v), o.precond(u, dt, v))
 
 
+@pytest.mark.parametrize("name,n", CASES + [("kh", 256)])
+def test_newton_solve_parity_ew_forcing(torch_cuda, name, n):
+    """Newton solves with the Eisenstat-Walker forcing of the linear
+    tolerance: the same Newton and GMRES counts as the oracle's, states within
+    1e-10 overall and per field."""
+    from workloads import FORCING_EW
+    desc, opts, u, g, o = _pair(name, n, gmres_forcing=FORCING_EW)
+    ts = o.time_step(u)
+    dt = ts["dt"]
+    rg, sg = g.newton_solve(dt)
+    ro, so = o.newton_solve(dt)
+    print("gpu", sg["newton_its"], sg["gmres_its"], "oracle", so["newton_its"], so["gmres_its"], flush=True)
+    assert rg == 0 and ro == 0
+    assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+    ug, uo = g.get_state(), o.get_state()
+    assert rel_l2(ug, uo) <= 1e-10
+    for k, e in _fields_rel(ug, uo, desc, ts["scales"]).items():
+        assert e <= 1e-10, (k, e)
+
+
 @pytest.mark.parametrize("name,n", [("kh", 1024), ("rt", 512)])
 def test_large_2d_preconditioner_bitwise(torch_cuda, name, n):
     """2D hierarchies whose finest level exceeds 2^18 cells (KH 1024^2

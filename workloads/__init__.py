@@ -7,7 +7,8 @@ preconditioner code).
 """
 from .configs import (  # noqa: F401
     BC_PERIODIC, BC_WALL, PC_NONE, PC_ACOUSTIC, PC_ACOUSTIC_DIFFUSION,
-    PREC_FP64, PREC_MIXED, PCS_MULTIGRID, PCS_ADI, ENERGY_TOTAL, ENERGY_INTERNAL, GEOM_CARTESIAN,
+    PREC_FP64, PREC_MIXED, PCS_MULTIGRID, PCS_ADI, FORCING_FIXED, FORCING_EW, ENERGY_TOTAL, ENERGY_INTERNAL,
+    GEOM_CARTESIAN,
     GEOM_SPHERICAL, CONFIG_NAMES,
     make_config, default_opts,
     n_cells, n_vars, split_state, join_state, unknown_mask, mirror_x,

@@ -44,6 +44,11 @@ PREC_MIXED = 1
 PCS_MULTIGRID = 0
 PCS_ADI = 1
 
+# the linear tolerance of each Newton iteration: gmres_eta throughout, or
+# Eisenstat-Walker choice 2 starting from (and capped at) gmres_eta
+FORCING_FIXED = 0
+FORCING_EW = 1
+
 # energy variable of the state: total energy E, or internal energy rho e (eq. 2)
 ENERGY_TOTAL = 0
 ENERGY_INTERNAL = 1
@@ -91,7 +96,8 @@ def default_opts(**over):
              pc=PC_ACOUSTIC, prec=PREC_FP64, cfl_hydro=1.0,
              cfl_adv_max=0.0, cfl_rad_max=0.0, dt_max=0.0, max_halvings=5,
              pc_solver=PCS_MULTIGRID, mg_nu1=2, mg_nu2=2, mg_nuc=4, mg_cycles=1,
-             newton_corr_tol=1e-12, mg_light_cells=0, newton_target=0, dt_grow=0.0, scalar_converge=1)
+             newton_corr_tol=1e-12, mg_light_cells=0, newton_target=0, dt_grow=0.0, scalar_converge=1,
+             gmres_forcing=0)
     for k, v in over.items():
         if k not in o:
             raise KeyError(k)
