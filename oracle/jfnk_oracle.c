@@ -23,6 +23,9 @@
  *   - physics-based preconditioner (sound waves and optionally thermal
  *     diffusion implicit): section 2, last paragraph, and section 6;
  *   - time-step choice from CFL numbers: section 2.1, eqs. (5)-(7);
+ *   - optionally, the linear tolerance of each Newton iteration from
+ *     Eisenstat and Walker's choice 2 with Kelley's safeguards (the paper
+ *     leaves it open; or_ew_forcing);
  *   - two-dimensional spherical geometry (r, theta) with azimuthal symmetry
  *     and radial gravity (section 2: constant or radial gravity as a body
  *     force; section 6: the radiative envelope in 2D spherical geometry):

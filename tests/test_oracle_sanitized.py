@@ -29,7 +29,8 @@ from oracle import Oracle
 from workloads import make_config
 for name, n, over in (("rt", 16, {}), ("kh", 16, {}), ("tg", 8, {}), ("rad", 16, {}), ("srad", 8, {}),
                       ("rt", 16, dict(energy_form=1)), ("kh", 16, dict(newton_max=4, max_halvings=6)),
-                      ("kh", 16, dict(dt_grow=1.5, newton_target=3, max_halvings=4))):
+                      ("kh", 16, dict(dt_grow=1.5, newton_target=3, max_halvings=4)),
+                      ("kh", 16, dict(gmres_forcing=1))):
     d, o, u = make_config(name, n=n, **over)
     orc = Oracle(d, o, u)
     for _ in range(2):
