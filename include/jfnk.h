@@ -133,6 +133,13 @@ typedef struct {
                                to 0.5 tol / f_k (tol the Newton tolerance, f_k = |S^-1 F(u_k)|)
                                and capped at gmres_eta again (the flow's solve; the passive
                                scalars' solve keeps gmres_eta). */
+    int newton_extrapolate; /* section 2.1 asks for efficiency within the limits; 1: the first
+                               Newton iterate of a step is u^n + (dt / dt_prev)(u^n - u^{n-1}),
+                               the linear extrapolation in time from the last two accepted
+                               states of this problem (none before its first accepted step, or
+                               after jfnk_set_state), used when its residual norm is below
+                               |S^-1 F(u^n)|; the stopping test stays relative to F(u^n).
+                               0 (default): the first iterate is u^n */
 } jfnk_solver_opts;
 #define JFNK_FORCING_FIXED 0
 #define JFNK_FORCING_EW 1
@@ -151,6 +158,9 @@ typedef struct {
                              tolerance, also when F0 already was), 1 the density-correction
                              test (max |d rho / rho| <= corr_tol) with |S^-1 F| still above
                              its tolerance, -1 failure */
+    int extrapolated;     /* newton_extrapolate: 1 when the accepted attempt started from the
+                             extrapolated iterate */
+    double f_extrap;      /* its |S^-1 F| (-1 when none was tried) */
 } jfnk_step_stats;
 
 typedef struct jfnk_problem jfnk_problem;

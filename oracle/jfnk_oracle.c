@@ -86,6 +86,13 @@ typedef struct {
      * iteration k (k < hist_n - 1) */
     double hist_f[64], hist_eta[64], hist_lin[64];
     int hist_n;
+    /* optional first Newton iterate extrapolated in time: u^n + (dt /
+     * dt_prev)(u^n - u^{n-1}) from the last two accepted states, used when
+     * its residual norm is below that of u^n */
+    int extrap, have_prev;
+    double *uprev, *ux, *Fx, dt_prev;
+    double st_fx;  /* residual norm of the extrapolated iterate (-1: none tried) */
+    int st_extrap; /* 1 when the last solve started from it */
     /* spherical metric, per radial index i and colatitude index j:
      *   Vr[i] = (r_{i+1/2}^3 - r_{i-1/2}^3)/3, Vt[j] = cos th_{j-1/2} - cos th_{j+1/2}
      *   (cell volume Vr Vt per radian of azimuth); r2f[i] = r_{i-1/2}^2 and
@@ -1401,8 +1408,26 @@ static int newton(Or *o, double dt) {
     if (floor_ > tol) tol = floor_;
     int status = 0, its = 0, gits = 0;
     double max_corr = 0.0;
-    double eta = o->eta, f_prev = f0;
-    o->hist_f[0] = f0;
+    /* optional extrapolated first iterate: kept when its residual is below
+     * F(u^n)'s; the stopping test stays relative to F(u^n) */
+    o->st_fx = -1.0;
+    o->st_extrap = 0;
+    if (o->extrap && o->have_prev && isfinite(f0)) {
+        const double r = dt / o->dt_prev;
+        for (long q = 0; q < nv; ++q) o->ux[q] = u[q] + r * (u[q] - o->uprev[q]);
+        cn_residual(o, o->ux, b, dt, o->Fx);
+        const double fx = snorm2(o, o->Fx);
+        o->st_fx = fx;
+        if (fx < f0) {
+            memcpy(u, o->ux, sizeof(double) * nv);
+            memcpy(F, o->Fx, sizeof(double) * nv);
+            memcpy(o->Ru, o->R1, sizeof(double) * nv);
+            f = fx;
+            o->st_extrap = 1;
+        }
+    }
+    double eta = o->eta, f_prev = f;
+    o->hist_f[0] = f;
     o->hist_n = 1;
     o->st_gmres_fail = 0;
     if (!isfinite(f0)) status = 3;
@@ -1607,6 +1632,12 @@ static int step_at(Or *o, double dt) {
         s = scalar_step(o, dt);
         if (s != 0) memcpy(o->u, o->un, sizeof(double) * o->nvec);
     }
+    if (s == 0) {
+        /* an accepted step: u^n and its dt are the next extrapolation's past */
+        memcpy(o->uprev, o->un, sizeof(double) * o->nvec);
+        o->dt_prev = dt;
+        o->have_prev = 1;
+    }
     return s;
 }
 
@@ -1617,7 +1648,7 @@ static void or_free(Or *o) {
     double **ptrs[] = {&o->u, &o->un, &o->sbal, &o->Vr, &o->Vt, &o->r2f, &o->hr2, &o->stf, &o->rfa, &o->rc,
                        &o->ith, &o->Vrc, &o->r2c, &o->hr2c, &o->Vtc, &o->stc, &o->rho, &o->eps, &o->p, &o->T, &o->chi, &o->q,
                        &o->b, &o->F, &o->w1, &o->w2, &o->R1, &o->Ru, &o->pc_W, &o->la, &o->lb, &o->lc,
-                       &o->ld, &o->lx, &o->lt1, &o->lt2};
+                       &o->ld, &o->lx, &o->lt1, &o->lt2, &o->uprev, &o->ux, &o->Fx};
     for (size_t i = 0; i < sizeof(ptrs) / sizeof(ptrs[0]); ++i) free(*ptrs[i]);
     for (int d = 0; d < 3; ++d) {
         free(o->uf[d]); free(o->m[d]); free(o->fr[d]); free(o->fe[d]);
@@ -1634,7 +1665,8 @@ static void or_free(Or *o) {
  *     max_cycles, pc, max_halvings, pc_solver, mg_nu1, mg_nu2, mg_nuc, mg_cycles,
  *     energy form (0 total, 1 internal), geometry (0 Cartesian, 1 2D spherical),
  *     mg_light (levels of at most this many cells take V(1,1), 0 = off),
- *     newton_target, scalar_converge, forcing (0 eta, 1 Eisenstat-Walker)
+ *     newton_target, scalar_converge, forcing (0 eta, 1 Eisenstat-Walker),
+ *     extrapolate (1: extrapolated first Newton iterate)
  * dp: lo0..2, hi0..2, gamma, g0..2, chi0, rtol, atol, eta, cfl_hydro,
  *     cfl_adv_max, cfl_rad_max, dt_max, corr_tol, dt_grow */
 void *or_create(const int *ip, const double *dp, const double *u0) {
@@ -1652,6 +1684,7 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     o->newton_target = ip[21];
     o->scalar_converge = ip[22];
     o->forcing = ip[23];
+    o->extrap = ip[24];
     o->dt_ctrl = 0.0;
     for (int d = 0; d < 3; ++d) { o->lo[d] = dp[d]; o->hi[d] = dp[3 + d]; o->g[d] = dp[7 + d]; }
     o->gamma = dp[6]; o->chi0 = dp[10]; o->rtol = dp[11]; o->atol = dp[12]; o->eta = dp[13];
@@ -1673,6 +1706,9 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
     for (int d = 0; d < o->ndim; ++d) if (o->bc[d] == BC_WALL) o->nunk -= o->N / o->n[d];
     o->u = calloc(o->nvec, sizeof(double));
     o->un = calloc(o->nvec, sizeof(double));
+    o->uprev = calloc(o->nvec, sizeof(double));
+    o->ux = calloc(o->nvec, sizeof(double));
+    o->Fx = calloc(o->nvec, sizeof(double));
     o->b = calloc(o->nvec, sizeof(double));
     o->F = calloc(o->nvec, sizeof(double));
     o->w1 = calloc(o->nvec, sizeof(double));
@@ -1708,7 +1744,18 @@ void *or_create(const int *ip, const double *dp, const double *u0) {
 
 void or_destroy(void *h) { or_free((Or *)h); }
 
-void or_set_state(void *h, const double *u) { Or *o = h; memcpy(o->u, u, sizeof(double) * o->nvec); }
+void or_set_state(void *h, const double *u) {
+    Or *o = h;
+    memcpy(o->u, u, sizeof(double) * o->nvec);
+    o->have_prev = 0;
+}
+/* the last solve's extrapolated first iterate: out[0] its residual norm
+ * (-1 when none was tried), out[1] 1 when the solve started from it */
+void or_extrap_info(void *h, double *out) {
+    Or *o = h;
+    out[0] = o->st_fx;
+    out[1] = o->st_extrap;
+}
 void or_get_state(void *h, double *u) { Or *o = h; memcpy(u, o->u, sizeof(double) * o->nvec); }
 
 /* R(u) */

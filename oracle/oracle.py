@@ -45,6 +45,7 @@ def _load(threaded=False):
         "or_newton_solve": (C.c_int, [vp, C.c_double, _dp]),
         "or_newton_history": (C.c_int, [vp, _dp, _dp, _dp, C.c_int]),
         "or_ew_forcing": (C.c_double, [C.c_double] * 5),
+        "or_extrap_info": (None, [vp, _dp]),
         "or_implicit_step": (C.c_int, [vp, _dp]),
         "or_get_sources": (None, [vp, _dp]),
         "or_set_scalars": (None, [vp, C.c_int, C.c_int, _dp]),
@@ -101,7 +102,7 @@ class Oracle:
                        opts["mg_nuc"], opts["mg_cycles"], desc.get("energy_form", 0),
                        desc.get("geometry", 0), opts.get("mg_light_cells", 0),
                        opts.get("newton_target", 0), opts.get("scalar_converge", 1),
-                       opts.get("gmres_forcing", 0)], dtype=np.int32)
+                       opts.get("gmres_forcing", 0), opts.get("newton_extrapolate", 0)], dtype=np.int32)
         dp = np.array(list(desc["lo"]) + list(desc["hi"]) + [desc["gamma"]] + list(desc["g"]) +
                       [desc["chi0"], opts["newton_rtol"], opts["newton_atol"], opts["gmres_eta"],
                        opts["cfl_hydro"], opts["cfl_adv_max"], opts["cfl_rad_max"], opts["dt_max"],
@@ -222,6 +223,17 @@ class Oracle:
         f, eta, lin = np.empty(64), np.empty(64), np.empty(64)
         n = self._lib.or_newton_history(self._h, _d(f), _d(eta), _d(lin), 64)
         return f[:n].copy(), eta[:n - 1].copy(), lin[:n - 1].copy()
+
+    def extrap_info(self):
+        """the last solve's extrapolated first iterate: its residual norm
+        (-1 when none was tried) and whether the solve started from it"""
+        return _extrap_info(self._lib, self._h)
+
+
+def _extrap_info(lib, h):
+    out = np.empty(2)
+    lib.or_extrap_info(h, _d(out))
+    return float(out[0]), bool(out[1])
 
 
 def ew_forcing(f, f_prev, eta_prev, eta_max, tol):

@@ -157,6 +157,8 @@ void launch_sub(const double* a, const double* b, double* r, long n, hipStream_t
 template <typename T>
 void launch_combine_update(const T* V, long ld, int k, const double* y, const double* x, bool acc, double* u,
                            const Grid& G, const double* scale5, double* part, int nblk, hipStream_t stream);
+// out = a + r (a - b)
+void launch_extrapolate(double* out, const double* a, const double* b, double r, long n, hipStream_t stream);
 void launch_update_state(double* u, const double* x, const Grid& G, const double* scale5, double* part,
                          int nblk, hipStream_t stream);
 void launch_copy(double* dst, const double* src, long n, hipStream_t stream);

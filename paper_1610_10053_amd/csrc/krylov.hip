@@ -329,6 +329,18 @@ void launch_combine_update(const T* V, long ld, int k, const double* y, const do
 }
 
 // ---------------------------------------------------------------- small vector kernels
+// out = a + r (a - b): the state extrapolated in time from a (now) and b (one
+// step back), r the ratio of the step to the previous one
+__global__ void __launch_bounds__(kBlock) k_extrapolate(double* __restrict__ out, const double* __restrict__ a,
+                                                        const double* __restrict__ b, double r, long n) {
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        out[e] = a[e] + r * (a[e] - b[e]);
+}
+void launch_extrapolate(double* out, const double* a, const double* b, double r, long n, hipStream_t stream) {
+    JFNK_PROF(KC_OTHER, stream);
+    JFNK_KLAUNCH(k_extrapolate, dim3(grid_blocks(n, kBlock * 4)), dim3(kBlock), 0, stream, out, a, b, r, n);
+}
+
 __global__ void __launch_bounds__(kBlock) k_add(double* __restrict__ x, const double* __restrict__ z, long n) {
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         x[e] += z[e];

@@ -65,6 +65,12 @@ struct jfnk_problem {
            *r = nullptr, *w = nullptr, *t = nullptr, *z = nullptr, *s1 = nullptr,
            *s2 = nullptr;
     double* Ru = nullptr;  // R at the current Newton iterate (Jacobian-free products)
+    // the state at the start of the last accepted step and its dt (the
+    // extrapolated first iterate); have_prev false until a step is accepted
+    // and after jfnk_set_state
+    double* uprev = nullptr;
+    double dt_prev = 0.0;
+    bool have_prev = false;
     void* V = nullptr;
     void* Zb = nullptr;  // preconditioned basis vectors M^-1 v_j of a GMRES cycle (FP64, or FP32 in the mixed form)
     Prim P{};
@@ -197,6 +203,7 @@ int validate(const jfnk_problem_desc* d, const jfnk_solver_opts* o) {
     if (o->scalar_converge != 0 && o->scalar_converge != 1) return fail(-1, "scalar_converge must be 0 or 1");
     if (o->gmres_forcing != JFNK_FORCING_FIXED && o->gmres_forcing != JFNK_FORCING_EW)
         return fail(-1, "unknown gmres_forcing");
+    if (o->newton_extrapolate != 0 && o->newton_extrapolate != 1) return fail(-1, "newton_extrapolate must be 0 or 1");
     if (!(o->dt_grow == o->dt_grow)) return fail(-1, "dt_grow must be a number");
     return 0;
 }
@@ -984,7 +991,29 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh) {
     if (floor_ > tol) tol = floor_;
     int status = 0, its = 0, gits = 0;
     double max_corr = 0.0;
-    double eta = o.gmres_eta, f_prev = f0;
+    // optional extrapolated first iterate, kept when its residual is below
+    // F(u^n)'s (the stopping test stays relative to F(u^n)); the residual's
+    // outputs (right-hand side, R for the products, primitives, |S^-1 u|)
+    // are those of the iterate Newton starts from
+    int extrapolated = 0;
+    double f_extrap = -1.0;
+    if (o.newton_extrapolate && p->have_prev && std::isfinite(f0)) {
+        launch_extrapolate(p->r, p->u, p->uprev, dt / p->dt_prev, n, p->stream);
+        launch_residual(G, view(p, p->r, nullptr), p->P, p->Fx, p->W, p->sbal,
+                        newton_spec(p, OUT_RESIDUAL, dt, p->rhs, nullptr, p->b), p->stream);
+        usq_from_residual(p);
+        CK(residual_norm(p, &f_extrap));
+        if (f_extrap < f0) {
+            launch_copy(p->u, p->r, n, p->stream);
+            f = f_extrap;
+            extrapolated = 1;
+        } else {
+            launch_residual(G, view(p, p->u, nullptr), p->P, p->Fx, p->W, p->sbal,
+                            newton_spec(p, OUT_RESIDUAL, dt, p->rhs, nullptr, p->b), p->stream);
+            usq_from_residual(p);
+        }
+    }
+    double eta = o.gmres_eta, f_prev = f;
     if (!std::isfinite(f0)) status = 3;
     while (status == 0 && f > tol) {
         if (its >= o.newton_max) {
@@ -1034,6 +1063,8 @@ int newton(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh) {
         st->dt = dt;
         st->status = status;
         st->newton_exit = status != 0 ? -1 : (f > tol ? 1 : 0);
+        st->extrapolated = extrapolated;
+        st->f_extrap = f_extrap;
     }
     if (status != 0) launch_copy(p->u, p->un, n, p->stream);
     HIPCHK(hipGetLastError());
@@ -1169,6 +1200,12 @@ int step_at(jfnk_problem* p, double dt, jfnk_step_stats* st, bool fresh = false)
         if (rc != 0) launch_copy(p->u, p->un, p->G.nvec, p->stream);
         if (rc > 0 && st) st->status = rc;
     }
+    if (rc == 0) {
+        // an accepted step: u^n and its dt are the next extrapolation's past
+        launch_copy(p->uprev, p->un, p->G.nvec, p->stream);
+        p->dt_prev = dt;
+        p->have_prev = true;
+    }
     if (st) {
         st->scalar_newton_its = p->sc_newton;
         st->scalar_gmres_its = p->sc_gmres;
@@ -1297,7 +1334,7 @@ int freeze_sources(jfnk_problem* p) {
 // device bytes create_problem requests (buffer for buffer)
 size_t footprint(const Grid& G, const jfnk_solver_opts& o, int nlev, int nl[][3]) {
     const size_t nv = (size_t)G.nvec, N = (size_t)G.N;
-    size_t b = 12 * nv * 8;                                                       // vectors
+    size_t b = 13 * nv * 8;                                                       // vectors
     b += (size_t)(o.gmres_restart + 1) * nv * (o.prec == JFNK_MIXED ? 4 : 8);    // basis
     b += (size_t)o.gmres_restart * nv * (o.prec == JFNK_MIXED ? 4 : 8);          // preconditioned basis
     b += 9 * N * 8 + (size_t)(2 * G.ndim + G.ndim * G.ndim) * N * 8;             // primitives, fluxes
@@ -1433,7 +1470,7 @@ int create_problem_in(const jfnk_problem_desc* desc, const jfnk_solver_opts* opt
         if (r_) return cleanup(r_);      \
     } while (0)
     AL(p->u, n); AL(p->un, n); AL(p->b, n); AL(p->x, n); AL(p->rhs, n); AL(p->r, n); AL(p->Ru, n);
-    AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->s1, n); AL(p->s2, n);
+    AL(p->w, n); AL(p->t, n); AL(p->z, n); AL(p->s1, n); AL(p->s2, n); AL(p->uprev, n);
     if (opts->prec == JFNK_MIXED) {
         float* V = nullptr;
         AL(V, (size_t)(opts->gmres_restart + 1) * n);
@@ -1571,6 +1608,7 @@ int jfnk_set_state(jfnk_problem* p, const double* u, int on_device) {
     if (rc) return rc;
     launch_zero_walls(p->u, p->G, p->stream);
     HIPCHK(hipStreamSynchronize(p->stream));
+    p->have_prev = false;
     return 0;
 }
 

@@ -34,7 +34,7 @@ class SolverOpts(C.Structure):
                 ("cfl_hydro", C.c_double), ("cfl_adv_max", C.c_double), ("cfl_rad_max", C.c_double),
                 ("dt_max", C.c_double), ("max_halvings", C.c_int), ("mg_light_cells", C.c_int),
                 ("newton_target", C.c_int), ("dt_grow", C.c_double), ("scalar_converge", C.c_int),
-                ("gmres_forcing", C.c_int)]
+                ("gmres_forcing", C.c_int), ("newton_extrapolate", C.c_int)]
 
 
 class StepStats(C.Structure):
@@ -43,7 +43,8 @@ class StepStats(C.Structure):
                 ("mass_drift", C.c_double), ("energy_drift", C.c_double), ("f0", C.c_double),
                 ("f", C.c_double), ("newton_its", C.c_int), ("gmres_its", C.c_int),
                 ("rejections", C.c_int), ("status", C.c_int), ("wall_ms", C.c_double),
-                ("scalar_newton_its", C.c_int), ("scalar_gmres_its", C.c_int), ("newton_exit", C.c_int)]
+                ("scalar_newton_its", C.c_int), ("scalar_gmres_its", C.c_int), ("newton_exit", C.c_int),
+                ("extrapolated", C.c_int), ("f_extrap", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -171,6 +171,57 @@ def test_newton_solve_parity_ew_forcing(torch_cuda, name, n):
         assert e <= 1e-10, (k, e)
 
 
+@pytest.mark.parametrize("name,n", [("rt", 16), ("kh", 32), ("tg", 16), ("rad", 16), ("rt", None)])
+def test_steps_parity_extrapolated_first_iterate(torch_cuda, name, n):
+    """Implicit steps with the extrapolated first Newton iterate: per step the
+    same choice (taken or not) as the oracle, the same Newton and GMRES
+    counts, the extrapolated residual norm within 1e-8 relative (1e-12
+    absolute where it is a cancellation-level residual of a near-static
+    state), and the states within 1e-10 overall and per field."""
+    desc, opts, u, g, o = _pair(name, n, newton_extrapolate=1)
+    taken = 0
+    for k in range(4):
+        rg, sg = g.implicit_step()
+        ro, so = o.implicit_step()
+        fx, tk = o.extrap_info()
+        print("step", k, "gpu", sg["newton_its"], sg["gmres_its"], sg["extrapolated"], sg["f_extrap"],
+              "oracle", so["newton_its"], so["gmres_its"], tk, fx, flush=True)
+        assert rg == 0 and ro == 0
+        assert bool(sg["extrapolated"]) == tk
+        assert (sg["newton_its"], sg["gmres_its"]) == (so["newton_its"], so["gmres_its"])
+        if fx < 0.0:
+            assert sg["f_extrap"] == -1.0
+        else:
+            assert sg["f_extrap"] == pytest.approx(fx, rel=1e-8, abs=1e-12)
+        taken += tk
+    ug, uo = g.get_state(), o.get_state()
+    assert rel_l2(ug, uo) <= 1e-10
+    for k, e in _fields_rel(ug, uo, desc, o.time_step(uo)["scales"]).items():
+        assert e <= 1e-10, (k, e)
+
+
+def test_extrapolated_iterate_uniform_gravity_gpu(torch_cuda):
+    """A uniform gas under uniform gravity (m linear, E quadratic in time):
+    the GPU's extrapolated iterate after steps 0.4, 0.4 and then 0.7 is taken
+    and its residual norm is the closed form of the oracle's pin."""
+    from _helpers import desc2d, opts
+    from oracle import Oracle
+    jfnk = _lib()
+    desc = desc2d(8, 8, g=(0.3, -0.7), gamma=1.4)
+    rho, p, vx, vy = 1.3, 2.0, 0.2, -0.1
+    E0 = p / (desc["gamma"] - 1.0) + 0.5 * rho * (vx * vx + vy * vy)
+    u = np.concatenate([np.full(64, rho), np.full(64, E0), np.full(64, rho * vx), np.full(64, rho * vy)])
+    o_ = opts(newton_rtol=1e-13, newton_extrapolate=1)
+    g, o = jfnk.Problem(desc, o_, u), Oracle(desc, o_, u)
+    for dt in (0.4, 0.4):
+        assert g.newton_solve(dt)[0] == 0 and o.newton_solve(dt)[0] == 0
+    S_E = o.time_step(o.get_state())["scales"][1]
+    rg, sg = g.newton_solve(0.7)
+    assert rg == 0 and sg["extrapolated"] == 1
+    g2 = 0.3 ** 2 + 0.7 ** 2
+    assert sg["f_extrap"] == pytest.approx(8.0 * 0.5 * rho * g2 * 0.7 * (0.4 + 0.7) / S_E, rel=1e-9)
+
+
 @pytest.mark.parametrize("name,n", [("kh", 1024), ("rt", 512)])
 def test_large_2d_preconditioner_bitwise(torch_cuda, name, n):
     """2D hierarchies whose finest level exceeds 2^18 cells (KH 1024^2

@@ -97,7 +97,7 @@ def default_opts(**over):
              cfl_adv_max=0.0, cfl_rad_max=0.0, dt_max=0.0, max_halvings=5,
              pc_solver=PCS_MULTIGRID, mg_nu1=2, mg_nu2=2, mg_nuc=4, mg_cycles=1,
              newton_corr_tol=1e-12, mg_light_cells=0, newton_target=0, dt_grow=0.0, scalar_converge=1,
-             gmres_forcing=0)
+             gmres_forcing=0, newton_extrapolate=0)
     for k, v in over.items():
         if k not in o:
             raise KeyError(k)
