@@ -353,6 +353,9 @@ def main():
         "config": {"workload": "taylor_green_%d^3" % args.n, "cells": cells, "grid": desc["n"],
                    "cfl_hydro": opts["cfl_hydro"], "newton_rtol": opts["newton_rtol"],
                    "gmres_restart": opts["gmres_restart"], "preconditioner": "acoustic, %d multigrid V(2,2) cycle(s)" % opts["mg_cycles"],
+                   "first_newton_iterate": ("u^n, or its extrapolation in time from the last two accepted states "
+                                            "when that has the smaller residual; stopping test relative to F(u^n)"
+                                            if opts.get("newton_extrapolate") else "u^n"),
                    "form": main_form, "timed_steps": "steps 1..%d of the run from t=0 (warm-up on a "
                    "separate instance)" % args.steps},
         "p50_ms": s0["p50_ms"], "p99_ms": s0["p99_ms"], "first_step_ms": s0["first_step_ms"],
