@@ -118,8 +118,9 @@ typedef struct {
                                creation and after jfnk_set_opts; it survives jfnk_set_state.
                                <= 1: off, every step at its CFL dt */
     int scalar_converge;    /* passive scalars (section 2.2): 1 (default) their Newton iterations run
-                               until their own residual meets the flow's tolerances (the option of
-                               section 3.3 that "requires the scalars' corrections to converge");
+                               until their own residual meets the flow's tolerances (the option
+                               section 3.3 compares, in which the scalars' corrections must converge
+                               as far as the primary variables');
                                0 they take as many Newton iterations as the flow's solve of the
                                step did (at least one), relying on the convergence of the flow
                                alone, with no test of their own (the paper's default) */
