@@ -90,8 +90,10 @@ MG_LIGHT_CELLS = {"rt": 0, "kh": 0, "tg": 32768, "rad": 0}
 # states (used only when its residual is below F(u^n)'s), judged like the
 # linear tolerance on the full runs: on the Taylor-Green vortex at 128^3 it
 # saves a Newton iteration in the early steps (36.8 -> 34.6 ms/step over
-# steps 1-20) but nothing over the 100-step run (41.37 -> 41.32 ms/step, and
-# the internal-energy form 40.8 -> 41.3); on the shear layer and the
+# steps 1-20) but little over the 100-step run (41.37 -> 41.32 ms/step; about
+# 1 % in interleaved runs on one host, inside their spread; the internal-energy
+# form 40.8 -> 41.3), because the extrapolated residual relative to F(u^n)
+# rises from 0.16 early to 0.51 late in the run; on the shear layer and the
 # radiative layer it is never taken, on Rayleigh-Taylor taken without saving
 # an iteration.  So it is off everywhere.
 EXTRAPOLATE = {"rt": 0, "kh": 0, "tg": 0, "rad": 0}
