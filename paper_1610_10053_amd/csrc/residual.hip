@@ -215,6 +215,15 @@ __device__ __forceinline__ double uf_tangential(const Grid& G, const Prim& P, co
     return P.uf[c][flat(G, e == 0 ? a : q.v[0], e == 1 ? a : q.v[1], e == 2 ? a : q.v[2])];
 }
 
+// Momentum transported by the mass flux F through a side of a staggered
+// control volume: F times the velocity extrapolated upstream to the side
+// from the four values ua, ub | uc, ud around it (van Leer slopes).
+__device__ __forceinline__ double transported(double F, double ua, double ub, double uc, double ud) {
+    const double sl = van_leer(uc - ub, ub - ua);
+    const double sr = van_leer(ud - uc, uc - ub);
+    return F * upstream(F, ub, sl, uc, sr);
+}
+
 // Cell-centred momentum flux of component d along d at the cell with
 // coordinates x (x on or inside the domain along d).
 template <bool WALLS>
@@ -227,9 +236,7 @@ __device__ __forceinline__ double phi_cell(const Grid& G, const Prim& P, const F
     const int a0 = x.v[d];
     const double ua = uf_normal<WALLS>(G, P, x, d, a0 - 1), ub = uf_normal<WALLS>(G, P, x, d, a0);
     const double uc = uf_normal<WALLS>(G, P, x, d, a0 + 1), ud = uf_normal<WALLS>(G, P, x, d, a0 + 2);
-    const double sl = van_leer(uc - ub, ub - ua);
-    const double sr = van_leer(ud - uc, uc - ub);
-    return Fb * upstream(Fb, ub, sl, uc, sr);
+    return transported(Fb, ua, ub, uc, ud);
 }
 
 // Edge momentum flux of component d along e != d at the lower e-side of the
@@ -251,9 +258,7 @@ __device__ __forceinline__ double phi_edge(const Grid& G, const Prim& P, const F
     }
     const double ua = uf_tangential<WALLS>(G, P, x, d, e, a0 - 2), ub = uf_tangential<WALLS>(G, P, x, d, e, a0 - 1);
     const double uc = uf_tangential<WALLS>(G, P, x, d, e, a0), ud = uf_tangential<WALLS>(G, P, x, d, e, a0 + 1);
-    const double sl = van_leer(uc - ub, ub - ua);
-    const double sr = van_leer(ud - uc, uc - ub);
-    return Gm * upstream(Gm, ub, sl, uc, sr);
+    return transported(Gm, ua, ub, uc, ud);
 }
 
 // Momentum transport fluxes of the staggered control volumes, one per
@@ -274,6 +279,62 @@ __global__ void __launch_bounds__(kBlock) k_mflux(Grid G, Prim P, Flux Fx) {
         for (int e = 0; e < ND; ++e) {
             if (e == d) continue;
             Fx.phie[d][e][c] = wallface ? 0.0 : phi_edge<WALLS>(G, P, Fx, q, d, e);
+        }
+    }
+}
+
+// The same fluxes on a 3D grid without walls, with the workgroup's in-plane
+// tile of face velocities and mass fluxes (kBx x kBy cells and 2 on every
+// in-plane side) staged in LDS: per cell 12 of the 54 loads above stay in
+// memory, those one or two planes away along z.  Every axis has at least 4
+// cells, so one periodic wrap brings each halo entry a cell of the tile reads
+// into the grid; entries still outside it (a tile wider than the grid) are
+// left unset and never read.
+constexpr int kMhx = kBx + 4, kMhy = kBy + 4;
+struct MfluxTile {
+    double uf[3][kMhy][kMhx], fr[3][kMhy][kMhx];
+};
+
+__global__ void __launch_bounds__(kBlock) k_mflux_tile3(Grid G, Prim P, Flux Fx) {
+    __shared__ MfluxTile sm;
+    const Tile tl = xcd_tile();
+    const int i0 = (int)tl.x * kBx, j0 = (int)tl.y * kBy, k = (int)tl.z;
+    const int tid = (int)(threadIdx.x + kBx * threadIdx.y);
+    for (int e = tid; e < kMhx * kMhy; e += kBlock) {
+        const int hx = e % kMhx, hy = e / kMhx;
+        int i = i0 - 2 + hx, j = j0 - 2 + hy;
+        if (i < 0) i += G.n[0];
+        else if (i >= G.n[0]) i -= G.n[0];
+        if (j < 0) j += G.n[1];
+        else if (j >= G.n[1]) j -= G.n[1];
+        if (i >= G.n[0] || j >= G.n[1]) continue;  // tile wider than the grid
+        const long c = flat(G, i, j, k);
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            sm.uf[f][hy][hx] = P.uf[f][c];
+            sm.fr[f][hy][hx] = Fx.fr[f][c];
+        }
+    }
+    __syncthreads();
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+    const int tx = (int)threadIdx.x + 2, ty = (int)threadIdx.y + 2;
+    // value of array a (component f) at s cells along axis ax from q
+    const auto at = [&](const double* const* a, const double (*t)[kMhy][kMhx], int f, int ax, int s) {
+        return ax == 2 && s != 0 ? a[f][shifted(G, q, 2, s)] : t[f][ty + (ax == 1 ? s : 0)][tx + (ax == 0 ? s : 0)];
+    };
+    const auto U = [&](int f, int ax, int s) { return at(P.uf, sm.uf, f, ax, s); };
+    const auto FR = [&](int f, int ax, int s) { return at(Fx.fr, sm.fr, f, ax, s); };
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double Fb = 0.5 * (FR(d, d, 0) + FR(d, d, 1));
+        Fx.phic[d][c] = transported(Fb, U(d, d, -1), U(d, d, 0), U(d, d, 1), U(d, d, 2));
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            if (e == d) continue;
+            const double Gm = 0.5 * (FR(e, d, -1) + FR(e, d, 0));
+            Fx.phie[d][e][c] = transported(Gm, U(d, e, -2), U(d, e, -1), U(d, e, 0), U(d, e, 1));
         }
     }
 }
@@ -611,7 +672,7 @@ void launch_residual(const Grid& G, const StateView& s, const Prim& P, const Flu
         const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
         if (G.ndim == 3) {
             if (G.has_wall) JFNK_KLAUNCH((k_mflux<3, true>), g, bl, 0, stream, G, P, Fx);
-            else JFNK_KLAUNCH((k_mflux<3, false>), g, bl, 0, stream, G, P, Fx);
+            else JFNK_KLAUNCH(k_mflux_tile3, g, bl, 0, stream, G, P, Fx);
         } else {
             if (G.has_wall) JFNK_KLAUNCH((k_mflux<2, true>), g, bl, 0, stream, G, P, Fx);
             else JFNK_KLAUNCH((k_mflux<2, false>), g, bl, 0, stream, G, P, Fx);
