@@ -68,6 +68,80 @@ __global__ void __launch_bounds__(kBlock) k_prim(Grid G, StateView s, Prim P) {
     if (G.has_wall) P.q[c] = qk;
 }
 
+// The same sweep on a 3D grid without walls, with the workgroup's in-plane
+// tile (kBx x kBy cells and 1 on every in-plane side) of the density and of
+// the momenta along x and y, each formed once (perturbed when PERT), staged
+// in LDS: per cell the loads of the neighbours one plane away along z and of
+// the cell's own energy and z momentum stay in memory.  Every axis has at
+// least 4 cells, so one periodic wrap brings each halo entry into the grid;
+// entries still outside it (a tile wider than the grid) are left unset and
+// never read.  The values and the order of the arithmetic are those of k_prim.
+constexpr int kPhx = kBx + 2, kPhy = kBy + 2;
+template <int PERT>
+__global__ void __launch_bounds__(kBlock) k_prim_tile3(Grid G, StateView s, Prim P) {
+    __shared__ double srho[kPhy][kPhx], sm0[kPhy][kPhx], sm1[kPhy][kPhx];
+    const auto st = [&](int f, long cc) { return st_t<PERT>(s, f, cc); };
+    const Tile tl = xcd_tile();
+    const int i0 = (int)tl.x * kBx, j0 = (int)tl.y * kBy, k = (int)tl.z;
+    const int tid = (int)(threadIdx.x + kBx * threadIdx.y);
+    for (int e = tid; e < kPhx * kPhy; e += kBlock) {
+        const int hx = e % kPhx, hy = e / kPhx;
+        int i = i0 - 1 + hx, j = j0 - 1 + hy;
+        if (i < 0) i += G.n[0];
+        else if (i >= G.n[0]) i -= G.n[0];
+        if (j < 0) j += G.n[1];
+        else if (j >= G.n[1]) j -= G.n[1];
+        if (i >= G.n[0] || j >= G.n[1]) continue;  // tile wider than the grid
+        const long c = flat(G, i, j, k);
+        srho[hy][hx] = st(0, c);
+        // m_x is read at the cell and its upper x neighbour, m_y at the cell
+        // and its upper y neighbour
+        if (hy >= 1 && hy <= kBy && hx >= 1) sm0[hy][hx] = st(2, c);
+        if (hx >= 1 && hx <= kBx && hy >= 1) sm1[hy][hx] = st(3, c);
+    }
+    __syncthreads();
+    Ijk q;
+    long c;
+    if (!cell_from_launch(G, q, c)) return;
+    const int tx = (int)threadIdx.x + 1, ty = (int)threadIdx.y + 1;
+    const double rho = srho[ty][tx], E = st(1, c);
+    double qk = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double rl, ru, ml, mu;
+        if (d == 0) {
+            rl = srho[ty][tx - 1];
+            ru = srho[ty][tx + 1];
+            ml = sm0[ty][tx];
+            mu = sm0[ty][tx + 1];
+        } else if (d == 1) {
+            rl = srho[ty - 1][tx];
+            ru = srho[ty + 1][tx];
+            ml = sm1[ty][tx];
+            mu = sm1[ty + 1][tx];
+        } else {
+            const long cu = shifted(G, q, 2, 1);
+            rl = st(0, shifted(G, q, 2, -1));
+            ru = st(0, cu);
+            ml = st(4, c);
+            mu = st(4, cu);
+        }
+        const double a = ml / (0.5 * (rl + rho)), b = mu / (0.5 * (rho + ru));
+        qk = qk + 0.5 * (a * a + b * b);
+        P.uf[d][c] = a;
+    }
+    const double kin = 0.5 * rho * qk;
+    const double p = G.internal ? G.gm1 * E : G.gm1 * (E - kin);  // E holds rho e in the internal form
+    P.rho[c] = rho;
+    P.p[c] = p;
+    P.eps[c] = E / rho;
+    if (G.has_chi) {
+        const double T = p / rho;
+        P.T[c] = T;
+        P.chi[c] = G.chi0 * (T * T * T);
+    }
+}
+
 // ---------------------------------------------------------------- sweep 2: fluxes on lower faces
 
 // Ghost-cell values one layer beyond a wall: temperature extrapolated
@@ -625,9 +699,15 @@ static void launch_out_nd(const Grid& G, const StateView& s, const Prim& P, cons
 static void launch_prim_kernel(const Grid& G, const StateView& s, const Prim& P, hipStream_t stream) {
     const dim3 g = cell_grid3(G.n), bl(kBx, kBy);
     if (G.ndim == 3) {
-        if (s.v) JFNK_KLAUNCH((k_prim<3, 1>), g, bl, 0, stream, G, s, P);
-        else if (s.vf) JFNK_KLAUNCH((k_prim<3, 2>), g, bl, 0, stream, G, s, P);
-        else JFNK_KLAUNCH((k_prim<3, 0>), g, bl, 0, stream, G, s, P);
+        if (G.has_wall) {
+            if (s.v) JFNK_KLAUNCH((k_prim<3, 1>), g, bl, 0, stream, G, s, P);
+            else if (s.vf) JFNK_KLAUNCH((k_prim<3, 2>), g, bl, 0, stream, G, s, P);
+            else JFNK_KLAUNCH((k_prim<3, 0>), g, bl, 0, stream, G, s, P);
+        } else {
+            if (s.v) JFNK_KLAUNCH((k_prim_tile3<1>), g, bl, 0, stream, G, s, P);
+            else if (s.vf) JFNK_KLAUNCH((k_prim_tile3<2>), g, bl, 0, stream, G, s, P);
+            else JFNK_KLAUNCH((k_prim_tile3<0>), g, bl, 0, stream, G, s, P);
+        }
     } else {
         if (s.v) JFNK_KLAUNCH((k_prim<2, 1>), g, bl, 0, stream, G, s, P);
         else if (s.vf) JFNK_KLAUNCH((k_prim<2, 2>), g, bl, 0, stream, G, s, P);
