@@ -272,6 +272,40 @@ def test_odd_and_large_coarsest_level_parity(torch_cuda, name, n):
     assert rel_l2(g.get_state(), o.get_state()) <= 1e-10
 
 
+# ---------------------------------------------------------------- ragged in-plane tiles
+
+@pytest.mark.parametrize("shape,form", [((96, 10, 6), 0), ((4, 70, 12), 1)])
+def test_periodic_3d_ragged_tiles_bitwise(torch_cuda, shape, form):
+    """A periodic 3D grid of unequal axes whose x rows end in a partial
+    64-cell tile or are narrower than one, and whose y extent ends in a
+    partial 4-row tile (the sweeps that stage in-plane tiles in LDS), in the
+    total- and internal-energy forms: residual and Jacobian-free product at a
+    common difference step bit for bit against the oracle, on a random
+    state."""
+    from oracle import Oracle
+    jfnk = _lib()
+    desc, opts, _ = make_config("tg", n=16, energy_form=ENERGY_INTERNAL if form else 0)
+    desc = dict(desc, n=list(shape))
+    N = shape[0] * shape[1] * shape[2]
+    rng = np.random.default_rng(11)
+    rho = 1.0 + 0.3 * rng.uniform(-1, 1, N)
+    E = 20.0 + rng.uniform(-1, 1, N)
+    m = 0.5 * rng.uniform(-1, 1, 3 * N)
+    u = np.concatenate([rho, E, m])
+    print("case", shape, form, flush=True)
+    g, o = jfnk.Problem(desc, opts, u), Oracle(desc, opts, u)
+    assert np.array_equal(g.eval_rhs(u), o.rhs(u))
+    ts = o.time_step(u)
+    g.eval_time_step(u)
+    dt = ts["dt"]
+    b = o.cn_old(u, dt)
+    assert np.array_equal(g.eval_cn_old(u, dt), b)
+    u1 = u + 1e-3 * np.abs(u) * _direction(desc, 6)
+    assert np.array_equal(g.eval_residual(u1, b, dt), o.residual(u1, b, dt))
+    v = _direction(desc, 7)
+    assert np.array_equal(g.apply_jv_eps(u1, b, dt, v, 1.3e-8), o.jv_eps(u1, b, dt, v, 1.3e-8))
+
+
 # ---------------------------------------------------------------- the smallest grids
 
 @pytest.mark.parametrize("name,n", [("rt", 4), ("kh", 4), ("tg", 4), ("rad", 4)])
