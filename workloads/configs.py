@@ -87,7 +87,7 @@ MG_CYCLES = {"rt": 1, "kh": 1, "tg": 2, "rad": 3}
 MG_LIGHT_CELLS = {"rt": 0, "kh": 0, "tg": 32768, "rad": 0}
 
 # The first Newton iterate extrapolated in time from the last two accepted
-# states (used only when its residual is below F(u^n)'s), judged like the
+# states (used only when its residual is below F(u^n)'s), assessed like the
 # linear tolerance on the full runs: on the Taylor-Green vortex at 128^3 it
 # saves a Newton iteration in the early steps (36.8 -> 34.6 ms/step over
 # steps 1-20) but little over the 100-step run (41.37 -> 41.32 ms/step; about
